@@ -1,0 +1,236 @@
+/*
+ * CPU oracle for partial modular polynomial evaluation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test suite, the smoke check and the CPU baseline
+ * leg of the benchmark may use it.  It shares no code with the HIP path.
+ *
+ * What it computes (paper, Section 2.1 and Section 2.3, Eq. (1)):
+ *
+ *   f = sum_i a_i x1^{d_i} x2^{e_i} x3^{g_i3} ... xn^{g_in}  over F_p,
+ *   b_t(x1, x2) = f(x1, x2, beta_3^t, ..., beta_n^t),   1 <= t <= T,
+ *
+ * and b_t is returned densely: the coefficient of x1^d x2^e in b_t is
+ *
+ *   out[t][(d,e)] = sum_{i : (d_i, e_i) = (d, e)} a_i * prod_{k=3..n} (beta_k^t)^{g_ik}  mod p.
+ *
+ * The columns are the distinct (d, e) pairs present in the input, sorted in
+ * descending lexicographic order with x1 > x2 (the monomial order named in
+ * Section 2.3 for the coefficient reductions).  Zero coefficients are kept.
+ *
+ * This is the plain definition written out: for every t the point beta^t is
+ * formed first, then every term is evaluated at it by square-and-multiply.
+ * It does NOT use the matrix method's recurrence M_i(beta^t) = m_i^t: the
+ * oracle must stay independent of the method it checks.  Every product is a
+ * 128-bit integer product reduced with the % operator, so every result is the
+ * canonical residue in [0, p).
+ *
+ * Inputs are taken as integers and reduced modulo p on entry (coefficients
+ * and base point), matching the convention that elements of F_p are residues.
+ * 0^0 is 1 (an exponent of zero contributes the factor 1 for any base).
+ *
+ * Any modulus p >= 2 is accepted here (primality is not needed for the
+ * definition); the product library restricts p further.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <pthread.h>
+
+typedef unsigned __int128 u128;
+
+static uint64_t mulmod(uint64_t a, uint64_t b, uint64_t p)
+{
+    return (uint64_t)(((u128)a * (u128)b) % p);
+}
+
+static uint64_t addmod(uint64_t a, uint64_t b, uint64_t p)
+{
+    return (uint64_t)(((u128)a + (u128)b) % p);
+}
+
+/* base^e mod p by square-and-multiply; powmod(x, 0) = 1 mod p. */
+static uint64_t powmod(uint64_t base, uint64_t e, uint64_t p)
+{
+    uint64_t r = 1 % p;
+    base %= p;
+    while (e) {
+        if (e & 1) r = mulmod(r, base, p);
+        base = mulmod(base, base, p);
+        e >>= 1;
+    }
+    return r;
+}
+
+/* descending lexicographic order on (d, e): x1 first, then x2 */
+static int key_cmp_desc(uint64_t a, uint64_t b)
+{
+    return (a > b) ? -1 : (a < b) ? 1 : 0;
+}
+
+static int cmp_u64_desc(const void *x, const void *y)
+{
+    return key_cmp_desc(*(const uint64_t *)x, *(const uint64_t *)y);
+}
+
+static uint64_t group_key(const uint32_t *row)
+{
+    return ((uint64_t)row[0] << 32) | (uint64_t)row[1];
+}
+
+/*
+ * Distinct (d, e) pairs of the s terms (row i of exps holds the exponents of
+ * x1..xn of term i), descending lexicographic order.  Writes up to s keys to
+ * gd/ge and the count to *G.  Returns 0, or -1 on allocation failure.
+ */
+int oracle_groups(uint64_t s, uint32_t n, const uint32_t *exps,
+                  uint32_t *gd, uint32_t *ge, uint64_t *G)
+{
+    *G = 0;
+    if (s == 0) return 0;
+    uint64_t *keys = (uint64_t *)malloc(s * sizeof(uint64_t));
+    if (!keys) return -1;
+    for (uint64_t i = 0; i < s; ++i) keys[i] = group_key(exps + i * n);
+    qsort(keys, s, sizeof(uint64_t), cmp_u64_desc);
+    uint64_t g = 0;
+    for (uint64_t i = 0; i < s; ++i) {
+        if (i == 0 || keys[i] != keys[i - 1]) {
+            gd[g] = (uint32_t)(keys[i] >> 32);
+            ge[g] = (uint32_t)(keys[i] & 0xffffffffu);
+            ++g;
+        }
+    }
+    *G = g;
+    free(keys);
+    return 0;
+}
+
+/* position of key in the descending list gk[0..G-1] (binary search) */
+static uint64_t find_group(const uint64_t *gk, uint64_t G, uint64_t key)
+{
+    uint64_t lo = 0, hi = G;
+    while (lo < hi) {
+        uint64_t mid = lo + (hi - lo) / 2;
+        if (gk[mid] > key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+/* One evaluation b_t: the coefficient of every group at the point beta^t. */
+static void eval_one_t(uint64_t p, uint32_t n, uint64_t s, const uint32_t *exps,
+                       const uint64_t *coeffs, const uint64_t *beta, uint64_t t,
+                       const uint64_t *gk, uint64_t G, uint64_t *row, uint64_t *bt)
+{
+    /* the point beta^t = (beta_3^t, ..., beta_n^t) */
+    for (uint32_t k = 0; k + 2 < n; ++k) bt[k] = powmod(beta[k] % p, t, p);
+    memset(row, 0, G * sizeof(uint64_t));
+    for (uint64_t i = 0; i < s; ++i) {
+        const uint32_t *r = exps + i * n;
+        uint64_t v = coeffs[i] % p;                       /* a_i */
+        for (uint32_t k = 2; k < n; ++k)                  /* * (beta_k^t)^{g_ik} */
+            v = mulmod(v, powmod(bt[k - 2], r[k], p), p);
+        uint64_t g = find_group(gk, G, group_key(r));
+        row[g] = addmod(row[g], v, p);
+    }
+}
+
+struct job {
+    uint64_t p; uint32_t n; uint64_t s;
+    const uint32_t *exps; const uint64_t *coeffs; const uint64_t *beta;
+    const uint64_t *gk; uint64_t G;
+    uint64_t t_first, t_count, t0;
+    uint64_t *out;
+    int rc;
+};
+
+static void *run_job(void *arg)
+{
+    struct job *j = (struct job *)arg;
+    uint64_t *bt = (uint64_t *)malloc((j->n > 2 ? j->n - 2 : 1) * sizeof(uint64_t));
+    if (!bt) { j->rc = -1; return NULL; }
+    for (uint64_t q = 0; q < j->t_count; ++q) {
+        uint64_t t = j->t_first + q;
+        eval_one_t(j->p, j->n, j->s, j->exps, j->coeffs, j->beta, t, j->gk, j->G,
+                   j->out + (t - j->t0) * j->G, bt);
+    }
+    free(bt);
+    j->rc = 0;
+    return NULL;
+}
+
+/*
+ * Dense bivariate images b_t for t = t0 .. t0+T-1.
+ *
+ * p >= 2; n >= 2; exps: s rows of n uint32 exponents; coeffs: s values;
+ * beta: n-2 values (beta_3..beta_n).  out: T*G values, row (t - t0) holds
+ * b_t in the column order of oracle_groups.  nthreads >= 1 splits the t range
+ * into contiguous chunks, one per thread; the result does not depend on it.
+ * Returns 0, -1 on allocation failure, -2 on invalid arguments.
+ */
+int oracle_eval(uint64_t p, uint32_t n, uint64_t s, const uint32_t *exps,
+                const uint64_t *coeffs, const uint64_t *beta, uint64_t t0, uint64_t T,
+                uint64_t *out, uint32_t nthreads)
+{
+    if (p < 2 || n < 2 || nthreads == 0) return -2;
+    if (T == 0) return 0;
+    uint32_t *gd = (uint32_t *)malloc((s ? s : 1) * sizeof(uint32_t));
+    uint32_t *ge = (uint32_t *)malloc((s ? s : 1) * sizeof(uint32_t));
+    uint64_t *gk = (uint64_t *)malloc((s ? s : 1) * sizeof(uint64_t));
+    uint64_t G = 0;
+    int rc = -1;
+    if (!gd || !ge || !gk) goto done;
+    if (oracle_groups(s, n, exps, gd, ge, &G) != 0) goto done;
+    for (uint64_t g = 0; g < G; ++g) gk[g] = ((uint64_t)gd[g] << 32) | ge[g];
+    if (G == 0) { rc = 0; goto done; }
+    {
+        if (nthreads > T) nthreads = (uint32_t)T;
+        struct job *jobs = (struct job *)calloc(nthreads, sizeof(struct job));
+        pthread_t *th = (pthread_t *)calloc(nthreads, sizeof(pthread_t));
+        if (!jobs || !th) { free(jobs); free(th); goto done; }
+        uint64_t base = T / nthreads, extra = T % nthreads, next = t0;
+        for (uint32_t w = 0; w < nthreads; ++w) {
+            uint64_t cnt = base + (w < extra ? 1 : 0);
+            jobs[w] = (struct job){p, n, s, exps, coeffs, beta, gk, G, next, cnt, t0, out, -1};
+            next += cnt;
+        }
+        rc = 0;
+        if (nthreads == 1) {
+            run_job(&jobs[0]);
+            rc = jobs[0].rc;
+        } else {
+            uint32_t started = 0;
+            for (; started < nthreads; ++started)
+                if (pthread_create(&th[started], NULL, run_job, &jobs[started]) != 0) break;
+            for (uint32_t w = 0; w < started; ++w) pthread_join(th[w], NULL);
+            if (started < nthreads) rc = -1;
+            for (uint32_t w = 0; w < started; ++w) if (jobs[w].rc) rc = jobs[w].rc;
+        }
+        free(jobs);
+        free(th);
+    }
+done:
+    free(gd); free(ge); free(gk);
+    return rc;
+}
+
+/*
+ * One coefficient: the coefficient of x1^d x2^e in b_t, straight from the
+ * definition (for spot checks at sizes where the full table is too large).
+ * Returns the canonical residue; a (d, e) absent from the input gives 0.
+ */
+uint64_t oracle_entry(uint64_t p, uint32_t n, uint64_t s, const uint32_t *exps,
+                      const uint64_t *coeffs, const uint64_t *beta, uint64_t t,
+                      uint32_t d, uint32_t e)
+{
+    uint64_t acc = 0;
+    for (uint64_t i = 0; i < s; ++i) {
+        const uint32_t *r = exps + i * n;
+        if (r[0] != d || r[1] != e) continue;
+        uint64_t v = coeffs[i] % p;
+        for (uint32_t k = 2; k < n; ++k)
+            v = mulmod(v, powmod(powmod(beta[k - 2] % p, t, p), r[k], p), p);
+        acc = addmod(acc, v, p);
+    }
+    return acc;
+}

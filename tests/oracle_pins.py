@@ -1,0 +1,302 @@
+"""Pins for the CPU oracle: checks that do not reuse the oracle's own formula.
+
+Each function takes an ``oracle.Oracle`` and raises AssertionError on a
+mismatch.  They are run as ordinary tests (test_oracle_pins.py) and against
+deliberately broken copies of the oracle (test_oracle_mutations.py), which
+must each fail at least one of them.
+
+What pins what (paper sections in brackets):
+
+* ``pin_full_point_bigint``: the images b_t(x1, x2) are checked by evaluating
+  f at full points (x1, x2, beta^t) over the integers, with no modular
+  reduction until the very end [Section 2.1, definition of b_t].  This never
+  groups terms and never forms coefficients, so it is a different
+  computation from the oracle's.
+* ``pin_small_prime_exhaustive``: for p <= 13 and x1, x2 degrees < p, equality
+  of b_t as a function on all of F_p^2 fixes every coefficient; all base
+  points in F_p^{n-2} (zero included) are tried, and Fermat periodicity
+  b_{t+p-1} = b_t is checked when no beta_k is zero.
+* ``pin_closed_forms``: single term a*x1^d*x2^e*M(x) gives a*M(beta)^t at
+  (d, e) [Section 2.3: M_i(beta^t) = m_i^t]; beta = (1,..,1) gives the grouped
+  coefficient sums for every t; beta_k = 0 kills exactly the terms using x_k.
+* ``pin_linearity``: images are linear in the coefficient vector; duplicate
+  exponent rows add up.
+* ``pin_power_consistency``: row j*k of the images at beta equals row j of the
+  images at beta^k [Section 2.3: powers of beta].
+* ``pin_group_order``: columns are the distinct (d, e) in descending
+  lexicographic order [Section 2.3: lex order x1 > x2 > ... makes like
+  monomials adjacent].
+* ``pin_gcd_example``: the worked example of Section 2.1 (golden fixture).
+"""
+from __future__ import annotations
+
+import itertools
+import os
+import random
+
+import numpy as np
+
+from paper_2004_11571_amd import workloads as W
+
+PRIMES_SMALL = [2, 3, 5, 7, 11, 13]
+PRIMES_WORD = [3, 5, 7, 13, W.P31, W.P50, W.P63]
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def image_at(out_row, gd, ge, x1, x2, p):
+    """Evaluate a dense bivariate image at (x1, x2) in F_p."""
+    acc = 0
+    for c, d, e in zip(out_row, gd, ge):
+        acc += int(c) * pow(x1, int(d), p) * pow(x2, int(e), p)
+    return acc % p
+
+
+def full_value(exps, coeffs, p, x1, x2, beta, t):
+    """f(x1, x2, beta^t) over the integers, reduced only at the end."""
+    total = 0
+    bt = [int(b) ** t for b in beta]
+    for row, a in zip(exps.tolist(), coeffs.tolist()):
+        term = int(a) * x1 ** row[0] * x2 ** row[1]
+        for k in range(2, len(row)):
+            term *= bt[k - 2] ** row[k]
+        total += term
+    return total % p
+
+
+def pin_full_point_bigint(orc, seed=1, cases=24):
+    rng = np.random.default_rng(seed)
+    pyr = random.Random(seed)
+    for case in range(cases):
+        p = PRIMES_WORD[case % len(PRIMES_WORD)]
+        n = 2 + case % 4
+        s = [1, 3, 7, 20][case % 4]
+        T = 1 + case % 6
+        poly = W.random_small(rng, p, n, s, T, dmax=5, allow_dup=(case % 3 == 0))
+        if case % 5 == 0 and p > 3:
+            poly.beta[:] = np.asarray([pyr.randrange(0, p) for _ in range(n - 2)], np.uint64)
+        out = orc.evaluate(p, poly.exps, poly.coeffs, poly.beta, T)
+        gd, ge = orc.groups(poly.exps)
+        for t in range(1, T + 1):
+            for _ in range(3):
+                x1, x2 = pyr.randrange(0, p), pyr.randrange(0, p)
+                want = full_value(poly.exps, poly.coeffs, p, x1, x2, poly.beta, t)
+                got = image_at(out[t - 1], gd, ge, x1, x2, p)
+                assert got == want, (case, p, n, s, t)
+
+
+def pin_small_prime_exhaustive(orc, seed=2, primes=PRIMES_SMALL):
+    rng = np.random.default_rng(seed)
+    for p in primes:
+        for n in ([3, 4] if p <= 7 else [3]):
+            s = 6 if p <= 3 else 12
+            exps = np.concatenate([
+                rng.integers(0, p, size=(s, 2)),            # x1, x2 degree < p
+                rng.integers(0, 2 * p + 1, size=(s, n - 2)),
+            ], axis=1).astype(np.uint32)
+            coeffs = rng.integers(0, p, size=s, dtype=np.uint64)
+            gd, ge = orc.groups(exps)
+            T = 2 * p
+            for beta in itertools.product(range(p), repeat=n - 2):
+                beta = np.asarray(beta, np.uint64)
+                out = orc.evaluate(p, exps, coeffs, beta, T)
+                for t in range(1, T + 1):
+                    for x1 in range(p):
+                        for x2 in range(p):
+                            want = full_value(exps, coeffs, p, x1, x2, beta, t)
+                            assert image_at(out[t - 1], gd, ge, x1, x2, p) == want, (p, n, tuple(beta), t)
+                if all(int(b) != 0 for b in beta):
+                    for t in range(1, T - (p - 1) + 1):
+                        assert np.array_equal(out[t - 1], out[t - 1 + p - 1]), (p, tuple(beta), t)
+
+
+def _group_sums(exps, coeffs, p):
+    sums = {}
+    for row, a in zip(exps.tolist(), coeffs.tolist()):
+        key = (row[0], row[1])
+        sums[key] = (sums.get(key, 0) + int(a)) % p
+    return sums
+
+
+def pin_closed_forms(orc, seed=3):
+    rng = np.random.default_rng(seed)
+    pyr = random.Random(seed)
+    for p in PRIMES_WORD:
+        # single term: a * x1^d x2^e * prod x_k^{g_k}  ->  a * (prod beta_k^{g_k})^t
+        for n in (2, 3, 6):
+            row = [pyr.randrange(0, 9) for _ in range(n)]
+            a = pyr.randrange(0, p)
+            beta = [pyr.randrange(1, p) if p > 2 else 1 for _ in range(n - 2)]
+            m = 1
+            for k in range(2, n):
+                m = m * pow(beta[k - 2], row[k], p) % p
+            T = 7
+            out = orc.evaluate(p, np.asarray([row], np.uint32), np.asarray([a], np.uint64),
+                               np.asarray(beta, np.uint64), T)
+            assert out.shape == (T, 1)
+            for t in range(1, T + 1):
+                assert int(out[t - 1, 0]) == a * pow(m, t, p) % p, (p, n, t)
+        # beta = (1, ..., 1): every row is the grouped coefficient sum
+        poly = W.random_small(rng, p, 5, 25, 4, dmax=3, allow_dup=True)
+        ones = np.ones(3, np.uint64)
+        out = orc.evaluate(p, poly.exps, poly.coeffs, ones, 4)
+        gd, ge = orc.groups(poly.exps)
+        sums = _group_sums(poly.exps, poly.coeffs, p)
+        for g, key in enumerate(zip(gd.tolist(), ge.tolist())):
+            for t in range(4):
+                assert int(out[t, g]) == sums[key], (p, key, t)
+        # beta_k = 0: only terms with exponent 0 in x_k survive (0^0 = 1)
+        if p > 2:
+            beta = np.asarray([pyr.randrange(1, p), 0, pyr.randrange(1, p)], np.uint64)
+            out0 = orc.evaluate(p, poly.exps, poly.coeffs, beta, 3)
+            keep = poly.exps[:, 3] == 0
+            out1 = orc.evaluate(p, poly.exps[keep], poly.coeffs[keep], beta, 3)
+            gd1, ge1 = orc.groups(poly.exps[keep])
+            col = {k: j for j, k in enumerate(zip(gd.tolist(), ge.tolist()))}
+            for j, key in enumerate(zip(gd1.tolist(), ge1.tolist())):
+                assert np.array_equal(out0[:, col[key]], out1[:, j])
+            absent = set(col) - set(zip(gd1.tolist(), ge1.tolist()))
+            for key in absent:
+                assert not out0[:, col[key]].any()
+
+
+def pin_linearity(orc, seed=4):
+    rng = np.random.default_rng(seed)
+    for p in (W.P31, W.P50, W.P63, 7):
+        poly = W.random_small(rng, p, 5, 40, 5, dmax=4)
+        a2 = rng.integers(0, p, size=poly.s, dtype=np.uint64)
+        c = int(rng.integers(1, p))
+        r1 = orc.evaluate(p, poly.exps, poly.coeffs, poly.beta, 5)
+        r2 = orc.evaluate(p, poly.exps, a2, poly.beta, 5)
+        summed = np.asarray([(int(x) + int(y)) % p for x, y in zip(poly.coeffs, a2)], np.uint64)
+        r12 = orc.evaluate(p, poly.exps, summed, poly.beta, 5)
+        for x, y, z in zip(r1.ravel(), r2.ravel(), r12.ravel()):
+            assert (int(x) + int(y)) % p == int(z)
+        scaled = np.asarray([int(x) * c % p for x in poly.coeffs], np.uint64)
+        rc = orc.evaluate(p, poly.exps, scaled, poly.beta, 5)
+        for x, z in zip(r1.ravel(), rc.ravel()):
+            assert int(x) * c % p == int(z)
+        # duplicate rows add: terms (row, a) and (row, b) == (row, a + b)
+        exps2 = np.concatenate([poly.exps, poly.exps[:5]], axis=0)
+        co2 = np.concatenate([poly.coeffs, a2[:5]])
+        merged = poly.coeffs.copy()
+        merged[:5] = [(int(x) + int(y)) % p for x, y in zip(poly.coeffs[:5], a2[:5])]
+        assert np.array_equal(orc.evaluate(p, exps2, co2, poly.beta, 5),
+                              orc.evaluate(p, poly.exps, merged, poly.beta, 5))
+
+
+def pin_power_consistency(orc, seed=5):
+    rng = np.random.default_rng(seed)
+    for p in (W.P31, W.P63, 11):
+        poly = W.random_small(rng, p, 6, 30, 12, dmax=4)
+        full = orc.evaluate(p, poly.exps, poly.coeffs, poly.beta, 12)
+        for k in (2, 3, 4):
+            bk = np.asarray([pow(int(b), k, p) for b in poly.beta], np.uint64)
+            rows = orc.evaluate(p, poly.exps, poly.coeffs, bk, 12 // k)
+            for j in range(1, 12 // k + 1):
+                assert np.array_equal(rows[j - 1], full[j * k - 1]), (p, k, j)
+        # t0 offset: rows t0.. of a longer run
+        part = orc.evaluate(p, poly.exps, poly.coeffs, poly.beta, 5, t0=6)
+        assert np.array_equal(part, full[5:10])
+
+
+def pin_group_order(orc, seed=6):
+    rng = np.random.default_rng(seed)
+    poly = W.random_small(rng, W.P31, 4, 60, 1, dmax=3, allow_dup=True)
+    gd, ge = orc.groups(poly.exps)
+    want = sorted({(r[0], r[1]) for r in poly.exps.tolist()}, reverse=True)
+    assert list(zip(gd.tolist(), ge.tolist())) == want
+    # a zero coefficient keeps its group
+    co = poly.coeffs.copy()
+    co[:] = 0
+    out = orc.evaluate(W.P31, poly.exps, co, poly.beta, 2)
+    assert out.shape == (2, len(want)) and not out.any()
+
+
+def load_golden_gcd():
+    """Parse tests/golden/gcd_example.txt into {name: (terms, beta, expected)}."""
+    polys = {}
+    cur = None
+    with open(os.path.join(GOLDEN, "gcd_example.txt")) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if not line:
+                continue
+            tok = line.split()
+            if tok[0] == "poly":
+                cur = polys.setdefault(tok[1], {"terms": [], "beta": None, "expect": {}})
+            elif tok[0] == "term":
+                cur["terms"].append((int(tok[1]), [int(x) for x in tok[2:]]))
+            elif tok[0] == "beta":
+                cur["beta"] = [int(x) for x in tok[1:]]
+            elif tok[0] == "expect":
+                cur["expect"][(int(tok[1]), int(tok[2]))] = int(tok[3])
+    return polys
+
+
+def _poly_mul(f, g, p):
+    h = {}
+    for ef, cf in f.items():
+        for eg, cg in g.items():
+            e = tuple(x + y for x, y in zip(ef, eg))
+            h[e] = (h.get(e, 0) + cf * cg) % p
+    return h
+
+
+def pin_gcd_example(orc, p=W.P63, T=5, seed=7):
+    """Section 2.1: with c = x1 x2 + x3 x4 and d = x3 - x4, d vanishes at
+    beta = (1, 1) and c becomes x1 x2 + 1, so every image of gc and gc + gd at
+    (1, 1)^t coincides (the point is unlucky); at a random beta they differ."""
+    gold = load_golden_gcd()
+    for name, spec in gold.items():
+        exps = np.asarray([e for _, e in spec["terms"]], np.uint32)
+        coeffs = np.asarray([a % p for a, _ in spec["terms"]], np.uint64)
+        out = orc.evaluate(p, exps, coeffs, np.asarray(spec["beta"], np.uint64), T)
+        gd, ge = orc.groups(exps)
+        got = {(int(d), int(e)): out[:, j] for j, (d, e) in enumerate(zip(gd, ge))}
+        for key, val in spec["expect"].items():
+            assert key in got, (name, key)
+            assert all(int(v) == val % p for v in got[key]), (name, key)
+        assert set(got) == set(spec["expect"]), name
+    rng = random.Random(seed)
+    g = {}
+    for _ in range(6):
+        g[tuple(rng.randrange(0, 3) for _ in range(4))] = rng.randrange(1, p)
+    c = {(1, 1, 0, 0): 1, (0, 0, 1, 1): 1}
+    d = {(0, 0, 1, 0): 1, (0, 0, 0, 1): p - 1}
+    f = _poly_mul(g, c, p)
+    h = dict(f)
+    for e, v in _poly_mul(g, d, p).items():
+        h[e] = (h.get(e, 0) + v) % p
+
+    def run(poly, beta):
+        ex = np.asarray(list(poly.keys()), np.uint32)
+        co = np.asarray(list(poly.values()), np.uint64)
+        out = orc.evaluate(p, ex, co, np.asarray(beta, np.uint64), T)
+        gd, ge = orc.groups(ex)
+        return {(int(a), int(b)): out[:, j] for j, (a, b) in enumerate(zip(gd, ge))}
+
+    def same(u, v):
+        keys = set(u) | set(v)
+        zero = np.zeros(T, np.uint64)
+        return all(np.array_equal(u.get(k, zero), v.get(k, zero)) for k in keys)
+
+    assert same(run(f, [1, 1]), run(h, [1, 1]))
+    beta = [rng.randrange(2, p), rng.randrange(2, p)]
+    assert not same(run(f, beta), run(h, beta))
+    # image of f at (1,1)^t is g(x1, x2, 1, 1) * (x1 x2 + 1)
+    gb = {}
+    for e, v in g.items():
+        gb[(e[0], e[1])] = (gb.get((e[0], e[1]), 0) + v) % p
+    want = {}
+    for (a, b), v in gb.items():
+        for (da, db) in ((1, 1), (0, 0)):
+            k = (a + da, b + db)
+            want[k] = (want.get(k, 0) + v) % p
+    got = run(f, [1, 1])
+    for k in set(want) | set(got):
+        vals = got.get(k, np.zeros(T, np.uint64))
+        assert all(int(x) == want.get(k, 0) for x in vals), k
+
+
+ALL_PINS = [pin_full_point_bigint, pin_small_prime_exhaustive, pin_closed_forms,
+            pin_linearity, pin_power_consistency, pin_group_order, pin_gcd_example]
