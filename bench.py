@@ -1,0 +1,169 @@
+"""Benchmark: partial modular evaluation (matrix method) on one MI355X.
+
+One step = one pass of the whole evaluation path (power tables, monomial
+values and chain starts, Hadamard products with coefficient reductions,
+combine) for one resident polynomial and one base point, i.e. one
+``peval_run_async`` of T evaluations.  The polynomial is ingested once before
+timing (its data is resident in HBM when the timed region starts).
+
+Default workload: n = 6 variables, 1e6 distinct terms, x1/x2 degree <= 40,
+x3..x6 total degree <= 20, p = 2^63 - 25, T = 1024 evaluations.
+
+Prints one JSON line (see the design doc for the roofline definition).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "term-evals/s mod p (terms×points) vs oracle; %roofline; p99 latency"
+
+# MI355X: 256 CUs x 64 lanes x 2.4 GHz; 32-bit integer multiplies (mul_lo,
+# mul_hi, mad_u64_u32) issue at the full VALU rate on gfx950.
+VALU_PEAK_OPS = 256 * 64 * 2.4e9
+HBM_PEAK = 8.0e12
+
+# Algorithmic VALU operations per term-evaluation: one lazy Shoup product
+# on 32-bit limbs plus one lazy addition into the coefficient sum, counting
+# each gfx950 integer instruction of the shortest sequence as one op (a
+# 32x32->64 multiply-add, a 32-bit add/sub with carry, a three-input add or a
+# 64-bit add each count once):
+#   64-bit residues: high half of x*w' (mul_hi + 3 mad_u64_u32 + one 64-bit
+#   add) = 5; low half of x*w (mad + 2 mul_lo + add3) = 4; low half of q*p
+#   = 4; x*w - q*p (sub, sub-with-borrow) = 2; 96-bit lazy sum (add, 2x
+#   add-with-carry) = 3; total 18.
+#   32-bit residues: mul_hi, mul_lo, mul_lo, sub = 4; 64-bit lazy sum = 2.
+ALGO_OPS = {8: 18, 4: 6}
+# Algorithmic HBM bytes per run: resident term data read once (coefficient
+# and n-2 16-bit exponents per term) plus the dense output written once.
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="config2", choices=["config1", "config2", "config4"])
+    ap.add_argument("--tuning", default="", help="K,P,C override")
+    ap.add_argument("--cpu-rows", type=int, default=96, help="oracle sample: first rows of the images")
+    ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def profile_traffic(kernel_sha: str, workload: str):
+    """HBM bytes per launch of the evaluation kernel from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", f"eval_kernel_{workload}_counters.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_sha = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", text)
+    m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_sha or not m_b or m_sha.group(1) != kernel_sha:
+        return None
+    return float(m_b.group(1))
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("kernels.hpp", "modarith.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2004_11571_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
+                          "design note (DESIGN.md), not implemented"}), flush=True)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2004_11571_amd import peval as PV
+    from paper_2004_11571_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    w = {"config1": W.config1, "config2": W.config2, "config4": W.config4}[args.workload]()
+    t_gen = time.time()
+    poly = PV.Poly(w.p, w.exps, w.coeffs)
+    create_s = time.time() - t_gen
+    if args.tuning:
+        poly.set_tuning(*[int(x) for x in args.tuning.split(",")])
+    K, P, C = poly.get_tuning(w.T)
+    dt = torch.int64 if poly.elem_bytes == 8 else torch.int32
+    out = torch.empty((w.T, poly.G), dtype=dt, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    for _ in range(args.warmup):
+        poly.run_async(w.beta, w.T, out, stream=stream)
+    torch.cuda.synchronize()
+    PV.prof_read()  # drop anything recorded so far
+    PV.prof_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        poly.run_async(w.beta, w.T, out, stream=stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    PV.prof_enable(False)
+    kern = PV.prof_read()
+
+    te = w.s * w.T
+    value = te * args.steps / elapsed
+    eval_ms, eval_n = kern["eval"]
+    eval_avg_s = eval_ms / max(eval_n, 1) / 1e3
+    te_per_launch = te * args.steps / max(eval_n, 1)
+    ops = ALGO_OPS[poly.elem_bytes]
+    achieved = ops * te_per_launch / eval_avg_s
+    sha = kernel_source_sha()
+    traffic = profile_traffic(sha, args.workload)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+            "unit": "Tops/s (int32 lane-ops)", "frac": achieved / VALU_PEAK_OPS,
+            "traffic": traffic, "kernel": "eval_kernel", "ops_per_term_eval": ops,
+            "eval_launch_ms": eval_avg_s * 1e3, "kernel_source_sha256": sha}
+
+    got = out.cpu().numpy().view(poly.dtype)
+    res = {
+        "metric": METRIC, "value": value, "unit": "term-evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64" if poly.elem_bytes == 8 else "u32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "s": w.s, "T": w.T, "p": w.p, "G": poly.G,
+                   "tuning": {"K": K, "P": P, "C": C}},
+        "roofline": roof,
+        "kernels_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in kern.items()},
+        "create_s": create_s,
+    }
+
+    if not args.no_cpu:
+        from oracle import Oracle
+        orc = Oracle()
+        rows = args.cpu_rows
+        threads = min(args.cpu_threads, rows)
+        c0 = time.perf_counter()
+        ref = orc.evaluate(w.p, w.exps, w.coeffs, w.beta, rows, t0=1, threads=threads)
+        csec = time.perf_counter() - c0
+        res["cpu_baseline"] = {"value": w.s * rows / csec, "unit": "term-evals/s", "cores": threads,
+                               "kind": "oracle", "seconds": csec,
+                               "sample": f"images b_1..b_{rows} of the same polynomial (all {w.s} terms), "
+                                         f"{threads} threads over t"}
+        res["parity_sample"] = bool(np.array_equal(got[:rows].astype(np.uint64), ref))
+    poly.destroy()
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,214 @@
+// Device modular arithmetic for gfx950.
+//
+// The paper (Section 3.1) reviews the ways to multiply modulo a word-size
+// p without a divide (floating-point quotient, Barrett, Montgomery,
+// Moller-Granlund) and builds on the FP64 FMA product of van der Hoeven,
+// Lecerf and Quintin (Alg. 2), which needs p <= 50 bits.  On gfx950 the
+// 32-bit integer multiplies (mul_lo, mul_hi, mad_u64_u32) issue at the
+// same rate as FP64 FMA, so an integer product on 32-bit limbs is exact for
+// any p < 2^63 and cheaper than Alg. 2 even for 31-bit p.
+//
+// The evaluation kernel multiplies every running value by a multiplier
+// that stays fixed for a whole run (m_i, or Gamma_i = m_i^C), which is the
+// setting of Shoup's precomputed-quotient product (V. Shoup, NTL; also
+// Harvey, "Faster arithmetic for number-theoretic transforms", 2014):
+// with w' = floor(w * 2^64 / p), q = floor(x * w' / 2^64) and
+// r = x*w - q*p (mod 2^64) lies in [0, 2p) for every x < 2^64.  So the
+// running values may stay in [0, 2p) ("lazy") and are only made canonical
+// when a coefficient is output.
+//
+// w' itself is obtained without a 128-by-64 division: r = w*2^64 mod p is a
+// Shoup product of w by the fixed constant (2^64 mod p), and since
+// w*2^64 - r is divisible by p and the quotient is below 2^64,
+// w' = (-r) * p^{-1} mod 2^64 (exact division by multiplication with the
+// inverse of p modulo 2^64; Jebelean 1993).
+//
+// Everything here is plain 32/64-bit integer code; hipcc selects
+// v_mad_u64_u32 / v_mul_hi_u32 / v_mul_lo_u32 for it.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace peval {
+
+// Per-modulus constants, computed on the host.
+struct Mod64 {
+  uint64_t p;     // odd modulus, p < 2^63
+  uint64_t pinv;  // p^{-1} mod 2^64
+  uint64_t R;     // 2^64 mod p
+  uint64_t Rq;    // floor(R * 2^64 / p)
+  uint64_t oneq;  // floor(2^64 / p)       (Shoup quotient of w = 1)
+};
+
+struct Mod32 {
+  uint32_t p;     // odd modulus, p < 2^31
+  uint32_t pinv;  // p^{-1} mod 2^32
+  uint32_t R;     // 2^32 mod p
+  uint32_t Rq;    // floor(R * 2^32 / p)
+  uint32_t oneq;  // floor(2^32 / p)
+};
+
+__device__ __forceinline__ uint64_t mad_wide(uint32_t a, uint32_t b, uint64_t c) {
+  return (uint64_t)a * b + c;
+}
+
+// floor(a * b / 2^64) from four 32x32 products.
+__device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) {
+  uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  uint64_t t = mad_wide(a1, b0, __umulhi(a0, b0));
+  uint64_t u = mad_wide(a0, b1, (uint32_t)t);
+  return mad_wide(a1, b1, (t >> 32) + (u >> 32));
+}
+
+// ---------------------------------------------------------------------------
+// 64-bit residues (3 <= p < 2^63)
+// ---------------------------------------------------------------------------
+
+// x * w mod p in [0, 2p), for any x < 2^64, w < p, wq = floor(w 2^64 / p).
+__device__ __forceinline__ uint64_t shoup_mul(uint64_t x, uint64_t w, uint64_t wq, uint64_t p) {
+  uint64_t q = mulhi64(x, wq);
+  return x * w - q * p;
+}
+
+__device__ __forceinline__ uint64_t canon(uint64_t x, uint64_t p) {  // [0, 2p) -> [0, p)
+  return x >= p ? x - p : x;
+}
+
+// Shoup quotient floor(w 2^64 / p) of a canonical w.
+__device__ __forceinline__ uint64_t shoup_quot(uint64_t w, const Mod64 &m) {
+  uint64_t r = canon(shoup_mul(w, m.R, m.Rq, m.p), m.p);  // w 2^64 mod p
+  return (0 - r) * m.pinv;
+}
+
+// General product of canonical x, y; canonical result.
+__device__ __forceinline__ uint64_t mul_mod(uint64_t x, uint64_t y, const Mod64 &m) {
+  return canon(shoup_mul(x, y, shoup_quot(y, m), m.p), m.p);
+}
+
+__device__ __forceinline__ uint64_t add_mod(uint64_t x, uint64_t y, uint64_t p) {  // canonical in/out
+  uint64_t s = x + y;  // < 2p < 2^64
+  return s >= p ? s - p : s;
+}
+
+// Any x < 2^64 -> canonical.
+__device__ __forceinline__ uint64_t reduce64(uint64_t x, const Mod64 &m) {
+  return canon(shoup_mul(x, 1, m.oneq, m.p), m.p);
+}
+
+// hi * 2^64 + lo -> canonical (hi < 2^32).
+__device__ __forceinline__ uint64_t reduce96(uint64_t lo, uint32_t hi, const Mod64 &m) {
+  uint64_t a = canon(shoup_mul(hi, m.R, m.Rq, m.p), m.p);
+  return add_mod(a, reduce64(lo, m), m.p);
+}
+
+// base^e mod p by square-and-multiply, canonical base, e >= 0.
+__device__ __forceinline__ uint64_t pow_mod(uint64_t base, uint64_t e, const Mod64 &m) {
+  uint64_t r = 1 % m.p;
+  while (e) {
+    if (e & 1) r = mul_mod(r, base, m);
+    e >>= 1;
+    if (e) base = mul_mod(base, base, m);
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// 32-bit residues (3 <= p < 2^31)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t shoup_mul(uint32_t x, uint32_t w, uint32_t wq, uint32_t p) {
+  uint32_t q = __umulhi(x, wq);
+  return x * w - q * p;
+}
+
+__device__ __forceinline__ uint32_t canon(uint32_t x, uint32_t p) {
+  return x >= p ? x - p : x;
+}
+
+__device__ __forceinline__ uint32_t shoup_quot(uint32_t w, const Mod32 &m) {
+  uint32_t r = canon(shoup_mul(w, m.R, m.Rq, m.p), m.p);
+  return (0u - r) * m.pinv;
+}
+
+__device__ __forceinline__ uint32_t mul_mod(uint32_t x, uint32_t y, const Mod32 &m) {
+  return canon(shoup_mul(x, y, shoup_quot(y, m), m.p), m.p);
+}
+
+__device__ __forceinline__ uint32_t add_mod(uint32_t x, uint32_t y, uint32_t p) {
+  uint32_t s = x + y;  // < 2p < 2^32
+  return s >= p ? s - p : s;
+}
+
+__device__ __forceinline__ uint32_t reduce32(uint32_t x, const Mod32 &m) {
+  return canon(shoup_mul(x, 1u, m.oneq, m.p), m.p);
+}
+
+// hi * 2^32 + lo -> canonical.
+__device__ __forceinline__ uint32_t reduce64(uint64_t v, const Mod32 &m) {
+  uint32_t a = canon(shoup_mul((uint32_t)(v >> 32), m.R, m.Rq, m.p), m.p);
+  return add_mod(a, reduce32((uint32_t)v, m), m.p);
+}
+
+__device__ __forceinline__ uint32_t pow_mod(uint32_t base, uint64_t e, const Mod32 &m) {
+  uint32_t r = 1u % m.p;
+  while (e) {
+    if (e & 1) r = mul_mod(r, base, m);
+    e >>= 1;
+    if (e) base = mul_mod(base, base, m);
+  }
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Width policies used to template the kernels
+// ---------------------------------------------------------------------------
+
+// 64-bit residues; lazy sums of up to 2^32 values below 2^64 in 96 bits.
+struct W64 {
+  using T = uint64_t;
+  using M = Mod64;
+  struct Acc {
+    uint32_t w0, w1, w2;
+  };
+  static constexpr int bytes = 8;
+  __device__ static __forceinline__ Acc zero() { return Acc{0u, 0u, 0u}; }
+  __device__ static __forceinline__ void add(Acc &a, T x) {
+    unsigned c0, c1;
+    a.w0 = __builtin_addc(a.w0, (uint32_t)x, 0u, &c0);
+    a.w1 = __builtin_addc(a.w1, (uint32_t)(x >> 32), c0, &c1);
+    a.w2 += c1;
+  }
+  __device__ static __forceinline__ void add(Acc &a, const Acc &b) {
+    unsigned c0, c1;
+    a.w0 = __builtin_addc(a.w0, b.w0, 0u, &c0);
+    a.w1 = __builtin_addc(a.w1, b.w1, c0, &c1);
+    a.w2 = a.w2 + b.w2 + c1;
+  }
+  __device__ static __forceinline__ T reduce(const Acc &a, const M &m) {
+    return reduce96(((uint64_t)a.w1 << 32) | a.w0, a.w2, m);
+  }
+  __device__ static __forceinline__ T mul_lazy(T x, T w, T wq, const M &m) {
+    return shoup_mul(x, w, wq, m.p);
+  }
+};
+
+// 32-bit residues; lazy sums in 64 bits.
+struct W32 {
+  using T = uint32_t;
+  using M = Mod32;
+  struct Acc {
+    uint64_t v;
+  };
+  static constexpr int bytes = 4;
+  __device__ static __forceinline__ Acc zero() { return Acc{0}; }
+  __device__ static __forceinline__ void add(Acc &a, T x) { a.v += x; }
+  __device__ static __forceinline__ void add(Acc &a, const Acc &b) { a.v += b.v; }
+  __device__ static __forceinline__ T reduce(const Acc &a, const M &m) { return reduce64(a.v, m); }
+  __device__ static __forceinline__ T mul_lazy(T x, T w, T wq, const M &m) {
+    return shoup_mul(x, w, wq, m.p);
+  }
+};
+
+}  // namespace peval

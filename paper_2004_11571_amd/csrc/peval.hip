@@ -1,0 +1,665 @@
+// C ABI of the peval library: ingest, planning, kernel launches.
+#include "peval.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "peval_internal.hpp"
+
+using namespace peval;
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+static thread_local std::string g_last_error;
+
+static int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(e_ == hipErrorOutOfMemory ? PEVAL_ENOMEM : PEVAL_EDEVICE, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                    \
+  } while (0)
+
+#define PEVAL_TRY(expr)        \
+  do {                         \
+    int rc_ = (expr);          \
+    if (rc_ != PEVAL_OK) return rc_; \
+  } while (0)
+
+extern "C" const char *peval_strerror(int code) {
+  switch (code) {
+    case PEVAL_OK: return "ok";
+    case PEVAL_EINVAL: return "invalid argument";
+    case PEVAL_ENOMEM: return "out of memory";
+    case PEVAL_EDEVICE: return "device error";
+    case PEVAL_EUNSUPPORTED: return "unsupported input";
+    case PEVAL_EBUSY: return "busy";
+    case PEVAL_ETIMEOUT: return "timed out";
+    default: return "unknown error";
+  }
+}
+
+extern "C" const char *peval_last_error(void) { return g_last_error.c_str(); }
+
+// ---------------------------------------------------------------------------
+// per-modulus constants (host, 128-bit arithmetic)
+// ---------------------------------------------------------------------------
+typedef unsigned __int128 u128;
+
+static Mod64 make_mod64(uint64_t p) {
+  Mod64 m;
+  m.p = p;
+  uint64_t inv = p;  // Newton iteration for p^{-1} mod 2^64 (p odd)
+  for (int i = 0; i < 6; ++i) inv *= 2 - p * inv;
+  m.pinv = inv;
+  m.R = (uint64_t)(((u128)1 << 64) % p);
+  m.Rq = (uint64_t)(((u128)m.R << 64) / p);
+  m.oneq = (uint64_t)(((u128)1 << 64) / p);
+  return m;
+}
+
+static Mod32 make_mod32(uint32_t p) {
+  Mod32 m;
+  m.p = p;
+  uint32_t inv = p;
+  for (int i = 0; i < 5; ++i) inv *= 2 - p * inv;
+  m.pinv = inv;
+  m.R = (uint32_t)((1ull << 32) % p);
+  m.Rq = (uint32_t)(((uint64_t)m.R << 32) / p);
+  m.oneq = (uint32_t)((1ull << 32) / p);
+  return m;
+}
+
+// ---------------------------------------------------------------------------
+// profiling
+// ---------------------------------------------------------------------------
+namespace {
+struct ProfRec {
+  hipEvent_t a, b;
+  int kind;
+};
+std::atomic<int> g_prof{0};
+std::mutex g_prof_mu;
+std::vector<ProfRec> g_prof_recs;
+double g_prof_ms[4] = {0, 0, 0, 0};
+uint64_t g_prof_n[4] = {0, 0, 0, 0};
+
+struct ProfScope {
+  hipStream_t st;
+  int kind;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(hipStream_t s, int k) : st(s), kind(k) {
+    if (!g_prof.load()) return;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+      a = b = nullptr;
+      return;
+    }
+    (void)hipEventRecord(a, st);
+  }
+  ~ProfScope() {
+    if (!a) return;
+    (void)hipEventRecord(b, st);
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof_recs.push_back({a, b, kind});
+  }
+};
+}  // namespace
+
+extern "C" int peval_prof_enable(int enable) {
+  g_prof.store(enable ? 1 : 0);
+  return PEVAL_OK;
+}
+
+extern "C" int peval_prof_read(double *ms, uint64_t *launches) {
+  if (!ms || !launches) return fail(PEVAL_EINVAL, "null output");
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  for (auto &r : g_prof_recs) {
+    float t = 0;
+    if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+      g_prof_ms[r.kind] += t;
+      g_prof_n[r.kind] += 1;
+    }
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  g_prof_recs.clear();
+  for (int k = 0; k < 4; ++k) {
+    ms[k] = g_prof_ms[k];
+    launches[k] = g_prof_n[k];
+    g_prof_ms[k] = 0;
+    g_prof_n[k] = 0;
+  }
+  return PEVAL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// layout planning (host)
+// ---------------------------------------------------------------------------
+namespace peval {
+
+HostPlan build_host_plan(const std::vector<uint64_t> &grp_off, uint32_t K, uint32_t P) {
+  HostPlan hp;
+  const uint64_t G = grp_off.size() - 1;
+  uint64_t nt_real = 0;
+  for (uint64_t g = 0; g < G; ++g) nt_real += (grp_off[g + 1] - grp_off[g] + K - 1) / K;
+  hp.NT = std::max<uint64_t>(64, (nt_real + 63) / 64 * 64);
+  hp.NW = hp.NT / 64;
+  hp.thr_first.assign(hp.NT, 0);
+  hp.thr_cnt.assign(hp.NT, 0);
+  std::vector<uint32_t> tgrp(hp.NT, G ? (uint32_t)(G - 1) : 0);
+  uint64_t j = 0;
+  for (uint64_t g = 0; g < G; ++g) {
+    for (uint64_t f = grp_off[g]; f < grp_off[g + 1]; f += K, ++j) {
+      hp.thr_first[j] = (uint32_t)f;
+      hp.thr_cnt[j] = (uint8_t)std::min<uint64_t>(K, grp_off[g + 1] - f);
+      tgrp[j] = (uint32_t)g;
+    }
+  }
+  hp.endmask.assign(hp.NW, 0);
+  hp.slot_base.assign(hp.NW, 0);
+  std::vector<uint64_t> per_group(G ? G : 1, 0);
+  uint64_t slots = 0;
+  for (uint64_t w = 0; w < hp.NW; ++w) {
+    hp.slot_base[w] = (uint32_t)slots;
+    uint64_t mask = 0;
+    for (uint32_t l = 0; l < 64; ++l) {
+      uint64_t t = w * 64 + l;
+      bool end = (l % P == P - 1) || (t + 1 == hp.NT) || (tgrp[t] != tgrp[t + 1]);
+      if (end) {
+        mask |= 1ull << l;
+        per_group[tgrp[t]] += 1;
+        ++slots;
+      }
+    }
+    hp.endmask[w] = mask;
+  }
+  hp.nslots = slots;
+  hp.slot_off.assign(G + 1, 0);
+  for (uint64_t g = 0; g < G; ++g) hp.slot_off[g + 1] = (uint32_t)(hp.slot_off[g] + per_group[g]);
+  return hp;
+}
+
+}  // namespace peval
+
+extern "C" int peval_layout(const uint64_t *group_sizes, uint64_t G, uint32_t K, uint32_t P,
+                            uint64_t *sizes, uint32_t *thr_first, uint8_t *thr_cnt,
+                            uint64_t *endmask, uint32_t *slot_base, uint32_t *slot_off) {
+  if ((G && !group_sizes) || !sizes) return fail(PEVAL_EINVAL, "null argument");
+  if (!(K == 1 || K == 2 || K == 4 || K == 8 || K == 16)) return fail(PEVAL_EINVAL, "K=%u", K);
+  if (!(P == 8 || P == 16 || P == 32)) return fail(PEVAL_EINVAL, "P=%u", P);
+  std::vector<uint64_t> off(G + 1, 0);
+  for (uint64_t g = 0; g < G; ++g) {
+    if (group_sizes[g] == 0) return fail(PEVAL_EINVAL, "empty group %llu", (unsigned long long)g);
+    off[g + 1] = off[g] + group_sizes[g];
+  }
+  HostPlan hp = build_host_plan(off, K, P);
+  sizes[0] = hp.NT;
+  sizes[1] = hp.NW;
+  sizes[2] = hp.nslots;
+  if (thr_first) std::copy(hp.thr_first.begin(), hp.thr_first.end(), thr_first);
+  if (thr_cnt) std::copy(hp.thr_cnt.begin(), hp.thr_cnt.end(), thr_cnt);
+  if (endmask) std::copy(hp.endmask.begin(), hp.endmask.end(), endmask);
+  if (slot_base) std::copy(hp.slot_base.begin(), hp.slot_base.end(), slot_base);
+  if (slot_off) std::copy(hp.slot_off.begin(), hp.slot_off.end(), slot_off);
+  return PEVAL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+static int ensure(Scratch &sc, size_t bytes, peval_poly *h) {
+  if (sc.bytes >= bytes && sc.ptr) return PEVAL_OK;
+  if (sc.ptr) {
+    if (h->have_done) HIP_TRY(hipEventSynchronize(h->done));
+    HIP_TRY(hipFree(sc.ptr));
+    sc.ptr = nullptr;
+    sc.bytes = 0;
+  }
+  size_t want = std::max<size_t>(bytes, 256);
+  HIP_TRY(hipMalloc(&sc.ptr, want));
+  sc.bytes = want;
+  return PEVAL_OK;
+}
+
+static void release(Scratch &sc) {
+  if (sc.ptr) (void)hipFree(sc.ptr);
+  sc.ptr = nullptr;
+  sc.bytes = 0;
+}
+
+template <class T>
+static int upload(T **dptr, const std::vector<T> &v) {
+  HIP_TRY(hipMalloc((void **)dptr, std::max<size_t>(v.size() * sizeof(T), 16)));
+  if (!v.empty()) HIP_TRY(hipMemcpy(*dptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return PEVAL_OK;
+}
+
+static void free_plan(Plan &pl) {
+  (void)hipFree(pl.d_thr_first);
+  (void)hipFree(pl.d_thr_cnt);
+  (void)hipFree(pl.d_endmask);
+  (void)hipFree(pl.d_slot_base);
+  (void)hipFree(pl.d_slot_off);
+  pl = Plan();
+}
+
+static int get_plan(peval_poly *h, uint32_t K, uint32_t P, Plan **out) {
+  uint32_t key = K << 8 | P;
+  auto it = h->plans.find(key);
+  if (it != h->plans.end()) {
+    *out = &it->second;
+    return PEVAL_OK;
+  }
+  HostPlan hp = build_host_plan(h->grp_off, K, P);
+  Plan pl;
+  pl.K = K;
+  pl.P = P;
+  pl.NT = hp.NT;
+  pl.NW = hp.NW;
+  pl.nslots = hp.nslots;
+  int rc = PEVAL_OK;
+  if ((rc = upload(&pl.d_thr_first, hp.thr_first)) != PEVAL_OK ||
+      (rc = upload(&pl.d_thr_cnt, hp.thr_cnt)) != PEVAL_OK ||
+      (rc = upload(&pl.d_endmask, hp.endmask)) != PEVAL_OK ||
+      (rc = upload(&pl.d_slot_base, hp.slot_base)) != PEVAL_OK ||
+      (rc = upload(&pl.d_slot_off, hp.slot_off)) != PEVAL_OK) {
+    free_plan(pl);
+    return rc;
+  }
+  pl.device_bytes = hp.NT * 5 + hp.NW * 12 + hp.slot_off.size() * 4;
+  auto res = h->plans.emplace(key, pl);
+  *out = &res.first->second;
+  return PEVAL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// create / destroy / info
+// ---------------------------------------------------------------------------
+extern "C" int peval_create(uint64_t p, uint32_t n, uint64_t s, const uint32_t *exponents,
+                            const uint64_t *coeffs, peval_poly **out) {
+  if (!out) return fail(PEVAL_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (p < 3 || (p & 1) == 0 || p >= (1ull << 63))
+    return fail(PEVAL_EINVAL, "p must be odd with 3 <= p < 2^63 (got %llu)", (unsigned long long)p);
+  if (n < 2 || n > 32) return fail(PEVAL_EINVAL, "n must be in [2, 32] (got %u)", n);
+  if (s && (!exponents || !coeffs)) return fail(PEVAL_EINVAL, "null exponents or coefficients");
+  if (s >= (1ull << 32) - 64) return fail(PEVAL_EUNSUPPORTED, "s >= 2^32 terms");
+  const uint32_t ntail = n - 2;
+  uint32_t maxe[32] = {0};
+  for (uint64_t i = 0; i < s; ++i)
+    for (uint32_t k = 0; k < n; ++k) maxe[k] = std::max(maxe[k], exponents[i * n + k]);
+  for (uint32_t k = 2; k < n; ++k)
+    if (maxe[k] > 65535)
+      return fail(PEVAL_EUNSUPPORTED, "exponent of x%u is %u > 65535", k + 1, maxe[k]);
+
+  peval_poly *h = new (std::nothrow) peval_poly();
+  if (!h) return fail(PEVAL_ENOMEM, "host allocation");
+  h->p = p;
+  h->n = n;
+  h->s = s;
+  h->w = p < (1ull << 31) ? 4 : 8;
+  h->m64 = make_mod64(p);
+  if (h->w == 4) h->m32 = make_mod32((uint32_t)p);
+  std::copy(maxe, maxe + 32, h->max_exp);
+  uint32_t off = 0;
+  for (uint32_t k = 0; k < ntail; ++k) {
+    h->tab.off[k] = off;
+    off += maxe[k + 2] + 1;
+  }
+  h->tab.off[ntail] = off;
+  h->tab_total = off;
+
+  // A1: sort terms by (d, e) descending so that like monomials are adjacent
+  std::vector<uint32_t> order(s);
+  std::iota(order.begin(), order.end(), 0u);
+  auto key = [&](uint64_t i) { return ((uint64_t)exponents[i * n] << 32) | exponents[i * n + 1]; };
+  const uint64_t ext0 = (uint64_t)maxe[0] + 1, ext1 = (uint64_t)maxe[1] + 1;
+  if (s && ext0 <= (1ull << 24) && ext1 <= (1ull << 24) && ext0 * ext1 <= (1ull << 24)) {
+    // counting sort over the dense (d, e) grid
+    const uint64_t span = ext0 * ext1;
+    std::vector<uint32_t> cnt(span + 1, 0);
+    auto dense = [&](uint64_t i) {
+      return (uint64_t)(maxe[0] - exponents[i * n]) * ext1 + (maxe[1] - exponents[i * n + 1]);
+    };
+    for (uint64_t i = 0; i < s; ++i) cnt[dense(i) + 1]++;
+    for (uint64_t b = 0; b < span; ++b) cnt[b + 1] += cnt[b];
+    for (uint64_t i = 0; i < s; ++i) order[cnt[dense(i)]++] = (uint32_t)i;
+  } else {
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return key(a) > key(b); });
+  }
+  h->grp_off.push_back(0);
+  for (uint64_t r = 0; r < s; ++r) {
+    uint64_t k = key(order[r]);
+    if (r == 0 || k != key(order[r - 1])) {
+      if (r) h->grp_off.push_back(r);
+      h->gd.push_back((uint32_t)(k >> 32));
+      h->ge.push_back((uint32_t)k);
+    }
+  }
+  if (s) h->grp_off.push_back(s);
+  h->G = h->gd.size();
+
+  // sorted structure-of-arrays: coefficients (reduced mod p) and tail exponents
+  std::vector<uint8_t> coeff(s * h->w);
+  std::vector<uint16_t> ex((size_t)ntail * s);
+  for (uint64_t r = 0; r < s; ++r) {
+    uint64_t i = order[r];
+    uint64_t a = coeffs[i] % p;
+    if (h->w == 4) {
+      uint32_t a32 = (uint32_t)a;
+      memcpy(&coeff[r * 4], &a32, 4);
+    } else {
+      memcpy(&coeff[r * 8], &a, 8);
+    }
+    for (uint32_t k = 0; k < ntail; ++k) ex[(size_t)k * s + r] = (uint16_t)exponents[i * n + 2 + k];
+  }
+
+  int rc = PEVAL_OK;
+  auto bail = [&](int code) {
+    peval_destroy(h);
+    return code;
+  };
+  if (hipGetDevice(&h->device) != hipSuccess) return bail(fail(PEVAL_EDEVICE, "hipGetDevice failed"));
+  if ((rc = upload((uint8_t **)&h->d_coeff, coeff)) != PEVAL_OK) return bail(rc);
+  if ((rc = upload(&h->d_exps, ex)) != PEVAL_OK) return bail(rc);
+  h->resident_bytes = coeff.size() + ex.size() * 2;
+  if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
+    return bail(fail(PEVAL_EDEVICE, "stream creation failed"));
+  if (hipEventCreateWithFlags(&h->done, hipEventDisableTiming) != hipSuccess)
+    return bail(fail(PEVAL_EDEVICE, "event creation failed"));
+  *out = h;
+  return PEVAL_OK;
+}
+
+extern "C" int peval_destroy(peval_poly *h) {
+  if (!h) return PEVAL_OK;
+  {
+    std::lock_guard<std::mutex> lk(h->mu);
+    if (h->have_done) (void)hipEventSynchronize(h->done);
+    for (auto &kv : h->plans) free_plan(kv.second);
+    h->plans.clear();
+    release(h->tabval);
+    release(h->tabquot);
+    release(h->lam);
+    release(h->gam);
+    release(h->gamq);
+    release(h->partial);
+    release(h->outbuf);
+    if (h->d_coeff) (void)hipFree(h->d_coeff);
+    if (h->d_exps) (void)hipFree(h->d_exps);
+    if (h->done) (void)hipEventDestroy(h->done);
+    if (h->stream) (void)hipStreamDestroy(h->stream);
+  }
+  delete h;
+  return PEVAL_OK;
+}
+
+extern "C" int peval_info(const peval_poly *h, peval_info_t *info) {
+  if (!h || !info) return fail(PEVAL_EINVAL, "null argument");
+  memset(info, 0, sizeof *info);
+  info->p = h->p;
+  info->n = h->n;
+  info->elem_bytes = h->w;
+  info->s = h->s;
+  info->G = h->G;
+  uint64_t b = h->resident_bytes + h->tabval.bytes + h->tabquot.bytes + h->lam.bytes + h->gam.bytes +
+               h->gamq.bytes + h->partial.bytes + h->outbuf.bytes;
+  for (auto &kv : h->plans) b += kv.second.device_bytes;
+  info->device_bytes = b;
+  for (uint32_t k = 0; k < h->n && k < 32; ++k) info->max_exp[k] = h->max_exp[k];
+  return PEVAL_OK;
+}
+
+extern "C" int peval_groups(const peval_poly *h, uint32_t *d, uint32_t *e) {
+  if (!h || ((!d || !e) && h->G)) return fail(PEVAL_EINVAL, "null argument");
+  if (h->G) {
+    memcpy(d, h->gd.data(), h->G * 4);
+    memcpy(e, h->ge.data(), h->G * 4);
+  }
+  return PEVAL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// tuning
+// ---------------------------------------------------------------------------
+static bool valid_K(uint32_t K) { return K == 1 || K == 2 || K == 4 || K == 8 || K == 16; }
+static bool valid_P(uint32_t P) { return P == 8 || P == 16 || P == 32; }
+
+extern "C" int peval_set_tuning(peval_poly *h, uint32_t K, uint32_t P, uint32_t C) {
+  if (!h) return fail(PEVAL_EINVAL, "null handle");
+  if (K && !valid_K(K)) return fail(PEVAL_EINVAL, "K must be 1, 2, 4, 8 or 16");
+  if (P && !valid_P(P)) return fail(PEVAL_EINVAL, "P must be 8, 16 or 32");
+  if (C > 65535) return fail(PEVAL_EINVAL, "C must be <= 65535");
+  std::lock_guard<std::mutex> lk(h->mu);
+  h->tune_K = K;
+  h->tune_P = P;
+  h->tune_C = C;
+  return PEVAL_OK;
+}
+
+// Automatic choice: the largest K whose zero padding stays under 1/8 of the
+// terms, P = 16, and enough chains for about 8 waves per SIMD.
+static void choose_tuning(const peval_poly *h, uint32_t T, uint32_t *K, uint32_t *P, uint32_t *C) {
+  uint32_t k = h->tune_K;
+  if (!k) {
+    k = 1;
+    for (uint32_t cand : {16u, 8u, 4u, 2u}) {
+      uint64_t padded = 0;
+      for (uint64_t g = 0; g < h->G; ++g) padded += (h->grp_off[g + 1] - h->grp_off[g] + cand - 1) / cand * cand;
+      if (padded * 8 <= h->s * 9) {
+        k = cand;
+        break;
+      }
+    }
+    if (k == 16) k = 8;  // 16 raises register pressure for little gain
+  }
+  uint32_t pp = h->tune_P ? h->tune_P : 16;
+  uint32_t c = h->tune_C;
+  if (!c) {
+    uint64_t nt = 0;
+    for (uint64_t g = 0; g < h->G; ++g) nt += (h->grp_off[g + 1] - h->grp_off[g] + k - 1) / k;
+    uint64_t nw = std::max<uint64_t>(1, (nt + 63) / 64);
+    uint64_t want = (8192 + nw - 1) / nw;
+    c = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 1), 64);
+  }
+  if (T) c = std::min<uint32_t>(c, T);
+  *K = k;
+  *P = pp;
+  *C = std::max<uint32_t>(c, 1);
+}
+
+extern "C" int peval_get_tuning(peval_poly *h, uint32_t T, uint32_t *K, uint32_t *P, uint32_t *C) {
+  if (!h || !K || !P || !C) return fail(PEVAL_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(h->mu);
+  choose_tuning(h, T, K, P, C);
+  return PEVAL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// evaluation
+// ---------------------------------------------------------------------------
+template <class A>
+struct Dispatch {
+  using EvalFn = void (*)(EvalArgs<A>);
+  static EvalFn eval(uint32_t K, uint32_t P) {
+#define PEVAL_CASE(k, pp) \
+  if (K == k && P == pp) return eval_kernel<A, k, pp>;
+#define PEVAL_CASES_K(k) PEVAL_CASE(k, 8) PEVAL_CASE(k, 16) PEVAL_CASE(k, 32)
+    PEVAL_CASES_K(1)
+    PEVAL_CASES_K(2)
+    PEVAL_CASES_K(4)
+    PEVAL_CASES_K(8)
+    PEVAL_CASES_K(16)
+#undef PEVAL_CASES_K
+#undef PEVAL_CASE
+    return nullptr;
+  }
+};
+
+template <class A>
+static const typename A::M &mod_of(const peval_poly *h);
+template <>
+const Mod64 &mod_of<W64>(const peval_poly *h) { return h->m64; }
+template <>
+const Mod32 &mod_of<W32>(const peval_poly *h) { return h->m32; }
+
+static constexpr size_t kPartialBudget = (size_t)2 << 30;  // bytes of partial sums per launch
+
+template <class A>
+static int run_impl(peval_poly *h, const BetaArg &beta, uint64_t t0, uint32_t T, void *dev_out,
+                    hipStream_t st) {
+  using T_ = typename A::T;
+  const auto &m = mod_of<A>(h);
+  const uint32_t ntail = h->n - 2;
+  uint32_t K, P, C;
+  choose_tuning(h, T, &K, &P, &C);
+  Plan *pl = nullptr;
+  PEVAL_TRY(get_plan(h, K, P, &pl));
+  const size_t w = sizeof(T_);
+
+  // A2: power tables
+  PEVAL_TRY(ensure(h->tabval, (size_t)std::max<uint32_t>(h->tab_total, 1) * w, h));
+  PEVAL_TRY(ensure(h->tabquot, (size_t)std::max<uint32_t>(h->tab_total, 1) * w, h));
+  if (ntail) {
+    ProfScope ps(st, 0);
+    uint32_t blocks = (h->tab_total + 255) / 256;
+    power_table_kernel<A><<<blocks, 256, 0, st>>>(beta, h->tab, ntail, h->tab_total, (T_ *)h->tabval.ptr,
+                                                  (T_ *)h->tabquot.ptr, m);
+    HIP_TRY(hipGetLastError());
+  }
+
+  // T is processed in chunks so that the partial sums stay within budget
+  uint64_t tc = std::max<uint64_t>(1, kPartialBudget / std::max<uint64_t>(1, pl->nslots * w));
+  tc = std::min<uint64_t>(tc, T);
+  if (tc < T && tc > C) tc = tc / C * C;
+  PEVAL_TRY(ensure(h->lam, (size_t)C * K * pl->NT * w, h));
+  PEVAL_TRY(ensure(h->gam, (size_t)K * pl->NT * w, h));
+  PEVAL_TRY(ensure(h->gamq, (size_t)K * pl->NT * w, h));
+  PEVAL_TRY(ensure(h->partial, (size_t)tc * pl->nslots * w, h));
+  auto eval = Dispatch<A>::eval(K, P);
+  if (!eval) return fail(PEVAL_EINVAL, "no kernel for K=%u P=%u", K, P);
+
+  for (uint64_t done = 0; done < T; done += tc) {
+    const uint32_t Tc = (uint32_t)std::min<uint64_t>(tc, T - done);
+    const uint32_t Cc = std::min<uint32_t>(C, Tc);
+    {  // A3: monomial values and chain starts
+      MonoArgs<A> ma;
+      ma.coeff = (const T_ *)h->d_coeff;
+      ma.exps = h->d_exps;
+      ma.tval = (const T_ *)h->tabval.ptr;
+      ma.tquot = (const T_ *)h->tabquot.ptr;
+      ma.to = h->tab;
+      ma.thr_first = pl->d_thr_first;
+      ma.thr_cnt = pl->d_thr_cnt;
+      ma.lam = (T_ *)h->lam.ptr;
+      ma.gam = (T_ *)h->gam.ptr;
+      ma.gamq = (T_ *)h->gamq.ptr;
+      ma.s = h->s;
+      ma.NT = pl->NT;
+      ma.t0 = t0 + done;
+      ma.ntail = ntail;
+      ma.K = K;
+      ma.C = Cc;
+      ma.m = m;
+      uint64_t total = (uint64_t)K * pl->NT;
+      ProfScope ps(st, 1);
+      monomial_kernel<A><<<(unsigned)((total + 255) / 256), 256, 0, st>>>(ma);
+      HIP_TRY(hipGetLastError());
+    }
+    {  // A4-A6: evaluations
+      EvalArgs<A> ea;
+      ea.lam = (const T_ *)h->lam.ptr;
+      ea.gam = (const T_ *)h->gam.ptr;
+      ea.gamq = (const T_ *)h->gamq.ptr;
+      ea.endmask = pl->d_endmask;
+      ea.slot_base = pl->d_slot_base;
+      ea.partial = (T_ *)h->partial.ptr;
+      ea.NT = pl->NT;
+      ea.NW = pl->NW;
+      ea.nslots = pl->nslots;
+      ea.C = Cc;
+      ea.T = Tc;
+      ea.m = m;
+      dim3 grid((unsigned)((pl->NW + 3) / 4), Cc);
+      ProfScope ps(st, 2);
+      eval<<<grid, kEvalBlock, 0, st>>>(ea);
+      HIP_TRY(hipGetLastError());
+    }
+    {  // A7: combine
+      uint64_t total = (uint64_t)Tc * h->G;
+      T_ *outp = (T_ *)dev_out + done * h->G;
+      ProfScope ps(st, 3);
+      combine_kernel<A><<<(unsigned)((total + 255) / 256), 256, 0, st>>>(
+          (const T_ *)h->partial.ptr, pl->d_slot_off, outp, h->G, pl->nslots, total, m);
+      HIP_TRY(hipGetLastError());
+    }
+  }
+  return PEVAL_OK;
+}
+
+static int check_run_args(peval_poly *h, const uint64_t *beta, uint64_t t0, uint32_t T, BetaArg *ba) {
+  if (!h) return fail(PEVAL_EINVAL, "null handle");
+  if (h->n > 2 && !beta) return fail(PEVAL_EINVAL, "null beta");
+  if (t0 < 1) return fail(PEVAL_EINVAL, "t0 must be >= 1");
+  if ((uint64_t)T * h->G > (1ull << 40)) return fail(PEVAL_EUNSUPPORTED, "T*G too large");
+  memset(ba, 0, sizeof *ba);
+  for (uint32_t k = 0; k + 2 < h->n; ++k) ba->b[k] = beta[k] % h->p;
+  return PEVAL_OK;
+}
+
+static int run_locked(peval_poly *h, const BetaArg &ba, uint64_t t0, uint32_t T, void *dev_out,
+                      hipStream_t st) {
+  HIP_TRY(hipSetDevice(h->device));
+  if (h->have_done) HIP_TRY(hipStreamWaitEvent(st, h->done, 0));
+  int rc = (h->w == 4) ? run_impl<W32>(h, ba, t0, T, dev_out, st) : run_impl<W64>(h, ba, t0, T, dev_out, st);
+  if (rc != PEVAL_OK) return rc;
+  HIP_TRY(hipEventRecord(h->done, st));
+  h->have_done = true;
+  return PEVAL_OK;
+}
+
+extern "C" int peval_run_async(peval_poly *h, const uint64_t *beta, uint64_t t0, uint32_t T,
+                               void *dev_out, void *stream) {
+  BetaArg ba;
+  PEVAL_TRY(check_run_args(h, beta, t0, T, &ba));
+  if (T == 0 || h->G == 0) return PEVAL_OK;
+  if (!dev_out) return fail(PEVAL_EINVAL, "null output");
+  std::lock_guard<std::mutex> lk(h->mu);
+  return run_locked(h, ba, t0, T, dev_out, (hipStream_t)stream);
+}
+
+extern "C" int peval_run(peval_poly *h, const uint64_t *beta, uint32_t T, void *out) {
+  BetaArg ba;
+  PEVAL_TRY(check_run_args(h, beta, 1, T, &ba));
+  if (T == 0 || h->G == 0) return PEVAL_OK;
+  if (!out) return fail(PEVAL_EINVAL, "null output");
+  std::lock_guard<std::mutex> lk(h->mu);
+  const size_t bytes = (size_t)T * h->G * h->w;
+  PEVAL_TRY(ensure(h->outbuf, bytes, h));
+  PEVAL_TRY(run_locked(h, ba, 1, T, h->outbuf.ptr, h->stream));
+  HIP_TRY(hipMemcpyAsync(out, h->outbuf.ptr, bytes, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return PEVAL_OK;
+}

@@ -1,0 +1,80 @@
+// Internal state of a resident polynomial and its evaluation plans.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "modarith.hpp"
+
+namespace peval {
+
+// Thread layout of one (K, P) choice (see kernels.hpp).
+struct Plan {
+  uint32_t K = 0, P = 0;
+  uint64_t NT = 0;      // threads, multiple of 64
+  uint64_t NW = 0;      // waves
+  uint64_t nslots = 0;  // segment slots (partial coefficients per evaluation)
+  uint32_t *d_thr_first = nullptr;
+  uint8_t *d_thr_cnt = nullptr;
+  uint64_t *d_endmask = nullptr;
+  uint32_t *d_slot_base = nullptr;
+  uint32_t *d_slot_off = nullptr;  // G + 1
+  uint64_t device_bytes = 0;
+};
+
+// Device scratch that grows on demand and is reused across runs.
+struct Scratch {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+
+// Host-side layout computation (pure C++; also used by the CPU tests through
+// peval_debug_plan).
+struct HostPlan {
+  uint64_t NT = 0, NW = 0, nslots = 0;
+  std::vector<uint32_t> thr_first;
+  std::vector<uint8_t> thr_cnt;
+  std::vector<uint64_t> endmask;
+  std::vector<uint32_t> slot_base;
+  std::vector<uint32_t> slot_off;
+};
+HostPlan build_host_plan(const std::vector<uint64_t> &grp_off, uint32_t K, uint32_t P);
+
+}  // namespace peval
+
+struct peval_poly {
+  uint64_t p = 0;
+  uint32_t n = 0;
+  uint64_t s = 0;
+  uint64_t G = 0;
+  uint32_t w = 8;  // bytes per residue
+  peval::Mod64 m64{};
+  peval::Mod32 m32{};
+  int device = 0;
+
+  std::vector<uint32_t> gd, ge;        // output columns
+  std::vector<uint64_t> grp_off;       // CSR of groups over the sorted terms (G + 1)
+  uint32_t max_exp[32] = {0};
+  peval::TableOffsets tab{};           // power-table offsets per tail variable
+  uint32_t tab_total = 0;
+
+  void *d_coeff = nullptr;             // s residues (w bytes)
+  uint16_t *d_exps = nullptr;          // (n - 2) * s tail exponents
+  uint64_t resident_bytes = 0;
+
+  std::map<uint32_t, peval::Plan> plans;  // key K << 8 | P
+  peval::Scratch tabval, tabquot, lam, gam, gamq, partial, outbuf;
+
+  uint32_t tune_K = 0, tune_P = 0, tune_C = 0;  // 0 = automatic
+
+  hipStream_t stream = nullptr;  // for peval_run
+  hipEvent_t done = nullptr;     // end of the last enqueued call
+  bool have_done = false;
+  std::mutex mu;
+};

@@ -1,0 +1,214 @@
+"""ctypes binding of libpeval (include/peval.h).  Argument marshalling only:
+every step of the evaluation runs in the HIP library.
+
+PyTorch is used by callers only for device memory and streams; this module
+accepts raw device pointers or torch tensors (``.data_ptr()``) and raw
+stream handles or torch streams (``.cuda_stream``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpeval.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EBUSY, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
+
+
+class PevalError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"peval error {code}: {msg}")
+        self.code = code
+
+
+class _Info(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_uint64), ("n", ctypes.c_uint32), ("elem_bytes", ctypes.c_uint32),
+                ("s", ctypes.c_uint64), ("G", ctypes.c_uint64), ("device_bytes", ctypes.c_uint64),
+                ("max_exp", ctypes.c_uint32 * 32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load the built library (never builds, never falls back)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    # The library must share PyTorch's HIP runtime (PyTorch ships its own
+    # libamdhip64 with the same soname): load torch first so that the dynamic
+    # loader binds libpeval to that runtime instead of a second copy.
+    import torch  # noqa: F401
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                           "or python paper_2004_11571_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    u64, u32, i32, vp = ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int, ctypes.c_void_p
+    sig = {
+        "peval_create": ([u64, u32, u64, vp, vp, ctypes.POINTER(vp)], i32),
+        "peval_info": ([vp, ctypes.POINTER(_Info)], i32),
+        "peval_groups": ([vp, vp, vp], i32),
+        "peval_run": ([vp, vp, u32, vp], i32),
+        "peval_run_async": ([vp, vp, u64, u32, vp, vp], i32),
+        "peval_destroy": ([vp], i32),
+        "peval_set_tuning": ([vp, u32, u32, u32], i32),
+        "peval_get_tuning": ([vp, u32, vp, vp, vp], i32),
+        "peval_prof_enable": ([i32], i32),
+        "peval_prof_read": ([vp, vp], i32),
+        "peval_layout": ([vp, u64, u32, u32, vp, vp, vp, vp, vp, vp], i32),
+        "peval_strerror": ([i32], ctypes.c_char_p),
+        "peval_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != OK:
+        L = lib()
+        raise PevalError(rc, f"{L.peval_strerror(rc).decode()}: {L.peval_last_error().decode()}")
+
+
+def _ptr(x) -> int:
+    if x is None:
+        return 0
+    if hasattr(x, "data_ptr"):
+        return int(x.data_ptr())
+    if isinstance(x, np.ndarray):
+        return int(x.ctypes.data)
+    return int(x)
+
+
+def _stream(st) -> int:
+    if st is None:
+        return 0
+    if hasattr(st, "cuda_stream"):
+        return int(st.cuda_stream)
+    return int(st)
+
+
+def out_dtype(p: int):
+    return np.uint32 if p < (1 << 31) else np.uint64
+
+
+class Poly:
+    """A polynomial resident on the current HIP device (peval_create)."""
+
+    def __init__(self, p: int, exps, coeffs):
+        exps = np.ascontiguousarray(exps, dtype=np.uint32)
+        coeffs = np.ascontiguousarray(coeffs, dtype=np.uint64)
+        if exps.ndim != 2 or coeffs.shape != (exps.shape[0],):
+            raise ValueError("exps must be (s, n) and coeffs (s,)")
+        s, n = exps.shape
+        h = ctypes.c_void_p()
+        _check(lib().peval_create(p, n, s, exps.ctypes.data, coeffs.ctypes.data, ctypes.byref(h)))
+        self._h = h
+        inf = self.info()
+        self.p, self.n, self.s, self.G = inf["p"], inf["n"], inf["s"], inf["G"]
+        self.elem_bytes = inf["elem_bytes"]
+        self.dtype = np.uint32 if self.elem_bytes == 4 else np.uint64
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise RuntimeError("polynomial destroyed")
+        return self._h
+
+    def info(self) -> dict:
+        inf = _Info()
+        _check(lib().peval_info(self.handle, ctypes.byref(inf)))
+        return {"p": inf.p, "n": inf.n, "elem_bytes": inf.elem_bytes, "s": inf.s, "G": inf.G,
+                "device_bytes": inf.device_bytes, "max_exp": list(inf.max_exp)[: inf.n]}
+
+    def groups(self) -> Tuple[np.ndarray, np.ndarray]:
+        d = np.zeros(max(self.G, 1), np.uint32)
+        e = np.zeros(max(self.G, 1), np.uint32)
+        _check(lib().peval_groups(self.handle, d.ctypes.data, e.ctypes.data))
+        return d[: self.G], e[: self.G]
+
+    def _beta(self, beta) -> np.ndarray:
+        b = np.ascontiguousarray(beta, dtype=np.uint64)
+        if b.shape != (self.n - 2,):
+            raise ValueError(f"beta must have n-2 = {self.n - 2} entries")
+        return b
+
+    def run(self, beta, T: int) -> np.ndarray:
+        """(T, G) images b_1..b_T in host memory."""
+        b = self._beta(beta)
+        out = np.zeros((T, self.G), self.dtype)
+        _check(lib().peval_run(self.handle, b.ctypes.data if b.size else None, T,
+                               out.ctypes.data if out.size else None))
+        return out
+
+    def run_async(self, beta, T: int, dev_out, t0: int = 1, stream=None):
+        """Enqueue b_{t0}..b_{t0+T-1} into device memory ``dev_out``."""
+        b = self._beta(beta)
+        _check(lib().peval_run_async(self.handle, b.ctypes.data if b.size else None, t0, T,
+                                     _ptr(dev_out), _stream(stream)))
+
+    def set_tuning(self, K: int = 0, P: int = 0, C: int = 0):
+        _check(lib().peval_set_tuning(self.handle, K, P, C))
+
+    def get_tuning(self, T: int) -> Tuple[int, int, int]:
+        k, p, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().peval_get_tuning(self.handle, T, ctypes.byref(k), ctypes.byref(p), ctypes.byref(c)))
+        return k.value, p.value, c.value
+
+    def destroy(self):
+        if self._h is not None:
+            _check(lib().peval_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def prof_enable(on: bool = True):
+    _check(lib().peval_prof_enable(1 if on else 0))
+
+
+KERNEL_KINDS = ("power_table", "monomial", "eval", "combine")
+
+
+def prof_read() -> dict:
+    ms = (ctypes.c_double * 4)()
+    n = (ctypes.c_uint64 * 4)()
+    _check(lib().peval_prof_read(ms, n))
+    return {k: (ms[i], n[i]) for i, k in enumerate(KERNEL_KINDS)}
+
+
+def layout(group_sizes, K: int, P: int) -> dict:
+    """Host-only thread layout of the evaluation kernel (peval_layout)."""
+    gs = np.ascontiguousarray(group_sizes, dtype=np.uint64)
+    sizes = np.zeros(3, np.uint64)
+    L = lib()
+    _check(L.peval_layout(gs.ctypes.data if gs.size else None, gs.size, K, P, sizes.ctypes.data,
+                          None, None, None, None, None))
+    NT, NW, ns = (int(x) for x in sizes)
+    thr_first = np.zeros(NT, np.uint32)
+    thr_cnt = np.zeros(NT, np.uint8)
+    endmask = np.zeros(NW, np.uint64)
+    slot_base = np.zeros(NW, np.uint32)
+    slot_off = np.zeros(gs.size + 1, np.uint32)
+    _check(L.peval_layout(gs.ctypes.data if gs.size else None, gs.size, K, P, sizes.ctypes.data,
+                          thr_first.ctypes.data, thr_cnt.ctypes.data, endmask.ctypes.data,
+                          slot_base.ctypes.data, slot_off.ctypes.data))
+    return {"NT": NT, "NW": NW, "nslots": ns, "thr_first": thr_first, "thr_cnt": thr_cnt,
+            "endmask": endmask, "slot_base": slot_base, "slot_off": slot_off}

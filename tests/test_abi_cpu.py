@@ -1,0 +1,134 @@
+"""The C-ABI library on the CPU: symbols, argument validation, host layout.
+
+No compute call is made here (there is no GPU in the build container);
+argument validation happens before any device call, so it is testable."""
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2004_11571_amd import peval as PV
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    names = set()
+    for path in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(path).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(peval_\w+)\s*\(", text))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    syms = declared_symbols()
+    assert "peval_create" in syms and "peval_run" in syms and "peval_destroy" in syms
+    L = ctypes.CDLL(PV.LIB_PATH)
+    missing = [s for s in syms if not hasattr(L, s)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("p,n,why", [
+    (2, 4, "even p"), (1, 4, "p < 3"), ((1 << 63) + 1, 4, "p >= 2^63"), (10, 4, "even p"),
+    (101, 1, "n < 2"), (101, 33, "n > 32"),
+])
+def test_create_rejects_bad_arguments(p, n, why):
+    L = PV.lib()
+    exps = np.zeros((1, max(n, 1)), np.uint32)
+    co = np.ones(1, np.uint64)
+    h = ctypes.c_void_p()
+    rc = L.peval_create(p % (1 << 64), n, 1, exps.ctypes.data, co.ctypes.data, ctypes.byref(h))
+    assert rc == PV.EINVAL, why
+    assert h.value is None
+    assert L.peval_last_error().decode()
+
+
+def test_create_rejects_large_tail_exponent():
+    L = PV.lib()
+    exps = np.asarray([[0, 0, 65536]], np.uint32)
+    co = np.ones(1, np.uint64)
+    h = ctypes.c_void_p()
+    assert L.peval_create(101, 3, 1, exps.ctypes.data, co.ctypes.data, ctypes.byref(h)) == PV.EUNSUPPORTED
+
+
+def test_null_arguments():
+    L = PV.lib()
+    h = ctypes.c_void_p()
+    assert L.peval_create(101, 3, 5, None, None, ctypes.byref(h)) == PV.EINVAL
+    assert L.peval_create(101, 3, 0, None, None, None) == PV.EINVAL
+    assert L.peval_run(None, None, 4, None) == PV.EINVAL
+    assert L.peval_run_async(None, None, 1, 4, None, None) == PV.EINVAL
+    assert L.peval_info(None, None) == PV.EINVAL
+    assert L.peval_destroy(None) == PV.OK
+    assert L.peval_set_tuning(None, 0, 0, 0) == PV.EINVAL
+    assert L.peval_strerror(PV.EINVAL) == b"invalid argument"
+
+
+def _check_layout(sizes, K, P):
+    lay = PV.layout(sizes, K, P)
+    NT, NW = lay["NT"], lay["NW"]
+    assert NT % 64 == 0 and NW * 64 == NT
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    # every term is covered exactly once, runs of <= K terms inside one group
+    covered = np.zeros(int(off[-1]), np.int64)
+    grp_of_thread = np.full(NT, -1)
+    for j in range(NT):
+        c = int(lay["thr_cnt"][j])
+        if c == 0:
+            continue
+        f = int(lay["thr_first"][j])
+        assert 1 <= c <= K
+        g = int(np.searchsorted(off, f, side="right") - 1)
+        assert f + c <= off[g + 1]
+        covered[f:f + c] += 1
+        grp_of_thread[j] = g
+    assert (covered == 1).all()
+    # threads of a group are contiguous and in group order
+    real = grp_of_thread[grp_of_thread >= 0]
+    assert (np.diff(real) >= 0).all()
+    # segment ends: group boundaries and sub-tile boundaries; slots per group contiguous
+    slots = []
+    last = -1
+    for w in range(NW):
+        assert int(lay["slot_base"][w]) == len(slots)
+        m = int(lay["endmask"][w])
+        for l in range(64):
+            j = w * 64 + l
+            g = grp_of_thread[j] if grp_of_thread[j] >= 0 else len(sizes) - 1
+            last = g
+            if (m >> l) & 1:
+                slots.append(g)
+            if l % P == P - 1:
+                assert (m >> l) & 1
+            if j + 1 < NT:
+                g2 = grp_of_thread[j + 1] if grp_of_thread[j + 1] >= 0 else len(sizes) - 1
+                if g2 != g:
+                    assert (m >> l) & 1
+    assert len(slots) == lay["nslots"]
+    so = lay["slot_off"]
+    for g in range(len(sizes)):
+        assert all(s == g for s in slots[so[g]:so[g + 1]])
+        assert so[g + 1] > so[g]
+    assert so[-1] == len(slots)
+
+
+@pytest.mark.parametrize("K", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("P", [8, 16, 32])
+def test_layout_invariants(K, P):
+    rng = np.random.default_rng(K * 100 + P)
+    sizes = np.concatenate([rng.integers(1, 5, 40), rng.integers(50, 400, 6), [1, 1, 1000]])
+    _check_layout(sizes, K, P)
+
+
+def test_layout_edges():
+    _check_layout(np.asarray([1]), 8, 16)
+    _check_layout(np.asarray([64 * 8]), 8, 16)
+    _check_layout(np.asarray([1] * 130), 1, 32)
+    with pytest.raises(PV.PevalError):
+        PV.layout(np.asarray([3, 0, 2]), 4, 16)
+    with pytest.raises(PV.PevalError):
+        PV.layout(np.asarray([3]), 3, 16)

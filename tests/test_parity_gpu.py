@@ -1,0 +1,216 @@
+"""HIP path vs the CPU oracle, element by element (bit-exact: the images are
+canonical residues, so there is exactly one correct answer)."""
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_2004_11571_amd import peval as PV
+from paper_2004_11571_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+P_SMALL_W8 = (1 << 31) + 11        # smallest odd modulus size on the 64-bit path
+P_COMPOSITE = 3 * 5 * 7 * 11 * 13 * 17 * 19 * 23 * 29 * 31 * 37 * 41 * 43 * 47   # odd, not prime
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return Oracle()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def check(orc, p, exps, coeffs, beta, T, tuning=None, t0=1):
+    exps = np.ascontiguousarray(exps, np.uint32)
+    coeffs = np.ascontiguousarray(coeffs, np.uint64)
+    beta = np.ascontiguousarray(beta, np.uint64)
+    _say(f"case p={p} s={exps.shape[0]} n={exps.shape[1]} T={T} tuning={tuning} t0={t0}")
+    with PV.Poly(p, exps, coeffs) as poly:
+        if tuning:
+            poly.set_tuning(*tuning)
+        gd, ge = poly.groups()
+        od, oe = orc.groups(exps)
+        assert np.array_equal(gd, od) and np.array_equal(ge, oe)
+        if t0 == 1:
+            got = poly.run(beta, T)
+        else:
+            import torch
+            buf = torch.empty((T, max(poly.G, 1)), dtype=torch.int64 if poly.elem_bytes == 8 else torch.int32,
+                              device="cuda")
+            poly.run_async(beta, T, buf, t0=t0)
+            torch.cuda.synchronize()
+            got = buf.cpu().numpy().view(poly.dtype)[:, :poly.G]
+    want = orc.evaluate(p, exps, coeffs, beta, T, t0=t0, threads=8).astype(got.dtype)
+    assert got.shape == want.shape
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, f"{len(bad)} mismatches, first at {bad[:3].tolist()}"
+    return got
+
+
+def test_config1_full(orc):
+    w = W.config1()
+    check(orc, w.p, w.exps, w.coeffs, w.beta, w.T)
+
+
+@pytest.mark.parametrize("p", [3, 5, 97, P_COMPOSITE % (1 << 31) | 1, W.P31, P_SMALL_W8, W.P50,
+                               P_COMPOSITE, W.P63])
+@pytest.mark.parametrize("n", [2, 3, 5, 8])
+def test_random_polys(orc, p, n):
+    rng = np.random.default_rng(p % 1000 + n)
+    poly = W.random_small(rng, p, n, 700, 37, dmax={2: 30, 3: 9}.get(n, 5))
+    check(orc, p, poly.exps, poly.coeffs, poly.beta, poly.T)
+
+
+@pytest.mark.parametrize("p", [W.P31, W.P63])
+@pytest.mark.parametrize("K", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("P", [8, 16, 32])
+def test_tuning_grid(orc, p, K, P):
+    rng = np.random.default_rng(K * 31 + P)
+    # a few big groups (span several waves), many small ones, a ragged tail
+    big = W.random_small(rng, p, 5, 3000, 1, dmax=12)
+    big.exps[:1500, :2] = [3, 1]
+    big.exps[1500:2200, :2] = [2, 2]
+    big.exps = np.unique(big.exps, axis=0)
+    big.coeffs = rng.integers(0, p, size=big.exps.shape[0], dtype=np.uint64)
+    for C in (1, 3, 7):
+        check(orc, p, big.exps, big.coeffs, big.beta, 45, tuning=(K, P, C))
+
+
+def test_edge_single_term(orc):
+    check(orc, W.P63, [[2, 3, 4, 0, 7]], [12345], [5, 6, 7], 9)
+    check(orc, W.P31, [[0, 0, 1]], [W.P31 - 1], [W.P31 - 1], 1)
+
+
+def test_edge_one_group(orc):
+    rng = np.random.default_rng(3)
+    e = W.draw_exponents(rng, 5000, 6, 0, 20)
+    for p in (W.P31, W.P63):
+        co = rng.integers(0, p, size=e.shape[0], dtype=np.uint64)
+        check(orc, p, e, co, rng.integers(1, p, 4, dtype=np.uint64), 33)
+
+
+def test_edge_all_groups_distinct(orc):
+    rng = np.random.default_rng(4)
+    e = np.stack([np.arange(2000) // 50, np.arange(2000) % 50, rng.integers(0, 9, 2000),
+                  rng.integers(0, 9, 2000)], axis=1).astype(np.uint32)
+    for p in (W.P31, W.P63):
+        check(orc, p, e, rng.integers(0, p, 2000, dtype=np.uint64), [3, 5], 20)
+
+
+def test_edge_T_values(orc):
+    w = W.config1()
+    for T in (1, 2, 15, 16, 17, 97):
+        check(orc, w.p, w.exps, w.coeffs, w.beta, T)
+
+
+def test_edge_special_points(orc):
+    rng = np.random.default_rng(5)
+    for p in (W.P31, W.P63, 7):
+        poly = W.random_small(rng, p, 6, 400, 12, dmax=4)
+        check(orc, p, poly.exps, poly.coeffs, np.ones(4, np.uint64), 12)
+        check(orc, p, poly.exps, poly.coeffs, np.asarray([0, 3, 0, 1], np.uint64), 12)
+        check(orc, p, poly.exps, np.full(poly.s, p - 1, np.uint64), poly.beta, 12)
+        check(orc, p, poly.exps, np.zeros(poly.s, np.uint64), poly.beta, 3)
+
+
+def test_edge_unreduced_inputs_and_duplicates(orc):
+    rng = np.random.default_rng(6)
+    p = W.P63
+    poly = W.random_small(rng, p, 5, 600, 10, dmax=3, allow_dup=True)
+    co = rng.integers(0, 2**64 - 1, size=poly.s, dtype=np.uint64)
+    beta = np.asarray([2**64 - 1, p, p + 5], np.uint64)
+    check(orc, p, poly.exps, co, beta, 10)
+
+
+def test_edge_large_exponents(orc):
+    rng = np.random.default_rng(7)
+    e = np.asarray([[2**32 - 1, 0, 65535, 1], [0, 2**32 - 1, 1, 65535], [5, 5, 65535, 65535],
+                    [5, 5, 0, 0], [2**31, 7, 40000, 3]], np.uint32)
+    for p in (W.P31, W.P63):
+        check(orc, p, e, rng.integers(0, p, 5, dtype=np.uint64), rng.integers(1, p, 2, dtype=np.uint64), 6)
+
+
+def test_edge_empty(orc):
+    with PV.Poly(W.P63, np.zeros((0, 4), np.uint32), np.zeros(0, np.uint64)) as poly:
+        assert poly.G == 0
+        out = poly.run([2, 3], 5)
+        assert out.shape == (5, 0)
+    with PV.Poly(W.P63, [[1, 2, 3, 4]], [9]) as poly:
+        assert poly.run([2, 3], 0).shape == (0, 1)
+
+
+def test_run_async_offset(orc):
+    w = W.config1()
+    check(orc, w.p, w.exps, w.coeffs, w.beta, 20, t0=40)
+    rng = np.random.default_rng(8)
+    poly = W.random_small(rng, W.P63, 6, 900, 1, dmax=4)
+    check(orc, W.P63, poly.exps, poly.coeffs, poly.beta, 50, t0=1000, tuning=(4, 16, 5))
+
+
+def test_deterministic_repeat():
+    w = W.config1()
+    with PV.Poly(w.p, w.exps, w.coeffs) as poly:
+        a = poly.run(w.beta, 64)
+        for _ in range(3):
+            assert np.array_equal(poly.run(w.beta, 64), a)
+
+
+def test_streams_and_handles_are_independent():
+    import torch
+    rng = np.random.default_rng(9)
+    polys = [W.random_small(rng, p, 6, 5000, 1, dmax=5) for p in (W.P31, W.P63, W.P63)]
+    hs = [PV.Poly(q.p, q.exps, q.coeffs) for q in polys]
+    try:
+        ref = [h.run(q.beta, 64) for h, q in zip(hs, polys)]
+        streams = [torch.cuda.Stream() for _ in hs]
+        bufs = []
+        for h, q, st in zip(hs, polys, streams):
+            dt = torch.int32 if h.elem_bytes == 4 else torch.int64
+            b = torch.empty((64, h.G), dtype=dt, device="cuda")
+            h.run_async(q.beta, 64, b, stream=st)
+            bufs.append(b)
+        torch.cuda.synchronize()
+        for h, b, r in zip(hs, bufs, ref):
+            assert np.array_equal(b.cpu().numpy().view(h.dtype), r)
+    finally:
+        for h in hs:
+            h.destroy()
+
+
+def _sampled_rows(orc, w, rows, got):
+    for t in rows:
+        want = orc.evaluate(w.p, w.exps, w.coeffs, w.beta, 1, t0=t, threads=1)[0]
+        assert np.array_equal(got[t - 1].astype(np.uint64), want), f"row t={t}"
+
+
+def test_config2_full_size_sampled(orc):
+    """n=6, 1e6 terms, p = 2^63-25, T = 1024, automatic tuning (the benchmark
+    configuration); full oracle rows at a few t."""
+    import concurrent.futures as cf
+    w = W.config2()
+    _say("config2: generated")
+    with PV.Poly(w.p, w.exps, w.coeffs) as poly:
+        got = poly.run(w.beta, w.T)
+        _say("config2: tuning", poly.get_tuning(w.T), "G", poly.G)
+        gd, ge = poly.groups()
+    rows = [1, 2, 5, 6, 513, w.T - 1, w.T]
+    with cf.ThreadPoolExecutor(len(rows)) as ex:
+        futs = {t: ex.submit(orc.evaluate, w.p, w.exps, w.coeffs, w.beta, 1, t, 1) for t in rows}
+        for t, f in futs.items():
+            want = f.result()[0]
+            assert np.array_equal(got[t - 1], want), f"row t={t}"
+    _say("config2: rows ok")
+
+
+def test_single_hip_runtime():
+    """libpeval and PyTorch must share one HIP runtime (pointers and streams
+    cross between them)."""
+    import re
+    PV.lib()
+    import torch
+    torch.cuda.init()
+    maps = open("/proc/self/maps").read()
+    runtimes = set(re.findall(r"\S*libamdhip64\S*", maps))
+    assert len(runtimes) == 1, runtimes
