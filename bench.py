@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--cpu-rows", type=int, default=96, help="oracle sample: first rows of the images")
     ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (counter calibration)")
     return ap.parse_args()
 
 
@@ -107,6 +109,13 @@ def main():
     out = torch.empty((w.T, poly.G), dtype=dt, device=dev)
     stream = torch.cuda.current_stream(dev)
 
+    if args.calib_copy_mib:
+        src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         poly.run_async(w.beta, w.T, out, stream=stream)
     torch.cuda.synchronize()
