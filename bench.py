@@ -53,7 +53,13 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="config2", choices=["config1", "config2", "config4"])
+    ap.add_argument("--workload", default="config2", choices=["config1", "config2", "config4", "batch", "serve"])
+    ap.add_argument("--rate", type=float, default=2000.0, help="served stream: mean arrivals per second")
+    ap.add_argument("--duration", type=float, default=3.0, help="served stream: seconds of arrivals")
+    ap.add_argument("--pool", type=int, default=20, help="served stream: polynomials (last 20%% start cold)")
+    ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--batch-count", type=int, default=256)
+    ap.add_argument("--batch-smax", type=float, default=1e6)
     ap.add_argument("--tuning", default="", help="K,P,C override")
     ap.add_argument("--cpu-rows", type=int, default=96, help="oracle sample: first rows of the images")
     ap.add_argument("--cpu-threads", type=int, default=16)
@@ -84,12 +90,187 @@ def kernel_source_sha() -> str:
     return h.hexdigest()[:16]
 
 
+def batch_main(args):
+    """Uneven batch of polynomials: one persistent hipGraph launch per step,
+    compared with the same members launched one after another."""
+    import torch
+
+    from paper_2004_11571_amd import peval as PV
+    from paper_2004_11571_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t_gen = time.time()
+    ws = W.batch_config(count=args.batch_count, s_max=args.batch_smax)
+    gen_s = time.time() - t_gen
+    t_c = time.time()
+    polys = [PV.Poly(w.p, w.exps, w.coeffs) for w in ws]
+    create_s = time.time() - t_c
+    Ts = [w.T for w in ws]
+    te = sum(w.s * w.T for w in ws)
+    outs = [torch.empty((w.T, q.G), dtype=torch.int32 if q.elem_bytes == 4 else torch.int64, device="cuda")
+            for w, q in zip(ws, polys)]
+    betas = [w.beta for w in ws]
+    stream = torch.cuda.current_stream()
+    b = PV.Batch(polys, Ts, graph=True)
+    info = b.info()
+    steps = max(1, args.steps // 100)
+    warm = max(1, args.warmup // 10)
+    for _ in range(warm):
+        b.run(betas, outs, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.run(betas, outs, stream=stream)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    batched = [o.cpu().numpy().view(q.dtype).copy() for o, q in zip(outs, polys)]
+
+    # the same members as plain launches, one after another on one stream
+    for q, w, o in zip(polys, ws, outs):
+        q.run_async(w.beta, w.T, o, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        for q, w, o in zip(polys, ws, outs):
+            q.run_async(w.beta, w.T, o, stream=stream)
+    torch.cuda.synchronize()
+    el_seq = time.perf_counter() - t1
+    same = all(np.array_equal(o.cpu().numpy().view(q.dtype), x) for o, q, x in zip(outs, polys, batched))
+    value = te * steps / el
+    ops = sum(ALGO_OPS[q.elem_bytes] * w.s * w.T for q, w in zip(polys, ws))
+    achieved = ops * steps / el
+    res = {
+        "metric": METRIC, "value": value, "unit": "term-evals/s", "n_gpus": 1, "steps": steps,
+        "warmup": warm, "ms_per_step": el / steps * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32+u64", "data": "synthetic",
+        "config": {"workload": f"batch{len(ws)}_uneven_s1e3-{args.batch_smax:.0e}_T32-2048_p31p63",
+                   "members": len(ws), "term_evals_per_step": te, **info},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+                     "unit": "Tops/s (int32 lane-ops)", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                     "kernel": "whole batched pass (graph replay), all kernels"},
+        "sequential_plain": {"value": te * steps / el_seq, "ms_per_step": el_seq / steps * 1e3,
+                             "batched_over_sequential": el_seq / el, "identical_outputs": same},
+        "generate_s": gen_s, "create_s": create_s,
+    }
+    b.destroy()
+    for q in polys:
+        q.destroy()
+    print(json.dumps(res), flush=True)
+
+
+def serve_main(args):
+    """Poisson stream of evaluation requests against the server; p50/p99
+    latency and throughput, then the same requests one at a time."""
+    import threading
+
+    import torch
+
+    from paper_2004_11571_amd import peval as PV
+    from paper_2004_11571_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t_gen = time.time()
+    pool = W.serve_pool(args.pool)
+    reqs = W.serve_stream(args.rate, args.duration, pool)
+    gen_s = time.time() - t_gen
+    n_cold = max(1, args.pool // 5)
+    srv = PV.Server(int(args.budget_gb * (1 << 30)))
+    pids = [srv.add_poly(w.p, w.exps, w.coeffs) for w in pool]
+    # resident part of the pool: one warm-up request each
+    for j in range(len(pool) - n_cold):
+        srv.wait(srv.submit(pids[j], pool[j].beta, 64), 600000)
+    def stream(paced: bool):
+        """Submit every request (at its arrival time if paced, else at once);
+        a collector thread waits for them in order and releases them."""
+        srv.reset_stats()
+        lock = threading.Lock()
+        pending = []
+        finished = threading.Event()
+
+        def collector():
+            while True:
+                with lock:
+                    item = pending.pop(0) if pending else None
+                if item is None:
+                    if finished.is_set():
+                        with lock:
+                            if not pending:
+                                return
+                    time.sleep(0.0002)
+                    continue
+                srv.wait(item, 600000)
+                srv.release(item)
+
+        col = threading.Thread(target=collector)
+        col.start()
+        t0 = time.perf_counter()
+        lag = 0.0
+        for r in reqs:
+            if paced:
+                delay = r.arrival_s - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(delay)
+                else:
+                    lag = max(lag, -delay)
+            rid = srv.submit(pids[r.poly_index], r.beta, r.T)
+            with lock:
+                pending.append(rid)
+        submit_s = time.perf_counter() - t0
+        finished.set()
+        col.join()
+        st = srv.stats()
+        st["submit_s"] = submit_s
+        st["max_submit_lag_s"] = lag
+        return st
+
+    te = sum(pool[r.poly_index].s * r.T for r in reqs)
+    st = stream(paced=True)
+    sat = stream(paced=False)
+    srv.destroy()
+
+    # the same requests (a prefix) one at a time, each a plain synchronous run
+    hs = [PV.Poly(w.p, w.exps, w.coeffs) for w in pool]
+    for j, h in enumerate(hs):
+        h.run(pool[j].beta, 16)
+    k = min(len(reqs), 400)
+    t1 = time.perf_counter()
+    te_seq = 0
+    for r in reqs[:k]:
+        hs[r.poly_index].run(r.beta, r.T)
+        te_seq += pool[r.poly_index].s * r.T
+    el_seq = time.perf_counter() - t1
+    for h in hs:
+        h.destroy()
+    res = {
+        "metric": METRIC, "value": st["term_evals"] / st["wall_s"], "unit": "term-evals/s", "n_gpus": 1,
+        "steps": len(reqs), "warmup": len(pool) - n_cold, "ms_per_step": st["mean_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32+u64", "data": "synthetic",
+        "config": {"workload": f"served_poisson{args.rate:g}_s1e3-5e6_T64-2048_p31p63",
+                   "rate_per_s": args.rate, "duration_s": args.duration, "requests": len(reqs),
+                   "pool": len(pool), "cold_polys": n_cold, "budget_gb": args.budget_gb,
+                   "offered_term_evals_per_s": te / args.duration},
+        "latency_ms": {"p50": st["p50_ms"], "p99": st["p99_ms"], "max": st["max_ms"], "mean": st["mean_ms"]},
+        "server": st,
+        "saturated": {"value": sat["term_evals"] / sat["wall_s"], "p50_ms": sat["p50_ms"], "p99_ms": sat["p99_ms"],
+                      "passes": sat["passes"]},
+        "sequential_plain": {"requests": k, "value": te_seq / el_seq,
+                             "saturated_served_over_sequential": (sat["term_evals"] / sat["wall_s"]) / (te_seq / el_seq)},
+        "generate_s": gen_s,
+    }
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
                           "design note (DESIGN.md), not implemented"}), flush=True)
         sys.exit(2)
+
+    if args.workload == "batch":
+        return batch_main(args)
+    if args.workload == "serve":
+        return serve_main(args)
 
     import torch
 

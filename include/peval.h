@@ -136,6 +136,114 @@ int peval_set_tuning(peval_poly *h, uint32_t K, uint32_t P, uint32_t C);
 int peval_get_tuning(peval_poly *h, uint32_t T, uint32_t *K, uint32_t *P, uint32_t *C);
 
 /*
+ * Autotuner (the analogue of the paper's (T_i, T_d, M) sweep, Section 4.4).
+ * Times candidate (K, P, C) on the device for this polynomial and T
+ * evaluations at base point beta, and records the fastest for the handle's
+ * shape class (residue width, term count, mean group size and T, each on a
+ * half-octave grid) in a process-wide cache that every later run of a
+ * matching shape uses (explicit peval_set_tuning values take precedence).
+ * exhaustive = 0: coordinate search over K, then P, then C (about a dozen
+ * timed runs); 1: the full grid.  Outputs (any may be NULL): the chosen
+ * K, P, C and its time in ms.  Blocks until the timing runs are done.
+ */
+int peval_autotune(peval_poly *h, const uint64_t *beta, uint32_t T, uint32_t exhaustive,
+                   uint32_t *K, uint32_t *P, uint32_t *C, float *ms);
+
+/* Tuning cache: forget everything, or save to / merge from a text file
+ * (one line per shape class: width s_class group_class T_class K P C ms). */
+int peval_tune_clear(void);
+int peval_tune_save(const char *path);
+int peval_tune_load(const char *path);
+
+/*
+ * Batched evaluation (many polynomials, uneven sizes, mixed moduli).
+ *
+ * peval_batch_create plans one pass over `count` resident polynomials,
+ * polys[j] evaluated Ts[j] times: it fixes every member's thread layout
+ * (K from the tuning cache or the heuristic, at most 8; P = 16) and its
+ * chains so that the work items (one wave of one chain of one polynomial)
+ * have similar costs, allocates all device scratch, and captures the pass
+ * (power tables, monomials, a persistent evaluation kernel fed by a work
+ * queue in decreasing item cost, combine) into a hipGraph unless flags has
+ * PEVAL_BATCH_NO_GRAPH.  The handles must outlive the batch.
+ *
+ * peval_batch_run evaluates polys[j] at betas[j] (n_j - 2 values each) for
+ * t = t0s[j] .. t0s[j]+Ts[j]-1 (t0s may be NULL: all 1) into dev_outs[j]
+ * (device, Ts[j] x G_j residues of that polynomial's width), on `stream`.
+ * Results equal those of peval_run_async member by member.  Consecutive
+ * runs of one batch are ordered; the call returns after enqueueing, but
+ * waits for the previous run of the same batch to finish first.
+ *
+ * peval_batch_info fills info[5]: members, work items, persistent blocks,
+ * scratch bytes, term-evaluations per run.
+ */
+typedef struct peval_batch peval_batch;
+#define PEVAL_BATCH_NO_GRAPH 1u
+int peval_batch_create(uint32_t count, peval_poly *const *polys, const uint32_t *Ts, uint32_t flags,
+                       peval_batch **out);
+int peval_batch_run(peval_batch *b, const uint64_t *const *betas, const uint64_t *t0s,
+                    void *const *dev_outs, void *stream);
+int peval_batch_info(const peval_batch *b, uint64_t *info);
+int peval_batch_destroy(peval_batch *b);
+
+/*
+ * Serving: a request loop over resident polynomials.
+ *
+ * peval_server_create starts a scheduler thread on the current device.  The
+ * server keeps polynomials resident within hbm_budget_bytes (resident term
+ * data + request outputs + per-pass scratch), evicting the least recently
+ * used polynomial with no request in flight when room is needed (its host
+ * copy is kept, so a later request re-uploads it).  Requests are admitted in
+ * arrival order when their memory fits; each is cut into slices of
+ * consecutive evaluations and every pass batches one slice of each admitted
+ * request into one batched launch; two passes run at a time on two streams,
+ * so arrivals join the next pass (continuous batching).  Finished results
+ * are copied to host memory by two copy threads.  A request's result
+ * is identical to a plain peval_run of it.  flags: PEVAL_SERVER_SIMULATE
+ * runs the same scheduler without any device call (passes take
+ * term-evaluations / sim_rate seconds and produce no output), for testing
+ * the policy on machines without a GPU.
+ *
+ * add_poly copies the polynomial (same rules as peval_create) and returns its
+ * id; it becomes resident at its first admitted request.  submit queues
+ * b_1..b_T at beta into host_out (T x G residues of the polynomial's width;
+ * G = number of distinct (x1, x2) exponent pairs), which must stay valid
+ * until the request is done; a request that could not fit in the budget
+ * even alone is refused with PEVAL_ENOMEM.  poll sets *done; wait blocks
+ * (timeout_ms < 0: forever; PEVAL_ETIMEOUT when it expires); both return the
+ * request's error if it failed.  release forgets a finished request.
+ * Latency = submit to result in host memory.
+ */
+typedef struct peval_server peval_server;
+#define PEVAL_SERVER_SIMULATE 1u
+typedef struct peval_server_stats_t {
+    uint64_t submitted, completed, rejected, queued, active, passes;
+    uint64_t term_evals;        /* of completed requests */
+    uint64_t uploads, evictions;  /* polynomials made resident / evicted */
+    uint64_t hbm_in_use, hbm_peak;
+    double wall_s;              /* from create (or reset) to the last completion */
+    double p50_ms, p99_ms, max_ms, mean_ms;  /* request latency */
+} peval_server_stats_t;
+int peval_server_create(uint64_t hbm_budget_bytes, uint32_t flags, peval_server **out);
+/* slice_work: target term-evaluations per request slice (default 2e9);
+ * pass_work: term-evaluations gathered into one pass before launching it
+ * (default 1.5e10; the oldest request always gets a slice, the others are
+ * taken shortest remaining work first); sim_rate: term-evaluations per
+ * second of the simulated executor. */
+int peval_server_configure(peval_server *srv, double slice_work, double pass_work, double sim_rate);
+int peval_server_add_poly(peval_server *srv, uint64_t p, uint32_t n, uint64_t s, const uint32_t *exponents,
+                          const uint64_t *coeffs, uint64_t *poly_id);
+int peval_server_remove_poly(peval_server *srv, uint64_t poly_id);
+int peval_server_submit(peval_server *srv, uint64_t poly_id, const uint64_t *beta, uint32_t T, void *host_out,
+                        uint64_t *req_id);
+int peval_server_poll(peval_server *srv, uint64_t req_id, int *done);
+int peval_server_wait(peval_server *srv, uint64_t req_id, int64_t timeout_ms);
+int peval_server_release(peval_server *srv, uint64_t req_id);
+int peval_server_stats(peval_server *srv, peval_server_stats_t *stats);
+int peval_server_reset_stats(peval_server *srv);
+int peval_server_destroy(peval_server *srv);
+
+/*
  * Kernel timing (HIP events around each kernel on the launch stream).
  * enable != 0 starts recording for every handle; peval_prof_read returns
  * cumulative milliseconds and launch counts per kernel kind and resets them:

@@ -1,0 +1,350 @@
+// Batched evaluation: many resident polynomials, uneven sizes, mixed moduli,
+// one persistent launch captured in a hipGraph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+#include "batch_internal.hpp"
+#include "batch_kernels.hpp"
+#include "errors.hpp"
+#include "peval.h"
+#include "peval_internal.hpp"
+
+namespace peval {
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+void batch_release(BatchCore &b) {
+  if (b.d_blob) (void)hipFree(b.d_blob);
+  if (b.arena && b.own_arena) (void)hipFree(b.arena);
+  b.d_blob = nullptr;
+  b.arena = nullptr;
+}
+
+int batch_persistent_blocks(int *blocks) {
+  static int cached = 0;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!cached) {
+    int dev = 0, per_cu = 0;
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipGetDeviceProperties(&prop, dev));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_eval_kernel, kEvalBlock, 0));
+    cached = std::max(1, per_cu) * prop.multiProcessorCount;
+  }
+  *blocks = cached;
+  return PEVAL_OK;
+}
+
+// Bytes of device scratch one member needs (power tables, chain starts,
+// Gamma, Gamma', partial sums).
+size_t member_scratch_bytes(const peval_poly *h, const Plan &pl, uint32_t C, uint32_t T) {
+  const size_t w = h->w;
+  size_t b = 0;
+  b += align_up((size_t)std::max<uint32_t>(h->tab_total, 1) * w, 256) * 2;
+  b += align_up((size_t)C * pl.K * pl.NT * w, 256);
+  b += align_up((size_t)pl.K * pl.NT * w, 256) * 2;
+  const size_t lmax = ((size_t)T + C - 1) / C;
+  b += align_up((size_t)C * lmax * pl.nslots * w, 256);
+  return b;
+}
+
+// Chains for one member so that its work items cost about target_cost
+// term-evaluations each.
+uint32_t member_chains(const Plan &pl, uint32_t T, double target_cost) {
+  double per_chain_full = 64.0 * pl.K * T;  // one wave, one chain over all T
+  double c = std::ceil(per_chain_full / std::max(target_cost, 1.0));
+  c = std::min<double>(std::max(c, 1.0), std::min<uint32_t>(T, 256));
+  return (uint32_t)c;
+}
+
+size_t batch_scratch_need(const std::vector<BatchMember> &mem) {
+  size_t need = 0;
+  for (const auto &m : mem) need += member_scratch_bytes(m.h, *m.plan, m.C, m.T);
+  return need;
+}
+
+void batch_plan(BatchCore &b, const std::vector<BatchMember> &mem, void *arena, const BatchRun *runs) {
+  const uint32_t count = (uint32_t)mem.size();
+  b.count = count;
+  b.descs.assign(count, BatchDesc{});
+  std::vector<uint64_t> ptab(count + 1, 0), pmono(count + 1, 0), pout(count + 1, 0);
+  std::vector<BatchItem> items;
+  b.scratch_bytes = batch_scratch_need(mem);
+  b.arena = arena;
+  char *cur = (char *)arena;
+  auto take = [&](size_t bytes) {
+    void *p = cur;
+    cur += align_up(bytes, 256);
+    return p;
+  };
+  for (uint32_t j = 0; j < count; ++j) {
+    const peval_poly *h = mem[j].h;
+    const Plan &pl = *mem[j].plan;
+    BatchDesc &d = b.descs[j];
+    const size_t w = h->w;
+    d.w = h->w;
+    d.ntail = h->n - 2;
+    d.K = pl.K;
+    d.C = mem[j].C;
+    d.T = mem[j].T;
+    d.Lmax = (d.T + d.C - 1) / d.C;
+    d.s = h->s;
+    d.NT = pl.NT;
+    d.NW = pl.NW;
+    d.nslots = pl.nslots;
+    d.G = h->G;
+    d.m64 = h->m64;
+    d.m32 = h->m32;
+    d.to = h->tab;
+    d.tab_total = h->tab_total;
+    d.coeff = h->d_coeff;
+    d.exps = h->d_exps;
+    d.tval = take((size_t)std::max<uint32_t>(h->tab_total, 1) * w);
+    d.tquot = take((size_t)std::max<uint32_t>(h->tab_total, 1) * w);
+    d.thr_first = pl.d_thr_first;
+    d.thr_cnt = pl.d_thr_cnt;
+    d.endmask = pl.d_endmask;
+    d.slot_base = pl.d_slot_base;
+    d.slot_off = pl.d_slot_off;
+    d.lam = take((size_t)d.C * pl.K * pl.NT * w);
+    d.gam = take((size_t)pl.K * pl.NT * w);
+    d.gamq = take((size_t)pl.K * pl.NT * w);
+    d.partial = take((size_t)d.C * d.Lmax * pl.nslots * w);
+    ptab[j + 1] = ptab[j] + (d.ntail ? h->tab_total : 0);
+    pmono[j + 1] = pmono[j] + (uint64_t)pl.K * pl.NT;
+    pout[j + 1] = pout[j] + ((h->G + kCombineTile - 1) / kCombineTile) * d.C *
+                               (((uint64_t)d.Lmax + kCombineTile - 1) / kCombineTile);
+  }
+  // Work items, biggest first.  An item costs K x (evaluations of its chain);
+  // within one member the chains differ by at most one evaluation, so
+  // ordering members by K x Lmax and emitting each member's items chain by
+  // chain gives the decreasing order without sorting every item.
+  std::vector<uint32_t> order(count);
+  std::iota(order.begin(), order.end(), 0u);
+  std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) {
+    return (uint64_t)b.descs[x].K * b.descs[x].Lmax > (uint64_t)b.descs[y].K * b.descs[y].Lmax;
+  });
+  uint64_t n_items = 0;
+  for (uint32_t j = 0; j < count; ++j) n_items += (uint64_t)b.descs[j].C * b.descs[j].NW;
+  items.reserve(n_items);
+  for (uint32_t j : order)
+    for (uint32_t c = 0; c < b.descs[j].C; ++c)
+      for (uint64_t wv = 0; wv < b.descs[j].NW; ++wv) items.push_back(BatchItem{j, (uint32_t)wv, c, 0});
+  b.n_items = (uint32_t)items.size();
+  b.tab_total = ptab[count];
+  b.mono_total = pmono[count];
+  b.out_total = pout[count];
+
+  // blob image: descriptors, runs, items, prefixes, queue counter
+  b.off_desc = 0;
+  b.off_run = align_up(b.off_desc + count * sizeof(BatchDesc), 256);
+  b.off_items = align_up(b.off_run + count * sizeof(BatchRun), 256);
+  b.off_ptab = align_up(b.off_items + std::max<size_t>(items.size(), 1) * sizeof(BatchItem), 256);
+  b.off_pmono = align_up(b.off_ptab + (count + 1) * 8, 256);
+  b.off_pout = align_up(b.off_pmono + (count + 1) * 8, 256);
+  b.off_ctr = align_up(b.off_pout + (count + 1) * 8, 256);
+  b.blob_bytes = b.off_ctr + 256;
+  b.image.assign(b.blob_bytes, 0);
+  char *img = b.image.data();
+  memcpy(img + b.off_desc, b.descs.data(), count * sizeof(BatchDesc));
+  if (runs) memcpy(img + b.off_run, runs, count * sizeof(BatchRun));
+  if (!items.empty()) memcpy(img + b.off_items, items.data(), items.size() * sizeof(BatchItem));
+  memcpy(img + b.off_ptab, ptab.data(), (count + 1) * 8);
+  memcpy(img + b.off_pmono, pmono.data(), (count + 1) * 8);
+  memcpy(img + b.off_pout, pout.data(), (count + 1) * 8);
+}
+
+void batch_bind(BatchCore &b, void *d_blob) {
+  char *base = (char *)d_blob;
+  b.d_blob = d_blob;
+  b.d_desc = (BatchDesc *)(base + b.off_desc);
+  b.d_run = (BatchRun *)(base + b.off_run);
+  b.d_items = (BatchItem *)(base + b.off_items);
+  b.d_ptab = (uint64_t *)(base + b.off_ptab);
+  b.d_pmono = (uint64_t *)(base + b.off_pmono);
+  b.d_pout = (uint64_t *)(base + b.off_pout);
+  b.d_counter = (uint32_t *)(base + b.off_ctr);
+}
+
+int batch_build(BatchCore &b, const std::vector<BatchMember> &mem) {
+  void *arena = nullptr, *blob = nullptr;
+  size_t need = batch_scratch_need(mem);
+  HIP_TRY(hipMalloc(&arena, std::max<size_t>(need, 256)));
+  b.own_arena = true;
+  batch_plan(b, mem, arena, nullptr);
+  HIP_TRY(hipMalloc(&blob, b.blob_bytes));
+  batch_bind(b, blob);
+  HIP_TRY(hipMemcpy(blob, b.image.data(), b.blob_bytes, hipMemcpyHostToDevice));
+  PEVAL_TRY(batch_persistent_blocks(&b.eval_blocks));
+  b.eval_blocks = (int)std::min<uint64_t>((uint64_t)b.eval_blocks, std::max<uint64_t>(1, (b.n_items + 3) / 4));
+  return PEVAL_OK;
+}
+
+// Kernels of one batched pass (the run table must already be on the device).
+int batch_enqueue(const BatchCore &b, hipStream_t st) {
+  batch_reset_kernel<<<1, 64, 0, st>>>(b.d_counter);
+  HIP_TRY(hipGetLastError());
+  if (b.tab_total) {
+    batch_power_kernel<<<(unsigned)((b.tab_total + 255) / 256), 256, 0, st>>>(b.d_desc, b.d_run, b.count, b.d_ptab);
+    HIP_TRY(hipGetLastError());
+  }
+  if (b.mono_total) {
+    batch_mono_kernel<<<(unsigned)((b.mono_total + 255) / 256), 256, 0, st>>>(b.d_desc, b.d_run, b.count, b.d_pmono);
+    HIP_TRY(hipGetLastError());
+  }
+  if (b.n_items) {
+    batch_eval_kernel<<<b.eval_blocks, kEvalBlock, 0, st>>>(b.d_desc, b.d_items, b.n_items, b.d_counter);
+    HIP_TRY(hipGetLastError());
+  }
+  if (b.out_total) {  // out_total counts combine tiles
+    batch_combine_kernel<<<(unsigned)b.out_total, kCombineBlock, 0, st>>>(b.d_desc, b.d_run, b.count, b.d_pout);
+    HIP_TRY(hipGetLastError());
+  }
+  return PEVAL_OK;
+}
+
+}  // namespace peval
+
+using namespace peval;
+
+struct peval_batch {
+  BatchCore core;
+  std::vector<peval_poly *> polys;
+  std::vector<uint32_t> Ts;
+  BatchRun *h_run = nullptr;  // pinned staging for the run table
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;
+  bool have_done = false;
+  bool use_graph = true;
+  std::mutex mu;
+};
+
+static void batch_free(peval_batch *b) {
+  if (!b) return;
+  if (b->have_done) (void)hipEventSynchronize(b->done);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->done) (void)hipEventDestroy(b->done);
+  if (b->h_run) (void)hipHostFree(b->h_run);
+  batch_release(b->core);
+  delete b;
+}
+
+extern "C" int peval_batch_create(uint32_t count, peval_poly *const *polys, const uint32_t *Ts, uint32_t flags,
+                                  peval_batch **out) {
+  if (!out) return fail(PEVAL_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (count == 0 || !polys || !Ts) return fail(PEVAL_EINVAL, "empty batch or null arrays");
+  for (uint32_t j = 0; j < count; ++j) {
+    if (!polys[j]) return fail(PEVAL_EINVAL, "polys[%u] is NULL", j);
+    if (Ts[j] == 0) return fail(PEVAL_EINVAL, "Ts[%u] is 0", j);
+    if ((uint64_t)Ts[j] * polys[j]->G > (1ull << 40)) return fail(PEVAL_EUNSUPPORTED, "T*G too large");
+  }
+  peval_batch *b = new (std::nothrow) peval_batch();
+  if (!b) return fail(PEVAL_ENOMEM, "host allocation");
+  b->polys.assign(polys, polys + count);
+  b->Ts.assign(Ts, Ts + count);
+  b->use_graph = !(flags & PEVAL_BATCH_NO_GRAPH);
+  auto bail = [&](int rc) {
+    batch_free(b);
+    return rc;
+  };
+
+  // plans (autotuned K where a cached tuning exists; P fixed for batches)
+  std::vector<BatchMember> mem(count);
+  double work = 0;
+  for (uint32_t j = 0; j < count; ++j) {
+    peval_poly *h = polys[j];
+    std::lock_guard<std::mutex> lk(h->mu);
+    Tuning t = choose_tuning(h, Ts[j]);
+    uint32_t K = std::min<uint32_t>(t.K, 8);
+    Plan *pl = nullptr;
+    int rc = get_plan(h, K, kBatchP, &pl);
+    if (rc != PEVAL_OK) return bail(rc);
+    mem[j] = BatchMember{h, pl, 1, Ts[j]};
+    work += 64.0 * pl->K * pl->NW * Ts[j];
+  }
+  const double target = std::max(work / 65536.0, 64.0 * 8 * 64);
+  for (auto &m : mem) m.C = member_chains(*m.plan, m.T, target);
+  int rc = batch_build(b->core, mem);
+  if (rc != PEVAL_OK) return bail(rc);
+  if (hipHostMalloc((void **)&b->h_run, count * sizeof(BatchRun), hipHostMallocDefault) != hipSuccess)
+    return bail(fail(PEVAL_ENOMEM, "pinned staging"));
+  memset(b->h_run, 0, count * sizeof(BatchRun));
+  if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess)
+    return bail(fail(PEVAL_EDEVICE, "event creation"));
+  if (b->use_graph) {
+    if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
+      return bail(fail(PEVAL_EDEVICE, "stream creation"));
+    if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return bail(fail(PEVAL_EDEVICE, "begin capture"));
+    int erc = batch_enqueue(b->core, b->cap_stream);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
+    if (erc != PEVAL_OK) return bail(erc);
+    if (e != hipSuccess) return bail(fail(PEVAL_EDEVICE, "end capture: %s", hipGetErrorString(e)));
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess)
+      return bail(fail(PEVAL_EDEVICE, "graph instantiate"));
+  }
+  *out = b;
+  return PEVAL_OK;
+}
+
+extern "C" int peval_batch_run(peval_batch *b, const uint64_t *const *betas, const uint64_t *t0s,
+                               void *const *dev_outs, void *stream) {
+  if (!b || !dev_outs) return fail(PEVAL_EINVAL, "null argument");
+  const uint32_t count = b->core.count;
+  for (uint32_t j = 0; j < count; ++j) {
+    if (!dev_outs[j]) return fail(PEVAL_EINVAL, "dev_outs[%u] is NULL", j);
+    if (b->polys[j]->n > 2 && (!betas || !betas[j])) return fail(PEVAL_EINVAL, "betas[%u] is NULL", j);
+    if (t0s && t0s[j] < 1) return fail(PEVAL_EINVAL, "t0s[%u] must be >= 1", j);
+  }
+  std::lock_guard<std::mutex> lk(b->mu);
+  hipStream_t st = (hipStream_t)stream;
+  // the staging buffer is reused: wait until the previous upload has been consumed
+  if (b->have_done) HIP_TRY(hipEventSynchronize(b->done));
+  for (uint32_t j = 0; j < count; ++j) {
+    BatchRun &r = b->h_run[j];
+    memset(&r.beta, 0, sizeof r.beta);
+    const peval_poly *h = b->polys[j];
+    for (uint32_t k = 0; k + 2 < h->n; ++k) r.beta.b[k] = betas[j][k] % h->p;
+    r.t0 = t0s ? t0s[j] : 1;
+    r.out = dev_outs[j];
+  }
+  HIP_TRY(hipMemcpyAsync(b->core.d_run, b->h_run, count * sizeof(BatchRun), hipMemcpyHostToDevice, st));
+  if (b->use_graph) {
+    HIP_TRY(hipGraphLaunch(b->exec, st));
+  } else {
+    PEVAL_TRY(batch_enqueue(b->core, st));
+  }
+  HIP_TRY(hipEventRecord(b->done, st));
+  b->have_done = true;
+  return PEVAL_OK;
+}
+
+extern "C" int peval_batch_info(const peval_batch *b, uint64_t *info) {
+  if (!b || !info) return fail(PEVAL_EINVAL, "null argument");
+  info[0] = b->core.count;
+  info[1] = b->core.n_items;
+  info[2] = (uint64_t)b->core.eval_blocks;
+  info[3] = b->core.scratch_bytes;
+  uint64_t te = 0;
+  for (uint32_t j = 0; j < b->core.count; ++j) te += b->polys[j]->s * (uint64_t)b->Ts[j];
+  info[4] = te;
+  return PEVAL_OK;
+}
+
+extern "C" int peval_batch_destroy(peval_batch *b) {
+  batch_free(b);
+  return PEVAL_OK;
+}

@@ -1,0 +1,58 @@
+// Shared machinery of batched launches (used by peval_batch_* and the server).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "batch_types.hpp"
+#include "peval_internal.hpp"
+
+namespace peval {
+
+struct BatchMember {
+  peval_poly *h;
+  Plan *plan;
+  uint32_t C;  // chains
+  uint32_t T;  // evaluations
+};
+
+// Device state of one batched pass.
+struct BatchCore {
+  uint32_t count = 0;
+  uint32_t n_items = 0;
+  int eval_blocks = 0;
+  uint64_t tab_total = 0, mono_total = 0, out_total = 0;
+  size_t scratch_bytes = 0;
+  std::vector<BatchDesc> descs;
+  void *d_blob = nullptr;  // descriptors, run table, items, prefixes, queue counter
+  BatchDesc *d_desc = nullptr;
+  BatchRun *d_run = nullptr;
+  BatchItem *d_items = nullptr;
+  uint64_t *d_ptab = nullptr, *d_pmono = nullptr, *d_pout = nullptr;
+  uint32_t *d_counter = nullptr;
+  void *arena = nullptr;  // per-member scratch
+  bool own_arena = false;
+  // host image of the blob and its layout
+  std::vector<char> image;
+  size_t blob_bytes = 0;
+  size_t off_desc = 0, off_run = 0, off_items = 0, off_ptab = 0, off_pmono = 0, off_pout = 0, off_ctr = 0;
+};
+
+size_t member_scratch_bytes(const peval_poly *h, const Plan &pl, uint32_t C, uint32_t T);
+uint32_t member_chains(const Plan &pl, uint32_t T, double target_cost);
+size_t batch_scratch_need(const std::vector<BatchMember> &mem);
+// Host planning: descriptors pointing into `arena` (batch_scratch_need bytes),
+// work items in decreasing cost, prefixes, and the blob image (with the run
+// table if `runs` is given).  No device call.
+void batch_plan(BatchCore &b, const std::vector<BatchMember> &mem, void *arena, const BatchRun *runs);
+// Points the device-side fields at a blob allocation holding the image.
+void batch_bind(BatchCore &b, void *d_blob);
+// Allocates scratch and blob with hipMalloc and uploads the image.  Handles
+// must stay alive while the batch is used.
+int batch_build(BatchCore &b, const std::vector<BatchMember> &mem);
+int batch_enqueue(const BatchCore &b, hipStream_t st);
+void batch_release(BatchCore &b);
+int batch_persistent_blocks(int *blocks);
+
+}  // namespace peval

@@ -1,0 +1,173 @@
+// Batched evaluation of many polynomials in one pass: flattened prologue and
+// combine kernels plus a persistent evaluation kernel that pulls work items
+// (polynomial, wave, chain) from a queue, biggest first.
+//
+// Each polynomial keeps its own modulus, residue width, thread layout and
+// chains; the per-wave work is exactly eval_wave of the single-polynomial
+// path, selected per item by a wave-uniform switch on (width, K).  The queue
+// counter only decides which wave does an item; every item writes its own
+// partial-sum slots, so results never depend on the schedule.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "batch_types.hpp"
+#include "kernels.hpp"
+
+namespace peval {
+
+// index of the polynomial whose flattened range holds idx (prefix has count+1 entries)
+__device__ __forceinline__ uint32_t find_poly(const uint64_t *prefix, uint32_t count, uint64_t idx) {
+  uint32_t lo = 0, hi = count;
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) / 2;
+    if (prefix[mid] <= idx) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void batch_reset_kernel(uint32_t *counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0;
+}
+
+__global__ void batch_power_kernel(const BatchDesc *D, const BatchRun *R, uint32_t count, const uint64_t *prefix) {
+  uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= prefix[count]) return;
+  uint32_t j = find_poly(prefix, count, idx);
+  const BatchDesc &d = D[j];
+  uint32_t local = (uint32_t)(idx - prefix[j]);
+  if (d.w == 4)
+    power_entry<W32>(R[j].beta, d.to.off, d.ntail, local, (uint32_t *)d.tval, (uint32_t *)d.tquot, d.m32);
+  else
+    power_entry<W64>(R[j].beta, d.to.off, d.ntail, local, (uint64_t *)d.tval, (uint64_t *)d.tquot, d.m64);
+}
+
+template <class A>
+__device__ __forceinline__ void batch_mono_one(const BatchDesc &d, uint64_t t0, uint64_t local, const typename A::M &m) {
+  using T = typename A::T;
+  MonoArgs<A> a;
+  a.coeff = (const T *)d.coeff;
+  a.exps = d.exps;
+  a.tval = (const T *)d.tval;
+  a.tquot = (const T *)d.tquot;
+  a.to = d.to;
+  a.thr_first = d.thr_first;
+  a.thr_cnt = d.thr_cnt;
+  a.lam = (T *)d.lam;
+  a.gam = (T *)d.gam;
+  a.gamq = (T *)d.gamq;
+  a.s = d.s;
+  a.NT = d.NT;
+  a.t0 = t0;
+  a.ntail = d.ntail;
+  a.K = d.K;
+  a.C = d.C;
+  a.m = m;
+  monomial_entry<A>(a, local);
+}
+
+__global__ void batch_mono_kernel(const BatchDesc *D, const BatchRun *R, uint32_t count, const uint64_t *prefix) {
+  uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= prefix[count]) return;
+  uint32_t j = find_poly(prefix, count, idx);
+  const BatchDesc &d = D[j];
+  uint64_t local = idx - prefix[j];
+  if (d.w == 4) batch_mono_one<W32>(d, R[j].t0, local, d.m32);
+  else batch_mono_one<W64>(d, R[j].t0, local, d.m64);
+}
+
+template <class A, int K>
+__device__ __forceinline__ void batch_eval_item(const BatchDesc &d, const BatchItem &it, void *lds, int lane,
+                                                const typename A::M &m) {
+  using T = typename A::T;
+  EvalArgs<A> a;
+  a.lam = (const T *)d.lam;
+  a.gam = (const T *)d.gam;
+  a.gamq = (const T *)d.gamq;
+  a.endmask = d.endmask;
+  a.slot_base = d.slot_base;
+  a.partial = (T *)d.partial;
+  a.NT = d.NT;
+  a.NW = d.NW;
+  a.nslots = d.nslots;
+  a.C = d.C;
+  a.T = d.T;
+  a.Lmax = d.Lmax;
+  a.m = m;
+  eval_wave<A, K, kBatchP>(a, it.wave, it.chain, *reinterpret_cast<Stage<A, kBatchP> *>(lds), lane);
+}
+
+constexpr size_t kStageBytes = sizeof(Stage<W64, kBatchP>) > sizeof(Stage<W32, kBatchP>)
+                                   ? sizeof(Stage<W64, kBatchP>)
+                                   : sizeof(Stage<W32, kBatchP>);
+
+__global__ __launch_bounds__(kEvalBlock) void batch_eval_kernel(const BatchDesc *D, const BatchItem *items,
+                                                                uint32_t n_items, uint32_t *counter) {
+  __shared__ __align__(16) unsigned char stage[kEvalBlock / 64][kStageBytes];
+  const int lane = threadIdx.x & 63;
+  const int warp = threadIdx.x >> 6;
+  void *lds = stage[warp];
+  while (true) {
+    uint32_t next = 0;
+    if (lane == 0) next = atomicAdd(counter, 1u);
+    next = __builtin_amdgcn_readfirstlane(next);
+    if (next >= n_items) break;  // every wave reaches this once the queue is drained
+    const BatchItem it = items[next];
+    const BatchDesc &d = D[it.poly];
+    if (d.w == 4) {
+      switch (d.K) {
+        case 1: batch_eval_item<W32, 1>(d, it, lds, lane, d.m32); break;
+        case 2: batch_eval_item<W32, 2>(d, it, lds, lane, d.m32); break;
+        case 4: batch_eval_item<W32, 4>(d, it, lds, lane, d.m32); break;
+        default: batch_eval_item<W32, 8>(d, it, lds, lane, d.m32); break;
+      }
+    } else {
+      switch (d.K) {
+        case 1: batch_eval_item<W64, 1>(d, it, lds, lane, d.m64); break;
+        case 2: batch_eval_item<W64, 2>(d, it, lds, lane, d.m64); break;
+        case 4: batch_eval_item<W64, 4>(d, it, lds, lane, d.m64); break;
+        default: batch_eval_item<W64, 8>(d, it, lds, lane, d.m64); break;
+      }
+    }
+  }
+}
+
+// Flattened combine tiles: member j owns tiles prefix[j] .. prefix[j+1]-1,
+// ordered (evaluation tile, chain, group tile) with the group tile fastest.
+template <class A>
+__device__ __forceinline__ void batch_combine_one(const BatchDesc &d, void *out, uint64_t local, const typename A::M &m,
+                                                  void *lds) {
+  using T = typename A::T;
+  CombineArgs<A> a;
+  a.partial = (const T *)d.partial;
+  a.slot_off = d.slot_off;
+  a.out = (T *)out;
+  a.G = d.G;
+  a.C = d.C;
+  a.T = d.T;
+  a.Lmax = d.Lmax;
+  a.m = m;
+  const uint64_t gt = (d.G + kCombineTile - 1) / kCombineTile;
+  const uint64_t g_tile = local % gt;
+  const uint64_t rest = local / gt;
+  const uint32_t c = (uint32_t)(rest % d.C);
+  const uint32_t i_tile = (uint32_t)(rest / d.C);
+  combine_tile<A>(a, g_tile * kCombineTile, c, i_tile * kCombineTile,
+                  reinterpret_cast<T(*)[kCombineTile + 1]>(lds));
+}
+
+__global__ __launch_bounds__(kCombineBlock) void batch_combine_kernel(const BatchDesc *D, const BatchRun *R,
+                                                                      uint32_t count, const uint64_t *prefix) {
+  __shared__ __align__(16) uint64_t tile[kCombineTile][kCombineTile + 1];
+  const uint64_t idx = blockIdx.x;  // one tile per block; uniform over the block
+  if (idx >= prefix[count]) return;
+  const uint32_t j = find_poly(prefix, count, idx);
+  const BatchDesc &d = D[j];
+  const uint64_t local = idx - prefix[j];
+  if (d.w == 4) batch_combine_one<W32>(d, R[j].out, local, d.m32, tile);
+  else batch_combine_one<W64>(d, R[j].out, local, d.m64, tile);
+}
+
+}  // namespace peval

@@ -39,17 +39,23 @@ struct TableOffsets {
 // A2: tables of powers beta_k^j (value and Shoup quotient)
 // ---------------------------------------------------------------------------
 template <class A>
-__global__ void power_table_kernel(BetaArg beta, TableOffsets to, uint32_t ntail, uint32_t total,
-                                   typename A::T *val, typename A::T *quot, typename A::M m) {
-  uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
+__device__ __forceinline__ void power_entry(const BetaArg &beta, const uint32_t *off, uint32_t ntail, uint32_t idx,
+                                            typename A::T *val, typename A::T *quot, const typename A::M &m) {
   uint32_t k = 0;
-  while (k + 1 < ntail && idx >= to.off[k + 1]) ++k;
-  uint32_t j = idx - to.off[k];
+  while (k + 1 < ntail && idx >= off[k + 1]) ++k;
+  uint32_t j = idx - off[k];
   typename A::T b = (typename A::T)beta.b[k];  // reduced on the host
   typename A::T v = pow_mod(b, (uint64_t)j, m);
   val[idx] = v;
   quot[idx] = shoup_quot(v, m);
+}
+
+template <class A>
+__global__ void power_table_kernel(BetaArg beta, TableOffsets to, uint32_t ntail, uint32_t total,
+                                   typename A::T *val, typename A::T *quot, typename A::M m) {
+  uint32_t idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  power_entry<A>(beta, to.off, ntail, idx, val, quot, m);
 }
 
 // ---------------------------------------------------------------------------
@@ -74,10 +80,8 @@ struct MonoArgs {
 };
 
 template <class A>
-__global__ void monomial_kernel(MonoArgs<A> a) {
+__device__ __forceinline__ void monomial_entry(const MonoArgs<A> &a, uint64_t idx) {
   using T = typename A::T;
-  uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (uint64_t)a.K * a.NT) return;
   uint32_t k = (uint32_t)(idx / a.NT);
   uint64_t j = idx - (uint64_t)k * a.NT;
   const uint64_t NTK = (uint64_t)a.K * a.NT;
@@ -117,6 +121,13 @@ __global__ void monomial_kernel(MonoArgs<A> a) {
   a.gamq[idx] = shoup_quot(g, a.m);
 }
 
+template <class A>
+__global__ void monomial_kernel(MonoArgs<A> a) {
+  uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (uint64_t)a.K * a.NT) return;
+  monomial_entry<A>(a, idx);
+}
+
 // ---------------------------------------------------------------------------
 // A4-A6: Hadamard products and coefficient reductions
 // ---------------------------------------------------------------------------
@@ -127,9 +138,10 @@ struct EvalArgs {
   const typename A::T *gamq;    // [K][NT]
   const uint64_t *endmask;      // per wave: bit l set if lane l closes a segment
   const uint32_t *slot_base;    // per wave: index of its first segment slot
-  typename A::T *partial;       // [T][nslots] canonical partial coefficients
+  typename A::T *partial;       // [nslots][C][Lmax] canonical partial coefficients
   uint64_t NT, NW, nslots;
   uint32_t C, T;                // chains, evaluations in this launch
+  uint32_t Lmax;                // ceil(T / C): evaluations of the longest chain
   typename A::M m;
 };
 
@@ -166,17 +178,12 @@ __device__ __forceinline__ void wave_sync() {
 
 constexpr int kEvalBlock = 256;  // 4 waves, each independent
 
+// One wave's share of the evaluations: threads wave*64 .. wave*64+63, chain c.
 template <class A, int K, int P>
-__global__ __launch_bounds__(kEvalBlock) void eval_kernel(EvalArgs<A> a) {
+__device__ __forceinline__ void eval_wave(const EvalArgs<A> &a, uint64_t wave, uint32_t c, Stage<A, P> &st,
+                                          int lane) {
   using T = typename A::T;
   static_assert(64 % P == 0, "P must divide the wave size");
-  __shared__ Stage<A, P> stage[kEvalBlock / 64];
-
-  const int lane = threadIdx.x & 63;
-  const int warp = threadIdx.x >> 6;
-  const uint64_t wave = (uint64_t)blockIdx.x * (kEvalBlock / 64) + warp;
-  if (wave >= a.NW) return;  // whole waves leave; no block-wide barrier is used
-  const uint32_t c = blockIdx.y;
   const uint64_t j = wave * 64 + lane;
   const uint64_t NTK = (uint64_t)K * a.NT;
 
@@ -191,7 +198,6 @@ __global__ __launch_bounds__(kEvalBlock) void eval_kernel(EvalArgs<A> a) {
   const uint32_t sbase = a.slot_base[wave];
   const uint32_t L = (c < a.T) ? (a.T - 1 - c) / a.C + 1 : 0;  // evaluations of chain c
   const int h = lane / P, pp = lane % P;
-  Stage<A, P> &st = stage[warp];
 
   for (uint32_t i0 = 0; i0 < L; i0 += P) {
     const int np = (L - i0 < (uint32_t)P) ? (int)(L - i0) : P;
@@ -210,15 +216,17 @@ __global__ __launch_bounds__(kEvalBlock) void eval_kernel(EvalArgs<A> a) {
     // transposed segmented sum: lane (h, pp) walks sub-tile h for evaluation pp
     if (pp < np) {
       typename A::Acc sum = A::zero();
-      const uint64_t row = (uint64_t)c + (uint64_t)(i0 + pp) * a.C;
-      T *prow = a.partial + row * a.nslots;
+      // partial[(slot * C + c) * Lmax + i]: the P lanes of a sub-tile write P
+      // consecutive evaluations of one slot
+      T *pcol = a.partial + (uint64_t)c * a.Lmax + i0 + pp;
+      const uint64_t slot_stride = (uint64_t)a.C * a.Lmax;
 #pragma unroll 4
       for (int jj = 0; jj < P; ++jj) {
         const int src = h * P + jj;
         A::add(sum, st.get(src, pp));
         if ((emask >> src) & 1ull) {
           const uint32_t slot = sbase + (uint32_t)__popcll(emask & ((1ull << src) - 1ull));
-          prow[slot] = A::reduce(sum, a.m);
+          pcol[slot * slot_stride] = A::reduce(sum, a.m);
           sum = A::zero();
         }
       }
@@ -227,22 +235,85 @@ __global__ __launch_bounds__(kEvalBlock) void eval_kernel(EvalArgs<A> a) {
   }
 }
 
+template <class A, int K, int P>
+__global__ __launch_bounds__(kEvalBlock) void eval_kernel(EvalArgs<A> a) {
+  __shared__ Stage<A, P> stage[kEvalBlock / 64];
+  const int lane = threadIdx.x & 63;
+  const int warp = threadIdx.x >> 6;
+  const uint64_t wave = (uint64_t)blockIdx.x * (kEvalBlock / 64) + warp;
+  if (wave >= a.NW) return;  // whole waves leave; no block-wide barrier is used
+  eval_wave<A, K, P>(a, wave, blockIdx.y, stage[warp], lane);
+}
+
 // ---------------------------------------------------------------------------
 // A7: combine partial coefficients into the dense images
 // ---------------------------------------------------------------------------
+constexpr int kCombineTile = 64;   // groups x evaluations per block
+constexpr int kCombineBlock = 256;
+
 template <class A>
-__global__ void combine_kernel(const typename A::T *partial, const uint32_t *slot_off,
-                               typename A::T *out, uint64_t G, uint64_t nslots, uint64_t total,
-                               typename A::M m) {
+struct CombineArgs {
+  const typename A::T *partial;   // [nslots][C][Lmax]
+  const uint32_t *slot_off;       // G + 1
+  typename A::T *out;             // [T][G]
+  uint64_t G;
+  uint32_t C, T, Lmax;
+  typename A::M m;
+};
+
+// One tile: groups g0..g0+63 x evaluations i0..i0+63 of chain c.  Each wave
+// sums 16 groups with one lane per evaluation (coalesced reads along i),
+// the tile is transposed in LDS and written row by row (coalesced along g).
+template <class A>
+__device__ __forceinline__ void combine_tile(const CombineArgs<A> &a, uint64_t g0, uint32_t c, uint32_t i0,
+                                             typename A::T (*tile)[kCombineTile + 1]) {
   using T = typename A::T;
-  uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= total) return;
-  uint64_t row = idx / G;
-  uint64_t g = idx - row * G;
-  const T *prow = partial + row * nslots;
-  T acc = 0;
-  for (uint32_t sl = slot_off[g]; sl < slot_off[g + 1]; ++sl) acc = add_mod(acc, prow[sl], (T)m.p);
-  out[idx] = acc;
+  const int lane = threadIdx.x & 63, warp = threadIdx.x >> 6;
+  const uint32_t Lc = (c < a.T) ? (a.T - 1 - c) / a.C + 1 : 0;
+  const bool live = i0 + lane < Lc;
+  const uint64_t slot_stride = (uint64_t)a.C * a.Lmax;
+  const T *col = a.partial + (uint64_t)c * a.Lmax + i0 + lane;
+  // the wave's 16 groups own one contiguous run of slots; walk it with four
+  // independent loads in flight and close a group whenever its slots end
+  const int gl_first = warp * (kCombineTile / 4), gl_last = gl_first + kCombineTile / 4;
+  for (int gl = gl_first; gl < gl_last; ++gl) tile[gl][lane] = 0;
+  const uint64_t ga = g0 + gl_first;
+  if (ga < a.G) {
+    const uint64_t gb = (g0 + gl_last < a.G) ? g0 + gl_last : a.G;
+    const uint32_t s_begin = a.slot_off[ga], s_end = a.slot_off[gb];
+    int gl = gl_first;
+    uint32_t next_end = a.slot_off[ga + 1];
+    T acc = 0;
+    for (uint32_t sl = s_begin; sl < s_end; sl += 4) {
+      T v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = (live && sl + u < s_end) ? col[(uint64_t)(sl + u) * slot_stride] : 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (sl + u >= s_end) break;
+        while (sl + u >= next_end) {  // uniform: slot boundaries are the same for every lane
+          tile[gl][lane] = acc;
+          acc = 0;
+          ++gl;
+          next_end = a.slot_off[g0 + gl + 1];
+        }
+        acc = add_mod(acc, v[u], (T)a.m.p);
+      }
+    }
+    tile[gl][lane] = acc;  // last group of the run
+  }
+  __syncthreads();
+  for (int r = warp; r < kCombineTile; r += 4) {
+    const uint32_t i = i0 + r;
+    const uint64_t g = g0 + lane;
+    if (i < Lc && g < a.G) a.out[((uint64_t)c + (uint64_t)i * a.C) * a.G + g] = tile[lane][r];
+  }
+}
+
+template <class A>
+__global__ __launch_bounds__(kCombineBlock) void combine_kernel(CombineArgs<A> a) {
+  __shared__ typename A::T tile[kCombineTile][kCombineTile + 1];
+  combine_tile<A>(a, (uint64_t)blockIdx.x * kCombineTile, blockIdx.y, blockIdx.z * kCombineTile, tile);
 }
 
 }  // namespace peval

@@ -14,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "errors.hpp"
 #include "kernels.hpp"
 #include "peval_internal.hpp"
 
@@ -22,31 +23,23 @@ using namespace peval;
 // ---------------------------------------------------------------------------
 // errors
 // ---------------------------------------------------------------------------
-static thread_local std::string g_last_error;
+namespace peval {
+std::string &last_error_slot() {
+  static thread_local std::string msg;
+  return msg;
+}
 
-static int fail(int code, const char *fmt, ...) {
+int fail(int code, const char *fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
-  g_last_error = buf;
+  last_error_slot() = buf;
   return code;
 }
+}  // namespace peval
 
-#define HIP_TRY(expr)                                                                   \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return fail(e_ == hipErrorOutOfMemory ? PEVAL_ENOMEM : PEVAL_EDEVICE, "%s: %s (%s:%d)", \
-                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                    \
-  } while (0)
-
-#define PEVAL_TRY(expr)        \
-  do {                         \
-    int rc_ = (expr);          \
-    if (rc_ != PEVAL_OK) return rc_; \
-  } while (0)
 
 extern "C" const char *peval_strerror(int code) {
   switch (code) {
@@ -61,7 +54,7 @@ extern "C" const char *peval_strerror(int code) {
   }
 }
 
-extern "C" const char *peval_last_error(void) { return g_last_error.c_str(); }
+extern "C" const char *peval_last_error(void) { return last_error_slot().c_str(); }
 
 // ---------------------------------------------------------------------------
 // per-modulus constants (host, 128-bit arithmetic)
@@ -229,7 +222,8 @@ extern "C" int peval_layout(const uint64_t *group_sizes, uint64_t G, uint32_t K,
 // ---------------------------------------------------------------------------
 // device helpers
 // ---------------------------------------------------------------------------
-static int ensure(Scratch &sc, size_t bytes, peval_poly *h) {
+namespace peval {
+int ensure(Scratch &sc, size_t bytes, peval_poly *h) {
   if (sc.bytes >= bytes && sc.ptr) return PEVAL_OK;
   if (sc.ptr) {
     if (h->have_done) HIP_TRY(hipEventSynchronize(h->done));
@@ -242,6 +236,7 @@ static int ensure(Scratch &sc, size_t bytes, peval_poly *h) {
   sc.bytes = want;
   return PEVAL_OK;
 }
+}  // namespace peval
 
 static void release(Scratch &sc) {
   if (sc.ptr) (void)hipFree(sc.ptr);
@@ -265,7 +260,8 @@ static void free_plan(Plan &pl) {
   pl = Plan();
 }
 
-static int get_plan(peval_poly *h, uint32_t K, uint32_t P, Plan **out) {
+namespace peval {
+int get_plan(peval_poly *h, uint32_t K, uint32_t P, Plan **out) {
   uint32_t key = K << 8 | P;
   auto it = h->plans.find(key);
   if (it != h->plans.end()) {
@@ -293,6 +289,7 @@ static int get_plan(peval_poly *h, uint32_t K, uint32_t P, Plan **out) {
   *out = &res.first->second;
   return PEVAL_OK;
 }
+}  // namespace peval
 
 // ---------------------------------------------------------------------------
 // create / destroy / info
@@ -444,8 +441,55 @@ extern "C" int peval_groups(const peval_poly *h, uint32_t *d, uint32_t *e) {
 // ---------------------------------------------------------------------------
 // tuning
 // ---------------------------------------------------------------------------
-static bool valid_K(uint32_t K) { return K == 1 || K == 2 || K == 4 || K == 8 || K == 16; }
-static bool valid_P(uint32_t P) { return P == 8 || P == 16 || P == 32; }
+namespace peval {
+
+bool valid_K(uint32_t K) { return K == 1 || K == 2 || K == 4 || K == 8 || K == 16; }
+bool valid_P(uint32_t P) { return P == 8 || P == 16 || P == 32; }
+
+uint64_t padded_threads(const peval_poly *h, uint32_t K) {
+  uint64_t nt = 0;
+  for (uint64_t g = 0; g < h->G; ++g) nt += (h->grp_off[g + 1] - h->grp_off[g] + K - 1) / K;
+  return nt;
+}
+
+uint32_t chains_for_waves(uint64_t nw, uint64_t target_waves, uint32_t T) {
+  uint64_t c = (target_waves + nw - 1) / std::max<uint64_t>(nw, 1);
+  c = std::min<uint64_t>(std::max<uint64_t>(c, 1), 256);
+  if (T) c = std::min<uint64_t>(c, T);
+  return (uint32_t)std::max<uint64_t>(c, 1);
+}
+
+// Heuristic used before any autotuning: the largest K whose zero padding
+// stays under 1/8 of the terms, P = 16, and enough chains for about 8192
+// waves.
+Tuning heuristic_tuning(const peval_poly *h, uint32_t T) {
+  Tuning t{1, 16, 1};
+  for (uint32_t cand : {16u, 8u, 4u, 2u}) {
+    if (padded_threads(h, cand) * cand * 8 <= h->s * 9) {
+      t.K = cand;
+      break;
+    }
+  }
+  uint64_t nw = (padded_threads(h, t.K) + 63) / 64;
+  t.C = chains_for_waves(nw, 8192, T);
+  return t;
+}
+
+// Tuning for a run of T evaluations: explicit settings first, then the
+// autotuner's cache for this shape, then the heuristic.
+Tuning choose_tuning(const peval_poly *h, uint32_t T) {
+  Tuning t = heuristic_tuning(h, T);
+  Tuning cached;
+  if (tune_cache_lookup(h, T, &cached)) t = cached;
+  if (h->tune_K) t.K = h->tune_K;
+  if (h->tune_P) t.P = h->tune_P;
+  if (h->tune_C) t.C = h->tune_C;
+  if (T) t.C = std::min<uint32_t>(t.C, T);
+  t.C = std::max<uint32_t>(t.C, 1);
+  return t;
+}
+
+}  // namespace peval
 
 extern "C" int peval_set_tuning(peval_poly *h, uint32_t K, uint32_t P, uint32_t C) {
   if (!h) return fail(PEVAL_EINVAL, "null handle");
@@ -459,41 +503,13 @@ extern "C" int peval_set_tuning(peval_poly *h, uint32_t K, uint32_t P, uint32_t 
   return PEVAL_OK;
 }
 
-// Automatic choice: the largest K whose zero padding stays under 1/8 of the
-// terms, P = 16, and enough chains for about 8 waves per SIMD.
-static void choose_tuning(const peval_poly *h, uint32_t T, uint32_t *K, uint32_t *P, uint32_t *C) {
-  uint32_t k = h->tune_K;
-  if (!k) {
-    k = 1;
-    for (uint32_t cand : {16u, 8u, 4u, 2u}) {
-      uint64_t padded = 0;
-      for (uint64_t g = 0; g < h->G; ++g) padded += (h->grp_off[g + 1] - h->grp_off[g] + cand - 1) / cand * cand;
-      if (padded * 8 <= h->s * 9) {
-        k = cand;
-        break;
-      }
-    }
-    if (k == 16) k = 8;  // 16 raises register pressure for little gain
-  }
-  uint32_t pp = h->tune_P ? h->tune_P : 16;
-  uint32_t c = h->tune_C;
-  if (!c) {
-    uint64_t nt = 0;
-    for (uint64_t g = 0; g < h->G; ++g) nt += (h->grp_off[g + 1] - h->grp_off[g] + k - 1) / k;
-    uint64_t nw = std::max<uint64_t>(1, (nt + 63) / 64);
-    uint64_t want = (8192 + nw - 1) / nw;
-    c = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(want, 1), 64);
-  }
-  if (T) c = std::min<uint32_t>(c, T);
-  *K = k;
-  *P = pp;
-  *C = std::max<uint32_t>(c, 1);
-}
-
 extern "C" int peval_get_tuning(peval_poly *h, uint32_t T, uint32_t *K, uint32_t *P, uint32_t *C) {
   if (!h || !K || !P || !C) return fail(PEVAL_EINVAL, "null argument");
   std::lock_guard<std::mutex> lk(h->mu);
-  choose_tuning(h, T, K, P, C);
+  Tuning t = choose_tuning(h, T);
+  *K = t.K;
+  *P = t.P;
+  *C = t.C;
   return PEVAL_OK;
 }
 
@@ -529,12 +545,11 @@ static constexpr size_t kPartialBudget = (size_t)2 << 30;  // bytes of partial s
 
 template <class A>
 static int run_impl(peval_poly *h, const BetaArg &beta, uint64_t t0, uint32_t T, void *dev_out,
-                    hipStream_t st) {
+                    hipStream_t st, const Tuning &tu) {
   using T_ = typename A::T;
   const auto &m = mod_of<A>(h);
   const uint32_t ntail = h->n - 2;
-  uint32_t K, P, C;
-  choose_tuning(h, T, &K, &P, &C);
+  const uint32_t K = tu.K, P = tu.P, C = tu.C;
   Plan *pl = nullptr;
   PEVAL_TRY(get_plan(h, K, P, &pl));
   const size_t w = sizeof(T_);
@@ -552,12 +567,13 @@ static int run_impl(peval_poly *h, const BetaArg &beta, uint64_t t0, uint32_t T,
 
   // T is processed in chunks so that the partial sums stay within budget
   uint64_t tc = std::max<uint64_t>(1, kPartialBudget / std::max<uint64_t>(1, pl->nslots * w));
+  tc = std::min<uint64_t>(tc, (uint64_t)C * kCombineTile * 32768);  // keeps grid.z of the combine in range
   tc = std::min<uint64_t>(tc, T);
   if (tc < T && tc > C) tc = tc / C * C;
   PEVAL_TRY(ensure(h->lam, (size_t)C * K * pl->NT * w, h));
   PEVAL_TRY(ensure(h->gam, (size_t)K * pl->NT * w, h));
   PEVAL_TRY(ensure(h->gamq, (size_t)K * pl->NT * w, h));
-  PEVAL_TRY(ensure(h->partial, (size_t)tc * pl->nslots * w, h));
+  PEVAL_TRY(ensure(h->partial, (size_t)((tc + C - 1) / C) * C * pl->nslots * w, h));
   auto eval = Dispatch<A>::eval(K, P);
   if (!eval) return fail(PEVAL_EINVAL, "no kernel for K=%u P=%u", K, P);
 
@@ -601,6 +617,7 @@ static int run_impl(peval_poly *h, const BetaArg &beta, uint64_t t0, uint32_t T,
       ea.nslots = pl->nslots;
       ea.C = Cc;
       ea.T = Tc;
+      ea.Lmax = (Tc + Cc - 1) / Cc;
       ea.m = m;
       dim3 grid((unsigned)((pl->NW + 3) / 4), Cc);
       ProfScope ps(st, 2);
@@ -608,18 +625,28 @@ static int run_impl(peval_poly *h, const BetaArg &beta, uint64_t t0, uint32_t T,
       HIP_TRY(hipGetLastError());
     }
     {  // A7: combine
-      uint64_t total = (uint64_t)Tc * h->G;
-      T_ *outp = (T_ *)dev_out + done * h->G;
+      CombineArgs<A> ca;
+      ca.partial = (const T_ *)h->partial.ptr;
+      ca.slot_off = pl->d_slot_off;
+      ca.out = (T_ *)dev_out + done * h->G;
+      ca.G = h->G;
+      ca.C = Cc;
+      ca.T = Tc;
+      ca.Lmax = (Tc + Cc - 1) / Cc;
+      ca.m = m;
+      dim3 grid((unsigned)((h->G + kCombineTile - 1) / kCombineTile), Cc,
+                (unsigned)((ca.Lmax + kCombineTile - 1) / kCombineTile));
       ProfScope ps(st, 3);
-      combine_kernel<A><<<(unsigned)((total + 255) / 256), 256, 0, st>>>(
-          (const T_ *)h->partial.ptr, pl->d_slot_off, outp, h->G, pl->nslots, total, m);
+      combine_kernel<A><<<grid, kCombineBlock, 0, st>>>(ca);
       HIP_TRY(hipGetLastError());
     }
   }
   return PEVAL_OK;
 }
 
-static int check_run_args(peval_poly *h, const uint64_t *beta, uint64_t t0, uint32_t T, BetaArg *ba) {
+namespace peval {
+
+int check_run_args(peval_poly *h, const uint64_t *beta, uint64_t t0, uint32_t T, BetaArg *ba) {
   if (!h) return fail(PEVAL_EINVAL, "null handle");
   if (h->n > 2 && !beta) return fail(PEVAL_EINVAL, "null beta");
   if (t0 < 1) return fail(PEVAL_EINVAL, "t0 must be >= 1");
@@ -629,16 +656,19 @@ static int check_run_args(peval_poly *h, const uint64_t *beta, uint64_t t0, uint
   return PEVAL_OK;
 }
 
-static int run_locked(peval_poly *h, const BetaArg &ba, uint64_t t0, uint32_t T, void *dev_out,
-                      hipStream_t st) {
+// Enqueue one run on stream st (handle lock held by the caller).
+int run_locked(peval_poly *h, const BetaArg &ba, uint64_t t0, uint32_t T, void *dev_out, hipStream_t st,
+               const Tuning &tu) {
   HIP_TRY(hipSetDevice(h->device));
   if (h->have_done) HIP_TRY(hipStreamWaitEvent(st, h->done, 0));
-  int rc = (h->w == 4) ? run_impl<W32>(h, ba, t0, T, dev_out, st) : run_impl<W64>(h, ba, t0, T, dev_out, st);
+  int rc = (h->w == 4) ? run_impl<W32>(h, ba, t0, T, dev_out, st, tu) : run_impl<W64>(h, ba, t0, T, dev_out, st, tu);
   if (rc != PEVAL_OK) return rc;
   HIP_TRY(hipEventRecord(h->done, st));
   h->have_done = true;
   return PEVAL_OK;
 }
+
+}  // namespace peval
 
 extern "C" int peval_run_async(peval_poly *h, const uint64_t *beta, uint64_t t0, uint32_t T,
                                void *dev_out, void *stream) {
@@ -647,7 +677,7 @@ extern "C" int peval_run_async(peval_poly *h, const uint64_t *beta, uint64_t t0,
   if (T == 0 || h->G == 0) return PEVAL_OK;
   if (!dev_out) return fail(PEVAL_EINVAL, "null output");
   std::lock_guard<std::mutex> lk(h->mu);
-  return run_locked(h, ba, t0, T, dev_out, (hipStream_t)stream);
+  return run_locked(h, ba, t0, T, dev_out, (hipStream_t)stream, choose_tuning(h, T));
 }
 
 extern "C" int peval_run(peval_poly *h, const uint64_t *beta, uint32_t T, void *out) {
@@ -658,7 +688,7 @@ extern "C" int peval_run(peval_poly *h, const uint64_t *beta, uint32_t T, void *
   std::lock_guard<std::mutex> lk(h->mu);
   const size_t bytes = (size_t)T * h->G * h->w;
   PEVAL_TRY(ensure(h->outbuf, bytes, h));
-  PEVAL_TRY(run_locked(h, ba, 1, T, h->outbuf.ptr, h->stream));
+  PEVAL_TRY(run_locked(h, ba, 1, T, h->outbuf.ptr, h->stream, choose_tuning(h, T)));
   HIP_TRY(hipMemcpyAsync(out, h->outbuf.ptr, bytes, hipMemcpyDeviceToHost, h->stream));
   HIP_TRY(hipStreamSynchronize(h->stream));
   return PEVAL_OK;

@@ -46,6 +46,10 @@ struct HostPlan {
 };
 HostPlan build_host_plan(const std::vector<uint64_t> &grp_off, uint32_t K, uint32_t P);
 
+struct Tuning {
+  uint32_t K, P, C;
+};
+
 }  // namespace peval
 
 struct peval_poly {
@@ -78,3 +82,21 @@ struct peval_poly {
   bool have_done = false;
   std::mutex mu;
 };
+
+namespace peval {
+
+bool valid_K(uint32_t K);
+bool valid_P(uint32_t P);
+uint64_t padded_threads(const peval_poly *h, uint32_t K);
+uint32_t chains_for_waves(uint64_t nw, uint64_t target_waves, uint32_t T);
+Tuning heuristic_tuning(const peval_poly *h, uint32_t T);
+Tuning choose_tuning(const peval_poly *h, uint32_t T);
+bool tune_cache_lookup(const peval_poly *h, uint32_t T, Tuning *out);
+
+int ensure(Scratch &sc, size_t bytes, peval_poly *h);
+int get_plan(peval_poly *h, uint32_t K, uint32_t P, Plan **out);
+int check_run_args(peval_poly *h, const uint64_t *beta, uint64_t t0, uint32_t T, BetaArg *ba);
+int run_locked(peval_poly *h, const BetaArg &ba, uint64_t t0, uint32_t T, void *dev_out, hipStream_t st,
+               const Tuning &tu);
+
+}  // namespace peval

@@ -31,6 +31,13 @@ class _Info(ctypes.Structure):
                 ("max_exp", ctypes.c_uint32 * 32)]
 
 
+class _ServerStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "rejected", "queued", "active",
+                                                "passes", "term_evals", "uploads", "evictions", "hbm_in_use",
+                                                "hbm_peak")] + \
+               [(n, ctypes.c_double) for n in ("wall_s", "p50_ms", "p99_ms", "max_ms", "mean_ms")]
+
+
 _lib = None
 
 
@@ -60,6 +67,25 @@ def lib() -> ctypes.CDLL:
         "peval_prof_enable": ([i32], i32),
         "peval_prof_read": ([vp, vp], i32),
         "peval_layout": ([vp, u64, u32, u32, vp, vp, vp, vp, vp, vp], i32),
+        "peval_autotune": ([vp, vp, u32, u32, vp, vp, vp, vp], i32),
+        "peval_server_create": ([u64, u32, ctypes.POINTER(vp)], i32),
+        "peval_server_configure": ([vp, ctypes.c_double, ctypes.c_double, ctypes.c_double], i32),
+        "peval_server_add_poly": ([vp, u64, u32, u64, vp, vp, ctypes.POINTER(u64)], i32),
+        "peval_server_remove_poly": ([vp, u64], i32),
+        "peval_server_submit": ([vp, u64, vp, u32, vp, ctypes.POINTER(u64)], i32),
+        "peval_server_poll": ([vp, u64, ctypes.POINTER(ctypes.c_int)], i32),
+        "peval_server_wait": ([vp, u64, ctypes.c_int64], i32),
+        "peval_server_release": ([vp, u64], i32),
+        "peval_server_stats": ([vp, ctypes.POINTER(_ServerStats)], i32),
+        "peval_server_reset_stats": ([vp], i32),
+        "peval_server_destroy": ([vp], i32),
+        "peval_batch_create": ([u32, vp, vp, u32, ctypes.POINTER(vp)], i32),
+        "peval_batch_run": ([vp, vp, vp, vp, vp], i32),
+        "peval_batch_info": ([vp, vp], i32),
+        "peval_batch_destroy": ([vp], i32),
+        "peval_tune_clear": ([], i32),
+        "peval_tune_save": ([ctypes.c_char_p], i32),
+        "peval_tune_load": ([ctypes.c_char_p], i32),
         "peval_strerror": ([i32], ctypes.c_char_p),
         "peval_last_error": ([], ctypes.c_char_p),
     }
@@ -162,6 +188,15 @@ class Poly:
         _check(lib().peval_get_tuning(self.handle, T, ctypes.byref(k), ctypes.byref(p), ctypes.byref(c)))
         return k.value, p.value, c.value
 
+    def autotune(self, beta, T: int, exhaustive: bool = False):
+        """Time candidate (K, P, C) for this polynomial and T; returns (K, P, C, ms)."""
+        b = self._beta(beta)
+        k, pp, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        ms = ctypes.c_float()
+        _check(lib().peval_autotune(self.handle, b.ctypes.data if b.size else None, T, int(exhaustive),
+                                    ctypes.byref(k), ctypes.byref(pp), ctypes.byref(c), ctypes.byref(ms)))
+        return k.value, pp.value, c.value, ms.value
+
     def destroy(self):
         if self._h is not None:
             _check(lib().peval_destroy(self._h))
@@ -178,6 +213,151 @@ class Poly:
             self.destroy()
         except Exception:
             pass
+
+
+BATCH_NO_GRAPH = 1
+
+
+class Batch:
+    """A planned batched pass over resident polynomials (peval_batch_*)."""
+
+    def __init__(self, polys, Ts, graph: bool = True):
+        self.polys = list(polys)
+        self.Ts = [int(t) for t in Ts]
+        if len(self.polys) != len(self.Ts) or not self.polys:
+            raise ValueError("polys and Ts must be non-empty and of equal length")
+        hs = (ctypes.c_void_p * len(self.polys))(*[q.handle.value for q in self.polys])
+        ts = np.ascontiguousarray(self.Ts, dtype=np.uint32)
+        b = ctypes.c_void_p()
+        _check(lib().peval_batch_create(len(self.polys), hs, ts.ctypes.data, 0 if graph else BATCH_NO_GRAPH,
+                                        ctypes.byref(b)))
+        self._b = b
+
+    def info(self) -> dict:
+        v = np.zeros(5, np.uint64)
+        _check(lib().peval_batch_info(self._b, v.ctypes.data))
+        return {"members": int(v[0]), "items": int(v[1]), "blocks": int(v[2]),
+                "scratch_bytes": int(v[3]), "term_evals": int(v[4])}
+
+    def run(self, betas, dev_outs, t0s=None, stream=None):
+        n = len(self.polys)
+        bs = [np.ascontiguousarray(b, dtype=np.uint64) for b in betas]
+        self._keep = bs
+        bp = (ctypes.c_void_p * n)(*[b.ctypes.data if b.size else None for b in bs])
+        op = (ctypes.c_void_p * n)(*[_ptr(o) for o in dev_outs])
+        t0 = None
+        if t0s is not None:
+            t0 = np.ascontiguousarray(t0s, dtype=np.uint64)
+        _check(lib().peval_batch_run(self._b, bp, t0.ctypes.data if t0 is not None else None, op, _stream(stream)))
+
+    def destroy(self):
+        if getattr(self, "_b", None) is not None:
+            _check(lib().peval_batch_destroy(self._b))
+            self._b = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+SERVER_SIMULATE = 1
+
+
+class Server:
+    """Request loop over resident polynomials (peval_server_*)."""
+
+    def __init__(self, hbm_budget_bytes: int, simulate: bool = False):
+        s = ctypes.c_void_p()
+        _check(lib().peval_server_create(int(hbm_budget_bytes), SERVER_SIMULATE if simulate else 0, ctypes.byref(s)))
+        self._s = s
+        self._outs = {}
+        self._meta = {}
+
+    def configure(self, slice_work: float = 2e9, pass_work: float = 1.5e10, sim_rate: float = 1e12):
+        _check(lib().peval_server_configure(self._s, float(slice_work), float(pass_work), float(sim_rate)))
+
+    def add_poly(self, p: int, exps, coeffs) -> int:
+        exps = np.ascontiguousarray(exps, dtype=np.uint32)
+        coeffs = np.ascontiguousarray(coeffs, dtype=np.uint64)
+        s, n = exps.shape
+        pid = ctypes.c_uint64()
+        _check(lib().peval_server_add_poly(self._s, p, n, s, exps.ctypes.data if s else None,
+                                           coeffs.ctypes.data if s else None, ctypes.byref(pid)))
+        G = len({(int(a), int(b)) for a, b in exps[:, :2].tolist()}) if s else 0
+        self._meta[pid.value] = (p, n, G)
+        return pid.value
+
+    def remove_poly(self, pid: int):
+        _check(lib().peval_server_remove_poly(self._s, pid))
+
+    def submit(self, pid: int, beta, T: int, out: Optional[np.ndarray] = None) -> int:
+        p, n, G = self._meta[pid]
+        if out is None:
+            out = np.zeros((T, G), out_dtype(p))
+        b = np.ascontiguousarray(beta, dtype=np.uint64)
+        rid = ctypes.c_uint64()
+        _check(lib().peval_server_submit(self._s, pid, b.ctypes.data if b.size else None, T,
+                                         out.ctypes.data if out.size else None, ctypes.byref(rid)))
+        self._outs[rid.value] = out
+        return rid.value
+
+    def poll(self, rid: int) -> bool:
+        d = ctypes.c_int()
+        _check(lib().peval_server_poll(self._s, rid, ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, rid: int, timeout_ms: int = -1) -> np.ndarray:
+        _check(lib().peval_server_wait(self._s, rid, timeout_ms))
+        return self._outs[rid]
+
+    def release(self, rid: int):
+        _check(lib().peval_server_release(self._s, rid))
+        self._outs.pop(rid, None)
+
+    def stats(self) -> dict:
+        st = _ServerStats()
+        _check(lib().peval_server_stats(self._s, ctypes.byref(st)))
+        return {f: getattr(st, f) for f, _ in st._fields_}
+
+    def reset_stats(self):
+        _check(lib().peval_server_reset_stats(self._s))
+
+    def destroy(self):
+        if getattr(self, "_s", None) is not None:
+            _check(lib().peval_server_destroy(self._s))
+            self._s = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.destroy()
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def tune_clear():
+    _check(lib().peval_tune_clear())
+
+
+def tune_save(path: str):
+    _check(lib().peval_tune_save(path.encode()))
+
+
+def tune_load(path: str):
+    _check(lib().peval_tune_load(path.encode()))
 
 
 def prof_enable(on: bool = True):

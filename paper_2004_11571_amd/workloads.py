@@ -124,11 +124,15 @@ def draw_exponents(rng: np.random.Generator, s: int, n: int, d12: int, dr: int,
 
     exps = draw(s)
     for _ in range(200):
-        _, first = np.unique(_pack_keys(exps), return_index=True)
-        if first.size == s:
+        keys = _pack_keys(exps)
+        order = np.argsort(keys)           # any order among equal keys will do
+        ks = keys[order]
+        dup = np.zeros(s, dtype=bool)
+        dup[order[1:][ks[1:] == ks[:-1]]] = True
+        ndup = int(dup.sum())
+        if ndup == 0:
             break
-        keep = np.sort(first)
-        exps = np.concatenate([exps[keep], draw(s - keep.size)], axis=0)
+        exps = np.concatenate([exps[~dup], draw(ndup)], axis=0)
     else:  # pragma: no cover - only for pathologically dense spaces
         raise RuntimeError("could not draw distinct exponent rows")
     # present terms in random order: the library sorts them itself

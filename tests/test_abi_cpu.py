@@ -132,3 +132,28 @@ def test_layout_edges():
         PV.layout(np.asarray([3, 0, 2]), 4, 16)
     with pytest.raises(PV.PevalError):
         PV.layout(np.asarray([3]), 3, 16)
+
+
+def test_tune_file_validation(tmp_path):
+    bad = tmp_path / "bad.txt"
+    bad.write_text("8 10 4 20 3 16 5 0.1\n")  # K = 3 is not a kernel
+    with pytest.raises(PV.PevalError):
+        PV.tune_load(str(bad))
+    good = tmp_path / "good.txt"
+    good.write_text("# comment\n8 10 4 20 8 16 5 0.1\n4 6 2 12 1 8 64 0.02\n")
+    PV.tune_load(str(good))
+    out = tmp_path / "out.txt"
+    PV.tune_save(str(out))
+    lines = [l for l in out.read_text().splitlines() if not l.startswith("#")]
+    assert len(lines) == 2
+    PV.tune_clear()
+    PV.tune_save(str(out))
+    assert [l for l in out.read_text().splitlines() if not l.startswith("#")] == []
+
+
+def test_batch_rejects_bad_arguments():
+    L = PV.lib()
+    b = ctypes.c_void_p()
+    assert L.peval_batch_create(0, None, None, 0, ctypes.byref(b)) == PV.EINVAL
+    assert L.peval_batch_run(None, None, None, None, None) == PV.EINVAL
+    assert L.peval_batch_destroy(None) == PV.OK

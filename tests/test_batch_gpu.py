@@ -1,0 +1,97 @@
+"""Batched persistent launch: every member equals its own plain run (and the
+oracle), for graph replays and direct launches, across replays."""
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_2004_11571_amd import peval as PV
+from paper_2004_11571_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _outs(polys, Ts):
+    import torch
+    return [torch.empty((T, q.G), dtype=torch.int32 if q.elem_bytes == 4 else torch.int64, device="cuda")
+            for q, T in zip(polys, Ts)]
+
+
+def _host(q, buf):
+    return buf.cpu().numpy().view(q.dtype)
+
+
+def _mixed(count, s_max, seed):
+    return W.batch_config(count=count, instance=seed, s_max=s_max, t_log2=(0, 9))
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_equals_plain_runs(graph):
+    import torch
+    ws = _mixed(24, 2e4, 1)
+    polys = [PV.Poly(w.p, w.exps, w.coeffs) for w in ws]
+    Ts = [w.T for w in ws]
+    _say("batch members", [(q.s, q.G, T, q.elem_bytes) for q, T in zip(polys, Ts)])
+    try:
+        with PV.Batch(polys, Ts, graph=graph) as b:
+            _say("info", b.info())
+            outs = _outs(polys, Ts)
+            for rep in range(3):
+                betas = [np.asarray((w.beta.astype(object) * (rep + 1)) % w.p, np.uint64) for w in ws]
+                b.run(betas, outs, stream=torch.cuda.current_stream())
+                torch.cuda.synchronize()
+                for q, w, beta, o in zip(polys, ws, betas, outs):
+                    want = q.run(beta, w.T)  # eager work between replays
+                    assert np.array_equal(_host(q, o), want), (rep, w.name)
+    finally:
+        for q in polys:
+            q.destroy()
+
+
+def test_batch_against_oracle_and_offsets():
+    import torch
+    orc = Oracle()
+    ws = _mixed(10, 3e3, 2)
+    polys = [PV.Poly(w.p, w.exps, w.coeffs) for w in ws]
+    Ts = [w.T for w in ws]
+    try:
+        with PV.Batch(polys, Ts) as b:
+            outs = _outs(polys, Ts)
+            t0s = [1 + 37 * j for j in range(len(ws))]
+            b.run([w.beta for w in ws], outs, t0s=t0s)
+            torch.cuda.synchronize()
+            for q, w, o, t0 in zip(polys, ws, outs, t0s):
+                want = orc.evaluate(w.p, w.exps, w.coeffs, w.beta, w.T, t0=t0, threads=8)
+                assert np.array_equal(_host(q, o).astype(np.uint64), want), w.name
+    finally:
+        for q in polys:
+            q.destroy()
+
+
+def test_batch_edge_members():
+    """Single-term and single-group members, T = 1, n = 2, 32-bit and 64-bit."""
+    import torch
+    orc = Oracle()
+    rng = np.random.default_rng(5)
+    ws = [W.random_small(rng, W.P31, 2, 1, 1, dmax=3),
+          W.random_small(rng, W.P63, 3, 1, 7, dmax=3),
+          W.random_small(rng, 97, 5, 300, 17, dmax=4),
+          W.random_small(rng, W.P63, 8, 2000, 33, dmax=3)]
+    ws[3].exps[:, :2] = 0  # one group
+    ws[3].exps = np.unique(ws[3].exps, axis=0)
+    ws[3].coeffs = ws[3].coeffs[:ws[3].exps.shape[0]]
+    polys = [PV.Poly(w.p, w.exps, w.coeffs) for w in ws]
+    try:
+        with PV.Batch(polys, [w.T for w in ws]) as b:
+            outs = _outs(polys, [w.T for w in ws])
+            b.run([w.beta for w in ws], outs)
+            torch.cuda.synchronize()
+            for q, w, o in zip(polys, ws, outs):
+                want = orc.evaluate(w.p, w.exps, w.coeffs, w.beta, w.T, threads=4)
+                assert np.array_equal(_host(q, o).astype(np.uint64), want)
+    finally:
+        for q in polys:
+            q.destroy()

@@ -1,0 +1,89 @@
+"""Server policy on the CPU (simulated executor: no device calls)."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_2004_11571_amd import peval as PV
+from paper_2004_11571_amd import workloads as W
+
+
+def _poly(seed, s, n=5, p=W.P63):
+    rng = np.random.default_rng(seed)
+    return W.random_small(rng, p, n, s, 1, dmax=6)
+
+
+def test_simulated_requests_complete_with_stats():
+    with PV.Server(1 << 30, simulate=True) as srv:
+        srv.configure(slice_work=1e6, sim_rate=1e9)
+        pids = [srv.add_poly(q.p, q.exps, q.coeffs) for q in (_poly(1, 2000), _poly(2, 500, p=W.P31))]
+        rids = [srv.submit(pids[j % 2], np.ones(3, np.uint64), 64 + 32 * j) for j in range(10)]
+        for r in rids:
+            srv.wait(r, 10000)
+        st = srv.stats()
+        assert st["completed"] == 10 and st["rejected"] == 0 and st["queued"] == 0
+        assert st["term_evals"] == sum((2000 if j % 2 == 0 else 500) * (64 + 32 * j) for j in range(10))
+        assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
+        assert st["passes"] >= 1
+
+
+def test_request_larger_than_budget_is_refused():
+    with PV.Server(2 << 20, simulate=True) as srv:
+        q = _poly(3, 3000)
+        pid = srv.add_poly(q.p, q.exps, q.coeffs)
+        with pytest.raises(PV.PevalError) as e:
+            srv.submit(pid, np.ones(3, np.uint64), 100000)
+        assert e.value.code == PV.ENOMEM
+        assert srv.stats()["rejected"] == 1
+
+
+def test_small_budget_queues_but_completes_in_order():
+    # each request's output is ~1 MB; a 4 MB budget holds only a few at once
+    with PV.Server(4 << 20, simulate=True) as srv:
+        srv.configure(slice_work=1e5, sim_rate=2e8)
+        q = _poly(4, 1500)
+        pid = srv.add_poly(q.p, q.exps, q.coeffs)
+        G = len({(a, b) for a, b in q.exps[:, :2].tolist()})
+        T = (1 << 20) // (8 * G)
+        rids = [srv.submit(pid, np.ones(3, np.uint64), T) for _ in range(12)]
+        peak_q = 0
+        for _ in range(200):
+            st = srv.stats()
+            peak_q = max(peak_q, st["queued"])
+            if st["completed"] == 12:
+                break
+            time.sleep(0.01)
+        for r in rids:
+            srv.wait(r, 20000)
+        st = srv.stats()
+        assert st["completed"] == 12 and peak_q > 0
+        assert st["hbm_peak"] <= 4 << 20
+
+
+def test_lru_eviction_and_remove():
+    with PV.Server(6 << 20, simulate=True) as srv:
+        srv.configure(slice_work=1e6, sim_rate=1e9)
+        qs = [_poly(10 + j, 40000, n=6) for j in range(8)]   # ~0.85 MB resident each
+        pids = [srv.add_poly(q.p, q.exps, q.coeffs) for q in qs]
+        for pid in pids * 2:
+            srv.wait(srv.submit(pid, np.ones(4, np.uint64), 8), 20000)
+        st = srv.stats()
+        assert st["completed"] == 16 and st["hbm_peak"] <= 6 << 20
+        assert st["evictions"] >= 1 and st["uploads"] > 8   # re-uploaded after eviction
+        srv.remove_poly(pids[0])
+        with pytest.raises(PV.PevalError):
+            srv.submit(pids[0], np.ones(4, np.uint64), 8)
+
+
+def test_bad_arguments():
+    with pytest.raises(PV.PevalError):
+        PV.Server(100, simulate=True)
+    with PV.Server(1 << 24, simulate=True) as srv:
+        with pytest.raises(PV.PevalError):
+            srv.add_poly(10, np.zeros((1, 3), np.uint32), np.ones(1, np.uint64))
+        q = _poly(5, 10)
+        pid = srv.add_poly(q.p, q.exps, q.coeffs)
+        with pytest.raises(PV.PevalError):
+            srv.submit(pid, np.ones(3, np.uint64), 0)
+        with pytest.raises(PV.PevalError):
+            srv.wait(12345, 10)

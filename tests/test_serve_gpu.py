@@ -1,0 +1,109 @@
+"""Served requests: each result is identical alone and in the mix (tolerance
+0: canonical residues), under continuous batching, slicing and a tight
+memory budget."""
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_2004_11571_amd import peval as PV
+from paper_2004_11571_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _pool(seed, count, s_max):
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(count):
+        n = int(rng.integers(4, 9))
+        s = int(round(10 ** rng.uniform(3, np.log10(s_max))))
+        p = W.P31 if j % 2 else W.P63
+        out.append(W.make_poly(int(rng.integers(0, 2**62)), p, n, s, 1, 40, W.raise_dr(s, n, 40, 20)))
+    return out
+
+
+def _alone(pool, reqs):
+    """Every request evaluated alone with a plain run on its own handle."""
+    hs = [PV.Poly(w.p, w.exps, w.coeffs) for w in pool]
+    try:
+        return [hs[j].run(beta, T) for j, beta, T in reqs]
+    finally:
+        for h in hs:
+            h.destroy()
+
+
+def _requests(pool, count, seed, t_max=600):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(count):
+        j = int(rng.integers(0, len(pool)))
+        T = int(rng.integers(1, t_max))
+        beta = rng.integers(1, pool[j].p, size=pool[j].n - 2, dtype=np.uint64)
+        reqs.append((j, beta, T))
+    return reqs
+
+
+@pytest.mark.parametrize("slice_work", [2e9, 2e5])
+def test_served_equals_alone(slice_work):
+    pool = _pool(1, 6, 5e4)
+    reqs = _requests(pool, 40, 2)
+    want = _alone(pool, reqs)
+    with PV.Server(8 << 30) as srv:
+        srv.configure(slice_work=slice_work)
+        pids = [srv.add_poly(w.p, w.exps, w.coeffs) for w in pool]
+        rids = []
+        for k, (j, beta, T) in enumerate(reqs):
+            rids.append(srv.submit(pids[j], beta, T))
+            if k == 20:
+                time.sleep(0.002)  # later arrivals join passes already in flight
+        got = [srv.wait(r, 60000) for r in rids]
+        st = srv.stats()
+        print("stats", st, flush=True)
+    for k, (g, w_) in enumerate(zip(got, want)):
+        assert np.array_equal(g, w_), f"request {k}"
+    assert st["completed"] == len(reqs) and st["rejected"] == 0
+
+
+def test_served_tight_budget_and_oracle():
+    pool = _pool(3, 4, 2e4)
+    reqs = _requests(pool, 16, 4, t_max=300)
+    orc = Oracle()
+    with PV.Server(96 << 20) as srv:
+        srv.configure(slice_work=1e6)
+        pids = [srv.add_poly(w.p, w.exps, w.coeffs) for w in pool]
+        rids = [srv.submit(pids[j], beta, T) for j, beta, T in reqs]
+        got = [srv.wait(r, 60000) for r in rids]
+        st = srv.stats()
+        print("stats", st, flush=True)
+        assert st["hbm_peak"] <= 96 << 20
+    for (j, beta, T), g in zip(reqs[:6], got[:6]):
+        w = pool[j]
+        assert np.array_equal(g.astype(np.uint64), orc.evaluate(w.p, w.exps, w.coeffs, beta, T, threads=8))
+    want = _alone(pool, reqs)
+    for g, w_ in zip(got, want):
+        assert np.array_equal(g, w_)
+
+
+def test_concurrent_submitters():
+    pool = _pool(5, 3, 1e4)
+    reqs = _requests(pool, 30, 6, t_max=200)
+    want = _alone(pool, reqs)
+    got = [None] * len(reqs)
+    with PV.Server(4 << 30) as srv:
+        pids = [srv.add_poly(w.p, w.exps, w.coeffs) for w in pool]
+
+        def worker(k0):
+            for k in range(k0, len(reqs), 3):
+                j, beta, T = reqs[k]
+                got[k] = srv.wait(srv.submit(pids[j], beta, T), 60000)
+
+        ths = [threading.Thread(target=worker, args=(k,)) for k in range(3)]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+    for g, w_ in zip(got, want):
+        assert np.array_equal(g, w_)

@@ -1,0 +1,41 @@
+"""Autotuner: picks a valid tuning, the cache steers later runs, results unchanged."""
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_2004_11571_amd import peval as PV
+from paper_2004_11571_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def test_autotune_and_cache(tmp_path):
+    orc = Oracle()
+    PV.tune_clear()
+    w = W.make_poly(W.config_seed(2, 7), W.P63, 6, 20000, 64, 40, 20)
+    with PV.Poly(w.p, w.exps, w.coeffs) as q:
+        heur = q.get_tuning(w.T)
+        K, P, C, ms = q.autotune(w.beta, w.T)
+        print("heuristic", heur, "tuned", (K, P, C), ms, flush=True)
+        assert K in (1, 2, 4, 8, 16) and P in (8, 16, 32) and 1 <= C <= w.T and ms > 0
+        assert q.get_tuning(w.T) == (K, P, C)
+        got = q.run(w.beta, w.T)
+    want = orc.evaluate(w.p, w.exps, w.coeffs, w.beta, w.T, threads=8)
+    assert np.array_equal(got, want)
+    path = str(tmp_path / "tune.txt")
+    PV.tune_save(path)
+    PV.tune_clear()
+    with PV.Poly(w.p, w.exps, w.coeffs) as q:
+        assert q.get_tuning(w.T) == heur
+        PV.tune_load(path)
+        assert q.get_tuning(w.T) == (K, P, C)
+    PV.tune_clear()
+
+
+def test_autotune_exhaustive_small():
+    w = W.config1()
+    with PV.Poly(w.p, w.exps, w.coeffs) as q:
+        K, P, C, ms = q.autotune(w.beta, w.T, exhaustive=True)
+        assert ms > 0
+        assert np.array_equal(q.run(w.beta, w.T), Oracle().evaluate(w.p, w.exps, w.coeffs, w.beta, w.T))
+    PV.tune_clear()
