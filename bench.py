@@ -135,6 +135,17 @@ def batch_main(args):
             q.run_async(w.beta, w.T, o, stream=stream)
     torch.cuda.synchronize()
     el_seq = time.perf_counter() - t1
+    # device -> page-locked host bandwidth, for context (results must cross it)
+    big = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    hb = torch.empty(1 << 30, dtype=torch.uint8, pin_memory=True)
+    hb.copy_(big)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    for _ in range(3):
+        hb.copy_(big)
+    torch.cuda.synchronize()
+    d2h_gbps = 3 * (1 << 30) / (time.perf_counter() - tb) / 1e9
+    del big, hb
     same = all(np.array_equal(o.cpu().numpy().view(q.dtype), x) for o, q, x in zip(outs, polys, batched))
     value = te * steps / el
     ops = sum(ALGO_OPS[q.elem_bytes] * w.s * w.T for q, w in zip(polys, ws))
@@ -178,28 +189,58 @@ def serve_main(args):
     pids = [srv.add_poly(w.p, w.exps, w.coeffs) for w in pool]
     # resident part of the pool: one warm-up request each
     for j in range(len(pool) - n_cold):
-        srv.wait(srv.submit(pids[j], pool[j].beta, 64), 600000)
+        rid = srv.submit(pids[j], pool[j].beta, 64)
+        srv.wait(rid, 600000)
+        srv.release(rid)
+    print(f"serve: pool ready ({len(pool)} polynomials, {len(reqs)} requests)", file=sys.stderr, flush=True)
+    # client-side result buffers: a pool of page-locked buffers reused after
+    # each result has been consumed
+    G = [srv._meta[pid][2] for pid in pids]
+    wb = [4 if w.p < 2**31 else 8 for w in pool]
+    max_bytes = max(r.T * G[r.poly_index] * wb[r.poly_index] for r in reqs)
+    n_buf = 256
+    bufs = [torch.empty(max_bytes, dtype=torch.uint8, pin_memory=True).numpy() for _ in range(n_buf)]
+    free_bufs = list(range(n_buf))
+
+    def out_view(r, b):
+        dt = np.uint32 if wb[r.poly_index] == 4 else np.uint64
+        n = r.T * G[r.poly_index]
+        return bufs[b][: n * wb[r.poly_index]].view(dt).reshape(r.T, G[r.poly_index])
+
     def stream(paced: bool):
         """Submit every request (at its arrival time if paced, else at once);
         a collector thread waits for them in order and releases them."""
         srv.reset_stats()
         lock = threading.Lock()
-        pending = []
+        owner = {}
+        n_sub = [0]
         finished = threading.Event()
 
+        errors = []
+
         def collector():
-            while True:
-                with lock:
-                    item = pending.pop(0) if pending else None
-                if item is None:
-                    if finished.is_set():
-                        with lock:
-                            if not pending:
-                                return
-                    time.sleep(0.0002)
-                    continue
-                srv.wait(item, 600000)
-                srv.release(item)
+            # consume results in completion order (small requests finish first)
+            n_done = 0
+            try:
+                while True:
+                    with lock:
+                        if finished.is_set() and n_done == n_sub[0]:
+                            return
+                    try:
+                        rid = srv.next_done(50)
+                    except PV.PevalError as e:
+                        if e.code == PV.ETIMEOUT:
+                            continue
+                        raise
+                    srv.wait(rid, 0)  # raises if the request failed
+                    srv.release(rid)
+                    with lock:
+                        bi = owner.pop(rid, None)
+                        if bi is not None:
+                            free_bufs.append(bi)
+                            n_done += 1
+            except Exception as e:  # surface it to the submitting thread
+                errors.append(e)
 
         col = threading.Thread(target=collector)
         col.start()
@@ -212,12 +253,27 @@ def serve_main(args):
                     time.sleep(delay)
                 else:
                     lag = max(lag, -delay)
-            rid = srv.submit(pids[r.poly_index], r.beta, r.T)
+            t_wait = time.perf_counter()
+            while True:
+                with lock:
+                    bi = free_bufs.pop() if free_bufs else None
+                if bi is not None:
+                    break
+                if errors:
+                    raise errors[0]
+                if time.perf_counter() - t_wait > 120:
+                    raise RuntimeError("no result buffer came back within 120 s")
+                time.sleep(0.0001)
             with lock:
-                pending.append(rid)
+                rid = srv.submit(pids[r.poly_index], r.beta, r.T, out=out_view(r, bi))
+                owner[rid] = bi
+                n_sub[0] += 1
         submit_s = time.perf_counter() - t0
         finished.set()
         col.join()
+        if errors:
+            raise errors[0]
+        print(f"serve: {'paced' if paced else 'saturated'} stream done", file=sys.stderr, flush=True)
         st = srv.stats()
         st["submit_s"] = submit_s
         st["max_submit_lag_s"] = lag
@@ -228,17 +284,35 @@ def serve_main(args):
     sat = stream(paced=False)
     srv.destroy()
 
-    # the same requests (a prefix) one at a time, each a plain synchronous run
+    # the same requests (a prefix) one at a time: a plain run into device
+    # memory, then the result copied to the same kind of page-locked buffer
     hs = [PV.Poly(w.p, w.exps, w.coeffs) for w in pool]
+    dev = torch.empty(max_bytes, dtype=torch.uint8, device="cuda")
+    pin = torch.from_numpy(bufs[0])
     for j, h in enumerate(hs):
-        h.run(pool[j].beta, 16)
-    k = min(len(reqs), 400)
+        h.run_async(pool[j].beta, 16, dev)
+    torch.cuda.synchronize()
+    k = len(reqs)
     t1 = time.perf_counter()
     te_seq = 0
     for r in reqs[:k]:
-        hs[r.poly_index].run(r.beta, r.T)
+        nb = r.T * G[r.poly_index] * wb[r.poly_index]
+        hs[r.poly_index].run_async(r.beta, r.T, dev)
+        pin[:nb].copy_(dev[:nb])
         te_seq += pool[r.poly_index].s * r.T
+    torch.cuda.synchronize()
     el_seq = time.perf_counter() - t1
+    # device -> page-locked host bandwidth, for context (results must cross it)
+    big = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+    hb = torch.empty(1 << 30, dtype=torch.uint8, pin_memory=True)
+    hb.copy_(big)
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    for _ in range(3):
+        hb.copy_(big)
+    torch.cuda.synchronize()
+    d2h_gbps = 3 * (1 << 30) / (time.perf_counter() - tb) / 1e9
+    del big, hb
     for h in hs:
         h.destroy()
     res = {
@@ -252,8 +326,12 @@ def serve_main(args):
         "latency_ms": {"p50": st["p50_ms"], "p99": st["p99_ms"], "max": st["max_ms"], "mean": st["mean_ms"]},
         "server": st,
         "saturated": {"value": sat["term_evals"] / sat["wall_s"], "p50_ms": sat["p50_ms"], "p99_ms": sat["p99_ms"],
-                      "passes": sat["passes"]},
-        "sequential_plain": {"requests": k, "value": te_seq / el_seq,
+                      "passes": sat["passes"], "slices": sat["slices"], "host_pass_s": sat["host_pass_s"],
+                      "gpu_pass_s": sat["gpu_pass_s"],
+                      "wall_s": sat["wall_s"]},
+        "d2h_pinned_GBps": d2h_gbps,
+        "output_GB": sum(r.T * G[r.poly_index] * wb[r.poly_index] for r in reqs) / 1e9,
+        "sequential_plain": {"requests": k, "value": te_seq / el_seq, "seconds": el_seq,
                              "saturated_served_over_sequential": (sat["term_evals"] / sat["wall_s"]) / (te_seq / el_seq)},
         "generate_s": gen_s,
     }

@@ -198,7 +198,8 @@ int peval_batch_destroy(peval_batch *b);
  * consecutive evaluations and every pass batches one slice of each admitted
  * request into one batched launch; two passes run at a time on two streams,
  * so arrivals join the next pass (continuous batching).  Finished results
- * are copied to host memory by two copy threads.  A request's result
+ * are copied to host memory by four copy threads (directly when host_out is
+ * page-locked, through pinned staging otherwise).  A request's result
  * is identical to a plain peval_run of it.  flags: PEVAL_SERVER_SIMULATE
  * runs the same scheduler without any device call (passes take
  * term-evaluations / sim_rate seconds and produce no output), for testing
@@ -211,7 +212,8 @@ int peval_batch_destroy(peval_batch *b);
  * until the request is done; a request that could not fit in the budget
  * even alone is refused with PEVAL_ENOMEM.  poll sets *done; wait blocks
  * (timeout_ms < 0: forever; PEVAL_ETIMEOUT when it expires); both return the
- * request's error if it failed.  release forgets a finished request.
+ * request's error if it failed.  next_done hands out finished requests in
+ * completion order.  release forgets a finished request.
  * Latency = submit to result in host memory.
  */
 typedef struct peval_server peval_server;
@@ -220,17 +222,22 @@ typedef struct peval_server_stats_t {
     uint64_t submitted, completed, rejected, queued, active, passes;
     uint64_t term_evals;        /* of completed requests */
     uint64_t uploads, evictions;  /* polynomials made resident / evicted */
+    uint64_t slices;            /* request slices launched (members over all passes) */
     uint64_t hbm_in_use, hbm_peak;
     double wall_s;              /* from create (or reset) to the last completion */
     double p50_ms, p99_ms, max_ms, mean_ms;  /* request latency */
+    double host_pass_s;         /* scheduler time spent planning and launching passes */
+    double gpu_pass_s;          /* device time of the passes (start to end, summed) */
 } peval_server_stats_t;
 int peval_server_create(uint64_t hbm_budget_bytes, uint32_t flags, peval_server **out);
 /* slice_work: target term-evaluations per request slice (default 2e9);
  * pass_work: term-evaluations gathered into one pass before launching it
  * (default 1.5e10; the oldest request always gets a slice, the others are
- * taken shortest remaining work first); sim_rate: term-evaluations per
- * second of the simulated executor. */
-int peval_server_configure(peval_server *srv, double slice_work, double pass_work, double sim_rate);
+ * taken shortest remaining work first); max_members: slices per pass
+ * (default 512); sim_rate: term-evaluations per second of the simulated
+ * executor. */
+int peval_server_configure(peval_server *srv, double slice_work, double pass_work, uint32_t max_members,
+                           double sim_rate);
 int peval_server_add_poly(peval_server *srv, uint64_t p, uint32_t n, uint64_t s, const uint32_t *exponents,
                           const uint64_t *coeffs, uint64_t *poly_id);
 int peval_server_remove_poly(peval_server *srv, uint64_t poly_id);
@@ -238,6 +245,9 @@ int peval_server_submit(peval_server *srv, uint64_t poly_id, const uint64_t *bet
                         uint64_t *req_id);
 int peval_server_poll(peval_server *srv, uint64_t req_id, int *done);
 int peval_server_wait(peval_server *srv, uint64_t req_id, int64_t timeout_ms);
+/* Completion queue: the id of the next finished (or failed) request, in
+ * completion order; waits up to timeout_ms (< 0: forever). */
+int peval_server_next_done(peval_server *srv, int64_t timeout_ms, uint64_t *req_id);
 int peval_server_release(peval_server *srv, uint64_t req_id);
 int peval_server_stats(peval_server *srv, peval_server_stats_t *stats);
 int peval_server_reset_stats(peval_server *srv);

@@ -52,7 +52,6 @@ __device__ __forceinline__ void batch_mono_one(const BatchDesc &d, uint64_t t0, 
   a.exps = d.exps;
   a.tval = (const T *)d.tval;
   a.tquot = (const T *)d.tquot;
-  a.to = d.to;
   a.thr_first = d.thr_first;
   a.thr_cnt = d.thr_cnt;
   a.lam = (T *)d.lam;
@@ -65,7 +64,7 @@ __device__ __forceinline__ void batch_mono_one(const BatchDesc &d, uint64_t t0, 
   a.K = d.K;
   a.C = d.C;
   a.m = m;
-  monomial_entry<A>(a, local);
+  monomial_entry<A>(a, d.to.off, local);
 }
 
 __global__ void batch_mono_kernel(const BatchDesc *D, const BatchRun *R, uint32_t count, const uint64_t *prefix) {

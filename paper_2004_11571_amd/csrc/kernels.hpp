@@ -79,8 +79,10 @@ struct MonoArgs {
   typename A::M m;
 };
 
+// off: power-table offsets per tail variable (read through a pointer so that
+// a dynamically indexed copy never lands in scratch memory)
 template <class A>
-__device__ __forceinline__ void monomial_entry(const MonoArgs<A> &a, uint64_t idx) {
+__device__ __forceinline__ void monomial_entry(const MonoArgs<A> &a, const uint32_t *off, uint64_t idx) {
   using T = typename A::T;
   uint32_t k = (uint32_t)(idx / a.NT);
   uint64_t j = idx - (uint64_t)k * a.NT;
@@ -97,7 +99,7 @@ __device__ __forceinline__ void monomial_entry(const MonoArgs<A> &a, uint64_t id
   T mi = (T)(1 % p);
   for (uint32_t v = 0; v < a.ntail; ++v) {
     uint32_t e = a.exps[(uint64_t)v * a.s + i];
-    uint32_t at = a.to.off[v] + e;
+    uint32_t at = off[v] + e;
     mi = (v == 0) ? a.tval[at] : A::mul_lazy(mi, a.tval[at], a.tquot[at], a.m);
   }
   mi = canon(mi, (T)p);
@@ -125,7 +127,7 @@ template <class A>
 __global__ void monomial_kernel(MonoArgs<A> a) {
   uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (uint64_t)a.K * a.NT) return;
-  monomial_entry<A>(a, idx);
+  monomial_entry<A>(a, a.to.off, idx);
 }
 
 // ---------------------------------------------------------------------------

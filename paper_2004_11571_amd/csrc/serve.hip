@@ -44,6 +44,7 @@ struct SPoly {
   std::vector<uint32_t> exps;  // host copy for re-upload after eviction
   std::vector<uint64_t> coeffs;
   peval_poly *h = nullptr;     // resident handle (null when not resident)
+  Plan *plan = nullptr;        // its thread layout for batched passes
   uint64_t bytes = 0;          // device bytes while resident
   uint64_t last_used = 0;
   uint32_t refs = 0;           // admitted requests using it
@@ -84,6 +85,9 @@ struct peval_server {
   double sim_rate = 1.0e12;          // simulated term-evaluations per second
   double slice_work = 2.0e9;         // target term-evaluations per request slice
   double pass_work = 1.5e10;         // term-evaluations per pass (bounds the latency one pass adds)
+  uint32_t max_members = 512;        // slices per pass (bounds the host work of one pass)
+  uint64_t slices = 0;               // stats: slices launched
+  double host_pass_s = 0;            // stats: scheduler time spent building and launching passes
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::thread worker;
@@ -105,14 +109,21 @@ struct peval_server {
   hipStream_t st[kStreams] = {nullptr, nullptr};
   hipStream_t copy_st = nullptr;
   hipEvent_t ev[kStreams] = {nullptr, nullptr};
+  hipEvent_t ev0[kStreams] = {nullptr, nullptr};  // pass start (timing)
+  double gpu_pass_s = 0;                           // stats: sum of pass durations on the device
   char *staging[kStreams] = {nullptr, nullptr};  // pinned blob images
+  void *slot_arena[kStreams] = {nullptr, nullptr};  // per-slot pass scratch (grow-only)
+  size_t slot_arena_bytes[kStreams] = {0, 0};
+  void *slot_blob[kStreams] = {nullptr, nullptr};   // per-slot descriptor blob (grow-only)
+  size_t slot_blob_bytes[kStreams] = {0, 0};
   size_t staging_bytes[kStreams] = {0, 0};
   bool slot_busy[kStreams] = {false, false};
   std::vector<void *> to_free;       // request outputs, freed when no pass is in flight
   std::deque<uint64_t> to_copy;      // finished on the device, result not yet in host memory
+  std::deque<uint64_t> done_q;       // finished requests, in completion order (for next_done)
   std::condition_variable cv_copy;
   std::vector<std::thread> copiers;
-  hipStream_t copy_sts[2] = {nullptr, nullptr};
+  hipStream_t copy_sts[4] = {nullptr, nullptr, nullptr, nullptr};
   int err = PEVAL_OK;                // sticky device error
 };
 
@@ -156,6 +167,7 @@ static void evict_for(peval_server *S, uint64_t need) {
     if (!victim) return;
     if (victim->h) peval_destroy(victim->h);
     victim->h = nullptr;
+    victim->plan = nullptr;
     S->used -= victim->bytes;
     victim->bytes = 0;
     S->evictions++;
@@ -175,7 +187,7 @@ static int make_resident(peval_server *S, SPoly &sp) {
 
 // Device part of residency: create the handle and its batched thread layout.
 // Touches no server state (called without the server lock).
-static int upload_poly(const SPoly &sp, peval_poly **out, uint64_t *bytes) {
+static int upload_poly(const SPoly &sp, peval_poly **out, Plan **plan_out, uint64_t *bytes) {
   peval_poly *h = nullptr;
   *out = nullptr;
   PEVAL_TRY(peval_create(sp.p, sp.n, sp.s, sp.exps.data(), sp.coeffs.data(), &h));
@@ -192,6 +204,7 @@ static int upload_poly(const SPoly &sp, peval_poly **out, uint64_t *bytes) {
   peval_info_t inf;
   peval_info(h, &inf);
   *out = h;
+  *plan_out = pl;
   *bytes = inf.device_bytes;
   return PEVAL_OK;
 }
@@ -201,6 +214,7 @@ static int upload_poly(const SPoly &sp, peval_poly **out, uint64_t *bytes) {
 // ---------------------------------------------------------------------------
 static void finish_request(peval_server *S, SReq &r, double t) {
   r.status = 0;
+  S->done_q.push_back(r.id);
   r.t_done = t;
   S->completed++;
   S->te_done += S->polys[r.poly].s * (uint64_t)r.T;
@@ -227,6 +241,8 @@ static void retire(peval_server *S) {
         S->err = fail(PEVAL_EDEVICE, "pass failed: %s", hipGetErrorString(q));
         return;
       }
+      float ms = 0;
+      if (hipEventElapsedTime(&ms, S->ev0[ps.slot], S->ev[ps.slot]) == hipSuccess) S->gpu_pass_s += ms * 1e-3;
     }
     S->slot_busy[ps.slot] = false;
     for (uint64_t rid : ps.reqs) {
@@ -255,6 +271,9 @@ static void admit(peval_server *S, std::unique_lock<std::mutex> &lk) {
     SReq &r = S->reqs[S->pending.front()];
     SPoly &sp = S->polys[r.poly];
     const bool resident = sp.h || (S->simulate && sp.bytes);
+    if (sp.plan) {  // resident: the reservation follows the actual thread layout
+      r.reserve = 2 * (member_scratch_bytes(sp.h, *sp.plan, r.cmax, r.ts) + (uint64_t)r.cmax * sp.plan->nslots * sp.w);
+    }
     uint64_t need = r.out_bytes + r.reserve + (resident ? 0 : estimate_poly_bytes(sp));
     if (S->used + need > S->budget) evict_for(S, need);
     if (S->used + need > S->budget) return;  // head of line waits for memory
@@ -268,8 +287,9 @@ static void admit(peval_server *S, std::unique_lock<std::mutex> &lk) {
       if (upload) S->used += estimate_poly_bytes(sp);  // held while uploading
       lk.unlock();
       peval_poly *h = sp.h;
+      Plan *plan = sp.plan;
       uint64_t bytes = 0;
-      if (upload) rc = upload_poly(sp, &h, &bytes);
+      if (upload) rc = upload_poly(sp, &h, &plan, &bytes);
       if (rc == PEVAL_OK && hipMalloc(&r.d_out, std::max<uint64_t>(r.out_bytes, 256)) != hipSuccess)
         rc = fail(PEVAL_ENOMEM, "output");
       lk.lock();
@@ -277,15 +297,21 @@ static void admit(peval_server *S, std::unique_lock<std::mutex> &lk) {
         S->used -= estimate_poly_bytes(sp);
         if (rc == PEVAL_OK || h) {
           sp.h = h;
+          sp.plan = plan;
           sp.bytes = bytes;
           S->used += bytes;
           S->uploads++;
+          // exact reservation now that the layout is known (never above the bound)
+          if (plan)
+            r.reserve = std::min<uint64_t>(
+                r.reserve, 2 * (member_scratch_bytes(h, *plan, r.cmax, r.ts) + (uint64_t)r.cmax * plan->nslots * sp.w));
         }
       }
     }
     S->pending.pop_front();
     if (rc != PEVAL_OK) {
       r.status = rc;
+      S->done_q.push_back(r.id);
       S->rejected++;
       S->cv_done.notify_all();
       continue;
@@ -301,7 +327,16 @@ static void admit(peval_server *S, std::unique_lock<std::mutex> &lk) {
 
 // Build and launch one pass over the active requests; returns false if
 // nothing could be launched.
+static bool launch_pass_impl(peval_server *S, std::unique_lock<std::mutex> &lk);
+
 static bool launch_pass(peval_server *S, std::unique_lock<std::mutex> &lk) {
+  const double t0 = now_s();
+  bool ok = launch_pass_impl(S, lk);
+  S->host_pass_s += now_s() - t0;
+  return ok;
+}
+
+static bool launch_pass_impl(peval_server *S, std::unique_lock<std::mutex> &lk) {
   int slot = -1;
   for (int k = 0; k < kStreams; ++k)
     if (!S->slot_busy[k]) slot = k;
@@ -330,7 +365,7 @@ static bool launch_pass(peval_server *S, std::unique_lock<std::mutex> &lk) {
       work = (double)S->polys[r0.poly].s * std::min<uint32_t>(r0.ts, r0.T - r0.t_next + 1);
     }
     for (auto &c : cand) {
-      if (work >= S->pass_work) break;
+      if (work >= S->pass_work || ids.size() >= S->max_members) break;
       const SReq &r = S->reqs[c.second];
       work += (double)S->polys[r.poly].s * std::min<uint32_t>(r.ts, r.T - r.t_next + 1);
       ids.push_back(c.second);
@@ -349,14 +384,7 @@ static bool launch_pass(peval_server *S, std::unique_lock<std::mutex> &lk) {
     SReq &r = S->reqs[rid];
     SPoly &sp = S->polys[r.poly];
     const uint32_t ts = std::min<uint32_t>(r.ts, r.T - r.t_next + 1);
-    BatchMember m{nullptr, nullptr, 1, ts};
-    if (!S->simulate) {
-      Plan *pl = nullptr;
-      std::lock_guard<std::mutex> lk(sp.h->mu);
-      Tuning t = choose_tuning(sp.h, ts);
-      if (get_plan(sp.h, std::min<uint32_t>(t.K, 8), kBatchP, &pl) != PEVAL_OK) continue;
-      m = BatchMember{sp.h, pl, 1, ts};
-    }
+    BatchMember m{sp.h, sp.plan, 1, ts};
     sl.push_back(Slice{rid, r.t_next, ts});
     mem.push_back(m);
     te += sp.s * (uint64_t)ts;
@@ -394,11 +422,21 @@ static bool launch_pass(peval_server *S, std::unique_lock<std::mutex> &lk) {
     BatchCore core;
     void *arena = nullptr, *blob = nullptr;
     do {
-      hipError_t e = hipMallocAsync(&arena, std::max<size_t>(scratch, 256), st);
-      if (e != hipSuccess) {
-        launch_rc = fail(PEVAL_ENOMEM, "pass scratch: %s", hipGetErrorString(e));
-        break;
+      (void)hipEventRecord(S->ev0[slot], st);
+      // the slot's previous pass has retired, so its buffers are free; they
+      // only grow (a larger pass reallocates them once)
+      if (S->slot_arena_bytes[slot] < scratch) {
+        if (S->slot_arena[slot]) (void)hipFree(S->slot_arena[slot]);
+        S->slot_arena[slot] = nullptr;
+        S->slot_arena_bytes[slot] = 0;
+        size_t want = std::max<size_t>(scratch + scratch / 4, 1 << 20);
+        if (hipMalloc(&S->slot_arena[slot], want) != hipSuccess) {
+          launch_rc = fail(PEVAL_ENOMEM, "pass scratch of %zu bytes", want);
+          break;
+        }
+        S->slot_arena_bytes[slot] = want;
       }
+      arena = S->slot_arena[slot];
       batch_plan(core, mem, arena, runs.data());
       if (S->staging_bytes[slot] < core.blob_bytes) {
         // the slot's previous pass has retired, so its staging buffer is free
@@ -412,8 +450,19 @@ static bool launch_pass(peval_server *S, std::unique_lock<std::mutex> &lk) {
         S->staging_bytes[slot] = core.blob_bytes * 2;
       }
       memcpy(S->staging[slot], core.image.data(), core.blob_bytes);
-      e = hipMallocAsync(&blob, core.blob_bytes, st);
-      if (e == hipSuccess) e = hipMemcpyAsync(blob, S->staging[slot], core.blob_bytes, hipMemcpyHostToDevice, st);
+      if (S->slot_blob_bytes[slot] < core.blob_bytes) {
+        if (S->slot_blob[slot]) (void)hipFree(S->slot_blob[slot]);
+        S->slot_blob[slot] = nullptr;
+        S->slot_blob_bytes[slot] = 0;
+        size_t want = std::max<size_t>(core.blob_bytes * 2, 1 << 20);
+        if (hipMalloc(&S->slot_blob[slot], want) != hipSuccess) {
+          launch_rc = fail(PEVAL_ENOMEM, "pass descriptors");
+          break;
+        }
+        S->slot_blob_bytes[slot] = want;
+      }
+      blob = S->slot_blob[slot];
+      hipError_t e = hipMemcpyAsync(blob, S->staging[slot], core.blob_bytes, hipMemcpyHostToDevice, st);
       if (e != hipSuccess) {
         launch_rc = fail(PEVAL_EDEVICE, "pass upload: %s", hipGetErrorString(e));
         break;
@@ -423,8 +472,6 @@ static bool launch_pass(peval_server *S, std::unique_lock<std::mutex> &lk) {
       batch_persistent_blocks(&bl);
       core.eval_blocks = (int)std::min<uint64_t>((uint64_t)bl, std::max<uint64_t>(1, (core.n_items + 3) / 4));
       launch_rc = batch_enqueue(core, st);
-      (void)hipFreeAsync(blob, st);
-      (void)hipFreeAsync(arena, st);
       if (launch_rc == PEVAL_OK && hipEventRecord(S->ev[slot], st) != hipSuccess)
         launch_rc = fail(PEVAL_EDEVICE, "event record");
     } while (false);
@@ -444,18 +491,48 @@ static bool launch_pass(peval_server *S, std::unique_lock<std::mutex> &lk) {
   S->slot_busy[slot] = true;
   S->inflight.push_back(ps);
   S->passes++;
+  S->slices += sl.size();
   return true;
 }
 
-// Result copies to host memory (pageable, so synchronous) run here, off the
-// scheduler thread, two at a time.
+// Result copies to host memory run here, off the scheduler thread, four at
+// a time.  A page-locked destination gets one direct DMA; pageable memory
+// goes device -> pinned staging -> destination in chunks, the next chunk's
+// DMA overlapping the previous chunk's host copy.
+static int copy_result(hipStream_t st, char *const stage[2], hipEvent_t ev[2], size_t chunk, void *dst,
+                       const void *src, uint64_t bytes) {
+  const uint64_t n = (bytes + chunk - 1) / chunk;
+  auto issue = [&](uint64_t i) {
+    const uint64_t off = i * chunk, len = std::min<uint64_t>(chunk, bytes - off);
+    hipError_t e = hipMemcpyAsync(stage[i & 1], (const char *)src + off, len, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[i & 1], st);
+    return e;
+  };
+  if (n && issue(0) != hipSuccess) return PEVAL_EDEVICE;
+  for (uint64_t i = 0; i < n; ++i) {
+    if (i + 1 < n && issue(i + 1) != hipSuccess) return PEVAL_EDEVICE;
+    if (hipEventSynchronize(ev[i & 1]) != hipSuccess) return PEVAL_EDEVICE;
+    const uint64_t off = i * chunk, len = std::min<uint64_t>(chunk, bytes - off);
+    memcpy((char *)dst + off, stage[i & 1], len);
+  }
+  return PEVAL_OK;
+}
+
 static void copier_main(peval_server *S, int idx) {
   (void)hipSetDevice(S->device);
+  constexpr size_t kChunk = 8u << 20;
+  char *stage[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool ready = true;
+  for (int k = 0; k < 2; ++k) {
+    ready = ready && hipHostMalloc((void **)&stage[k], kChunk, hipHostMallocDefault) == hipSuccess;
+    ready = ready && hipEventCreateWithFlags(&ev[k], hipEventDisableTiming) == hipSuccess;
+  }
   std::unique_lock<std::mutex> lk(S->mu);
   while (true) {
     S->cv_copy.wait(lk, [&] { return S->stop || !S->to_copy.empty(); });
     if (S->to_copy.empty()) {
-      if (S->stop) return;
+      if (S->stop) break;
       continue;
     }
     uint64_t rid = S->to_copy.front();
@@ -464,11 +541,21 @@ static void copier_main(peval_server *S, int idx) {
     void *dst = r.host_out, *src = r.d_out;
     uint64_t bytes = r.out_bytes;
     lk.unlock();  // the request is unfinished: nobody else touches it
-    hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, S->copy_sts[idx]);
-    if (e == hipSuccess) e = hipStreamSynchronize(S->copy_sts[idx]);
+    int rc = PEVAL_OK;
+    hipPointerAttribute_t attr;
+    bool pinned = hipPointerGetAttributes(&attr, dst) == hipSuccess && attr.type == hipMemoryTypeHost;
+    (void)hipGetLastError();  // a pageable pointer is not an error here
+    if (pinned) {  // page-locked destination: one direct DMA
+      hipError_t e = hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, S->copy_sts[idx]);
+      if (e == hipSuccess) e = hipStreamSynchronize(S->copy_sts[idx]);
+      if (e != hipSuccess) rc = PEVAL_EDEVICE;
+    } else {
+      rc = ready ? copy_result(S->copy_sts[idx], stage, ev, kChunk, dst, src, bytes) : PEVAL_ENOMEM;
+    }
     lk.lock();
-    if (e != hipSuccess) {
-      r.status = fail(PEVAL_EDEVICE, "result copy: %s", hipGetErrorString(e));
+    if (rc != PEVAL_OK) {
+      r.status = fail(rc, "result copy failed");
+      S->done_q.push_back(r.id);
       S->polys[r.poly].refs--;
       S->used -= r.out_bytes + r.reserve;
       S->cv_done.notify_all();
@@ -477,6 +564,11 @@ static void copier_main(peval_server *S, int idx) {
     finish_request(S, r, now_s());
     S->cv_done.notify_all();
     S->cv_work.notify_one();  // memory was released
+  }
+  lk.unlock();
+  for (int k = 0; k < 2; ++k) {
+    if (stage[k]) (void)hipHostFree(stage[k]);
+    if (ev[k]) (void)hipEventDestroy(ev[k]);
   }
 }
 
@@ -491,7 +583,9 @@ static void worker_main(peval_server *S) {
       }
     }
     bool busy = !S->inflight.empty();
-    if (!busy && !S->to_free.empty()) {
+    // hipFree waits for the device, so outputs are freed when it is idle, or
+    // in one go once many have piled up
+    if (!S->to_free.empty() && (!busy || S->to_free.size() >= 512)) {
       for (void *p : S->to_free) (void)hipFree(p);
       S->to_free.clear();
     }
@@ -514,16 +608,9 @@ extern "C" int peval_server_create(uint64_t hbm_budget_bytes, uint32_t flags, pe
     bool ok = hipGetDevice(&S->device) == hipSuccess;
     for (int k = 0; ok && k < kStreams; ++k)
       ok = hipStreamCreateWithFlags(&S->st[k], hipStreamNonBlocking) == hipSuccess &&
-           hipEventCreateWithFlags(&S->ev[k], hipEventDisableTiming) == hipSuccess;
+           hipEventCreate(&S->ev[k]) == hipSuccess && hipEventCreate(&S->ev0[k]) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&S->copy_st, hipStreamNonBlocking) == hipSuccess;
-    for (int k = 0; ok && k < 2; ++k) ok = hipStreamCreateWithFlags(&S->copy_sts[k], hipStreamNonBlocking) == hipSuccess;
-    if (ok) {  // keep pass scratch in the stream-ordered pool between passes
-      hipMemPool_t pool;
-      if (hipDeviceGetDefaultMemPool(&pool, S->device) == hipSuccess) {
-        uint64_t keep = hbm_budget_bytes;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
-      }
-    }
+    for (int k = 0; ok && k < 4; ++k) ok = hipStreamCreateWithFlags(&S->copy_sts[k], hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
       peval_server_destroy(S);
       return fail(PEVAL_EDEVICE, "stream creation");
@@ -532,14 +619,16 @@ extern "C" int peval_server_create(uint64_t hbm_budget_bytes, uint32_t flags, pe
   S->t_start = now_s();
   S->worker = std::thread(worker_main, S);
   if (!S->simulate)
-    for (int k = 0; k < 2; ++k) S->copiers.emplace_back(copier_main, S, k);
+    for (int k = 0; k < 4; ++k) S->copiers.emplace_back(copier_main, S, k);
   *out = S;
   return PEVAL_OK;
 }
 
-extern "C" int peval_server_configure(peval_server *S, double slice_work, double pass_work, double sim_rate) {
-  if (!S || slice_work < 1 || pass_work < 1 || sim_rate <= 0) return fail(PEVAL_EINVAL, "bad argument");
+extern "C" int peval_server_configure(peval_server *S, double slice_work, double pass_work, uint32_t max_members,
+                                      double sim_rate) {
+  if (!S || slice_work < 1 || pass_work < 1 || max_members < 1 || sim_rate <= 0) return fail(PEVAL_EINVAL, "bad argument");
   std::lock_guard<std::mutex> lk(S->mu);
+  S->max_members = max_members;
   S->slice_work = slice_work;
   S->pass_work = pass_work;
   S->sim_rate = sim_rate;
@@ -637,6 +726,7 @@ extern "C" int peval_server_submit(peval_server *S, uint64_t poly_id, const uint
     r.status = 0;
     r.t_done = r.t_submit;
     S->reqs.emplace(r.id, r);
+    S->done_q.push_back(r.id);
     S->completed++;
     S->lat_ms.push_back(0);
     return PEVAL_OK;
@@ -672,6 +762,21 @@ extern "C" int peval_server_wait(peval_server *S, uint64_t req_id, int64_t timeo
   return PEVAL_OK;
 }
 
+extern "C" int peval_server_next_done(peval_server *S, int64_t timeout_ms, uint64_t *req_id) {
+  if (!S || !req_id) return fail(PEVAL_EINVAL, "null argument");
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto pred = [&] { return !S->done_q.empty() || S->err != PEVAL_OK; };
+  if (timeout_ms < 0) {
+    S->cv_done.wait(lk, pred);
+  } else if (!S->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), pred)) {
+    return fail(PEVAL_ETIMEOUT, "no request finished");
+  }
+  if (S->done_q.empty()) return S->err;
+  *req_id = S->done_q.front();
+  S->done_q.pop_front();
+  return PEVAL_OK;
+}
+
 extern "C" int peval_server_release(peval_server *S, uint64_t req_id) {
   if (!S) return fail(PEVAL_EINVAL, "null server");
   std::lock_guard<std::mutex> lk(S->mu);
@@ -679,6 +784,8 @@ extern "C" int peval_server_release(peval_server *S, uint64_t req_id) {
   if (it == S->reqs.end()) return fail(PEVAL_EINVAL, "unknown request");
   if (it->second.status > 0) return fail(PEVAL_EBUSY, "request not finished");
   S->reqs.erase(it);
+  auto q = std::find(S->done_q.begin(), S->done_q.end(), req_id);
+  if (q != S->done_q.end()) S->done_q.erase(q);
   return PEVAL_OK;
 }
 
@@ -694,6 +801,9 @@ extern "C" int peval_server_stats(peval_server *S, peval_server_stats_t *st) {
   st->passes = S->passes;
   st->term_evals = S->te_done;
   st->uploads = S->uploads;
+  st->slices = S->slices;
+  st->host_pass_s = S->host_pass_s;
+  st->gpu_pass_s = S->gpu_pass_s;
   st->evictions = S->evictions;
   st->hbm_in_use = S->used;
   st->hbm_peak = S->peak;
@@ -716,6 +826,9 @@ extern "C" int peval_server_reset_stats(peval_server *S) {
   if (!S) return fail(PEVAL_EINVAL, "null server");
   std::lock_guard<std::mutex> lk(S->mu);
   S->submitted = S->completed = S->rejected = S->passes = S->te_done = S->uploads = S->evictions = 0;
+  S->slices = 0;
+  S->host_pass_s = 0;
+  S->gpu_pass_s = 0;
   S->lat_ms.clear();
   S->t_start = now_s();
   S->t_last_done = 0;
@@ -758,11 +871,14 @@ extern "C" int peval_server_destroy(peval_server *S) {
     if (kv.second.h) peval_destroy(kv.second.h);
   for (int k = 0; k < kStreams; ++k) {
     if (S->staging[k]) (void)hipHostFree(S->staging[k]);
+    if (S->slot_arena[k]) (void)hipFree(S->slot_arena[k]);
+    if (S->slot_blob[k]) (void)hipFree(S->slot_blob[k]);
     if (S->ev[k]) (void)hipEventDestroy(S->ev[k]);
+    if (S->ev0[k]) (void)hipEventDestroy(S->ev0[k]);
     if (S->st[k]) (void)hipStreamDestroy(S->st[k]);
   }
   if (S->copy_st) (void)hipStreamDestroy(S->copy_st);
-  for (int k = 0; k < 2; ++k)
+  for (int k = 0; k < 4; ++k)
     if (S->copy_sts[k]) (void)hipStreamDestroy(S->copy_sts[k]);
   delete S;
   return PEVAL_OK;

@@ -33,9 +33,10 @@ class _Info(ctypes.Structure):
 
 class _ServerStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "rejected", "queued", "active",
-                                                "passes", "term_evals", "uploads", "evictions", "hbm_in_use",
-                                                "hbm_peak")] + \
-               [(n, ctypes.c_double) for n in ("wall_s", "p50_ms", "p99_ms", "max_ms", "mean_ms")]
+                                                "passes", "term_evals", "uploads", "evictions", "slices",
+                                                "hbm_in_use", "hbm_peak")] + \
+               [(n, ctypes.c_double) for n in ("wall_s", "p50_ms", "p99_ms", "max_ms", "mean_ms", "host_pass_s",
+                                               "gpu_pass_s")]
 
 
 _lib = None
@@ -69,13 +70,14 @@ def lib() -> ctypes.CDLL:
         "peval_layout": ([vp, u64, u32, u32, vp, vp, vp, vp, vp, vp], i32),
         "peval_autotune": ([vp, vp, u32, u32, vp, vp, vp, vp], i32),
         "peval_server_create": ([u64, u32, ctypes.POINTER(vp)], i32),
-        "peval_server_configure": ([vp, ctypes.c_double, ctypes.c_double, ctypes.c_double], i32),
+        "peval_server_configure": ([vp, ctypes.c_double, ctypes.c_double, u32, ctypes.c_double], i32),
         "peval_server_add_poly": ([vp, u64, u32, u64, vp, vp, ctypes.POINTER(u64)], i32),
         "peval_server_remove_poly": ([vp, u64], i32),
         "peval_server_submit": ([vp, u64, vp, u32, vp, ctypes.POINTER(u64)], i32),
         "peval_server_poll": ([vp, u64, ctypes.POINTER(ctypes.c_int)], i32),
         "peval_server_wait": ([vp, u64, ctypes.c_int64], i32),
         "peval_server_release": ([vp, u64], i32),
+        "peval_server_next_done": ([vp, ctypes.c_int64, ctypes.POINTER(u64)], i32),
         "peval_server_stats": ([vp, ctypes.POINTER(_ServerStats)], i32),
         "peval_server_reset_stats": ([vp], i32),
         "peval_server_destroy": ([vp], i32),
@@ -281,8 +283,10 @@ class Server:
         self._outs = {}
         self._meta = {}
 
-    def configure(self, slice_work: float = 2e9, pass_work: float = 1.5e10, sim_rate: float = 1e12):
-        _check(lib().peval_server_configure(self._s, float(slice_work), float(pass_work), float(sim_rate)))
+    def configure(self, slice_work: float = 2e9, pass_work: float = 1.5e10, max_members: int = 512,
+                  sim_rate: float = 1e12):
+        _check(lib().peval_server_configure(self._s, float(slice_work), float(pass_work), int(max_members),
+                                            float(sim_rate)))
 
     def add_poly(self, p: int, exps, coeffs) -> int:
         exps = np.ascontiguousarray(exps, dtype=np.uint32)
@@ -317,6 +321,12 @@ class Server:
     def wait(self, rid: int, timeout_ms: int = -1) -> np.ndarray:
         _check(lib().peval_server_wait(self._s, rid, timeout_ms))
         return self._outs[rid]
+
+    def next_done(self, timeout_ms: int = -1) -> int:
+        """Id of the next finished request (completion order)."""
+        rid = ctypes.c_uint64()
+        _check(lib().peval_server_next_done(self._s, timeout_ms, ctypes.byref(rid)))
+        return rid.value
 
     def release(self, rid: int):
         _check(lib().peval_server_release(self._s, rid))

@@ -87,3 +87,19 @@ def test_bad_arguments():
             srv.submit(pid, np.ones(3, np.uint64), 0)
         with pytest.raises(PV.PevalError):
             srv.wait(12345, 10)
+
+
+def test_completion_queue_order():
+    with PV.Server(1 << 30, simulate=True) as srv:
+        srv.configure(slice_work=1e9, sim_rate=1e8)
+        big, small = _poly(20, 10000), _poly(21, 100)
+        pb, ps = srv.add_poly(big.p, big.exps, big.coeffs), srv.add_poly(small.p, small.exps, small.coeffs)
+        r_big = srv.submit(pb, np.ones(3, np.uint64), 500)      # ~0.1 s simulated
+        r_small = [srv.submit(ps, np.ones(3, np.uint64), 16) for _ in range(5)]
+        order = [srv.next_done(5000) for _ in range(6)]
+        assert set(order) == {r_big, *r_small}
+        for r in order:
+            srv.release(r)
+        with pytest.raises(PV.PevalError) as e:
+            srv.next_done(10)
+        assert e.value.code == PV.ETIMEOUT
