@@ -132,6 +132,20 @@ int peval_destroy(peval_poly *h);
  */
 int peval_set_tuning(peval_poly *h, uint32_t K, uint32_t P, uint32_t C);
 
+/*
+ * Modular product of the evaluation kernel.  PEVAL_ARITH_INT: Shoup's
+ * precomputed-quotient product on 32-bit limbs, for every p.
+ * PEVAL_ARITH_FP64: the paper's FP64-FMA product (Alg. 2, with Alg. 3 for
+ * the additions), allowed for 2^31 <= p < 2^50; terms per thread are capped
+ * at 8 (exact double sums).  PEVAL_ARITH_AUTO (the default at create):
+ * FP64 for 2^31 <= p < 2^50, where it is faster on gfx950, integer
+ * otherwise.  Results are identical; only speed differs.
+ */
+#define PEVAL_ARITH_AUTO 0u
+#define PEVAL_ARITH_INT 1u
+#define PEVAL_ARITH_FP64 2u
+int peval_set_arith(peval_poly *h, uint32_t mode);
+
 /* The tuning the next run with T evaluations would use. */
 int peval_get_tuning(peval_poly *h, uint32_t T, uint32_t *K, uint32_t *P, uint32_t *C);
 

@@ -63,6 +63,7 @@ __device__ __forceinline__ void batch_mono_one(const BatchDesc &d, uint64_t t0, 
   a.ntail = d.ntail;
   a.K = d.K;
   a.C = d.C;
+  a.as_double = 0;
   a.m = m;
   monomial_entry<A>(a, d.to.off, local);
 }

@@ -76,6 +76,7 @@ struct MonoArgs {
   uint64_t s, NT;
   uint64_t t0;
   uint32_t ntail, K, C;
+  uint32_t as_double;           // store canonical values as doubles (for the FP64 product)
   typename A::M m;
 };
 
@@ -87,7 +88,14 @@ __device__ __forceinline__ void monomial_entry(const MonoArgs<A> &a, const uint3
   uint32_t k = (uint32_t)(idx / a.NT);
   uint64_t j = idx - (uint64_t)k * a.NT;
   const uint64_t NTK = (uint64_t)a.K * a.NT;
-  if (k >= a.thr_cnt[j]) {  // padding: a zero term stays zero
+  // canonical value, or its double image when the evaluation uses Alg. 2
+  auto out = [&](T v) -> T {
+    if constexpr (sizeof(T) == 8) {
+      if (a.as_double) return (T)__double_as_longlong((double)canon(v, (T)a.m.p));
+    }
+    return v;
+  };
+  if (k >= a.thr_cnt[j]) {  // padding: a zero term stays zero (0.0 has the same bits)
     for (uint32_t c = 0; c < a.C; ++c) a.lam[c * NTK + idx] = 0;
     a.gam[idx] = 0;
     a.gamq[idx] = 0;
@@ -112,14 +120,14 @@ __device__ __forceinline__ void monomial_entry(const MonoArgs<A> &a, const uint3
     T mt = pow_mod(mi, a.t0, a.m);
     lam = A::mul_lazy(a.coeff[i], mt, shoup_quot(mt, a.m), a.m);
   }
-  a.lam[idx] = lam;
+  a.lam[idx] = out(lam);
   for (uint32_t c = 1; c < a.C; ++c) {
     lam = A::mul_lazy(lam, mi, mq, a.m);
-    a.lam[c * NTK + idx] = lam;
+    a.lam[c * NTK + idx] = out(lam);
   }
   // Gamma = m_i^C, the multiplier of every chain
   T g = (a.C == 1) ? mi : pow_mod(mi, (uint64_t)a.C, a.m);
-  a.gam[idx] = g;
+  a.gam[idx] = out(g);
   a.gamq[idx] = shoup_quot(g, a.m);
 }
 
@@ -140,7 +148,7 @@ struct EvalArgs {
   const typename A::T *gamq;    // [K][NT]
   const uint64_t *endmask;      // per wave: bit l set if lane l closes a segment
   const uint32_t *slot_base;    // per wave: index of its first segment slot
-  typename A::T *partial;       // [nslots][C][Lmax] canonical partial coefficients
+  typename A::PT *partial;      // [nslots][C][Lmax] canonical partial coefficients
   uint64_t NT, NW, nslots;
   uint32_t C, T;                // chains, evaluations in this launch
   uint32_t Lmax;                // ceil(T / C): evaluations of the longest chain
@@ -163,6 +171,13 @@ struct Stage<W64, P> {
     uint64_t v = lo[lane][q];
     return W64::Acc{(uint32_t)v, (uint32_t)(v >> 32), hi[lane][q]};
   }
+};
+
+template <int P>
+struct Stage<WF64, P> {
+  double v[64][P + 1];
+  __device__ __forceinline__ void put(int lane, int q, const WF64::Acc &a) { v[lane][q] = a.s; }
+  __device__ __forceinline__ WF64::Acc get(int lane, int q) const { return WF64::Acc{v[lane][q]}; }
 };
 
 template <int P>
@@ -212,7 +227,7 @@ __device__ __forceinline__ void eval_wave(const EvalArgs<A> &a, uint64_t wave, u
         A::add(acc, lam[k]);
         lam[k] = A::mul_lazy(lam[k], g[k], gq[k], a.m);
       }
-      st.put(lane, q, acc);
+      st.put(lane, q, A::stage(acc, a.m));
     }
     wave_sync();
     // transposed segmented sum: lane (h, pp) walks sub-tile h for evaluation pp
@@ -220,12 +235,12 @@ __device__ __forceinline__ void eval_wave(const EvalArgs<A> &a, uint64_t wave, u
       typename A::Acc sum = A::zero();
       // partial[(slot * C + c) * Lmax + i]: the P lanes of a sub-tile write P
       // consecutive evaluations of one slot
-      T *pcol = a.partial + (uint64_t)c * a.Lmax + i0 + pp;
+      typename A::PT *pcol = a.partial + (uint64_t)c * a.Lmax + i0 + pp;
       const uint64_t slot_stride = (uint64_t)a.C * a.Lmax;
 #pragma unroll 4
       for (int jj = 0; jj < P; ++jj) {
         const int src = h * P + jj;
-        A::add(sum, st.get(src, pp));
+        A::add_walk(sum, st.get(src, pp), a.m);
         if ((emask >> src) & 1ull) {
           const uint32_t slot = sbase + (uint32_t)__popcll(emask & ((1ull << src) - 1ull));
           pcol[slot * slot_stride] = A::reduce(sum, a.m);

@@ -23,8 +23,10 @@
 // w' = (-r) * p^{-1} mod 2^64 (exact division by multiplication with the
 // inverse of p modulo 2^64; Jebelean 1993).
 //
-// Everything here is plain 32/64-bit integer code; hipcc selects
-// v_mad_u64_u32 / v_mul_hi_u32 / v_mul_lo_u32 for it.
+// The integer code is plain 32/64-bit C; hipcc selects v_mad_u64_u32 /
+// v_mul_hi_u32 / v_mul_lo_u32 for it.  The paper's FP64 product (Alg. 2,
+// p < 2^50) is kept as a second policy so that both can be measured on the
+// same kernel.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -168,6 +170,7 @@ __device__ __forceinline__ uint32_t pow_mod(uint32_t base, uint64_t e, const Mod
 // 64-bit residues; lazy sums of up to 2^32 values below 2^64 in 96 bits.
 struct W64 {
   using T = uint64_t;
+  using PT = uint64_t;  // partial sums and output
   using M = Mod64;
   struct Acc {
     uint32_t w0, w1, w2;
@@ -189,6 +192,8 @@ struct W64 {
   __device__ static __forceinline__ T reduce(const Acc &a, const M &m) {
     return reduce96(((uint64_t)a.w1 << 32) | a.w0, a.w2, m);
   }
+  __device__ static __forceinline__ Acc stage(const Acc &a, const M &) { return a; }
+  __device__ static __forceinline__ void add_walk(Acc &a, const Acc &b, const M &) { add(a, b); }
   __device__ static __forceinline__ T mul_lazy(T x, T w, T wq, const M &m) {
     return shoup_mul(x, w, wq, m.p);
   }
@@ -197,6 +202,7 @@ struct W64 {
 // 32-bit residues; lazy sums in 64 bits.
 struct W32 {
   using T = uint32_t;
+  using PT = uint32_t;
   using M = Mod32;
   struct Acc {
     uint64_t v;
@@ -206,9 +212,83 @@ struct W32 {
   __device__ static __forceinline__ void add(Acc &a, T x) { a.v += x; }
   __device__ static __forceinline__ void add(Acc &a, const Acc &b) { a.v += b.v; }
   __device__ static __forceinline__ T reduce(const Acc &a, const M &m) { return reduce64(a.v, m); }
+  __device__ static __forceinline__ Acc stage(const Acc &a, const M &) { return a; }
+  __device__ static __forceinline__ void add_walk(Acc &a, const Acc &b, const M &) { add(a, b); }
   __device__ static __forceinline__ T mul_lazy(T x, T w, T wq, const M &m) {
     return shoup_mul(x, w, wq, m.p);
   }
+};
+
+// ---------------------------------------------------------------------------
+// FP64 residues (p < 2^50): the paper's product, Alg. 2 (van der Hoeven,
+// Lecerf and Quintin).  Values are exact integers held in doubles.
+// ---------------------------------------------------------------------------
+struct ModF64 {
+  double p;   // the modulus
+  double u;   // 1 / p, rounded to nearest
+  Mod64 m;    // integer constants, for the output conversion
+};
+
+// Alg. 2: x, y in [0, p), p < 2^50.  h + l = x*y exactly (FMA error-free
+// product), c is the quotient up to one, g the remainder up to p, and the
+// two tests of the algorithm bring g into [0, p).
+__device__ __forceinline__ double alg2_mul(double x, double y, double p, double u) {
+#pragma clang fp contract(off)
+  double h = x * y;
+  double l = __builtin_fma(x, y, -h);
+  double b = h * u;
+  double c = __builtin_floor(b);
+  double d = __builtin_fma(-c, p, h);
+  double g = d + l;
+  g = (g >= p) ? g - p : g;
+  g = (g < 0.0) ? g + p : g;
+  return g;
+}
+
+// Alg. 3: x, y in [0, p).
+__device__ __forceinline__ double alg3_add(double x, double y, double p) {
+#pragma clang fp contract(off)
+  double s = x + y;
+  return (s >= p) ? s - p : s;
+}
+
+// An exact integer s in [0, 2^53) reduced into [0, p) (quotient from 1/p,
+// remainder by one FMA, then the same two corrections as Alg. 2).
+__device__ __forceinline__ double fp_reduce(double s, double p, double u) {
+#pragma clang fp contract(off)
+  double c = __builtin_floor(s * u);
+  double r = __builtin_fma(-c, p, s);
+  r = (r >= p) ? r - p : r;
+  r = (r < 0.0) ? r + p : r;
+  return r;
+}
+
+// Exact integer in [0, 2^53) held in a double -> uint64.
+__device__ __forceinline__ uint64_t fp_to_u64(double v) {
+#pragma clang fp contract(off)
+  double hi = __builtin_floor(v * 0x1p-32);
+  double lo = __builtin_fma(-hi, 0x1p32, v);
+  return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
+}
+
+// Running values in [0, p) as doubles; a thread sums at most 8 of them
+// (< 2^53, exact) before reducing, and partial sums travel as canonical
+// uint64 residues (shared with the 64-bit integer path).
+struct WF64 {
+  using T = double;
+  using PT = uint64_t;
+  using M = ModF64;
+  struct Acc {
+    double s;
+  };
+  static constexpr int bytes = 8;
+  __device__ static __forceinline__ Acc zero() { return Acc{0.0}; }
+  __device__ static __forceinline__ void add(Acc &a, T x) { a.s += x; }
+  // both canonical (staged values and walk sums): Alg. 3
+  __device__ static __forceinline__ void add_walk(Acc &a, const Acc &b, const M &m) { a.s = alg3_add(a.s, b.s, m.p); }
+  __device__ static __forceinline__ PT reduce(const Acc &a, const M &) { return fp_to_u64(a.s); }
+  __device__ static __forceinline__ Acc stage(const Acc &a, const M &m) { return Acc{fp_reduce(a.s, m.p, m.u)}; }
+  __device__ static __forceinline__ T mul_lazy(T x, T w, T, const M &m) { return alg2_mul(x, w, m.p, m.u); }
 };
 
 }  // namespace peval

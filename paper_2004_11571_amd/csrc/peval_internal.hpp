@@ -60,6 +60,8 @@ struct peval_poly {
   uint32_t w = 8;  // bytes per residue
   peval::Mod64 m64{};
   peval::Mod32 m32{};
+  peval::ModF64 mf{};
+  uint32_t arith = 0;  // 0: integer products; 1: FP64 product (Alg. 2), 2^31 <= p < 2^50
   int device = 0;
 
   std::vector<uint32_t> gd, ge;        // output columns

@@ -174,6 +174,23 @@ def config2(instance: int = 0) -> Poly:
                      name="n6_s1e6_p63_T1024")
 
 
+def config2_p31(instance: int = 0) -> Poly:
+    """The 1e6-term shape of config2 with the 31-bit prime 2^31-1 (32-bit
+    residues)."""
+    return make_poly(config_seed(2, 500 + instance), P31, 6, 1_000_000, 1024, 40, 20,
+                     name="n6_s1e6_p31_T1024")
+
+
+def paper_table2(instance: int = 0) -> Poly:
+    """The paper's default workload (Section 2.3; timed in Table 2): n = 6
+    (4 evaluated variables), 5e5 terms, degree <= 10 in each variable,
+    T = 1e4 evaluations, 64-bit integers with a prime below 2^50 (the FP64
+    product of Alg. 2 needs p <= 50 bits).  The exponent distribution is not
+    given in the paper: per-variable uniform in [0, 10] here."""
+    return make_poly(config_seed(6, instance), P50, 6, 500_000, 10_000, 10, 10, per_var=True,
+                     name="n6_s5e5_d10_p50_T1e4")
+
+
 def config4(instance: int = 0) -> Poly:
     """n=8, 1e7 distinct terms, x1,x2 degree <= 60, x3..x8 total degree <= 30,
     p=2^63-25, T=4096."""

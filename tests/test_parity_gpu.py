@@ -214,3 +214,62 @@ def test_single_hip_runtime():
     maps = open("/proc/self/maps").read()
     runtimes = set(re.findall(r"\S*libamdhip64\S*", maps))
     assert len(runtimes) == 1, runtimes
+
+
+P40 = (1 << 40) - 87   # prime below 2^40
+
+
+@pytest.mark.parametrize("p", [P_SMALL_W8, P40, W.P50, (1 << 50) - 1 - 2 * 12345])
+@pytest.mark.parametrize("K", [1, 2, 4, 8])
+@pytest.mark.parametrize("P", [8, 16, 32])
+def test_fp64_product_path(orc, p, K, P):
+    """The paper's FP64-FMA product (Alg. 2) on the evaluation kernel."""
+    rng = np.random.default_rng(K * 7 + P + p % 97)
+    poly = W.random_small(rng, p, 6, 1500, 1, dmax=6)
+    poly.exps[:600, :2] = [4, 4]  # one group spanning several waves
+    poly.exps = np.unique(poly.exps, axis=0)
+    poly.coeffs = rng.integers(0, p, size=poly.exps.shape[0], dtype=np.uint64)
+    poly.coeffs[:7] = p - 1
+    for C in (1, 5):
+        exps = np.ascontiguousarray(poly.exps, np.uint32)
+        with PV.Poly(p, exps, poly.coeffs) as q:
+            q.set_arith("fp64")
+            q.set_tuning(K, P, C)
+            got = q.run(poly.beta, 41)
+        want = orc.evaluate(p, exps, poly.coeffs, poly.beta, 41, threads=8)
+        assert np.array_equal(got, want), (p, K, P, C)
+
+
+def test_fp64_offsets_and_edges(orc):
+    p = W.P50
+    rng = np.random.default_rng(77)
+    poly = W.random_small(rng, p, 5, 400, 1, dmax=4)
+    with PV.Poly(p, poly.exps, poly.coeffs) as q:
+        q.set_arith("fp64")
+        for beta in (poly.beta, np.ones(3, np.uint64), np.asarray([0, p - 1, 2], np.uint64)):
+            assert np.array_equal(q.run(beta, 9), orc.evaluate(p, poly.exps, poly.coeffs, beta, 9))
+    check(orc, p, poly.exps, poly.coeffs, poly.beta, 30, t0=500)
+
+
+def test_fp64_mode_limits():
+    with PV.Poly(W.P31, [[1, 2, 3]], [5]) as q:
+        with pytest.raises(PV.PevalError):
+            q.set_arith("fp64")
+    with PV.Poly(W.P63, [[1, 2, 3]], [5]) as q:
+        with pytest.raises(PV.PevalError):
+            q.set_arith("fp64")
+        q.set_arith("int")
+
+
+@pytest.mark.parametrize("p", [P_SMALL_W8, P40, W.P50])
+def test_integer_product_below_2_50(orc, p):
+    """2^31 <= p < 2^50 defaults to the FP64 product; the integer one must agree."""
+    rng = np.random.default_rng(p % 1009)
+    poly = W.random_small(rng, p, 6, 2500, 1, dmax=6)
+    want = orc.evaluate(p, poly.exps, poly.coeffs, poly.beta, 50, threads=8)
+    with PV.Poly(p, poly.exps, poly.coeffs) as q:
+        for mode in ("int", "fp64", "auto"):
+            q.set_arith(mode)
+            for tun in ((16, 16, 3), (8, 32, 1), (1, 8, 7)):
+                q.set_tuning(*tun)
+                assert np.array_equal(q.run(poly.beta, 50), want), (mode, tun)
