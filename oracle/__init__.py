@@ -10,7 +10,8 @@ bivariate images (paper, Section 2.1 and Section 2.3, Eq. (1)):
     out[t - t0][g] = sum_{i in group g} a_i * prod_{k>=3} (beta_k^t)^{g_ik}  mod p
 
 with groups = distinct (x1, x2) exponent pairs in descending lexicographic
-order.  Parity status of each function is recorded in the test suite's pins
+order, and the same images at T arbitrary points x_t in place of beta^t
+(``evaluate_points``).  Parity status of each function is recorded in the test suite's pins
 (tests/test_oracle_pins.py).
 """
 from __future__ import annotations
@@ -45,6 +46,8 @@ def load(path: str = _LIB) -> ctypes.CDLL:
     lib.oracle_eval.restype = ctypes.c_int
     lib.oracle_entry.argtypes = [u64, u32, u64, ptr, ptr, ptr, u64, u32, u32]
     lib.oracle_entry.restype = u64
+    lib.oracle_eval_points.argtypes = [u64, u32, u64, ptr, ptr, ptr, u64, ptr, u32]
+    lib.oracle_eval_points.restype = ctypes.c_int
     return lib
 
 
@@ -89,6 +92,28 @@ class Oracle:
                                       beta.ctypes.data, t0, T, out.ctypes.data, threads)
             if rc != 0:
                 raise RuntimeError(f"oracle_eval failed ({rc})")
+        return out
+
+    def evaluate_points(self, p, exps, coeffs, points, threads=1):
+        """(T, G) uint64 array, row t = the images at the point points[t]
+        (T rows of n-2 values for x3..xn)."""
+        exps = np.ascontiguousarray(exps, dtype=np.uint32)
+        coeffs = np.ascontiguousarray(coeffs, dtype=np.uint64)
+        s, n = exps.shape
+        points = np.ascontiguousarray(points, dtype=np.uint64)
+        if points.ndim != 2 or points.shape[1] != n - 2:
+            raise ValueError("points must be (T, n-2)")
+        if coeffs.shape != (s,):
+            raise ValueError("shape mismatch")
+        T = points.shape[0]
+        gd, _ = self.groups(exps)
+        G = gd.size
+        out = np.zeros((T, G), np.uint64)
+        if T and G:
+            rc = self.lib.oracle_eval_points(p, n, s, exps.ctypes.data, coeffs.ctypes.data,
+                                             points.ctypes.data, T, out.ctypes.data, threads)
+            if rc != 0:
+                raise RuntimeError(f"oracle_eval_points failed ({rc})")
         return out
 
     def entry(self, p, exps, coeffs, beta, t, d, e):

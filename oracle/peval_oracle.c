@@ -117,6 +117,25 @@ static uint64_t find_group(const uint64_t *gk, uint64_t G, uint64_t key)
     return lo;
 }
 
+/*
+ * The coefficient of every group at one point x = (x_3, ..., x_n) of
+ * F_p^{n-2}: row[g] = sum_{i in g} a_i prod_k x_k^{g_ik} mod p.
+ */
+static void eval_at_point(uint64_t p, uint32_t n, uint64_t s, const uint32_t *exps,
+                          const uint64_t *coeffs, const uint64_t *x,
+                          const uint64_t *gk, uint64_t G, uint64_t *row)
+{
+    memset(row, 0, G * sizeof(uint64_t));
+    for (uint64_t i = 0; i < s; ++i) {
+        const uint32_t *r = exps + i * n;
+        uint64_t v = coeffs[i] % p;                       /* a_i */
+        for (uint32_t k = 2; k < n; ++k)                  /* * x_k^{g_ik} */
+            v = mulmod(v, powmod(x[k - 2], r[k], p), p);
+        uint64_t g = find_group(gk, G, group_key(r));
+        row[g] = addmod(row[g], v, p);
+    }
+}
+
 /* One evaluation b_t: the coefficient of every group at the point beta^t. */
 static void eval_one_t(uint64_t p, uint32_t n, uint64_t s, const uint32_t *exps,
                        const uint64_t *coeffs, const uint64_t *beta, uint64_t t,
@@ -124,21 +143,14 @@ static void eval_one_t(uint64_t p, uint32_t n, uint64_t s, const uint32_t *exps,
 {
     /* the point beta^t = (beta_3^t, ..., beta_n^t) */
     for (uint32_t k = 0; k + 2 < n; ++k) bt[k] = powmod(beta[k] % p, t, p);
-    memset(row, 0, G * sizeof(uint64_t));
-    for (uint64_t i = 0; i < s; ++i) {
-        const uint32_t *r = exps + i * n;
-        uint64_t v = coeffs[i] % p;                       /* a_i */
-        for (uint32_t k = 2; k < n; ++k)                  /* * (beta_k^t)^{g_ik} */
-            v = mulmod(v, powmod(bt[k - 2], r[k], p), p);
-        uint64_t g = find_group(gk, G, group_key(r));
-        row[g] = addmod(row[g], v, p);
-    }
+    eval_at_point(p, n, s, exps, coeffs, bt, gk, G, row);
 }
 
 struct job {
     uint64_t p; uint32_t n; uint64_t s;
     const uint32_t *exps; const uint64_t *coeffs; const uint64_t *beta;
     const uint64_t *gk; uint64_t G;
+    const uint64_t *points;     /* NULL: the powers beta^t; else T rows of n-2 values */
     uint64_t t_first, t_count, t0;
     uint64_t *out;
     int rc;
@@ -149,28 +161,26 @@ static void *run_job(void *arg)
     struct job *j = (struct job *)arg;
     uint64_t *bt = (uint64_t *)malloc((j->n > 2 ? j->n - 2 : 1) * sizeof(uint64_t));
     if (!bt) { j->rc = -1; return NULL; }
+    uint32_t m = j->n - 2;
     for (uint64_t q = 0; q < j->t_count; ++q) {
         uint64_t t = j->t_first + q;
-        eval_one_t(j->p, j->n, j->s, j->exps, j->coeffs, j->beta, t, j->gk, j->G,
-                   j->out + (t - j->t0) * j->G, bt);
+        uint64_t *row = j->out + (t - j->t0) * j->G;
+        if (j->points) {
+            for (uint32_t k = 0; k < m; ++k) bt[k] = j->points[(t - j->t0) * m + k] % j->p;
+            eval_at_point(j->p, j->n, j->s, j->exps, j->coeffs, bt, j->gk, j->G, row);
+        } else {
+            eval_one_t(j->p, j->n, j->s, j->exps, j->coeffs, j->beta, t, j->gk, j->G, row, bt);
+        }
     }
     free(bt);
     j->rc = 0;
     return NULL;
 }
 
-/*
- * Dense bivariate images b_t for t = t0 .. t0+T-1.
- *
- * p >= 2; n >= 2; exps: s rows of n uint32 exponents; coeffs: s values;
- * beta: n-2 values (beta_3..beta_n).  out: T*G values, row (t - t0) holds
- * b_t in the column order of oracle_groups.  nthreads >= 1 splits the t range
- * into contiguous chunks, one per thread; the result does not depend on it.
- * Returns 0, -1 on allocation failure, -2 on invalid arguments.
- */
-int oracle_eval(uint64_t p, uint32_t n, uint64_t s, const uint32_t *exps,
-                const uint64_t *coeffs, const uint64_t *beta, uint64_t t0, uint64_t T,
-                uint64_t *out, uint32_t nthreads)
+/* shared driver: t ranges split over threads; points == NULL selects beta^t */
+static int eval_images(uint64_t p, uint32_t n, uint64_t s, const uint32_t *exps,
+                       const uint64_t *coeffs, const uint64_t *beta, const uint64_t *points,
+                       uint64_t t0, uint64_t T, uint64_t *out, uint32_t nthreads)
 {
     if (p < 2 || n < 2 || nthreads == 0) return -2;
     if (T == 0) return 0;
@@ -191,7 +201,7 @@ int oracle_eval(uint64_t p, uint32_t n, uint64_t s, const uint32_t *exps,
         uint64_t base = T / nthreads, extra = T % nthreads, next = t0;
         for (uint32_t w = 0; w < nthreads; ++w) {
             uint64_t cnt = base + (w < extra ? 1 : 0);
-            jobs[w] = (struct job){p, n, s, exps, coeffs, beta, gk, G, next, cnt, t0, out, -1};
+            jobs[w] = (struct job){p, n, s, exps, coeffs, beta, gk, G, points, next, cnt, t0, out, -1};
             next += cnt;
         }
         rc = 0;
@@ -212,6 +222,39 @@ int oracle_eval(uint64_t p, uint32_t n, uint64_t s, const uint32_t *exps,
 done:
     free(gd); free(ge); free(gk);
     return rc;
+}
+
+/*
+ * Dense bivariate images b_t for t = t0 .. t0+T-1.
+ *
+ * p >= 2; n >= 2; exps: s rows of n uint32 exponents; coeffs: s values;
+ * beta: n-2 values (beta_3..beta_n).  out: T*G values, row (t - t0) holds
+ * b_t in the column order of oracle_groups.  nthreads >= 1 splits the t range
+ * into contiguous chunks, one per thread; the result does not depend on it.
+ * Returns 0, -1 on allocation failure, -2 on invalid arguments.
+ */
+int oracle_eval(uint64_t p, uint32_t n, uint64_t s, const uint32_t *exps,
+                const uint64_t *coeffs, const uint64_t *beta, uint64_t t0, uint64_t T,
+                uint64_t *out, uint32_t nthreads)
+{
+    return eval_images(p, n, s, exps, coeffs, beta, NULL, t0, T, out, nthreads);
+}
+
+/*
+ * Images at T arbitrary points instead of the powers of one base point (the
+ * random evaluation points of Zippel's original method, Section 2.1; cost
+ * O(nT(d+s)), Section 2.3):
+ *
+ *   out[t][(d,e)] = sum_{i : (d_i, e_i) = (d, e)} a_i prod_{k=3..n} x_{t,k}^{g_ik}  mod p
+ *
+ * points: T rows of n-2 values (x_{t,3} .. x_{t,n}), reduced mod p on entry.
+ * Same column order, threading and return codes as oracle_eval.
+ */
+int oracle_eval_points(uint64_t p, uint32_t n, uint64_t s, const uint32_t *exps,
+                       const uint64_t *coeffs, const uint64_t *points, uint64_t T,
+                       uint64_t *out, uint32_t nthreads)
+{
+    return eval_images(p, n, s, exps, coeffs, NULL, points, 0, T, out, nthreads);
 }
 
 /*

@@ -27,6 +27,22 @@ What pins what (paper sections in brackets):
   lexicographic order [Section 2.3: lex order x1 > x2 > ... makes like
   monomials adjacent].
 * ``pin_gcd_example``: the worked example of Section 2.1 (golden fixture).
+
+Arbitrary points (the random points of Zippel's method, Section 2.1):
+
+* ``pin_points_full_point_bigint``: as above, at full points (x1, x2, x_t)
+  with x_t arbitrary (zeros and unreduced values included).
+* ``pin_points_character_sums``: for small p, summing the images over every
+  point of (F_p^*)^m weighted by prod_k x_k^{-j_k} gives (p-1)^m times the
+  sum of a_i over the terms whose tail exponents are congruent to j modulo
+  p-1 (orthogonality of the characters x -> x^j of F_p^*), and the plain sum
+  over all of F_p^m gives sum_i a_i prod_k S(g_ik) with S(0) = 0 and
+  S(g) = -1 if (p-1) | g > 0, else 0.  Both identities are number theory,
+  not the oracle's formula.
+* ``pin_points_match_powers``: the points beta^1 .. beta^T give the images
+  of the power mode (each side pinned on its own above).
+* ``pin_points_zero_and_linearity``: at x = 0 only terms without tail
+  variables survive; images are linear in the coefficients.
 """
 from __future__ import annotations
 
@@ -298,5 +314,121 @@ def pin_gcd_example(orc, p=W.P63, T=5, seed=7):
         assert all(int(x) == want.get(k, 0) for x in vals), k
 
 
+
+
+# ---------------------------------------------------------------------------
+# Arbitrary points
+# ---------------------------------------------------------------------------
+
+def full_value_at(exps, coeffs, p, x1, x2, x):
+    """f(x1, x2, x) over the integers, reduced only at the end."""
+    total = 0
+    for row, a in zip(exps.tolist(), coeffs.tolist()):
+        term = int(a) * x1 ** row[0] * x2 ** row[1]
+        for k in range(2, len(row)):
+            term *= int(x[k - 2]) ** row[k]
+        total += term
+    return total % p
+
+
+def pin_points_full_point_bigint(orc, seed=21, cases=20):
+    rng = np.random.default_rng(seed)
+    pyr = random.Random(seed)
+    for case in range(cases):
+        p = PRIMES_WORD[case % len(PRIMES_WORD)]
+        n = 2 + case % 5
+        s = [1, 4, 9, 25][case % 4]
+        T = 1 + case % 5
+        poly = W.random_small(rng, p, n, s, T, dmax=4, allow_dup=(case % 3 == 1))
+        pts = [[pyr.choice([0, 1, p - 1, pyr.randrange(0, p), p + pyr.randrange(0, 1000)])
+                for _ in range(n - 2)] for _ in range(T)]
+        points = np.asarray(pts, np.uint64).reshape(T, n - 2)
+        out = orc.evaluate_points(p, poly.exps, poly.coeffs, points)
+        gd, ge = orc.groups(poly.exps)
+        for t in range(T):
+            for _ in range(3):
+                x1, x2 = pyr.randrange(0, p), pyr.randrange(0, p)
+                want = full_value_at(poly.exps, poly.coeffs, p, x1, x2, pts[t])
+                assert image_at(out[t], gd, ge, x1, x2, p) == want, (case, p, n, s, t)
+
+
+def pin_points_character_sums(orc, seed=22):
+    rng = np.random.default_rng(seed)
+    for p, m in ((5, 2), (7, 1), (7, 2), (3, 3)):
+        s = 16
+        exps = np.concatenate([rng.integers(0, 3, size=(s, 2)),
+                               rng.integers(0, 3 * (p - 1) + 1, size=(s, m))], axis=1).astype(np.uint32)
+        # a few terms whose tail exponents are all positive multiples of p-1
+        exps[:3, 2:] = (p - 1) * rng.integers(1, 3, size=(3, m))
+        coeffs = rng.integers(0, p, size=s, dtype=np.uint64)
+        gd, ge = orc.groups(exps)
+        G = len(gd)
+        col = {(int(d), int(e)): j for j, (d, e) in enumerate(zip(gd, ge))}
+        # every point of F_p^m
+        allpts = np.asarray(list(itertools.product(range(p), repeat=m)), np.uint64)
+        out = orc.evaluate_points(p, exps, coeffs, allpts)
+        S = lambda g: (p - 1) if (g > 0 and g % (p - 1) == 0) else 0     # -1 mod p, else 0
+        want = [0] * G
+        for row, a in zip(exps.tolist(), coeffs.tolist()):
+            v = int(a)
+            for g in row[2:]:
+                v *= S(g)
+            want[col[(row[0], row[1])]] += v
+        got = [int(x) for x in (out.astype(object).sum(axis=0) % p)]
+        assert got == [w % p for w in want], (p, m)
+        # weighted sums over (F_p^*)^m pick out exponent classes mod p-1
+        units = np.asarray(list(itertools.product(range(1, p), repeat=m)), np.uint64)
+        outu = orc.evaluate_points(p, exps, coeffs, units)
+        for j in itertools.product(range(p - 1), repeat=m):
+            w = [1] * len(units)
+            for r, x in enumerate(units.tolist()):
+                for k in range(m):
+                    w[r] = w[r] * pow(int(x[k]), (p - 1 - j[k]) % (p - 1), p) % p
+            lhs = [sum(w[r] * int(outu[r, g]) for r in range(len(units))) % p for g in range(G)]
+            rhs = [0] * G
+            for row, a in zip(exps.tolist(), coeffs.tolist()):
+                if all(row[2 + k] % (p - 1) == j[k] for k in range(m)):
+                    rhs[col[(row[0], row[1])]] += int(a)
+            scale = pow(p - 1, m, p)
+            assert lhs == [scale * r % p for r in rhs], (p, m, j)
+
+
+def pin_points_match_powers(orc, seed=23):
+    rng = np.random.default_rng(seed)
+    for p, n, s, T in ((W.P63, 6, 40, 7), (W.P31, 4, 30, 5), (101, 3, 10, 9), (W.P50, 8, 25, 3)):
+        poly = W.random_small(rng, p, n, s, T, dmax=5)
+        pts = np.asarray([[pow(int(b), t, p) for b in poly.beta] for t in range(1, T + 1)],
+                         np.uint64).reshape(T, n - 2)
+        a = orc.evaluate_points(p, poly.exps, poly.coeffs, pts)
+        b = orc.evaluate(p, poly.exps, poly.coeffs, poly.beta, T)
+        assert np.array_equal(a, b), (p, n)
+
+
+def pin_points_zero_and_linearity(orc, seed=24):
+    rng = np.random.default_rng(seed)
+    p, n, s, T = W.P63, 5, 60, 4
+    poly = W.random_small(rng, p, n, s, T, dmax=3)
+    poly.exps[:10, 2:] = 0                       # some terms without tail variables
+    zero = np.zeros((1, n - 2), np.uint64)
+    out = orc.evaluate_points(p, poly.exps, poly.coeffs, zero)
+    gd, ge = orc.groups(poly.exps)
+    want = {}
+    for row, a in zip(poly.exps.tolist(), poly.coeffs.tolist()):
+        if not any(row[2:]):
+            want[(row[0], row[1])] = (want.get((row[0], row[1]), 0) + int(a)) % p
+    for j, (d, e) in enumerate(zip(gd, ge)):
+        assert int(out[0, j]) == want.get((int(d), int(e)), 0)
+    pts = rng.integers(0, p, size=(T, n - 2), dtype=np.uint64)
+    c2 = rng.integers(0, p, size=s, dtype=np.uint64)
+    k = 987654321
+    mix = np.asarray([(int(a) * k + int(b)) % p for a, b in zip(poly.coeffs, c2)], np.uint64)
+    o1 = orc.evaluate_points(p, poly.exps, poly.coeffs, pts).astype(object)
+    o2 = orc.evaluate_points(p, poly.exps, c2, pts).astype(object)
+    om = orc.evaluate_points(p, poly.exps, mix, pts).astype(object)
+    assert np.array_equal(om, (o1 * k + o2) % p)
+
+
 ALL_PINS = [pin_full_point_bigint, pin_small_prime_exhaustive, pin_closed_forms,
-            pin_linearity, pin_power_consistency, pin_group_order, pin_gcd_example]
+            pin_linearity, pin_power_consistency, pin_group_order, pin_gcd_example,
+            pin_points_full_point_bigint, pin_points_character_sums, pin_points_match_powers,
+            pin_points_zero_and_linearity]

@@ -15,11 +15,11 @@ SRC = os.path.join(os.path.dirname(oracle.__file__), "peval_oracle.c")
 
 MUTANTS = {
     "drop_first_tail_variable": (
-        "for (uint32_t k = 2; k < n; ++k)                  /* * (beta_k^t)^{g_ik} */",
-        "for (uint32_t k = 3; k < n; ++k)                  /* * (beta_k^t)^{g_ik} */"),
+        "for (uint32_t k = 2; k < n; ++k)                  /* * x_k^{g_ik} */",
+        "for (uint32_t k = 3; k < n; ++k)                  /* * x_k^{g_ik} */"),
     "wrong_beta_index": (
-        "v = mulmod(v, powmod(bt[k - 2], r[k], p), p);",
-        "v = mulmod(v, powmod(bt[(k - 1) % (n - 2)], r[k], p), p);"),
+        "v = mulmod(v, powmod(x[k - 2], r[k], p), p);",
+        "v = mulmod(v, powmod(x[(k - 1) % (n - 2)], r[k], p), p);"),
     "t_starts_at_zero": (
         "bt[k] = powmod(beta[k] % p, t, p);",
         "bt[k] = powmod(beta[k] % p, t - 1, p);"),
@@ -39,11 +39,20 @@ MUTANTS = {
         "return (uint64_t)(((u128)a * (u128)b) % p);",
         "return (a * b) % p;"),
     "exponent_off_by_one": (
-        "v = mulmod(v, powmod(bt[k - 2], r[k], p), p);",
-        "v = mulmod(v, powmod(bt[k - 2], r[k] + 1, p), p);"),
+        "v = mulmod(v, powmod(x[k - 2], r[k], p), p);",
+        "v = mulmod(v, powmod(x[k - 2], r[k] + 1, p), p);"),
     "coefficient_dropped": (
         "uint64_t v = coeffs[i] % p;                       /* a_i */",
         "uint64_t v = 1;                       /* a_i */"),
+    "points_wrong_variable": (
+        "bt[k] = j->points[(t - j->t0) * m + k] % j->p;",
+        "bt[k] = j->points[(t - j->t0) * m + (k + 1) % m] % j->p;"),
+    "points_first_row_only": (
+        "bt[k] = j->points[(t - j->t0) * m + k] % j->p;",
+        "bt[k] = j->points[k] % j->p;"),
+    "points_ignored": (
+        "        if (j->points) {",
+        "        if (0) {"),
     "powmod_zero_exponent": (
         "uint64_t r = 1 % p;",
         "uint64_t r = base % p;"),
@@ -60,7 +69,9 @@ orc = oracle.Oracle({lib!r})
 pins = [lambda o: P.pin_full_point_bigint(o, cases=14),
         lambda o: P.pin_small_prime_exhaustive(o, primes=[3, 5]),
         P.pin_closed_forms, P.pin_linearity, P.pin_power_consistency,
-        P.pin_group_order, P.pin_gcd_example]
+        P.pin_group_order, P.pin_gcd_example,
+        lambda o: P.pin_points_full_point_bigint(o, cases=10), P.pin_points_character_sums,
+        P.pin_points_match_powers, P.pin_points_zero_and_linearity]
 caught = 0
 for pin in pins:
     try:
