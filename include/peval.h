@@ -119,6 +119,34 @@ int peval_run(peval_poly *h, const uint64_t *beta, uint32_t T, void *out);
 int peval_run_async(peval_poly *h, const uint64_t *beta, uint64_t t0, uint32_t T,
                     void *dev_out, void *stream);
 
+/*
+ * Images at T arbitrary points instead of the powers of one base point
+ * (paper, Section 2.1: the random points of Zippel's method; the cost of
+ * evaluating at unrelated points is O(nT(d+s)), Section 2.3):
+ *
+ *   row t of out = f(x1, x2, points[t][0], ..., points[t][n-3]),  0 <= t < T,
+ *
+ * in the same dense T x G layout and column order as peval_run.
+ *
+ * points  T rows of n-2 uint64 values (x3..xn), row-major; any values,
+ *         reduced mod p on the device.  Host memory for peval_run_points,
+ *         device memory for peval_run_points_async (valid until the stream
+ *         has passed the call).  May be NULL when n == 2.
+ * Each term's monomial is formed from per-point tables of products of its
+ * tail variables' powers; a polynomial whose tail degrees need more than
+ * four such tables of 32 KiB per point gives PEVAL_EUNSUPPORTED.
+ */
+int peval_run_points(peval_poly *h, const uint64_t *points, uint32_t T, void *out);
+int peval_run_points_async(peval_poly *h, const uint64_t *points, uint32_t T, void *dev_out,
+                           void *stream);
+
+/*
+ * Host-only planner of the point mode's tables (for tests): residue width
+ * w (4 or 8), ntail = n-2 tail degree bounds -> number of factor tables nf
+ * and table entries per point E.  PEVAL_EUNSUPPORTED if no plan fits.
+ */
+int peval_points_factors(uint32_t w, uint32_t ntail, const uint32_t *maxdeg, uint32_t *nf, uint32_t *E);
+
 /* Release the handle and its device memory (waits for its pending work).
  * NULL is accepted. */
 int peval_destroy(peval_poly *h);

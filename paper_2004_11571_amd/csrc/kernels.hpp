@@ -195,6 +195,32 @@ __device__ __forceinline__ void wave_sync() {
 
 constexpr int kEvalBlock = 256;  // 4 waves, each independent
 
+// Transposed segmented sum of one pass of np <= P evaluations staged in st:
+// lane (h, pp) walks sub-tile h (lanes h*P .. h*P+P-1) for evaluation pp,
+// emitting a reduced partial at every segment end of the wave's endmask.
+// partial[(slot * C + c) * Lmax + i]: the P lanes of a sub-tile write P
+// consecutive evaluations of one slot.
+template <class A, int P>
+__device__ __forceinline__ void segmented_walk(const Stage<A, P> &st, int lane, int np, uint64_t emask,
+                                               uint32_t sbase, typename A::PT *partial, uint32_t c, uint32_t C,
+                                               uint32_t Lmax, uint32_t i0, const typename A::M &m) {
+  const int h = lane / P, pp = lane % P;
+  if (pp >= np) return;
+  typename A::Acc sum = A::zero();
+  typename A::PT *pcol = partial + (uint64_t)c * Lmax + i0 + pp;
+  const uint64_t slot_stride = (uint64_t)C * Lmax;
+#pragma unroll 4
+  for (int jj = 0; jj < P; ++jj) {
+    const int src = h * P + jj;
+    A::add_walk(sum, st.get(src, pp), m);
+    if ((emask >> src) & 1ull) {
+      const uint32_t slot = sbase + (uint32_t)__popcll(emask & ((1ull << src) - 1ull));
+      pcol[slot * slot_stride] = A::reduce(sum, m);
+      sum = A::zero();
+    }
+  }
+}
+
 // One wave's share of the evaluations: threads wave*64 .. wave*64+63, chain c.
 template <class A, int K, int P>
 __device__ __forceinline__ void eval_wave(const EvalArgs<A> &a, uint64_t wave, uint32_t c, Stage<A, P> &st,
@@ -214,7 +240,6 @@ __device__ __forceinline__ void eval_wave(const EvalArgs<A> &a, uint64_t wave, u
   const uint64_t emask = a.endmask[wave];
   const uint32_t sbase = a.slot_base[wave];
   const uint32_t L = (c < a.T) ? (a.T - 1 - c) / a.C + 1 : 0;  // evaluations of chain c
-  const int h = lane / P, pp = lane % P;
 
   for (uint32_t i0 = 0; i0 < L; i0 += P) {
     const int np = (L - i0 < (uint32_t)P) ? (int)(L - i0) : P;
@@ -230,24 +255,7 @@ __device__ __forceinline__ void eval_wave(const EvalArgs<A> &a, uint64_t wave, u
       st.put(lane, q, A::stage(acc, a.m));
     }
     wave_sync();
-    // transposed segmented sum: lane (h, pp) walks sub-tile h for evaluation pp
-    if (pp < np) {
-      typename A::Acc sum = A::zero();
-      // partial[(slot * C + c) * Lmax + i]: the P lanes of a sub-tile write P
-      // consecutive evaluations of one slot
-      typename A::PT *pcol = a.partial + (uint64_t)c * a.Lmax + i0 + pp;
-      const uint64_t slot_stride = (uint64_t)a.C * a.Lmax;
-#pragma unroll 4
-      for (int jj = 0; jj < P; ++jj) {
-        const int src = h * P + jj;
-        A::add_walk(sum, st.get(src, pp), a.m);
-        if ((emask >> src) & 1ull) {
-          const uint32_t slot = sbase + (uint32_t)__popcll(emask & ((1ull << src) - 1ull));
-          pcol[slot * slot_stride] = A::reduce(sum, a.m);
-          sum = A::zero();
-        }
-      }
-    }
+    segmented_walk<A, P>(st, lane, np, emask, sbase, a.partial, c, a.C, a.Lmax, i0, a.m);
     wave_sync();
   }
 }

@@ -105,26 +105,25 @@ std::vector<ProfRec> g_prof_recs;
 double g_prof_ms[4] = {0, 0, 0, 0};
 uint64_t g_prof_n[4] = {0, 0, 0, 0};
 
-struct ProfScope {
-  hipStream_t st;
-  int kind;
-  hipEvent_t a = nullptr, b = nullptr;
-  ProfScope(hipStream_t s, int k) : st(s), kind(k) {
-    if (!g_prof.load()) return;
-    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
-      a = b = nullptr;
-      return;
-    }
-    (void)hipEventRecord(a, st);
-  }
-  ~ProfScope() {
-    if (!a) return;
-    (void)hipEventRecord(b, st);
-    std::lock_guard<std::mutex> lk(g_prof_mu);
-    g_prof_recs.push_back({a, b, kind});
-  }
-};
 }  // namespace
+
+namespace peval {
+ProfScope::ProfScope(hipStream_t s, int k) : st(s), kind(k) {
+  if (!g_prof.load()) return;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    a = b = nullptr;
+    return;
+  }
+  (void)hipEventRecord(a, st);
+}
+
+ProfScope::~ProfScope() {
+  if (!a) return;
+  (void)hipEventRecord(b, st);
+  std::lock_guard<std::mutex> lk(g_prof_mu);
+  g_prof_recs.push_back({a, b, kind});
+}
+}  // namespace peval
 
 extern "C" int peval_prof_enable(int enable) {
   g_prof.store(enable ? 1 : 0);
@@ -414,6 +413,14 @@ extern "C" int peval_destroy(peval_poly *h) {
     release(h->gamq);
     release(h->partial);
     release(h->outbuf);
+    release(h->ptab);
+    release(h->ptsbuf);
+    for (auto &kv : h->pprep) {
+      (void)hipFree(kv.second.pa);
+      (void)hipFree(kv.second.paq);
+      (void)hipFree(kv.second.pidx);
+    }
+    h->pprep.clear();
     if (h->d_coeff) (void)hipFree(h->d_coeff);
     if (h->d_exps) (void)hipFree(h->d_exps);
     if (h->done) (void)hipEventDestroy(h->done);

@@ -11,6 +11,7 @@
 
 #include "kernels.hpp"
 #include "modarith.hpp"
+#include "points_kernels.hpp"
 
 namespace peval {
 
@@ -50,6 +51,26 @@ struct Tuning {
   uint32_t K, P, C;
 };
 
+// Per-thread-slot inputs of the point mode for one thread layout (K).
+struct PointsPrep {
+  void *pa = nullptr, *paq = nullptr;
+  uint64_t *pidx = nullptr;
+};
+
+// HIP-event timing of one kernel launch (active while profiling is enabled).
+// kind: 0 tables, 1 monomials / point prologue, 2 evaluation, 3 combine.
+struct ProfScope {
+  hipStream_t st;
+  int kind;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(hipStream_t s, int k);
+  ~ProfScope();
+};
+
+// Factor tables of the point mode from the per-variable degree bounds of the
+// tail (host only).  Returns PEVAL_OK or PEVAL_EUNSUPPORTED.
+int build_factor_plan(uint32_t w, uint32_t ntail, const uint32_t *maxdeg, FactorPlan *fp);
+
 }  // namespace peval
 
 struct peval_poly {
@@ -78,6 +99,12 @@ struct peval_poly {
   peval::Scratch tabval, tabquot, lam, gam, gamq, partial, outbuf;
 
   uint32_t tune_K = 0, tune_P = 0, tune_C = 0;  // 0 = automatic
+
+  // point mode (built on first use)
+  peval::FactorPlan fplan{};
+  int fplan_rc = 1;                          // 1: not built yet
+  std::map<uint32_t, peval::PointsPrep> pprep;  // key K
+  peval::Scratch ptab, ptsbuf;
 
   hipStream_t stream = nullptr;  // for peval_run
   hipEvent_t done = nullptr;     // end of the last enqueued call

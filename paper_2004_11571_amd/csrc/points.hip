@@ -1,0 +1,289 @@
+// Point mode: images at T arbitrary points (paper, Section 2.1: the random
+// points of Zippel's method; Section 2.3 puts their cost at O(nT(d+s))).
+// Kernels in points_kernels.hpp; the thread layout, partial sums and combine
+// are the power path's.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <type_traits>
+
+#include "errors.hpp"
+#include "peval.h"
+#include "peval_internal.hpp"
+
+using namespace peval;
+
+namespace peval {
+
+// Digits: a tail variable of degree bound D becomes one digit of radix D+1,
+// or two base-256 digits when D >= 256; variables that never occur are
+// dropped.  Digits are then spread over nf factors (smallest nf first),
+// largest radix first, each into the factor whose table grows least; a plan
+// is accepted when all tables of one point fit in kPointsTableBytes.
+int build_factor_plan(uint32_t w, uint32_t ntail, const uint32_t *maxdeg, FactorPlan *fp) {
+  FactorPlan f{};
+  struct Dig {
+    uint8_t var, shift;
+    uint16_t mask, radix;
+  };
+  std::vector<Dig> dig;
+  for (uint32_t v = 0; v < ntail; ++v) {
+    const uint32_t D = maxdeg[v];
+    if (D == 0) continue;
+    if (D + 1 <= 256) {
+      dig.push_back({(uint8_t)v, 0, 0xffff, (uint16_t)(D + 1)});
+    } else {
+      dig.push_back({(uint8_t)v, 0, 0xff, 256});
+      dig.push_back({(uint8_t)v, 8, 0xff, (uint16_t)((D >> 8) + 1)});
+    }
+  }
+  std::stable_sort(dig.begin(), dig.end(), [](const Dig &a, const Dig &b) { return a.radix > b.radix; });
+  const uint64_t emax = kPointsTableBytes / (2 * w);
+  if (dig.empty()) {  // the tail monomial is 1 for every term
+    f.nf = 1;
+    f.f_off[0] = 0;
+    f.f_off[1] = 1;
+    f.E = 2;
+    *fp = f;
+    return PEVAL_OK;
+  }
+  for (uint32_t nf = 1; nf <= (uint32_t)kMaxFactors; ++nf) {
+    uint64_t size[kMaxFactors] = {1, 1, 1, 1};
+    std::vector<uint32_t> fac(dig.size());
+    for (size_t d = 0; d < dig.size(); ++d) {
+      uint32_t best = 0;
+      for (uint32_t b = 1; b < nf; ++b)
+        if (size[b] < size[best]) best = b;  // smallest table grows least
+      fac[d] = best;
+      size[best] *= dig[d].radix;
+    }
+    uint64_t total = 0;
+    uint32_t used = 0;
+    for (uint32_t b = 0; b < nf; ++b)
+      if (size[b] > 1) total += size[b], ++used;
+    if (used < nf || total > emax) continue;
+    // strides inside each factor, in digit order
+    uint64_t place[kMaxFactors] = {1, 1, 1, 1};
+    f.ndig = (uint32_t)dig.size();
+    f.nf = nf;
+    for (size_t d = 0; d < dig.size(); ++d) {
+      f.var[d] = dig[d].var;
+      f.fac[d] = (uint8_t)fac[d];
+      f.shift[d] = dig[d].shift;
+      f.mask[d] = dig[d].mask;
+      f.radix[d] = dig[d].radix;
+      f.stride[d] = (uint32_t)place[fac[d]];
+      place[fac[d]] *= dig[d].radix;
+    }
+    f.f_off[0] = 0;
+    for (uint32_t b = 0; b < nf; ++b) f.f_off[b + 1] = f.f_off[b] + (uint32_t)size[b];
+    f.E = (f.f_off[nf] + 1) & ~1u;
+    *fp = f;
+    return PEVAL_OK;
+  }
+  return fail(PEVAL_EUNSUPPORTED,
+              "point mode: the tail degrees need more than %d factor tables of %u entries per point",
+              kMaxFactors, (unsigned)emax);
+}
+
+}  // namespace peval
+
+extern "C" int peval_points_factors(uint32_t w, uint32_t ntail, const uint32_t *maxdeg, uint32_t *nf,
+                                    uint32_t *E) {
+  if ((w != 4 && w != 8) || ntail > (uint32_t)kMaxTail || (ntail && !maxdeg) || !nf || !E)
+    return fail(PEVAL_EINVAL, "bad argument");
+  for (uint32_t v = 0; v < ntail; ++v)
+    if (maxdeg[v] > 65535) return fail(PEVAL_EINVAL, "tail degree above 65535");
+  FactorPlan fp;
+  PEVAL_TRY(build_factor_plan(w, ntail, maxdeg, &fp));
+  *nf = fp.nf;
+  *E = fp.E;
+  return PEVAL_OK;
+}
+
+namespace {
+
+template <class A>
+const typename A::M &mod_for(const peval_poly *h);
+template <>
+const Mod64 &mod_for<W64>(const peval_poly *h) { return h->m64; }
+template <>
+const Mod32 &mod_for<W32>(const peval_poly *h) { return h->m32; }
+
+template <class A>
+using PointsFn = void (*)(PointsArgs<A>);
+
+template <class A>
+PointsFn<A> points_kernel_for(uint32_t K, uint32_t NF) {
+#define PEVAL_PCASE(k, f) \
+  if (K == k && NF == f) return points_eval_kernel<A, k, f>;
+#define PEVAL_PCASES(k) PEVAL_PCASE(k, 1) PEVAL_PCASE(k, 2) PEVAL_PCASE(k, 3) PEVAL_PCASE(k, 4)
+  PEVAL_PCASES(1)
+  PEVAL_PCASES(2)
+  PEVAL_PCASES(4)
+  PEVAL_PCASES(8)
+  PEVAL_PCASES(16)
+#undef PEVAL_PCASES
+#undef PEVAL_PCASE
+  return nullptr;
+}
+
+constexpr size_t kPointsPartialBudget = (size_t)2 << 30;  // partial sums per launch
+constexpr size_t kPointsTablesBudget = (size_t)256 << 20;  // factor tables per launch
+
+template <class A>
+int run_points_impl(peval_poly *h, const uint64_t *points, uint32_t T, void *dev_out, hipStream_t st,
+                    uint32_t K, uint32_t C) {
+  using T_ = typename A::T;
+  const auto &m = mod_for<A>(h);
+  const size_t w = sizeof(T_);
+  const uint32_t ntail = h->n - 2;
+  const FactorPlan &fp = h->fplan;
+  Plan *pl = nullptr;
+  PEVAL_TRY(get_plan(h, K, kPointsP, &pl));
+  auto eval = points_kernel_for<A>(K, fp.nf);
+  if (!eval) return fail(PEVAL_EINVAL, "no point kernel for K=%u with %u factors", K, fp.nf);
+
+  auto it = h->pprep.find(K);
+  if (it == h->pprep.end()) {  // per-slot coefficients, quotients and entry indices
+    PointsPrep pp;
+    const uint64_t total = (uint64_t)K * pl->NT;
+    HIP_TRY(hipMalloc(&pp.pa, total * w));
+    HIP_TRY(hipMalloc(&pp.paq, total * w));
+    HIP_TRY(hipMalloc((void **)&pp.pidx, total * sizeof(uint64_t)));
+    it = h->pprep.emplace(K, pp).first;
+    ProfScope ps(st, 1);
+    points_prep_kernel<A><<<(unsigned)((total + 255) / 256), 256, 0, st>>>(
+        (const T_ *)h->d_coeff, h->d_exps, pl->d_thr_first, pl->d_thr_cnt, h->s, pl->NT, K, fp, (T_ *)pp.pa,
+        (T_ *)pp.paq, pp.pidx, m);
+    HIP_TRY(hipGetLastError());
+  }
+  const PointsPrep &pp = it->second;
+
+  uint64_t tc = std::max<uint64_t>(1, kPointsPartialBudget / std::max<uint64_t>(1, pl->nslots * w));
+  tc = std::min<uint64_t>(tc, std::max<uint64_t>(1, kPointsTablesBudget / ((uint64_t)fp.E * 2 * w)));
+  tc = std::min<uint64_t>(tc, (uint64_t)C * kCombineTile * 32768);
+  tc = std::min<uint64_t>(tc, T);
+  if (tc < T && tc > C) tc = tc / C * C;
+  PEVAL_TRY(ensure(h->ptab, (size_t)tc * fp.E * 2 * w, h));
+  PEVAL_TRY(ensure(h->partial, (size_t)((tc + C - 1) / C) * C * pl->nslots * w, h));
+  const size_t shmem = (kEvalBlock / 64) * sizeof(Stage<A, kPointsP>) + (size_t)fp.E * 2 * w;
+
+  for (uint64_t done = 0; done < T; done += tc) {
+    const uint32_t Tc = (uint32_t)std::min<uint64_t>(tc, T - done);
+    const uint32_t Cc = std::min<uint32_t>(C, Tc);
+    const uint32_t Lmax = (Tc + Cc - 1) / Cc;
+    {
+      const uint64_t total = (uint64_t)Tc * fp.E;
+      ProfScope ps(st, 0);
+      points_table_kernel<A><<<(unsigned)((total + 255) / 256), 256, 0, st>>>(
+          points + done * ntail, ntail, Tc, fp, (T_ *)h->ptab.ptr, m);
+      HIP_TRY(hipGetLastError());
+    }
+    {
+      PointsArgs<A> a;
+      a.pa = (const T_ *)pp.pa;
+      a.paq = (const T_ *)pp.paq;
+      a.pidx = pp.pidx;
+      a.tables = (const T_ *)h->ptab.ptr;
+      a.endmask = pl->d_endmask;
+      a.slot_base = pl->d_slot_base;
+      a.partial = (T_ *)h->partial.ptr;
+      a.NT = pl->NT;
+      a.NW = pl->NW;
+      a.C = Cc;
+      a.T = Tc;
+      a.Lmax = Lmax;
+      a.E = fp.E;
+      a.m = m;
+      dim3 grid((unsigned)((pl->NW + 3) / 4), Cc);
+      ProfScope ps(st, 2);
+      eval<<<grid, kEvalBlock, shmem, st>>>(a);
+      HIP_TRY(hipGetLastError());
+    }
+    {
+      CombineArgs<A> ca;
+      ca.partial = (const T_ *)h->partial.ptr;
+      ca.slot_off = pl->d_slot_off;
+      ca.out = (T_ *)dev_out + done * h->G;
+      ca.G = h->G;
+      ca.C = Cc;
+      ca.T = Tc;
+      ca.Lmax = Lmax;
+      ca.m = m;
+      dim3 grid((unsigned)((h->G + kCombineTile - 1) / kCombineTile), Cc,
+                (unsigned)((Lmax + kCombineTile - 1) / kCombineTile));
+      ProfScope ps(st, 3);
+      combine_kernel<A><<<grid, kCombineBlock, 0, st>>>(ca);
+      HIP_TRY(hipGetLastError());
+    }
+  }
+  return PEVAL_OK;
+}
+
+// Layout for the point mode: K as chosen for the power mode (explicit
+// setting, else the padding heuristic), P fixed, chains for ~8192 waves.
+Tuning points_tuning(peval_poly *h, uint32_t T) {
+  Tuning t = heuristic_tuning(h, T);
+  if (h->tune_K) t.K = h->tune_K;
+  t.P = kPointsP;
+  const uint64_t nw = (padded_threads(h, t.K) + 63) / 64;
+  t.C = h->tune_C ? h->tune_C : chains_for_waves(nw, 8192, T);
+  t.C = std::max<uint32_t>(1, std::min<uint32_t>(t.C, T));
+  return t;
+}
+
+int points_locked(peval_poly *h, const uint64_t *points_dev, uint32_t T, void *dev_out, hipStream_t st) {
+  HIP_TRY(hipSetDevice(h->device));
+  if (h->fplan_rc == 1) {
+    uint32_t maxdeg[kMaxTail] = {0};
+    for (uint32_t v = 0; v + 2 < h->n; ++v) maxdeg[v] = h->max_exp[v + 2];
+    h->fplan_rc = build_factor_plan(h->w, h->n - 2, maxdeg, &h->fplan);
+  }
+  if (h->fplan_rc != PEVAL_OK)
+    return fail(PEVAL_EUNSUPPORTED, "point mode: the tail degrees need too many factor tables");
+  if (h->have_done) HIP_TRY(hipStreamWaitEvent(st, h->done, 0));
+  const Tuning tu = points_tuning(h, T);
+  int rc = (h->w == 4) ? run_points_impl<W32>(h, points_dev, T, dev_out, st, tu.K, tu.C)
+                       : run_points_impl<W64>(h, points_dev, T, dev_out, st, tu.K, tu.C);
+  if (rc != PEVAL_OK) return rc;
+  HIP_TRY(hipEventRecord(h->done, st));
+  h->have_done = true;
+  return PEVAL_OK;
+}
+
+int check_points_args(peval_poly *h, const uint64_t *points, uint32_t T) {
+  if (!h) return fail(PEVAL_EINVAL, "null handle");
+  if (h->n > 2 && T && !points) return fail(PEVAL_EINVAL, "null points");
+  if ((uint64_t)T * h->G > (1ull << 40)) return fail(PEVAL_EUNSUPPORTED, "T*G too large");
+  return PEVAL_OK;
+}
+
+}  // namespace
+
+extern "C" int peval_run_points_async(peval_poly *h, const uint64_t *points_dev, uint32_t T, void *dev_out,
+                                      void *stream) {
+  PEVAL_TRY(check_points_args(h, points_dev, T));
+  if (T == 0 || h->G == 0) return PEVAL_OK;
+  if (!dev_out) return fail(PEVAL_EINVAL, "null output");
+  std::lock_guard<std::mutex> lk(h->mu);
+  return points_locked(h, points_dev, T, dev_out, (hipStream_t)stream);
+}
+
+extern "C" int peval_run_points(peval_poly *h, const uint64_t *points_host, uint32_t T, void *out) {
+  PEVAL_TRY(check_points_args(h, points_host, T));
+  if (T == 0 || h->G == 0) return PEVAL_OK;
+  if (!out) return fail(PEVAL_EINVAL, "null output");
+  std::lock_guard<std::mutex> lk(h->mu);
+  const size_t pbytes = (size_t)T * std::max<uint32_t>(h->n - 2, 1) * sizeof(uint64_t);
+  const size_t obytes = (size_t)T * h->G * h->w;
+  PEVAL_TRY(ensure(h->ptsbuf, pbytes, h));
+  PEVAL_TRY(ensure(h->outbuf, obytes, h));
+  if (h->n > 2)
+    HIP_TRY(hipMemcpyAsync(h->ptsbuf.ptr, points_host, pbytes, hipMemcpyHostToDevice, h->stream));
+  PEVAL_TRY(points_locked(h, (const uint64_t *)h->ptsbuf.ptr, T, h->outbuf.ptr, h->stream));
+  HIP_TRY(hipMemcpyAsync(out, h->outbuf.ptr, obytes, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  return PEVAL_OK;
+}

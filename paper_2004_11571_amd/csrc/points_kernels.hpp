@@ -1,0 +1,187 @@
+// Images at T arbitrary points (x_{t,3}, ..., x_{t,n}) instead of the powers
+// beta^t: the random evaluation points of Zippel's original method (paper,
+// Section 2.1), whose cost the paper puts at O(nT(d+s)) (Section 2.3).
+//
+// With no common ratio between points there is no recurrence m_i^t; every
+// term-evaluation forms its monomial afresh.  To keep that to a few products,
+// the tail variables are grouped into at most four "factors": a factor's table
+// holds, for one point, the products x_a^{e_a} x_b^{e_b} ... over every
+// exponent combination of its variables (a variable of large degree is first
+// split into two base-256 digits).  A term's monomial is then the product of
+// one entry per factor, and its contribution a_i * M_i(x_t) takes NF Shoup
+// products: every table entry carries its precomputed quotient, and so does
+// the coefficient (which is fixed per term).
+//
+//   points_table_kernel  factor tables for every point of the launch (HBM)
+//   points_prep_kernel   per thread slot: a_i, its quotient, packed entry
+//                        indices (once per polynomial and thread layout)
+//   points_eval_kernel   per point: the block stages the point's tables in
+//                        LDS, every thread sums its K terms; then the same
+//                        segmented walk as the power path
+//
+// The thread layout, partial-sum layout and combine are those of the power
+// path, so the images come out in the same dense T x G form.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+
+namespace peval {
+
+constexpr int kPointsP = 8;          // points per pass of the segmented walk
+constexpr int kMaxFactors = 4;
+constexpr int kMaxDigits = 2 * kMaxTail;
+constexpr uint32_t kPointsTableBytes = 32768;  // LDS for one point's tables
+
+// How a term's tail monomial is split into factor-table lookups.
+struct FactorPlan {
+  uint32_t ndig;                     // digit variables
+  uint32_t nf;                       // factors, 1..kMaxFactors
+  uint32_t E;                        // table entries per point, all factors (even)
+  uint32_t f_off[kMaxFactors + 1];   // factor f owns entries f_off[f] .. f_off[f+1]-1
+  uint8_t var[kMaxDigits];           // tail variable of the digit (0 = x3)
+  uint8_t fac[kMaxDigits];           // factor holding the digit
+  uint8_t shift[kMaxDigits];         // digit = (e >> shift) & mask
+  uint16_t mask[kMaxDigits];
+  uint16_t radix[kMaxDigits];        // digit values 0 .. radix-1
+  uint32_t stride[kMaxDigits];       // place value of the digit in its factor's index
+};
+
+template <class A>
+struct PointsArgs {
+  const typename A::T *pa;     // [K][NT] coefficients (0 for padding)
+  const typename A::T *paq;    // [K][NT] their Shoup quotients
+  const uint64_t *pidx;        // [K][NT] entry of each factor, 16 bits per factor
+  const typename A::T *tables; // [T][E][2] (value, quotient) per entry
+  const uint64_t *endmask;
+  const uint32_t *slot_base;
+  typename A::PT *partial;     // [nslots][C][Lmax]
+  uint64_t NT, NW;
+  uint32_t C, T, Lmax, E;
+  typename A::M m;
+};
+
+// One table entry for launch-local point t: the product over the factor's
+// digits of x_var^(digit << shift), with its Shoup quotient.
+template <class A>
+__global__ void points_table_kernel(const uint64_t *points, uint32_t ntail, uint32_t T, FactorPlan fp,
+                                    typename A::T *tables, typename A::M m) {
+  using T_ = typename A::T;
+  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (uint64_t)T * fp.E) return;
+  const uint32_t t = (uint32_t)(idx / fp.E);
+  const uint32_t e = (uint32_t)(idx - (uint64_t)t * fp.E);
+  T_ v = (T_)(1 % m.p);
+  if (e < fp.f_off[fp.nf]) {
+    uint32_t f = 0;
+    while (f + 1 < fp.nf && e >= fp.f_off[f + 1]) ++f;
+    const uint32_t local = e - fp.f_off[f];
+    for (uint32_t d = 0; d < fp.ndig; ++d) {
+      if (fp.fac[d] != f) continue;
+      const uint32_t digit = (local / fp.stride[d]) % fp.radix[d];
+      if (!digit) continue;
+      const T_ x = reduce64(points[(uint64_t)t * ntail + fp.var[d]], m);
+      v = mul_mod(v, pow_mod(x, (uint64_t)digit << fp.shift[d], m), m);
+    }
+  }  // entries past the last factor (padding to an even count) hold 1
+  tables[2 * idx] = v;
+  tables[2 * idx + 1] = shoup_quot(v, m);
+}
+
+// Per thread slot (k, j): coefficient, quotient and the entry index of each
+// factor; padding slots get a zero coefficient and in-range indices.
+template <class A>
+__global__ void points_prep_kernel(const typename A::T *coeff, const uint16_t *exps, const uint32_t *thr_first,
+                                   const uint8_t *thr_cnt, uint64_t s, uint64_t NT, uint32_t K, FactorPlan fp,
+                                   typename A::T *pa, typename A::T *paq, uint64_t *pidx, typename A::M m) {
+  const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (uint64_t)K * NT) return;
+  const uint32_t k = (uint32_t)(idx / NT);
+  const uint64_t j = idx - (uint64_t)k * NT;
+  uint32_t local[kMaxFactors] = {0, 0, 0, 0};
+  typename A::T a = 0, aq = 0;
+  if (k < thr_cnt[j]) {
+    const uint64_t i = (uint64_t)thr_first[j] + k;
+    a = coeff[i];
+    aq = shoup_quot(a, m);
+    for (uint32_t d = 0; d < fp.ndig; ++d) {
+      const uint32_t e = exps[(uint64_t)fp.var[d] * s + i];
+      const uint32_t digit = (e >> fp.shift[d]) & fp.mask[d];
+      const uint32_t add = digit * fp.stride[d];
+#pragma unroll
+      for (int f = 0; f < kMaxFactors; ++f)
+        if (fp.fac[d] == f) local[f] += add;
+    }
+  }
+  uint64_t packed = 0;
+#pragma unroll
+  for (int f = 0; f < kMaxFactors; ++f)
+    if ((uint32_t)f < fp.nf) packed |= (uint64_t)(fp.f_off[f] + local[f]) << (16 * f);
+  pa[idx] = a;
+  paq[idx] = aq;
+  pidx[idx] = packed;
+}
+
+template <class A, int K, int NF>
+__global__ __launch_bounds__(kEvalBlock) void points_eval_kernel(PointsArgs<A> a) {
+  using T = typename A::T;
+  constexpr int P = kPointsP;
+  extern __shared__ __align__(16) unsigned char smem[];
+  auto *stage = reinterpret_cast<Stage<A, P> *>(smem);
+  T *tab = reinterpret_cast<T *>(smem + (kEvalBlock / 64) * sizeof(Stage<A, P>));
+  const int lane = threadIdx.x & 63;
+  const int warp = threadIdx.x >> 6;
+  const uint64_t wave = (uint64_t)blockIdx.x * (kEvalBlock / 64) + warp;
+  const uint32_t c = blockIdx.y;
+  const bool active = wave < a.NW;  // idle waves still take part in the block barriers
+  const uint64_t j = wave * 64 + lane;
+
+  T av[K], aq[K];
+  uint64_t ix[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    av[k] = active ? a.pa[(uint64_t)k * a.NT + j] : 0;
+    aq[k] = active ? a.paq[(uint64_t)k * a.NT + j] : 0;
+    ix[k] = active ? a.pidx[(uint64_t)k * a.NT + j] : 0;
+  }
+  const uint64_t emask = active ? a.endmask[wave] : 0;
+  const uint32_t sbase = active ? a.slot_base[wave] : 0;
+  const uint32_t L = (c < a.T) ? (a.T - 1 - c) / a.C + 1 : 0;  // points of chain c
+  const uint32_t nvec = a.E * 2 * (uint32_t)sizeof(T) / 16;       // 16-byte pieces of one point's tables
+
+  for (uint32_t i0 = 0; i0 < L; i0 += P) {
+    const int np = (L - i0 < (uint32_t)P) ? (int)(L - i0) : P;
+#pragma unroll 1
+    for (int q = 0; q < np; ++q) {
+      const uint64_t t = (uint64_t)c + (uint64_t)(i0 + q) * a.C;
+      const uint4 *src = reinterpret_cast<const uint4 *>(a.tables + t * a.E * 2);
+      __syncthreads();  // the previous point's tables are no longer read
+      for (uint32_t u = threadIdx.x; u < nvec; u += kEvalBlock) reinterpret_cast<uint4 *>(tab)[u] = src[u];
+      __syncthreads();
+      if (active) {
+        typename A::Acc acc = A::zero();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const uint64_t x = ix[k];
+          T mv = tab[2 * (uint32_t)(x & 0xffff)];
+#pragma unroll
+          for (int f = 1; f < NF; ++f) {
+            const uint32_t e = (uint32_t)(x >> (16 * f)) & 0xffff;
+            mv = A::mul_lazy(mv, tab[2 * e], tab[2 * e + 1], a.m);
+          }
+          A::add(acc, A::mul_lazy(mv, av[k], aq[k], a.m));
+        }
+        stage[warp].put(lane, q, A::stage(acc, a.m));
+      }
+    }
+    if (active) {
+      wave_sync();
+      segmented_walk<A, P>(stage[warp], lane, np, emask, sbase, a.partial, c, a.C, a.Lmax, i0, a.m);
+      wave_sync();
+    }
+  }
+}
+
+}  // namespace peval

@@ -62,6 +62,9 @@ def lib() -> ctypes.CDLL:
         "peval_groups": ([vp, vp, vp], i32),
         "peval_run": ([vp, vp, u32, vp], i32),
         "peval_run_async": ([vp, vp, u64, u32, vp, vp], i32),
+        "peval_run_points": ([vp, vp, u32, vp], i32),
+        "peval_run_points_async": ([vp, vp, u32, vp, vp], i32),
+        "peval_points_factors": ([u32, u32, vp, vp, vp], i32),
         "peval_destroy": ([vp], i32),
         "peval_set_tuning": ([vp, u32, u32, u32], i32),
         "peval_get_tuning": ([vp, u32, vp, vp, vp], i32),
@@ -182,6 +185,27 @@ class Poly:
         b = self._beta(beta)
         _check(lib().peval_run_async(self.handle, b.ctypes.data if b.size else None, t0, T,
                                      _ptr(dev_out), _stream(stream)))
+
+    def _points(self, points):
+        pts = np.ascontiguousarray(points, dtype=np.uint64)
+        if pts.ndim != 2 or pts.shape[1] != self.n - 2:
+            raise ValueError(f"points must be (T, {self.n - 2})")
+        return pts
+
+    def run_points(self, points) -> np.ndarray:
+        """(T, G) images at the T rows of ``points`` (x3..xn each), host memory."""
+        pts = self._points(points)
+        T = pts.shape[0]
+        out = np.zeros((T, self.G), self.dtype)
+        _check(lib().peval_run_points(self.handle, pts.ctypes.data if pts.size else None, T,
+                                      out.ctypes.data if out.size else None))
+        return out
+
+    def run_points_async(self, points_dev, T: int, dev_out, stream=None):
+        """Enqueue the images at T points held in device memory (T x (n-2)
+        uint64, e.g. a torch tensor) into device memory ``dev_out``."""
+        _check(lib().peval_run_points_async(self.handle, _ptr(points_dev) or None, T, _ptr(dev_out),
+                                            _stream(stream)))
 
     def set_arith(self, mode: str = "auto"):
         """'auto' / 'int' (Shoup products) or 'fp64' (the paper's Alg. 2, 2^31 <= p < 2^50)."""
@@ -387,6 +411,15 @@ def prof_read() -> dict:
     n = (ctypes.c_uint64 * 4)()
     _check(lib().peval_prof_read(ms, n))
     return {k: (ms[i], n[i]) for i, k in enumerate(KERNEL_KINDS)}
+
+
+def points_factors(w: int, maxdeg) -> Tuple[int, int]:
+    """Host-only plan of the point mode's tables: (factors, entries per point)."""
+    d = np.ascontiguousarray(maxdeg, dtype=np.uint32)
+    nf, E = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib().peval_points_factors(w, d.size, d.ctypes.data if d.size else None, ctypes.byref(nf),
+                                      ctypes.byref(E)))
+    return nf.value, E.value
 
 
 def layout(group_sizes, K: int, P: int) -> dict:

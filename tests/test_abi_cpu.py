@@ -157,3 +157,41 @@ def test_batch_rejects_bad_arguments():
     assert L.peval_batch_create(0, None, None, 0, ctypes.byref(b)) == PV.EINVAL
     assert L.peval_batch_run(None, None, None, None, None) == PV.EINVAL
     assert L.peval_batch_destroy(None) == PV.OK
+
+
+# --- point mode: factor-table planner (host only) ---------------------------
+
+@pytest.mark.parametrize("w,maxdeg,want", [
+    (8, [20, 20, 20, 20], (2, 882)),            # 1e6-term shape: two tables of 21 x 21
+    (8, [30] * 6, (4, 1984)),                   # 1e7-term shape: 31^2, 31^2, 31, 31
+    (8, [10] * 4, (2, 242)),                    # Table 2 shape: 11^2 + 11^2
+    (4, [30] * 6, (3, 2884)),                   # 32-bit residues: twice the entries fit (3 x 961, even)
+    (8, [100, 100, 100], (3, 304)),             # 101 + 101 + 101, padded to even
+    (8, [65535], (2, 512)),                     # split into two base-256 digits
+    (8, [300], (1, 512)),                       # digits of radix 256 and 2 in one table
+    (8, [0, 0, 0], (1, 2)),                     # no tail variable occurs: one entry, 1
+    (8, [], (1, 2)),                            # n = 2
+])
+def test_points_factor_plans(w, maxdeg, want):
+    nf, E = PV.points_factors(w, maxdeg)
+    assert nf == want[0]
+    # every plan fits one point's tables in 32 KiB of LDS
+    assert E * 2 * w <= 32768 and E % 2 == 0
+    if want[1] is not None:
+        assert E == want[1]
+
+
+def test_points_factor_plan_unsupported():
+    with pytest.raises(PV.PevalError) as ei:
+        PV.points_factors(8, [10] * 30)
+    assert ei.value.code == PV.EUNSUPPORTED
+
+
+def test_points_factor_plan_bad_arguments():
+    for w, d in ((5, [3]), (8, [70000])):
+        with pytest.raises(PV.PevalError) as ei:
+            PV.points_factors(w, d)
+        assert ei.value.code == PV.EINVAL
+    L = PV.lib()
+    assert L.peval_run_points(None, None, 1, None) == PV.EINVAL
+    assert L.peval_run_points_async(None, None, 1, None, None) == PV.EINVAL
