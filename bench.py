@@ -47,6 +47,12 @@ HBM_PEAK = 8.0e12
 #   and two corrections (compare, add, 64-bit select as two 32-bit selects:
 #   4 each) = 8; the double sum (add) = 1; total 15.
 ALGO_OPS = {8: 18, 4: 6, "fp64": 15}
+# Point mode (arbitrary points): a term's contribution takes one lazy Shoup
+# product per factor table (NF - 1 for the monomial, one for the
+# coefficient) plus the lazy sum: NF * 15 + 3 ops (64-bit residues; the
+# product alone is 18 - 3 = 15), NF * 4 + 2 (32-bit residues).
+def points_ops(w: int, nf: int) -> int:
+    return nf * 15 + 3 if w == 8 else nf * 4 + 2
 # Algorithmic HBM bytes per run: resident term data read once (coefficient
 # and n-2 16-bit exponents per term) plus the dense output written once.
 
@@ -56,7 +62,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="config2", choices=["config1", "config2", "config2_p31", "config4", "paper_table2", "batch", "serve"])
+    ap.add_argument("--workload", default="config2",
+                    choices=["config1", "config2", "config2_p31", "config4", "paper_table2", "batch", "serve",
+                             "config2_points", "config2_p31_points", "paper_table2_points"])
     ap.add_argument("--rate", type=float, default=2000.0, help="served stream: mean arrivals per second")
     ap.add_argument("--duration", type=float, default=3.0, help="served stream: seconds of arrivals")
     ap.add_argument("--pool", type=int, default=20, help="served stream: polynomials (last 20%% start cold)")
@@ -74,10 +82,10 @@ def parse():
     return ap.parse_args()
 
 
-def profile_traffic(kernel_sha: str, workload: str):
+def profile_traffic(kernel_sha: str, workload: str, kernel: str = "eval_kernel"):
     """HBM bytes per launch of the evaluation kernel from the committed
     rocprofv3 counter summary, if it was taken on the current kernel source."""
-    path = os.path.join(ROOT, "profiles", f"eval_kernel_{workload}_counters.md")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
     if not os.path.exists(path):
         return None
     text = open(path).read()
@@ -90,7 +98,7 @@ def profile_traffic(kernel_sha: str, workload: str):
 
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "modarith.hpp"):
+    for f in ("kernels.hpp", "modarith.hpp", "points_kernels.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2004_11571_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -362,8 +370,10 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    points_mode = args.workload.endswith("_points")
+    base = args.workload[: -len("_points")] if points_mode else args.workload
     w = {"config1": W.config1, "config2": W.config2, "config2_p31": W.config2_p31,
-         "config4": W.config4, "paper_table2": W.paper_table2}[args.workload]()
+         "config4": W.config4, "paper_table2": W.paper_table2}[base]()
     t_gen = time.time()
     poly = PV.Poly(w.p, w.exps, w.coeffs)
     create_s = time.time() - t_gen
@@ -374,6 +384,16 @@ def main():
     dt = torch.int64 if poly.elem_bytes == 8 else torch.int32
     out = torch.empty((w.T, poly.G), dtype=dt, device=dev)
     stream = torch.cuda.current_stream(dev)
+    if points_mode:
+        pts = W.random_points(w)
+        dpts = torch.from_numpy(pts.view(np.int64)).to(dev)
+        nf, E = PV.points_factors(poly.elem_bytes, poly.info()["max_exp"][2:w.n])
+
+        def step():
+            poly.run_points_async(dpts, w.T, out, stream=stream)
+    else:
+        def step():
+            poly.run_async(w.beta, w.T, out, stream=stream)
 
     if args.calib_copy_mib:
         src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device=dev)
@@ -383,14 +403,14 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     for _ in range(args.warmup):
-        poly.run_async(w.beta, w.T, out, stream=stream)
+        step()
     torch.cuda.synchronize()
     PV.prof_read()  # drop anything recorded so far
     PV.prof_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        poly.run_async(w.beta, w.T, out, stream=stream)
+        step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     PV.prof_enable(False)
@@ -401,14 +421,22 @@ def main():
     eval_ms, eval_n = kern["eval"]
     eval_avg_s = eval_ms / max(eval_n, 1) / 1e3
     te_per_launch = te * args.steps / max(eval_n, 1)
-    ops = ALGO_OPS["fp64" if args.arith == "fp64" else poly.elem_bytes]
+    arith = poly.arith()
+    if points_mode:
+        ops = points_ops(poly.elem_bytes, nf)
+        kname = "points_eval_kernel"
+    else:
+        ops = ALGO_OPS["fp64" if arith == "fp64" else poly.elem_bytes]
+        kname = "eval_kernel"
     achieved = ops * te_per_launch / eval_avg_s
     sha = kernel_source_sha()
-    traffic = profile_traffic(sha, args.workload)
+    traffic = profile_traffic(sha, args.workload, kname)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
             "unit": "Tops/s (int32 lane-ops)", "frac": achieved / VALU_PEAK_OPS,
-            "traffic": traffic, "kernel": "eval_kernel", "ops_per_term_eval": ops,
+            "traffic": traffic, "kernel": kname, "ops_per_term_eval": ops,
             "eval_launch_ms": eval_avg_s * 1e3, "kernel_source_sha256": sha}
+    if points_mode:
+        roof["factor_tables"] = {"nf": nf, "entries_per_point": E}
 
     got = out.cpu().numpy().view(poly.dtype)
     res = {
@@ -421,8 +449,11 @@ def main():
         "vs_baseline": (value / (5e9 / 1.411)) if args.workload == "paper_table2" else None,
         "dtype": "u64" if poly.elem_bytes == 8 else "u32",
         "data": "synthetic",
-        "config": {"workload": w.name, "n": w.n, "s": w.s, "T": w.T, "p": w.p, "G": poly.G,
-                   "tuning": {"K": K, "P": P, "C": C}, "arith": args.arith},
+        "config": {"workload": w.name + ("_random_points" if points_mode else ""), "n": w.n, "s": w.s,
+                   "T": w.T, "p": w.p, "G": poly.G,
+                   "tuning": {"K": K, "P": 8 if points_mode else P, "C": C},
+                   "arith": "int" if points_mode else arith,
+                   "points": "uniform random in [1,p)^(n-2)" if points_mode else "powers of one base point"},
         "roofline": roof,
         "kernels_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in kern.items()},
         "create_s": create_s,
@@ -434,12 +465,15 @@ def main():
         rows = args.cpu_rows
         threads = min(args.cpu_threads, rows)
         c0 = time.perf_counter()
-        ref = orc.evaluate(w.p, w.exps, w.coeffs, w.beta, rows, t0=1, threads=threads)
+        if points_mode:
+            ref = orc.evaluate_points(w.p, w.exps, w.coeffs, pts[:rows], threads=threads)
+        else:
+            ref = orc.evaluate(w.p, w.exps, w.coeffs, w.beta, rows, t0=1, threads=threads)
         csec = time.perf_counter() - c0
         res["cpu_baseline"] = {"value": w.s * rows / csec, "unit": "term-evals/s", "cores": threads,
                                "kind": "oracle", "seconds": csec,
-                               "sample": f"images b_1..b_{rows} of the same polynomial (all {w.s} terms), "
-                                         f"{threads} threads over t"}
+                               "sample": f"the first {rows} images of the same polynomial (all {w.s} terms), "
+                                         f"{threads} threads over the points"}
         res["parity_sample"] = bool(np.array_equal(got[:rows].astype(np.uint64), ref))
     poly.destroy()
     print(json.dumps(res), flush=True)

@@ -174,6 +174,10 @@ int peval_set_tuning(peval_poly *h, uint32_t K, uint32_t P, uint32_t C);
 #define PEVAL_ARITH_FP64 2u
 int peval_set_arith(peval_poly *h, uint32_t mode);
 
+/* The product the power-mode evaluation kernel of this handle uses now:
+ * *mode = PEVAL_ARITH_INT or PEVAL_ARITH_FP64 (AUTO resolved). */
+int peval_get_arith(const peval_poly *h, uint32_t *mode);
+
 /* The tuning the next run with T evaluations would use. */
 int peval_get_tuning(peval_poly *h, uint32_t T, uint32_t *K, uint32_t *P, uint32_t *C);
 

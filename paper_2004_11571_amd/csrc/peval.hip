@@ -531,6 +531,12 @@ extern "C" int peval_set_arith(peval_poly *h, uint32_t mode) {
   return PEVAL_OK;
 }
 
+extern "C" int peval_get_arith(const peval_poly *h, uint32_t *mode) {
+  if (!h || !mode) return fail(PEVAL_EINVAL, "null argument");
+  *mode = h->arith == 1 ? PEVAL_ARITH_FP64 : PEVAL_ARITH_INT;
+  return PEVAL_OK;
+}
+
 extern "C" int peval_get_tuning(peval_poly *h, uint32_t T, uint32_t *K, uint32_t *P, uint32_t *C) {
   if (!h || !K || !P || !C) return fail(PEVAL_EINVAL, "null argument");
   std::lock_guard<std::mutex> lk(h->mu);

@@ -49,11 +49,28 @@ struct FactorPlan {
   uint32_t stride[kMaxDigits];       // place value of the digit in its factor's index
 };
 
+// One (value, quotient) table entry at byte offset off, read with a single
+// 8- or 16-byte LDS load.
+__device__ __forceinline__ void load_entry(const uint32_t *tab, uint32_t off, uint32_t &v, uint32_t &q) {
+  const uint2 x = *reinterpret_cast<const uint2 *>(reinterpret_cast<const unsigned char *>(tab) + off);
+  v = x.x;
+  q = x.y;
+}
+__device__ __forceinline__ void load_entry(const uint64_t *tab, uint32_t off, uint64_t &v, uint64_t &q) {
+  const uint4 x = *reinterpret_cast<const uint4 *>(reinterpret_cast<const unsigned char *>(tab) + off);
+  v = ((uint64_t)x.y << 32) | x.x;
+  q = ((uint64_t)x.w << 32) | x.z;
+}
+template <class T>
+__device__ __forceinline__ T load_value(const T *tab, uint32_t off) {
+  return *reinterpret_cast<const T *>(reinterpret_cast<const unsigned char *>(tab) + off);
+}
+
 template <class A>
 struct PointsArgs {
   const typename A::T *pa;     // [K][NT] coefficients (0 for padding)
   const typename A::T *paq;    // [K][NT] their Shoup quotients
-  const uint64_t *pidx;        // [K][NT] entry of each factor, 16 bits per factor
+  const uint64_t *pidx;        // [K][NT] byte offset of each factor's entry, 16 bits per factor
   const typename A::T *tables; // [T][E][2] (value, quotient) per entry
   const uint64_t *endmask;
   const uint32_t *slot_base;
@@ -115,10 +132,13 @@ __global__ void points_prep_kernel(const typename A::T *coeff, const uint16_t *e
         if (fp.fac[d] == f) local[f] += add;
     }
   }
+  // byte offsets of the (value, quotient) entries in one point's tables
+  // (entries of 2 * sizeof(T) bytes; every offset is below 32 KiB)
   uint64_t packed = 0;
 #pragma unroll
   for (int f = 0; f < kMaxFactors; ++f)
-    if ((uint32_t)f < fp.nf) packed |= (uint64_t)(fp.f_off[f] + local[f]) << (16 * f);
+    if ((uint32_t)f < fp.nf)
+      packed |= (uint64_t)((fp.f_off[f] + local[f]) * 2 * (uint32_t)sizeof(typename A::T)) << (16 * f);
   pa[idx] = a;
   paq[idx] = aq;
   pidx[idx] = packed;
@@ -165,11 +185,12 @@ __global__ __launch_bounds__(kEvalBlock) void points_eval_kernel(PointsArgs<A> a
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           const uint64_t x = ix[k];
-          T mv = tab[2 * (uint32_t)(x & 0xffff)];
+          T mv = load_value(tab, (uint32_t)x & 0xffff);
 #pragma unroll
           for (int f = 1; f < NF; ++f) {
-            const uint32_t e = (uint32_t)(x >> (16 * f)) & 0xffff;
-            mv = A::mul_lazy(mv, tab[2 * e], tab[2 * e + 1], a.m);
+            T tv, tq;
+            load_entry(tab, (uint32_t)(x >> (16 * f)) & 0xffff, tv, tq);
+            mv = A::mul_lazy(mv, tv, tq, a.m);
           }
           A::add(acc, A::mul_lazy(mv, av[k], aq[k], a.m));
         }

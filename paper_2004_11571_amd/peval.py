@@ -73,6 +73,7 @@ def lib() -> ctypes.CDLL:
         "peval_layout": ([vp, u64, u32, u32, vp, vp, vp, vp, vp, vp], i32),
         "peval_autotune": ([vp, vp, u32, u32, vp, vp, vp, vp], i32),
         "peval_set_arith": ([vp, u32], i32),
+        "peval_get_arith": ([vp, vp], i32),
         "peval_server_create": ([u64, u32, ctypes.POINTER(vp)], i32),
         "peval_server_configure": ([vp, ctypes.c_double, ctypes.c_double, u32, ctypes.c_double], i32),
         "peval_server_add_poly": ([vp, u64, u32, u64, vp, vp, ctypes.POINTER(u64)], i32),
@@ -210,6 +211,12 @@ class Poly:
     def set_arith(self, mode: str = "auto"):
         """'auto' / 'int' (Shoup products) or 'fp64' (the paper's Alg. 2, 2^31 <= p < 2^50)."""
         _check(lib().peval_set_arith(self.handle, {"auto": 0, "int": 1, "fp64": 2}[mode]))
+
+    def arith(self) -> str:
+        """The product the evaluation kernel uses now: 'int' or 'fp64'."""
+        m = ctypes.c_uint32()
+        _check(lib().peval_get_arith(self.handle, ctypes.byref(m)))
+        return "fp64" if m.value == 2 else "int"
 
     def set_tuning(self, K: int = 0, P: int = 0, C: int = 0):
         _check(lib().peval_set_tuning(self.handle, K, P, C))

@@ -215,6 +215,14 @@ def batch_config(count: int = 256, instance: int = 0, s_max: float = 1e6,
     return polys
 
 
+def random_points(poly: Poly, T: int = 0, instance: int = 0) -> np.ndarray:
+    """T points (x3..xn) drawn uniformly from [1, p)^(n-2), for the point
+    mode (Zippel's random points, Section 2.1); T defaults to poly.T."""
+    rng = np.random.default_rng(config_seed(7, instance))
+    T = T or poly.T
+    return rng.integers(1, poly.p, size=(T, poly.n - 2), dtype=np.uint64)
+
+
 @dataclasses.dataclass
 class Request:
     arrival_s: float
