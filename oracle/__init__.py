@@ -11,7 +11,9 @@ bivariate images (paper, Section 2.1 and Section 2.3, Eq. (1)):
 
 with groups = distinct (x1, x2) exponent pairs in descending lexicographic
 order, and the same images at T arbitrary points x_t in place of beta^t
-(``evaluate_points``).  Parity status of each function is recorded in the test suite's pins
+(``evaluate_points``), and the inverse step: the coefficients recovered
+from the images by solving each group's Vandermonde system
+(``interpolate``).  Parity status of each function is recorded in the test suite's pins
 (tests/test_oracle_pins.py).
 """
 from __future__ import annotations
@@ -48,7 +50,13 @@ def load(path: str = _LIB) -> ctypes.CDLL:
     lib.oracle_entry.restype = u64
     lib.oracle_eval_points.argtypes = [u64, u32, u64, ptr, ptr, ptr, u64, ptr, u32]
     lib.oracle_eval_points.restype = ctypes.c_int
+    lib.oracle_interpolate.argtypes = [u64, u32, u64, ptr, ptr, u64, ptr, ptr]
+    lib.oracle_interpolate.restype = ctypes.c_int
     return lib
+
+
+class SingularError(ArithmeticError):
+    pass
 
 
 class Oracle:
@@ -114,6 +122,26 @@ class Oracle:
                                              points.ctypes.data, T, out.ctypes.data, threads)
             if rc != 0:
                 raise RuntimeError(f"oracle_eval_points failed ({rc})")
+        return out
+
+    def interpolate(self, p, exps, beta, images):
+        """Coefficients (s,) uint64 of the support ``exps`` from the images
+        b_1..b_T (a (T, G) array in the column order of ``groups``), solving
+        each group's Vandermonde system by elimination.  Raises
+        ``SingularError`` when a group's system is singular."""
+        exps = np.ascontiguousarray(exps, dtype=np.uint32)
+        s, n = exps.shape
+        beta = np.ascontiguousarray(beta, dtype=np.uint64)
+        images = np.ascontiguousarray(images, dtype=np.uint64)
+        if beta.shape != (n - 2,) or images.ndim != 2:
+            raise ValueError("shape mismatch")
+        out = np.zeros(s, np.uint64)
+        rc = self.lib.oracle_interpolate(p, n, s, exps.ctypes.data, beta.ctypes.data, images.shape[0],
+                                         images.ctypes.data, out.ctypes.data)
+        if rc == -3:
+            raise SingularError("a group's Vandermonde system is singular")
+        if rc != 0:
+            raise RuntimeError(f"oracle_interpolate failed ({rc})")
         return out
 
     def entry(self, p, exps, coeffs, beta, t, d, e):

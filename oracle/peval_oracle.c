@@ -277,3 +277,121 @@ uint64_t oracle_entry(uint64_t p, uint32_t n, uint64_t s, const uint32_t *exps,
     }
     return acc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Sparse interpolation from the images (the step that follows the          */
+/* evaluations in Zippel's method, Section 2.1)                             */
+/* ------------------------------------------------------------------------ */
+
+/* inverse of a modulo p by the extended Euclidean algorithm; 0 if none */
+static uint64_t invmod(uint64_t a, uint64_t p)
+{
+    __int128 r0 = (__int128)p, r1 = (__int128)(a % p), s0 = 0, s1 = 1;
+    while (r1 != 0) {
+        __int128 q = r0 / r1, t;
+        t = r0 - q * r1; r0 = r1; r1 = t;
+        t = s0 - q * s1; s0 = s1; s1 = t;
+    }
+    if (r0 != 1) return 0;
+    s0 %= (__int128)p;
+    if (s0 < 0) s0 += p;
+    return (uint64_t)s0;
+}
+
+/*
+ * Solve V a = c over F_p by Gauss-Jordan elimination with row pivoting,
+ * where V is the m x m matrix (row-major) and c has m entries; the solution
+ * overwrites c.  Returns 0, or -3 if V is singular modulo p.
+ */
+static int gauss_solve(uint64_t *V, uint64_t *c, uint64_t m, uint64_t p)
+{
+    for (uint64_t col = 0; col < m; ++col) {
+        uint64_t piv = col;
+        while (piv < m && V[piv * m + col] == 0) ++piv;
+        if (piv == m) return -3;
+        if (piv != col) {
+            for (uint64_t j = 0; j < m; ++j) {
+                uint64_t t = V[col * m + j]; V[col * m + j] = V[piv * m + j]; V[piv * m + j] = t;
+            }
+            uint64_t t = c[col]; c[col] = c[piv]; c[piv] = t;
+        }
+        uint64_t inv = invmod(V[col * m + col], p);
+        if (inv == 0) return -3;
+        for (uint64_t j = 0; j < m; ++j) V[col * m + j] = mulmod(V[col * m + j], inv, p);
+        c[col] = mulmod(c[col], inv, p);
+        for (uint64_t r = 0; r < m; ++r) {
+            if (r == col || V[r * m + col] == 0) continue;
+            uint64_t f = V[r * m + col];
+            for (uint64_t j = 0; j < m; ++j)
+                V[r * m + j] = addmod(V[r * m + j], p - mulmod(f, V[col * m + j], p), p);
+            c[r] = addmod(c[r], p - mulmod(f, c[col], p), p);
+        }
+    }
+    return 0;
+}
+
+/*
+ * Coefficients from the images.  Given the support of f (exponent rows), the
+ * base point beta and the images b_1..b_T in the dense layout of oracle_eval
+ * (T rows of G columns), find the coefficients a_i: for every group (d, e)
+ * with terms i_1..i_m, the coefficient of x1^d x2^e in b_t is
+ *
+ *   c_t = sum_j a_{i_j} m_{i_j}^t,   m_i = prod_{k=3..n} beta_k^{g_ik},
+ *
+ * so the a's of the group solve the m x m system V a = c with
+ * V[t-1][j] = m_{i_j}^t, t = 1..m (a transposed Vandermonde system scaled by
+ * the m's; Section 2.1).  This is the plain definition solved by elimination,
+ * O(m^3) per group; only the first m rows of the group's column are used.
+ *
+ * coeffs_out: s values, in the order of the input rows (duplicate rows of
+ * the support are not allowed: their monomial values coincide).  Returns 0;
+ * -1 on allocation failure; -2 on invalid arguments or T smaller than the
+ * largest group; -3 if some group's system is singular (two of its terms
+ * share a monomial value, or a monomial value is 0 or not invertible).
+ */
+int oracle_interpolate(uint64_t p, uint32_t n, uint64_t s, const uint32_t *exps,
+                       const uint64_t *beta, uint64_t T, const uint64_t *images,
+                       uint64_t *coeffs_out)
+{
+    if (p < 2 || n < 2) return -2;
+    int rc = -1;
+    uint32_t *gd = (uint32_t *)malloc((s ? s : 1) * sizeof(uint32_t));
+    uint32_t *ge = (uint32_t *)malloc((s ? s : 1) * sizeof(uint32_t));
+    uint64_t *gk = (uint64_t *)malloc((s ? s : 1) * sizeof(uint64_t));
+    uint64_t *gid = (uint64_t *)malloc((s ? s : 1) * sizeof(uint64_t));
+    uint64_t *mono = (uint64_t *)malloc((s ? s : 1) * sizeof(uint64_t));
+    uint64_t *members = (uint64_t *)malloc((s ? s : 1) * sizeof(uint64_t));
+    uint64_t *V = NULL, *c = NULL;
+    uint64_t G = 0;
+    if (!gd || !ge || !gk || !gid || !mono || !members) goto done;
+    if (oracle_groups(s, n, exps, gd, ge, &G) != 0) goto done;
+    for (uint64_t g = 0; g < G; ++g) gk[g] = ((uint64_t)gd[g] << 32) | ge[g];
+    for (uint64_t i = 0; i < s; ++i) {
+        const uint32_t *r = exps + i * n;
+        gid[i] = find_group(gk, G, group_key(r));
+        uint64_t v = 1 % p;
+        for (uint32_t k = 2; k < n; ++k) v = mulmod(v, powmod(beta[k - 2] % p, r[k], p), p);
+        mono[i] = v;
+    }
+    rc = 0;
+    for (uint64_t g = 0; g < G && rc == 0; ++g) {
+        uint64_t m = 0;
+        for (uint64_t i = 0; i < s; ++i) if (gid[i] == g) members[m++] = i;
+        if (m > T) { rc = -2; break; }
+        V = (uint64_t *)malloc(m * m * sizeof(uint64_t));
+        c = (uint64_t *)malloc(m * sizeof(uint64_t));
+        if (!V || !c) { rc = -1; break; }
+        for (uint64_t t = 1; t <= m; ++t) {
+            for (uint64_t j = 0; j < m; ++j) V[(t - 1) * m + j] = powmod(mono[members[j]], t, p);
+            c[t - 1] = images[(t - 1) * G + g] % p;
+        }
+        rc = gauss_solve(V, c, m, p);
+        if (rc == 0)
+            for (uint64_t j = 0; j < m; ++j) coeffs_out[members[j]] = c[j];
+        free(V); free(c); V = NULL; c = NULL;
+    }
+done:
+    free(V); free(c);
+    free(gd); free(ge); free(gk); free(gid); free(mono); free(members);
+    return rc;
+}

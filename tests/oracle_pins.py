@@ -43,6 +43,16 @@ Arbitrary points (the random points of Zippel's method, Section 2.1):
   of the power mode (each side pinned on its own above).
 * ``pin_points_zero_and_linearity``: at x = 0 only terms without tail
   variables survive; images are linear in the coefficients.
+
+Interpolation (coefficients back from the images, Section 2.1):
+
+* ``pin_interp_round_trip``: images from the (separately pinned) evaluation
+  give back the coefficients, for several primes and shapes.
+* ``pin_interp_exhaustive``: for p = 7 and a group of three terms, every one
+  of the 7^3 coefficient vectors comes back (the map is a bijection).
+* ``pin_interp_closed_forms``: a one-term group gives c_1 / m; extra image
+  rows beyond the group size do not matter; a group with two equal monomial
+  values is reported singular.
 """
 from __future__ import annotations
 
@@ -428,7 +438,86 @@ def pin_points_zero_and_linearity(orc, seed=24):
     assert np.array_equal(om, (o1 * k + o2) % p)
 
 
+# ---------------------------------------------------------------------------
+# Interpolation
+# ---------------------------------------------------------------------------
+
+def _distinct_support(rng, p, n, s, dmax, d12=3):
+    exps = W.draw_exponents(rng, s, n, d12, dmax, per_var=True)
+    return exps
+
+
+def pin_interp_round_trip(orc, seed=31):
+    rng = np.random.default_rng(seed)
+    for p, n, s in ((W.P63, 5, 300), (W.P50, 6, 200), (W.P31, 4, 150), (1000003, 3, 60), (101, 4, 12)):
+        exps = _distinct_support(rng, p, n, s, 6 if n > 3 else 40)
+        coeffs = rng.integers(0, p, size=s, dtype=np.uint64)
+        T = s  # more rows than any group needs
+        for attempt in range(20):
+            beta = rng.integers(1, p, size=n - 2, dtype=np.uint64)
+            images = orc.evaluate(p, exps, coeffs, beta, T)
+            try:
+                got = orc.interpolate(p, exps, beta, images)
+            except Exception:        # an unlucky beta (equal monomial values) for tiny p
+                if p > 10**6:
+                    raise
+                continue
+            assert np.array_equal(got, coeffs % np.uint64(p)), (p, n, s)
+            break
+        else:
+            raise AssertionError(f"no usable beta for p={p}")
+
+
+def pin_interp_exhaustive(orc, p=7):
+    exps = np.asarray([[1, 0, 1, 0], [1, 0, 0, 1], [1, 0, 2, 2]], np.uint32)
+    beta = np.asarray([2, 3], np.uint64)       # monomial values 2, 3, 36 = 1 mod 7: distinct
+    seen = set()
+    for a in itertools.product(range(p), repeat=3):
+        coeffs = np.asarray(a, np.uint64)
+        images = orc.evaluate(p, exps, coeffs, beta, 3)
+        got = tuple(int(x) for x in orc.interpolate(p, exps, beta, images))
+        assert got == a, (a, got)
+        seen.add(tuple(int(x) for x in images[:, 0]))
+    assert len(seen) == p ** 3                 # distinct coefficient vectors give distinct images
+
+
+def pin_interp_closed_forms(orc, seed=32):
+    import oracle as O
+    rng = np.random.default_rng(seed)
+    p = W.P63
+    exps = np.asarray([[2, 1, 3, 1], [0, 0, 2, 5]], np.uint32)     # two one-term groups
+    beta = rng.integers(2, p, size=2, dtype=np.uint64)
+    images = rng.integers(0, p, size=(4, 2), dtype=np.uint64)       # any values are consistent
+    gd, ge = orc.groups(exps)
+    got = orc.interpolate(p, exps, beta, images)
+    for i, row in enumerate(exps.tolist()):
+        g = [j for j in range(len(gd)) if (int(gd[j]), int(ge[j])) == (row[0], row[1])][0]
+        m = pow(int(beta[0]), row[2], p) * pow(int(beta[1]), row[3], p) % p
+        assert int(got[i]) == int(images[0, g]) * pow(m, p - 2, p) % p
+    # rows past the largest group are not used
+    exps = _distinct_support(rng, p, 5, 120, 5)
+    coeffs = rng.integers(0, p, size=120, dtype=np.uint64)
+    beta = rng.integers(1, p, size=3, dtype=np.uint64)
+    images = orc.evaluate(p, exps, coeffs, beta, 200)
+    sizes = {}
+    for row in exps.tolist():
+        sizes[(row[0], row[1])] = sizes.get((row[0], row[1]), 0) + 1
+    mx = max(sizes.values())
+    noisy = images.copy()
+    noisy[mx:] = rng.integers(0, p, size=noisy[mx:].shape, dtype=np.uint64)
+    assert np.array_equal(orc.interpolate(p, exps, beta, noisy), coeffs)
+    # beta_3 = 1 makes terms that differ only in x3 share a monomial value
+    exps = np.asarray([[1, 1, 0, 2], [1, 1, 3, 2]], np.uint32)
+    try:
+        orc.interpolate(p, exps, np.asarray([1, 5], np.uint64), np.ones((2, 1), np.uint64))
+    except O.SingularError:
+        pass
+    else:
+        raise AssertionError("singular system not reported")
+
+
 ALL_PINS = [pin_full_point_bigint, pin_small_prime_exhaustive, pin_closed_forms,
             pin_linearity, pin_power_consistency, pin_group_order, pin_gcd_example,
             pin_points_full_point_bigint, pin_points_character_sums, pin_points_match_powers,
-            pin_points_zero_and_linearity]
+            pin_points_zero_and_linearity, pin_interp_round_trip, pin_interp_exhaustive,
+            pin_interp_closed_forms]

@@ -53,6 +53,15 @@ MUTANTS = {
     "points_ignored": (
         "        if (j->points) {",
         "        if (0) {"),
+    "interp_rows_from_t0": (
+        "for (uint64_t j = 0; j < m; ++j) V[(t - 1) * m + j] = powmod(mono[members[j]], t, p);",
+        "for (uint64_t j = 0; j < m; ++j) V[(t - 1) * m + j] = powmod(mono[members[j]], t - 1, p);"),
+    "interp_wrong_column": (
+        "c[t - 1] = images[(t - 1) * G + g] % p;",
+        "c[t - 1] = images[(t - 1) * G + (g + 1) % G] % p;"),
+    "interp_no_back_substitution": (
+        "if (r == col || V[r * m + col] == 0) continue;",
+        "if (r <= col || V[r * m + col] == 0) continue;"),
     "powmod_zero_exponent": (
         "uint64_t r = 1 % p;",
         "uint64_t r = base % p;"),
@@ -71,7 +80,8 @@ pins = [lambda o: P.pin_full_point_bigint(o, cases=14),
         P.pin_closed_forms, P.pin_linearity, P.pin_power_consistency,
         P.pin_group_order, P.pin_gcd_example,
         lambda o: P.pin_points_full_point_bigint(o, cases=10), P.pin_points_character_sums,
-        P.pin_points_match_powers, P.pin_points_zero_and_linearity]
+        P.pin_points_match_powers, P.pin_points_zero_and_linearity,
+        P.pin_interp_round_trip, P.pin_interp_exhaustive, P.pin_interp_closed_forms]
 caught = 0
 for pin in pins:
     try:
