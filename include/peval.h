@@ -50,7 +50,8 @@ enum {
     PEVAL_EDEVICE = -3,       /* HIP runtime or kernel error */
     PEVAL_EUNSUPPORTED = -4,  /* valid input outside what this build supports */
     PEVAL_EBUSY = -5,         /* resource temporarily unavailable (server) */
-    PEVAL_ETIMEOUT = -6       /* wait ended before completion */
+    PEVAL_ETIMEOUT = -6,      /* wait ended before completion */
+    PEVAL_ESINGULAR = -7      /* interpolation: a group's system has no unique solution */
 };
 
 typedef struct peval_poly peval_poly;
@@ -146,6 +147,33 @@ int peval_run_points_async(peval_poly *h, const uint64_t *points, uint32_t T, vo
  * and table entries per point E.  PEVAL_EUNSUPPORTED if no plan fits.
  */
 int peval_points_factors(uint32_t w, uint32_t ntail, const uint32_t *maxdeg, uint32_t *nf, uint32_t *E);
+
+/*
+ * Coefficients back from the images: the sparse interpolation step that
+ * follows the evaluations in Zippel's method (paper, Section 2.1).  Because
+ * the images are taken at the powers beta^t, each (d, e) group's linear
+ * system is a transposed Vandermonde system, solved here in O(m^2)
+ * operations for a group of m terms.
+ *
+ * h       a handle whose exponent rows are the support of the polynomial to
+ *         recover (its coefficients are not used; zeros are fine).  The
+ *         rows must be distinct and p prime.
+ * beta    the base point the images were taken at (n-2 values).
+ * images  b_1..b_T in the dense layout of peval_run (T rows of G residues
+ *         of elem_bytes); T must be at least the largest group's term
+ *         count, and only that many rows are read.  Host memory for
+ *         peval_interpolate, device memory for peval_interpolate_async.
+ * coeffs  s uint64 coefficients, canonical, in the order of the rows given
+ *         to peval_create (host / device).
+ * Groups of more than 8191 terms give PEVAL_EUNSUPPORTED.  A group whose
+ * system is singular (two of its terms with equal monomial values at beta,
+ * a zero monomial value, or p not prime) gives PEVAL_ESINGULAR from
+ * peval_interpolate; peval_interpolate_async writes 0 or 1 to *dev_status
+ * (a device int32) instead, and 0 to the affected coefficients.
+ */
+int peval_interpolate(peval_poly *h, const uint64_t *beta, uint32_t T, const void *images, uint64_t *coeffs);
+int peval_interpolate_async(peval_poly *h, const uint64_t *beta, uint32_t T, const void *dev_images,
+                            uint64_t *dev_coeffs, int32_t *dev_status, void *stream);
 
 /* Release the handle and its device memory (waits for its pending work).
  * NULL is accepted. */

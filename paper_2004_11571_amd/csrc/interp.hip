@@ -1,0 +1,166 @@
+// Coefficients back from the images (Zippel's sparse interpolation with a
+// known support, paper Section 2.1).  Kernels in interp_kernels.hpp.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <numeric>
+
+#include "errors.hpp"
+#include "interp_kernels.hpp"
+#include "peval.h"
+#include "peval_internal.hpp"
+
+using namespace peval;
+
+namespace {
+
+__global__ void interp_status_reset(int32_t *status) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) status[0] = 0;
+}
+
+template <class A>
+const typename A::M &mod_for(const peval_poly *h);
+template <>
+const Mod64 &mod_for<W64>(const peval_poly *h) { return h->m64; }
+template <>
+const Mod32 &mod_for<W32>(const peval_poly *h) { return h->m32; }
+
+// Device copies of the sort order and group structure (first call only).
+int interp_setup(peval_poly *h) {
+  if (h->d_order) return PEVAL_OK;
+  std::vector<uint32_t> off32(h->G + 1), gord(h->G);
+  for (uint64_t g = 0; g <= h->G; ++g) off32[g] = (uint32_t)h->grp_off[g];
+  std::iota(gord.begin(), gord.end(), 0u);
+  std::stable_sort(gord.begin(), gord.end(), [&](uint32_t x, uint32_t y) {
+    return h->grp_off[x + 1] - h->grp_off[x] > h->grp_off[y + 1] - h->grp_off[y];
+  });
+  HIP_TRY(hipMalloc((void **)&h->d_order, std::max<size_t>(h->order.size(), 1) * 4));
+  HIP_TRY(hipMalloc((void **)&h->d_grp_off32, off32.size() * 4));
+  HIP_TRY(hipMalloc((void **)&h->d_gorder, std::max<size_t>(gord.size(), 1) * 4));
+  HIP_TRY(hipMemcpy(h->d_order, h->order.data(), h->order.size() * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->d_grp_off32, off32.data(), off32.size() * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->d_gorder, gord.data(), gord.size() * 4, hipMemcpyHostToDevice));
+  return PEVAL_OK;
+}
+
+uint64_t largest_group(const peval_poly *h) {
+  uint64_t mx = 0;
+  for (uint64_t g = 0; g < h->G; ++g) mx = std::max<uint64_t>(mx, h->grp_off[g + 1] - h->grp_off[g]);
+  return mx;
+}
+
+template <class A>
+int interp_impl(peval_poly *h, const BetaArg &beta, const void *images, uint64_t *out, int32_t *status,
+                hipStream_t st) {
+  using T_ = typename A::T;
+  const auto &m = mod_for<A>(h);
+  const size_t w = sizeof(T_);
+  const uint32_t ntail = h->n - 2;
+  PEVAL_TRY(interp_setup(h));
+  PEVAL_TRY(ensure(h->tabval, (size_t)std::max<uint32_t>(h->tab_total, 1) * w, h));
+  PEVAL_TRY(ensure(h->tabquot, (size_t)std::max<uint32_t>(h->tab_total, 1) * w, h));
+  PEVAL_TRY(ensure(h->iscr, (size_t)5 * h->s * w, h));
+  interp_status_reset<<<1, 64, 0, st>>>(status);
+  HIP_TRY(hipGetLastError());
+  if (ntail) {
+    ProfScope ps(st, 0);
+    power_table_kernel<A><<<(h->tab_total + 255) / 256, 256, 0, st>>>(beta, h->tab, ntail, h->tab_total,
+                                                                      (T_ *)h->tabval.ptr, (T_ *)h->tabquot.ptr, m);
+    HIP_TRY(hipGetLastError());
+  }
+  InterpArgs<A> a;
+  T_ *scr = (T_ *)h->iscr.ptr;
+  a.images = (const T_ *)images;
+  a.tval = (const T_ *)h->tabval.ptr;
+  a.tquot = (const T_ *)h->tabquot.ptr;
+  a.to = h->tab;
+  a.exps = h->d_exps;
+  a.grp_off = h->d_grp_off32;
+  a.gorder = h->d_gorder;
+  a.order = h->d_order;
+  a.mval = scr;
+  a.mquot = scr + h->s;
+  a.cval = scr + 2 * h->s;
+  a.cquot = scr + 3 * h->s;
+  a.bval = scr + 4 * h->s;
+  a.out = out;
+  a.status = status;
+  a.s = h->s;
+  a.G = h->G;
+  a.ntail = ntail;
+  a.m = m;
+  {
+    ProfScope ps(st, 1);
+    interp_prep_kernel<A><<<(unsigned)((h->s + 255) / 256), 256, 0, st>>>(a);
+    HIP_TRY(hipGetLastError());
+  }
+  {
+    const size_t shmem = (largest_group(h) + 1) * w;
+    ProfScope ps(st, 2);
+    interp_group_kernel<A><<<(unsigned)h->G, kInterpBlock, shmem, st>>>(a);
+    HIP_TRY(hipGetLastError());
+  }
+  return PEVAL_OK;
+}
+
+int check_interp(peval_poly *h, const uint64_t *beta, uint32_t T, const void *images, const void *out,
+                 BetaArg *ba) {
+  if (!h) return fail(PEVAL_EINVAL, "null handle");
+  if (h->n > 2 && !beta) return fail(PEVAL_EINVAL, "null beta");
+  if (h->s && (!images || !out)) return fail(PEVAL_EINVAL, "null images or output");
+  const uint64_t mx = largest_group(h);
+  if (T < mx) return fail(PEVAL_EINVAL, "T = %u images, the largest group has %llu terms", T, (unsigned long long)mx);
+  if (mx > kInterpMaxGroup)
+    return fail(PEVAL_EUNSUPPORTED, "a group of %llu terms (at most %u)", (unsigned long long)mx, kInterpMaxGroup);
+  memset(ba, 0, sizeof *ba);
+  for (uint32_t k = 0; k + 2 < h->n; ++k) ba->b[k] = beta[k] % h->p;
+  return PEVAL_OK;
+}
+
+int interp_locked(peval_poly *h, const BetaArg &ba, const void *images, uint64_t *out, int32_t *status,
+                  hipStream_t st) {
+  HIP_TRY(hipSetDevice(h->device));
+  if (h->have_done) HIP_TRY(hipStreamWaitEvent(st, h->done, 0));
+  int rc = (h->w == 4) ? interp_impl<W32>(h, ba, images, out, status, st)
+                       : interp_impl<W64>(h, ba, images, out, status, st);
+  if (rc != PEVAL_OK) return rc;
+  HIP_TRY(hipEventRecord(h->done, st));
+  h->have_done = true;
+  return PEVAL_OK;
+}
+
+}  // namespace
+
+extern "C" int peval_interpolate_async(peval_poly *h, const uint64_t *beta, uint32_t T, const void *dev_images,
+                                       uint64_t *dev_coeffs, int32_t *dev_status, void *stream) {
+  BetaArg ba;
+  PEVAL_TRY(check_interp(h, beta, T, dev_images, dev_coeffs, &ba));
+  if (!dev_status) return fail(PEVAL_EINVAL, "null status");
+  if (h->s == 0) return PEVAL_OK;
+  std::lock_guard<std::mutex> lk(h->mu);
+  return interp_locked(h, ba, dev_images, dev_coeffs, dev_status, (hipStream_t)stream);
+}
+
+extern "C" int peval_interpolate(peval_poly *h, const uint64_t *beta, uint32_t T, const void *images,
+                                 uint64_t *coeffs) {
+  BetaArg ba;
+  PEVAL_TRY(check_interp(h, beta, T, images, coeffs, &ba));
+  if (h->s == 0) return PEVAL_OK;
+  std::lock_guard<std::mutex> lk(h->mu);
+  // only the first (largest group) rows of the images are read
+  const uint64_t rows = largest_group(h);
+  const size_t ibytes = ((size_t)rows * h->G * h->w + 255) / 256 * 256;
+  const size_t obytes = (size_t)h->s * 8;
+  PEVAL_TRY(ensure(h->ptsbuf, ibytes + obytes + 256, h));
+  unsigned char *base = (unsigned char *)h->ptsbuf.ptr;
+  int32_t *dstatus = (int32_t *)(base + ibytes + obytes);
+  HIP_TRY(hipMemcpyAsync(base, images, (size_t)rows * h->G * h->w, hipMemcpyHostToDevice, h->stream));
+  PEVAL_TRY(interp_locked(h, ba, base, (uint64_t *)(base + ibytes), dstatus, h->stream));
+  int32_t status = 0;
+  HIP_TRY(hipMemcpyAsync(coeffs, base + ibytes, obytes, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipMemcpyAsync(&status, dstatus, sizeof status, hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  if (status) return fail(PEVAL_ESINGULAR, "a group's system is singular (equal or zero monomial values, or p not prime)");
+  return PEVAL_OK;
+}

@@ -51,6 +51,7 @@ extern "C" const char *peval_strerror(int code) {
     case PEVAL_EUNSUPPORTED: return "unsupported input";
     case PEVAL_EBUSY: return "busy";
     case PEVAL_ETIMEOUT: return "timed out";
+    case PEVAL_ESINGULAR: return "singular system";
     default: return "unknown error";
   }
 }
@@ -391,6 +392,7 @@ extern "C" int peval_create(uint64_t p, uint32_t n, uint64_t s, const uint32_t *
   if ((rc = upload((uint8_t **)&h->d_coeff, coeff)) != PEVAL_OK) return bail(rc);
   if ((rc = upload(&h->d_exps, ex)) != PEVAL_OK) return bail(rc);
   h->resident_bytes = coeff.size() + ex.size() * 2;
+  h->order = std::move(order);
   if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
     return bail(fail(PEVAL_EDEVICE, "stream creation failed"));
   if (hipEventCreateWithFlags(&h->done, hipEventDisableTiming) != hipSuccess)
@@ -421,6 +423,10 @@ extern "C" int peval_destroy(peval_poly *h) {
       (void)hipFree(kv.second.pidx);
     }
     h->pprep.clear();
+    release(h->iscr);
+    if (h->d_order) (void)hipFree(h->d_order);
+    if (h->d_grp_off32) (void)hipFree(h->d_grp_off32);
+    if (h->d_gorder) (void)hipFree(h->d_gorder);
     if (h->d_coeff) (void)hipFree(h->d_coeff);
     if (h->d_exps) (void)hipFree(h->d_exps);
     if (h->done) (void)hipEventDestroy(h->done);

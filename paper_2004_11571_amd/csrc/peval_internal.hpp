@@ -106,6 +106,11 @@ struct peval_poly {
   std::map<uint32_t, peval::PointsPrep> pprep;  // key K
   peval::Scratch ptab, ptsbuf;
 
+  // interpolation (built on first use)
+  std::vector<uint32_t> order;         // sorted position -> caller's term index
+  uint32_t *d_order = nullptr, *d_grp_off32 = nullptr, *d_gorder = nullptr;
+  peval::Scratch iscr;
+
   hipStream_t stream = nullptr;  // for peval_run
   hipEvent_t done = nullptr;     // end of the last enqueued call
   bool have_done = false;

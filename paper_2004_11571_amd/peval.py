@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpeval.so")
 
-OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EBUSY, ETIMEOUT = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EBUSY, ETIMEOUT, ESINGULAR = 0, -1, -2, -3, -4, -5, -6, -7
 
 
 class PevalError(RuntimeError):
@@ -65,6 +65,8 @@ def lib() -> ctypes.CDLL:
         "peval_run_points": ([vp, vp, u32, vp], i32),
         "peval_run_points_async": ([vp, vp, u32, vp, vp], i32),
         "peval_points_factors": ([u32, u32, vp, vp, vp], i32),
+        "peval_interpolate": ([vp, vp, u32, vp, vp], i32),
+        "peval_interpolate_async": ([vp, vp, u32, vp, vp, vp, vp], i32),
         "peval_destroy": ([vp], i32),
         "peval_set_tuning": ([vp, u32, u32, u32], i32),
         "peval_get_tuning": ([vp, u32, vp, vp, vp], i32),
@@ -207,6 +209,27 @@ class Poly:
         uint64, e.g. a torch tensor) into device memory ``dev_out``."""
         _check(lib().peval_run_points_async(self.handle, _ptr(points_dev) or None, T, _ptr(dev_out),
                                             _stream(stream)))
+
+    def interpolate(self, beta, images) -> np.ndarray:
+        """Coefficients (s,) uint64, in the order of the rows given at
+        creation, recovered from the images b_1..b_T (a (T, G) array) taken
+        at base point ``beta``; raises PevalError(ESINGULAR) if a group's
+        system is singular."""
+        b = self._beta(beta)
+        img = np.ascontiguousarray(images, dtype=self.dtype)
+        if img.ndim != 2 or img.shape[1] != self.G:
+            raise ValueError(f"images must be (T, {self.G})")
+        out = np.zeros(self.s, np.uint64)
+        _check(lib().peval_interpolate(self.handle, b.ctypes.data if b.size else None, img.shape[0],
+                                       img.ctypes.data if img.size else None, out.ctypes.data if out.size else None))
+        return out
+
+    def interpolate_async(self, beta, T: int, dev_images, dev_coeffs, dev_status, stream=None):
+        """Device-memory form: images (T, G), coefficients (s,) uint64 and a
+        device int32 status word (set to 1 if some group is singular)."""
+        b = self._beta(beta)
+        _check(lib().peval_interpolate_async(self.handle, b.ctypes.data if b.size else None, T, _ptr(dev_images),
+                                             _ptr(dev_coeffs), _ptr(dev_status), _stream(stream)))
 
     def set_arith(self, mode: str = "auto"):
         """'auto' / 'int' (Shoup products) or 'fp64' (the paper's Alg. 2, 2^31 <= p < 2^50)."""

@@ -195,3 +195,10 @@ def test_points_factor_plan_bad_arguments():
     L = PV.lib()
     assert L.peval_run_points(None, None, 1, None) == PV.EINVAL
     assert L.peval_run_points_async(None, None, 1, None, None) == PV.EINVAL
+
+
+def test_interpolate_null_arguments():
+    L = PV.lib()
+    assert L.peval_interpolate(None, None, 1, None, None) == PV.EINVAL
+    assert L.peval_interpolate_async(None, None, 1, None, None, None, None) == PV.EINVAL
+    assert L.peval_strerror(PV.ESINGULAR) == b"singular system"

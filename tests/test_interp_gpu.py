@@ -1,0 +1,154 @@
+"""Interpolation (coefficients back from the images) on the GPU: bit-exact
+against the oracle's elimination on arbitrary images, and round trips
+through the evaluation path at full size."""
+import numpy as np
+import pytest
+
+from oracle import Oracle
+from paper_2004_11571_amd import peval as PV
+from paper_2004_11571_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+P_COMPOSITE = 3 * 5 * 7 * 11 * 13 * 17 * 19 * 23 * 29 * 31 * 37 * 41 * 43 * 47
+
+
+@pytest.fixture(scope="module")
+def orc():
+    return Oracle()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def support(rng, p, n, s, d12, dmax):
+    return W.draw_exponents(rng, s, n, d12, dmax, per_var=True)
+
+
+def group_sizes(exps):
+    _, cnt = np.unique(exps[:, :2], axis=0, return_counts=True)
+    return cnt
+
+
+@pytest.mark.parametrize("p", [101, 65537, W.P31, (1 << 31) + 11, W.P50, W.P63])
+@pytest.mark.parametrize("shape", [(3, 300, 2, 60), (5, 800, 3, 6), (8, 500, 4, 3), (2, 40, 6, 0)])
+def test_parity_arbitrary_images(orc, p, shape):
+    """Any image values determine one coefficient vector; GPU == oracle."""
+    n, s, d12, dmax = shape
+    rng = np.random.default_rng(p % 1009 + n)
+    exps = support(rng, p, n, s, d12, dmax)
+    T = int(group_sizes(exps).max()) + 3
+    for attempt in range(10):
+        beta = rng.integers(1, p, size=n - 2, dtype=np.uint64)
+        with PV.Poly(p, exps, np.zeros(s, np.uint64)) as h:
+            images = rng.integers(0, p, size=(T, h.G), dtype=np.uint64).astype(h.dtype)
+            _say(f"interp case p={p} n={n} s={s} G={h.G} T={T} attempt={attempt}")
+            try:
+                want = orc.interpolate(p, exps, beta, images)
+            except Exception:
+                with pytest.raises(PV.PevalError) as ei:   # a colliding beta: both must say so
+                    h.interpolate(beta, images)
+                assert ei.value.code == PV.ESINGULAR
+                continue
+            got = h.interpolate(beta, images)
+        assert np.array_equal(got, want)
+        return
+    pytest.skip("no beta without monomial collisions (tiny p)")
+
+
+@pytest.mark.parametrize("p", [W.P31, W.P63])
+def test_round_trip(orc, p):
+    rng = np.random.default_rng(3)
+    exps = support(rng, p, 6, 20000, 8, 5)
+    coeffs = rng.integers(0, p, size=exps.shape[0], dtype=np.uint64)
+    beta = rng.integers(1, p, size=4, dtype=np.uint64)
+    T = int(group_sizes(exps).max())
+    with PV.Poly(p, exps, coeffs) as h:
+        images = h.run(beta, T)
+        got = h.interpolate(beta, images)
+    assert np.array_equal(got, coeffs)
+
+
+def test_largest_group(orc):
+    """One group of 8191 terms (the largest supported), x3 exponents 0..8190."""
+    p = W.P63
+    rng = np.random.default_rng(4)
+    m = 8191
+    exps = np.zeros((m, 3), np.uint32)
+    exps[:, 0], exps[:, 1] = 2, 5
+    exps[:, 2] = rng.permutation(m)
+    coeffs = rng.integers(0, p, size=m, dtype=np.uint64)
+    beta = rng.integers(2, p, size=1, dtype=np.uint64)
+    with PV.Poly(p, exps, coeffs) as h:
+        images = h.run(beta, m)
+        got = h.interpolate(beta, images)
+        assert np.array_equal(got, coeffs)
+        with pytest.raises(PV.PevalError) as ei:
+            h.interpolate(beta, images[: m - 1])               # fewer images than the group needs
+        assert ei.value.code == PV.EINVAL
+    exps2 = np.concatenate([exps, [[2, 5, 9000]]]).astype(np.uint32)
+    with PV.Poly(p, exps2, np.zeros(m + 1, np.uint64)) as h:
+        with pytest.raises(PV.PevalError) as ei:
+            h.interpolate(beta, np.zeros((m + 1, 1), np.uint64))
+        assert ei.value.code == PV.EUNSUPPORTED
+
+
+def test_singular_and_composite():
+    p = W.P63
+    exps = np.asarray([[1, 1, 0, 2], [1, 1, 3, 2], [0, 0, 1, 1]], np.uint32)
+    with PV.Poly(p, exps, np.zeros(3, np.uint64)) as h:
+        with pytest.raises(PV.PevalError) as ei:
+            h.interpolate(np.asarray([1, 5], np.uint64), np.ones((2, h.G), np.uint64))   # beta_3 = 1
+        assert ei.value.code == PV.ESINGULAR
+    rng = np.random.default_rng(8)
+    exps = support(rng, P_COMPOSITE, 4, 200, 2, 8)
+    with PV.Poly(P_COMPOSITE, exps, np.zeros(200, np.uint64)) as h:
+        beta = rng.integers(2, P_COMPOSITE, size=2, dtype=np.uint64)
+        with pytest.raises(PV.PevalError) as ei:
+            h.interpolate(beta, np.ones((200, h.G), np.uint64))
+        assert ei.value.code == PV.ESINGULAR
+
+
+def test_async_and_order(orc):
+    """Device buffers and a stream; rows given in a shuffled order come back
+    in that order."""
+    import torch
+    p = W.P63
+    rng = np.random.default_rng(9)
+    exps = support(rng, p, 5, 3000, 5, 6)
+    coeffs = rng.integers(0, p, size=3000, dtype=np.uint64)
+    beta = rng.integers(1, p, size=3, dtype=np.uint64)
+    T = int(group_sizes(exps).max())
+    st = torch.cuda.Stream()
+    with PV.Poly(p, exps, coeffs) as h:
+        img = torch.empty((T, h.G), dtype=torch.int64, device="cuda")
+        out = torch.empty(3000, dtype=torch.int64, device="cuda")
+        status = torch.full((1,), 7, dtype=torch.int32, device="cuda")
+        with torch.cuda.stream(st):
+            h.run_async(beta, T, img, stream=st)
+            h.interpolate_async(beta, T, img, out, status, stream=st)
+        st.synchronize()
+        assert int(status.item()) == 0
+        assert np.array_equal(out.cpu().numpy().view(np.uint64), coeffs)
+
+
+def test_full_size_round_trip():
+    """The 1e6-term workload: its 1024 images give back all 1e6 coefficients."""
+    w = W.config2()
+    T = int(group_sizes(w.exps).max())
+    assert T <= w.T
+    with PV.Poly(w.p, w.exps, w.coeffs) as h:
+        images = h.run(w.beta, T)
+        got = h.interpolate(w.beta, images)
+    assert np.array_equal(got, w.coeffs)
+
+
+def test_table2_shape_round_trip():
+    """The Table 2 shape (groups of about 4100 terms, 50-bit prime)."""
+    w = W.paper_table2()
+    T = int(group_sizes(w.exps).max())
+    with PV.Poly(w.p, w.exps, w.coeffs) as h:
+        images = h.run(w.beta, T)
+        got = h.interpolate(w.beta, images)
+    assert np.array_equal(got, w.coeffs)
