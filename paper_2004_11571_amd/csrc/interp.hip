@@ -41,6 +41,18 @@ int interp_setup(peval_poly *h) {
   HIP_TRY(hipMemcpy(h->d_order, h->order.data(), h->order.size() * 4, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(h->d_grp_off32, off32.data(), off32.size() * 4, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(h->d_gorder, gord.data(), gord.size() * 4, hipMemcpyHostToDevice));
+  // solve tasks: one wave per 64 consecutive terms of one group
+  std::vector<uint32_t> tg, tf;
+  for (uint64_t g = 0; g < h->G; ++g)
+    for (uint64_t j = 0; j < h->grp_off[g + 1] - h->grp_off[g]; j += 64) {
+      tg.push_back((uint32_t)g);
+      tf.push_back((uint32_t)j);
+    }
+  h->ntasks = tg.size();
+  HIP_TRY(hipMalloc((void **)&h->d_task_group, std::max<size_t>(tg.size(), 1) * 4));
+  HIP_TRY(hipMalloc((void **)&h->d_task_first, std::max<size_t>(tf.size(), 1) * 4));
+  HIP_TRY(hipMemcpy(h->d_task_group, tg.data(), tg.size() * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(h->d_task_first, tf.data(), tf.size() * 4, hipMemcpyHostToDevice));
   return PEVAL_OK;
 }
 
@@ -60,7 +72,7 @@ int interp_impl(peval_poly *h, const BetaArg &beta, const void *images, uint64_t
   PEVAL_TRY(interp_setup(h));
   PEVAL_TRY(ensure(h->tabval, (size_t)std::max<uint32_t>(h->tab_total, 1) * w, h));
   PEVAL_TRY(ensure(h->tabquot, (size_t)std::max<uint32_t>(h->tab_total, 1) * w, h));
-  PEVAL_TRY(ensure(h->iscr, (size_t)5 * h->s * w, h));
+  PEVAL_TRY(ensure(h->iscr, (size_t)6 * h->s * w, h));
   interp_status_reset<<<1, 64, 0, st>>>(status);
   HIP_TRY(hipGetLastError());
   if (ntail) {
@@ -84,6 +96,10 @@ int interp_impl(peval_poly *h, const BetaArg &beta, const void *images, uint64_t
   a.cval = scr + 2 * h->s;
   a.cquot = scr + 3 * h->s;
   a.bval = scr + 4 * h->s;
+  a.dval = scr + 5 * h->s;
+  a.task_group = h->d_task_group;
+  a.task_first = h->d_task_first;
+  a.ntasks = h->ntasks;
   a.out = out;
   a.status = status;
   a.s = h->s;
@@ -96,9 +112,20 @@ int interp_impl(peval_poly *h, const BetaArg &beta, const void *images, uint64_t
     HIP_TRY(hipGetLastError());
   }
   {
-    const size_t shmem = (largest_group(h) + 1) * w;
+    // blocks of 256 threads hold groups of up to 8 * 256 - 1 terms; larger
+    // groups (or few groups, which then need whole CUs) take 1024
+    const uint64_t mx = largest_group(h);
+    const size_t shmem = (mx + 1) * w;
     ProfScope ps(st, 2);
-    interp_group_kernel<A><<<(unsigned)h->G, kInterpBlock, shmem, st>>>(a);
+    if (mx >= (uint64_t)kInterpPer * 256 || h->G < 256)
+      interp_group_kernel<A, 1024><<<(unsigned)h->G, 1024, shmem, st>>>(a);
+    else
+      interp_group_kernel<A, 256><<<(unsigned)h->G, 256, shmem, st>>>(a);
+    HIP_TRY(hipGetLastError());
+  }
+  {
+    ProfScope ps(st, 3);
+    interp_solve_kernel<A><<<(unsigned)((h->ntasks + 3) / 4), 256, 0, st>>>(a);
     HIP_TRY(hipGetLastError());
   }
   return PEVAL_OK;

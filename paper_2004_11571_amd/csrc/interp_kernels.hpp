@@ -18,9 +18,10 @@
 //                        column c laid out along the sorted terms, with
 //                        Shoup quotients
 //   interp_group_kernel  one block per group: Q by m multiplications with
-//                        (z - v_j) in LDS, then b_l, then per term B(v_j)
-//                        and Q'(v_j) by Horner, one inversion, the result
-//                        scattered to the caller's term order
+//                        (z - v_j) in LDS, then the coefficients of B and Q'
+//   interp_solve_kernel  per term, over the whole chip: B(v_j) and Q'(v_j)
+//                        by Horner, one inversion, the result scattered to
+//                        the caller's term order
 //
 // Every multiplier that is used more than once (v_j in Q and in Horner, c_k
 // in b_l) carries its precomputed Shoup quotient.  The inversion is by
@@ -36,9 +37,8 @@
 
 namespace peval {
 
-constexpr int kInterpBlock = 1024;
-constexpr int kInterpPer = 8;                                  // LDS entries per thread in a Q update
-constexpr uint32_t kInterpMaxGroup = kInterpBlock * kInterpPer - 1;  // 8191 terms
+constexpr int kInterpPer = 8;               // coefficients per thread in the per-group kernel
+constexpr uint32_t kInterpMaxGroup = 8191;  // terms per group: 1024 threads x 8, and Q in 64 KiB of LDS
 
 template <class T>
 __device__ __forceinline__ T sub_mod(T a, T b, T p) {  // canonical in/out
@@ -58,6 +58,9 @@ struct InterpArgs {
   T *mval, *mquot;          // s: monomial values and quotients
   T *cval, *cquot;          // s: group image columns along the sorted terms
   T *bval;                  // s: coefficients of B per group
+  T *dval;                  // s: coefficients of Q' per group
+  const uint32_t *task_group, *task_first;  // per wave of the solve: group, first term
+  uint64_t ntasks;
   uint64_t *out;            // s coefficients in the caller's order
   int32_t *status;          // set to 1 when some group cannot be solved
   uint64_t s, G;
@@ -92,9 +95,15 @@ __global__ void interp_prep_kernel(InterpArgs<A> a) {
   a.cquot[i] = shoup_quot(c, a.m);
 }
 
-template <class A>
-__global__ __launch_bounds__(kInterpBlock) void interp_group_kernel(InterpArgs<A> a) {
+// Per group (one block of BS threads): Q in LDS, then b_l and the
+// coefficients (l+1) q_{l+1} of Q', both written along the sorted terms.
+// Thread tid owns coefficients tid + r*BS, r < kInterpPer, so a group may
+// have up to kInterpPer * BS - 1 terms.  The operand of the next step (v of
+// the next root, c of the next k) is loaded one step ahead.
+template <class A, int BS>
+__global__ __launch_bounds__(BS) void interp_group_kernel(InterpArgs<A> a) {
   using T = typename A::T;
+  constexpr int R = kInterpPer;
   extern __shared__ __align__(16) unsigned char smem[];
   T *q = reinterpret_cast<T *>(smem);  // m + 1 coefficients
   const T p = (T)a.m.p;
@@ -104,14 +113,16 @@ __global__ __launch_bounds__(kInterpBlock) void interp_group_kernel(InterpArgs<A
   const int tid = threadIdx.x;
 
   // Q(z) = 1, then multiply by (z - v_i) for each term of the group
-  for (uint32_t k = tid; k <= m; k += kInterpBlock) q[k] = (k == 0) ? (T)(1 % p) : (T)0;
+  for (uint32_t k = tid; k <= m; k += BS) q[k] = (k == 0) ? (T)(1 % p) : (T)0;
   __syncthreads();
+  T v = a.mval[base], vq = a.mquot[base];
   for (uint32_t i = 0; i < m; ++i) {
-    const T v = a.mval[base + i], vq = a.mquot[base + i];
-    T nv[kInterpPer];
+    const uint32_t inext = (i + 1 < m) ? i + 1 : i;
+    const T vn = a.mval[base + inext], vqn = a.mquot[base + inext];
+    T nv[R];
 #pragma unroll
-    for (int r = 0; r < kInterpPer; ++r) {
-      const uint32_t k = tid + r * kInterpBlock;
+    for (int r = 0; r < R; ++r) {
+      const uint32_t k = tid + r * BS;
       if (k <= i + 1) {
         const T lo = k ? q[k - 1] : (T)0;
         const T hi = (k <= i) ? q[k] : (T)0;
@@ -120,56 +131,73 @@ __global__ __launch_bounds__(kInterpBlock) void interp_group_kernel(InterpArgs<A
     }
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < kInterpPer; ++r) {
-      const uint32_t k = tid + r * kInterpBlock;
+    for (int r = 0; r < R; ++r) {
+      const uint32_t k = tid + r * BS;
       if (k <= i + 1) q[k] = nv[r];
     }
     __syncthreads();
+    v = vn;
+    vq = vqn;
   }
 
-  // b_l = sum_{k=0}^{m-1-l} q_{k+l+1} c_{k+1}
-  for (uint32_t l = tid; l < m; l += kInterpBlock) {
-    typename A::Acc acc = A::zero();
-    for (uint32_t k = 0; k + l < m; ++k)
-      A::add(acc, A::mul_lazy(q[k + l + 1], a.cval[base + k], a.cquot[base + k], a.m));
-    a.bval[base + l] = A::reduce(acc, a.m);
-  }
-  // Q'(z) = sum_l (l+1) q_{l+1} z^l, in place of q
-  {
-    T nv[kInterpPer];
+  // b_l = sum_{k=0}^{m-1-l} q_{k+l+1} c_{k+1}, for l = tid + r*BS at once
+  typename A::Acc acc[R];
 #pragma unroll
-    for (int r = 0; r < kInterpPer; ++r) {
-      const uint32_t l = tid + r * kInterpBlock;
-      if (l < m) nv[r] = mul_mod(q[l + 1], (T)((l + 1) % a.m.p), a.m);
-    }
-    __syncthreads();
+  for (int r = 0; r < R; ++r) acc[r] = A::zero();
+  T c = a.cval[base], cq = a.cquot[base];
+  for (uint32_t k = 0; k < m; ++k) {
+    const uint32_t knext = (k + 1 < m) ? k + 1 : k;
+    const T cn = a.cval[base + knext], cqn = a.cquot[base + knext];
 #pragma unroll
-    for (int r = 0; r < kInterpPer; ++r) {
-      const uint32_t l = tid + r * kInterpBlock;
-      if (l < m) q[l] = nv[r];
+    for (int r = 0; r < R; ++r) {
+      const uint32_t l = tid + r * BS;
+      if (l + k < m) A::add(acc[r], A::mul_lazy(q[k + l + 1], c, cq, a.m));
+    }
+    c = cn;
+    cq = cqn;
+  }
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const uint32_t l = tid + r * BS;
+    if (l < m) {
+      a.bval[base + l] = A::reduce(acc[r], a.m);
+      a.dval[base + l] = mul_mod(q[l + 1], (T)((l + 1) % a.m.p), a.m);
     }
   }
-  __threadfence_block();  // b_l written by other threads of the block
-  __syncthreads();
+}
 
-  // a_j = B(v_j) / (v_j Q'(v_j))
-  for (uint32_t j = tid; j < m; j += kInterpBlock) {
-    const T v = a.mval[base + j], vq = a.mquot[base + j];
-    T b = 0, d = 0;
-    for (uint32_t l = m; l-- > 0;) {
-      b = add_mod(canon(A::mul_lazy(b, v, vq, a.m), p), a.bval[base + l], p);
-      d = add_mod(canon(A::mul_lazy(d, v, vq, a.m), p), q[l], p);
-    }
-    const T den = canon(A::mul_lazy(d, v, vq, a.m), p);
-    T res = 0;
-    const T inv = den ? pow_mod(den, (uint64_t)a.m.p - 2, a.m) : (T)0;
-    if (den && mul_mod(den, inv, a.m) == (T)(1 % p)) {
-      res = mul_mod(b, inv, a.m);
-    } else {
-      a.status[0] = 1;
-    }
-    a.out[a.order[base + j]] = (uint64_t)res;
+// Per term: a_j = B(v_j) / (v_j Q'(v_j)) by Horner.  Every wave works on
+// one group (a task = group and first term), so the group's b_l and Q'
+// coefficients are read at wave-uniform addresses.
+template <class A>
+__global__ __launch_bounds__(256) void interp_solve_kernel(InterpArgs<A> a) {
+  using T = typename A::T;
+  const T p = (T)a.m.p;
+  const uint64_t task = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+  if (task >= a.ntasks) return;  // whole waves leave together
+  const uint32_t g = __builtin_amdgcn_readfirstlane(a.task_group[task]);
+  const uint32_t j0 = __builtin_amdgcn_readfirstlane(a.task_first[task]);
+  const uint64_t base = __builtin_amdgcn_readfirstlane(a.grp_off[g]);
+  const uint32_t m = __builtin_amdgcn_readfirstlane(a.grp_off[g + 1]) - (uint32_t)base;
+  const uint32_t j = j0 + (threadIdx.x & 63);
+  const bool live = j < m;
+  const T v = live ? a.mval[base + j] : (T)0, vq = live ? a.mquot[base + j] : (T)0;
+  const T *bv = a.bval + base, *dv = a.dval + base;
+  T b = 0, d = 0;
+  for (uint32_t l = m; l-- > 0;) {
+    b = add_mod(canon(A::mul_lazy(b, v, vq, a.m), p), bv[l], p);
+    d = add_mod(canon(A::mul_lazy(d, v, vq, a.m), p), dv[l], p);
   }
+  if (!live) return;
+  const T den = canon(A::mul_lazy(d, v, vq, a.m), p);
+  T res = 0;
+  const T inv = den ? pow_mod(den, (uint64_t)a.m.p - 2, a.m) : (T)0;
+  if (den && mul_mod(den, inv, a.m) == (T)(1 % p)) {
+    res = mul_mod(b, inv, a.m);
+  } else {
+    a.status[0] = 1;
+  }
+  a.out[a.order[base + j]] = (uint64_t)res;
 }
 
 }  // namespace peval

@@ -427,6 +427,8 @@ extern "C" int peval_destroy(peval_poly *h) {
     if (h->d_order) (void)hipFree(h->d_order);
     if (h->d_grp_off32) (void)hipFree(h->d_grp_off32);
     if (h->d_gorder) (void)hipFree(h->d_gorder);
+    if (h->d_task_group) (void)hipFree(h->d_task_group);
+    if (h->d_task_first) (void)hipFree(h->d_task_first);
     if (h->d_coeff) (void)hipFree(h->d_coeff);
     if (h->d_exps) (void)hipFree(h->d_exps);
     if (h->done) (void)hipEventDestroy(h->done);

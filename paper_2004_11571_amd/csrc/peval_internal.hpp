@@ -109,6 +109,8 @@ struct peval_poly {
   // interpolation (built on first use)
   std::vector<uint32_t> order;         // sorted position -> caller's term index
   uint32_t *d_order = nullptr, *d_grp_off32 = nullptr, *d_gorder = nullptr;
+  uint32_t *d_task_group = nullptr, *d_task_first = nullptr;
+  uint64_t ntasks = 0;
   peval::Scratch iscr;
 
   hipStream_t stream = nullptr;  // for peval_run
