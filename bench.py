@@ -73,7 +73,7 @@ def parse():
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-smax", type=float, default=1e6)
     ap.add_argument("--tuning", default="", help="K,P,C override")
-    ap.add_argument("--arith", default="auto", choices=["auto", "int", "fp64"],
+    ap.add_argument("--arith", default="auto", choices=["auto", "int", "fp64", "pm"],
                     help="modular product of the evaluation kernel (fp64: the paper's Alg. 2, p < 2^50)")
     ap.add_argument("--cpu-rows", type=int, default=96, help="oracle sample: first rows of the images")
     ap.add_argument("--cpu-threads", type=int, default=16)

@@ -200,10 +200,18 @@ int peval_set_tuning(peval_poly *h, uint32_t K, uint32_t P, uint32_t C);
 #define PEVAL_ARITH_AUTO 0u
 #define PEVAL_ARITH_INT 1u
 #define PEVAL_ARITH_FP64 2u
+#define PEVAL_ARITH_PMERSENNE 3u
 int peval_set_arith(peval_poly *h, uint32_t mode);
 
+/* PEVAL_ARITH_PMERSENNE: for p = 2^63 - c (c < 2^20) or p = 2^31 - c
+ * (c < 2^12), the full product folded twice with 2^k = c (mod p), with no
+ * precomputed quotient (not in the paper; measured slower than Shoup's
+ * product on gfx950, so never chosen by AUTO).  Evaluations per pass are
+ * fixed at 16 with it. */
+
 /* The product the power-mode evaluation kernel of this handle uses now:
- * *mode = PEVAL_ARITH_INT or PEVAL_ARITH_FP64 (AUTO resolved). */
+ * *mode = PEVAL_ARITH_INT, PEVAL_ARITH_FP64 or PEVAL_ARITH_PMERSENNE
+ * (AUTO resolved). */
 int peval_get_arith(const peval_poly *h, uint32_t *mode);
 
 /* The tuning the next run with T evaluations would use. */

@@ -187,6 +187,12 @@ struct Stage<W32, P> {
   __device__ __forceinline__ W32::Acc get(int lane, int q) const { return W32::Acc{v[lane][q]}; }
 };
 
+// the pseudo-Mersenne policies stage exactly what their Shoup counterparts do
+template <int P>
+struct Stage<W64PM, P> : Stage<W64, P> {};
+template <int P>
+struct Stage<W32PM, P> : Stage<W32, P> {};
+
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();

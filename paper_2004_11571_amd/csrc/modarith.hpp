@@ -220,6 +220,73 @@ struct W32 {
 };
 
 // ---------------------------------------------------------------------------
+// Pseudo-Mersenne moduli p = 2^k - c with small c (both 2^31 - 1 and
+// 2^63 - 25 have this form): the full product x w = H 2^k + L is folded
+// twice with 2^k = c (mod p), r = L + c H, which needs no precomputed
+// quotient.  Kept as a third product so that it can be measured against
+// Shoup's on the same kernel; the running value stays lazy in [0, 2p).
+// ---------------------------------------------------------------------------
+struct ModPM64 {
+  uint64_t p;  // 2^63 - c
+  uint64_t c;  // 1 <= c < 2^20
+  Mod64 m;     // for the sums and the output reduction
+};
+
+__device__ __forceinline__ uint64_t pm63_mul_lazy(uint64_t x, uint64_t w, uint64_t c) {
+  const uint64_t M63 = 0x7fffffffffffffffull;
+  const uint64_t lo = x * w, hi = mulhi64(x, w);  // x < 2^64, w < 2^63: product < 2^127
+  const uint64_t H = (hi << 1) | (lo >> 63);      // product >> 63, < 2^64
+  const uint64_t L = lo & M63;
+  // r1 = L + c H < 2^63 + 2^84, as (r1h, r1l)
+  const uint64_t chl = c * H, chh = mulhi64(c, H);
+  const uint64_t r1l = L + chl;
+  const uint64_t r1h = chh + (r1l < L ? 1u : 0u);
+  // second fold: r1 >> 63 < 2^22, so the result is below 2^63 + 2^42 < 2p
+  const uint64_t h2 = (r1h << 1) | (r1l >> 63);
+  return (r1l & M63) + c * h2;
+}
+
+struct W64PM {
+  using T = uint64_t;
+  using PT = uint64_t;
+  using M = ModPM64;
+  using Acc = W64::Acc;
+  static constexpr int bytes = 8;
+  __device__ static __forceinline__ Acc zero() { return W64::zero(); }
+  __device__ static __forceinline__ void add(Acc &a, T x) { W64::add(a, x); }
+  __device__ static __forceinline__ T reduce(const Acc &a, const M &m) { return W64::reduce(a, m.m); }
+  __device__ static __forceinline__ Acc stage(const Acc &a, const M &) { return a; }
+  __device__ static __forceinline__ void add_walk(Acc &a, const Acc &b, const M &) { W64::add(a, b); }
+  __device__ static __forceinline__ T mul_lazy(T x, T w, T, const M &m) { return pm63_mul_lazy(x, w, m.c); }
+};
+
+struct ModPM32 {
+  uint32_t p;  // 2^31 - c
+  uint32_t c;  // 1 <= c < 2^12
+  Mod32 m;
+};
+
+__device__ __forceinline__ uint32_t pm31_mul_lazy(uint32_t x, uint32_t w, uint32_t c) {
+  const uint64_t prod = (uint64_t)x * w;                     // < 2^63
+  const uint64_t r1 = (prod & 0x7fffffffu) + (uint64_t)c * (uint32_t)(prod >> 31);  // < 2^31 + 2^44
+  return (uint32_t)(r1 & 0x7fffffffu) + c * (uint32_t)(r1 >> 31);                 // < 2^31 + 2^25
+}
+
+struct W32PM {
+  using T = uint32_t;
+  using PT = uint32_t;
+  using M = ModPM32;
+  using Acc = W32::Acc;
+  static constexpr int bytes = 4;
+  __device__ static __forceinline__ Acc zero() { return W32::zero(); }
+  __device__ static __forceinline__ void add(Acc &a, T x) { W32::add(a, x); }
+  __device__ static __forceinline__ T reduce(const Acc &a, const M &m) { return W32::reduce(a, m.m); }
+  __device__ static __forceinline__ Acc stage(const Acc &a, const M &) { return a; }
+  __device__ static __forceinline__ void add_walk(Acc &a, const Acc &b, const M &) { W32::add(a, b); }
+  __device__ static __forceinline__ T mul_lazy(T x, T w, T, const M &m) { return pm31_mul_lazy(x, w, m.c); }
+};
+
+// ---------------------------------------------------------------------------
 // FP64 residues (p < 2^50): the paper's product, Alg. 2 (van der Hoeven,
 // Lecerf and Quintin).  Values are exact integers held in doubles.
 // ---------------------------------------------------------------------------

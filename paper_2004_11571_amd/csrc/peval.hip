@@ -529,19 +529,33 @@ extern "C" int peval_set_tuning(peval_poly *h, uint32_t K, uint32_t P, uint32_t 
   return PEVAL_OK;
 }
 
+// p = 2^63 - c with c < 2^20, or p = 2^31 - c with c < 2^12
+static bool pseudo_mersenne(uint64_t p) {
+  if (p < (1ull << 63) && p > (1ull << 63) - (1ull << 20)) return true;
+  return p < (1ull << 31) && p > (1ull << 31) - (1ull << 12);
+}
+
 extern "C" int peval_set_arith(peval_poly *h, uint32_t mode) {
   if (!h) return fail(PEVAL_EINVAL, "null handle");
-  if (mode > PEVAL_ARITH_FP64) return fail(PEVAL_EINVAL, "unknown arithmetic %u", mode);
+  if (mode > PEVAL_ARITH_PMERSENNE) return fail(PEVAL_EINVAL, "unknown arithmetic %u", mode);
   if (mode == PEVAL_ARITH_FP64 && (h->p < (1ull << 31) || h->p >= (1ull << 50)))
     return fail(PEVAL_EUNSUPPORTED, "the FP64 product needs 2^31 <= p < 2^50");
+  if (mode == PEVAL_ARITH_PMERSENNE && !pseudo_mersenne(h->p))
+    return fail(PEVAL_EUNSUPPORTED, "the pseudo-Mersenne product needs p = 2^63 - c (c < 2^20) or 2^31 - c (c < 2^12)");
   std::lock_guard<std::mutex> lk(h->mu);
+  if (mode == PEVAL_ARITH_PMERSENNE) {
+    h->arith = 2;
+    h->mpm64 = ModPM64{h->p, (1ull << 63) - h->p, h->m64};
+    if (h->w == 4) h->mpm32 = ModPM32{(uint32_t)h->p, (uint32_t)((1ull << 31) - h->p), h->m32};
+    return PEVAL_OK;
+  }
   h->arith = (mode == PEVAL_ARITH_FP64 || (mode == PEVAL_ARITH_AUTO && fp64_by_default(h->p))) ? 1 : 0;
   return PEVAL_OK;
 }
 
 extern "C" int peval_get_arith(const peval_poly *h, uint32_t *mode) {
   if (!h || !mode) return fail(PEVAL_EINVAL, "null argument");
-  *mode = h->arith == 1 ? PEVAL_ARITH_FP64 : PEVAL_ARITH_INT;
+  *mode = h->arith == 1 ? PEVAL_ARITH_FP64 : h->arith == 2 ? PEVAL_ARITH_PMERSENNE : PEVAL_ARITH_INT;
   return PEVAL_OK;
 }
 
@@ -593,6 +607,30 @@ struct Dispatch<WF64> {  // a thread sums at most 8 doubles exactly: K <= 8
   }
 };
 
+// Pseudo-Mersenne products: P = 16 only.
+template <class A>
+struct DispatchPM {
+  using EvalFn = void (*)(EvalArgs<A>);
+  static EvalFn eval(uint32_t K) {
+    switch (K) {
+      case 1: return eval_kernel<A, 1, 16>;
+      case 2: return eval_kernel<A, 2, 16>;
+      case 4: return eval_kernel<A, 4, 16>;
+      case 8: return eval_kernel<A, 8, 16>;
+      case 16: return eval_kernel<A, 16, 16>;
+      default: return nullptr;
+    }
+  }
+};
+template <>
+struct Dispatch<W64PM> {
+  static void (*eval(uint32_t K, uint32_t))(EvalArgs<W64PM>) { return DispatchPM<W64PM>::eval(K); }
+};
+template <>
+struct Dispatch<W32PM> {
+  static void (*eval(uint32_t K, uint32_t))(EvalArgs<W32PM>) { return DispatchPM<W32PM>::eval(K); }
+};
+
 template <class A>
 static const typename A::M &mod_of(const peval_poly *h);
 template <>
@@ -601,6 +639,10 @@ template <>
 const Mod32 &mod_of<W32>(const peval_poly *h) { return h->m32; }
 template <>
 const ModF64 &mod_of<WF64>(const peval_poly *h) { return h->mf; }
+template <>
+const ModPM64 &mod_of<W64PM>(const peval_poly *h) { return h->mpm64; }
+template <>
+const ModPM32 &mod_of<W32PM>(const peval_poly *h) { return h->mpm32; }
 
 static constexpr size_t kPartialBudget = (size_t)2 << 30;  // bytes of partial sums per launch
 
@@ -611,9 +653,10 @@ static int run_impl(peval_poly *h, const BetaArg &beta, uint64_t t0, uint32_t T,
                     hipStream_t st, const Tuning &tu) {
   using T_ = typename A::T;
   const auto &m = mod_of<A>(h);
-  constexpr bool fp = !std::is_same<A, E>::value;
+  constexpr bool fp = std::is_same<E, WF64>::value;
+  constexpr bool pm = std::is_same<E, W64PM>::value || std::is_same<E, W32PM>::value;
   const uint32_t ntail = h->n - 2;
-  const uint32_t K = tu.K, P = tu.P, C = tu.C;
+  const uint32_t K = tu.K, P = pm ? 16 : tu.P, C = tu.C;
   Plan *pl = nullptr;
   PEVAL_TRY(get_plan(h, K, P, &pl));
   const size_t w = sizeof(T_);
@@ -727,9 +770,14 @@ int run_locked(peval_poly *h, const BetaArg &ba, uint64_t t0, uint32_t T, void *
                const Tuning &tu) {
   HIP_TRY(hipSetDevice(h->device));
   if (h->have_done) HIP_TRY(hipStreamWaitEvent(st, h->done, 0));
-  int rc = (h->w == 4)     ? run_impl<W32>(h, ba, t0, T, dev_out, st, tu)
-           : (h->arith == 1) ? run_impl<W64, WF64>(h, ba, t0, T, dev_out, st, tu)
-                             : run_impl<W64>(h, ba, t0, T, dev_out, st, tu);
+  int rc;
+  if (h->w == 4)
+    rc = (h->arith == 2) ? run_impl<W32, W32PM>(h, ba, t0, T, dev_out, st, tu)
+                         : run_impl<W32>(h, ba, t0, T, dev_out, st, tu);
+  else
+    rc = (h->arith == 1)   ? run_impl<W64, WF64>(h, ba, t0, T, dev_out, st, tu)
+         : (h->arith == 2) ? run_impl<W64, W64PM>(h, ba, t0, T, dev_out, st, tu)
+                           : run_impl<W64>(h, ba, t0, T, dev_out, st, tu);
   if (rc != PEVAL_OK) return rc;
   HIP_TRY(hipEventRecord(h->done, st));
   h->have_done = true;

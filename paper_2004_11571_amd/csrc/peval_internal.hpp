@@ -82,7 +82,9 @@ struct peval_poly {
   peval::Mod64 m64{};
   peval::Mod32 m32{};
   peval::ModF64 mf{};
-  uint32_t arith = 0;  // 0: integer products; 1: FP64 product (Alg. 2), 2^31 <= p < 2^50
+  peval::ModPM64 mpm64{};
+  peval::ModPM32 mpm32{};
+  uint32_t arith = 0;  // 0: Shoup products; 1: FP64 product (Alg. 2), 2^31 <= p < 2^50; 2: pseudo-Mersenne
   int device = 0;
 
   std::vector<uint32_t> gd, ge;        // output columns

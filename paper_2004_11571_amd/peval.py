@@ -232,14 +232,15 @@ class Poly:
                                              _ptr(dev_coeffs), _ptr(dev_status), _stream(stream)))
 
     def set_arith(self, mode: str = "auto"):
-        """'auto' / 'int' (Shoup products) or 'fp64' (the paper's Alg. 2, 2^31 <= p < 2^50)."""
-        _check(lib().peval_set_arith(self.handle, {"auto": 0, "int": 1, "fp64": 2}[mode]))
+        """'auto' / 'int' (Shoup products), 'fp64' (the paper's Alg. 2, 2^31 <= p < 2^50) or
+        'pm' (pseudo-Mersenne folding, p = 2^63 - c or 2^31 - c with small c)."""
+        _check(lib().peval_set_arith(self.handle, {"auto": 0, "int": 1, "fp64": 2, "pm": 3}[mode]))
 
     def arith(self) -> str:
         """The product the evaluation kernel uses now: 'int' or 'fp64'."""
         m = ctypes.c_uint32()
         _check(lib().peval_get_arith(self.handle, ctypes.byref(m)))
-        return "fp64" if m.value == 2 else "int"
+        return {2: "fp64", 3: "pm"}.get(m.value, "int")
 
     def set_tuning(self, K: int = 0, P: int = 0, C: int = 0):
         _check(lib().peval_set_tuning(self.handle, K, P, C))

@@ -273,3 +273,51 @@ def test_integer_product_below_2_50(orc, p):
             for tun in ((16, 16, 3), (8, 32, 1), (1, 8, 7)):
                 q.set_tuning(*tun)
                 assert np.array_equal(q.run(poly.beta, 50), want), (mode, tun)
+
+
+# --- pseudo-Mersenne product (p = 2^63 - c or 2^31 - c, small c) -----------
+
+PM_MODULI = [W.P63, (1 << 63) - 1, (1 << 63) - ((1 << 20) - 1), W.P31, (1 << 31) - 4095, (1 << 31) - 3]
+
+
+def check_pm(orc, p, exps, coeffs, beta, T, K=0, C=0):
+    exps = np.ascontiguousarray(exps, np.uint32)
+    _say(f"pm case p={p} s={exps.shape[0]} n={exps.shape[1]} T={T} K={K} C={C}")
+    with PV.Poly(p, exps, coeffs) as poly:
+        poly.set_arith("pm")
+        assert poly.arith() == "pm"
+        if K or C:
+            poly.set_tuning(K, 0, C)
+        got = poly.run(beta, T)
+    want = orc.evaluate(p, exps, coeffs, beta, T, threads=8).astype(got.dtype)
+    bad = np.argwhere(got != want)
+    assert bad.size == 0, f"{len(bad)} mismatches, first at {bad[:3].tolist()}"
+
+
+@pytest.mark.parametrize("p", PM_MODULI)
+def test_pseudo_mersenne_random(orc, p):
+    rng = np.random.default_rng(p % 4099)
+    poly = W.random_small(rng, p, 5, 2500, 41, dmax=6)
+    for K, C in ((0, 0), (1, 3), (4, 1), (16, 7)):
+        check_pm(orc, p, poly.exps, poly.coeffs, poly.beta, poly.T, K=K, C=C)
+
+
+@pytest.mark.parametrize("p", PM_MODULI)
+def test_pseudo_mersenne_extremes(orc, p):
+    """Coefficients and base point at p - 1 keep every running value and
+    product at the top of its range."""
+    rng = np.random.default_rng(7)
+    poly = W.random_small(rng, p, 4, 800, 33, dmax=9)
+    poly.coeffs[:] = p - 1
+    beta = np.full(2, p - 1, np.uint64)
+    check_pm(orc, p, poly.exps, poly.coeffs, beta, 33)
+    beta = np.asarray([p - 2, 2], np.uint64)
+    check_pm(orc, p, poly.exps, poly.coeffs, beta, 33)
+
+
+def test_pseudo_mersenne_refused():
+    for p in (W.P50, 1000003, (1 << 63) - (1 << 21) - 1):
+        with PV.Poly(p, np.asarray([[1, 1, 1]], np.uint32), np.asarray([1], np.uint64)) as h:
+            with pytest.raises(PV.PevalError) as ei:
+                h.set_arith("pm")
+            assert ei.value.code == PV.EUNSUPPORTED
