@@ -266,7 +266,7 @@ extern "C" int peval_batch_create(uint32_t count, peval_poly *const *polys, cons
     peval_poly *h = polys[j];
     std::lock_guard<std::mutex> lk(h->mu);
     Tuning t = choose_tuning(h, Ts[j]);
-    uint32_t K = std::min<uint32_t>(t.K, 8);
+    uint32_t K = t.K;
     Plan *pl = nullptr;
     int rc = get_plan(h, K, kBatchP, &pl);
     if (rc != PEVAL_OK) return bail(rc);

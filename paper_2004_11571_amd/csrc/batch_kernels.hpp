@@ -121,14 +121,16 @@ __global__ __launch_bounds__(kEvalBlock) void batch_eval_kernel(const BatchDesc 
         case 1: batch_eval_item<W32, 1>(d, it, lds, lane, d.m32); break;
         case 2: batch_eval_item<W32, 2>(d, it, lds, lane, d.m32); break;
         case 4: batch_eval_item<W32, 4>(d, it, lds, lane, d.m32); break;
-        default: batch_eval_item<W32, 8>(d, it, lds, lane, d.m32); break;
+        case 8: batch_eval_item<W32, 8>(d, it, lds, lane, d.m32); break;
+        default: batch_eval_item<W32, 16>(d, it, lds, lane, d.m32); break;
       }
     } else {
       switch (d.K) {
         case 1: batch_eval_item<W64, 1>(d, it, lds, lane, d.m64); break;
         case 2: batch_eval_item<W64, 2>(d, it, lds, lane, d.m64); break;
         case 4: batch_eval_item<W64, 4>(d, it, lds, lane, d.m64); break;
-        default: batch_eval_item<W64, 8>(d, it, lds, lane, d.m64); break;
+        case 8: batch_eval_item<W64, 8>(d, it, lds, lane, d.m64); break;
+        default: batch_eval_item<W64, 16>(d, it, lds, lane, d.m64); break;
       }
     }
   }

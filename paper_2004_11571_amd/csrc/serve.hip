@@ -61,6 +61,7 @@ struct SReq {
   uint32_t launched_passes = 0, finished_passes = 0;
   void *d_out = nullptr;
   uint64_t out_bytes = 0;
+  uint64_t out_alloc = 0;     // size of the pooled output block
   uint64_t reserve = 0;       // scratch reserved for its slices while admitted
   uint32_t ts = 0;            // evaluations per slice
   uint32_t cmax = 1;          // chains per slice allowed by the reservation
@@ -118,7 +119,11 @@ struct peval_server {
   size_t slot_blob_bytes[kStreams] = {0, 0};
   size_t staging_bytes[kStreams] = {0, 0};
   bool slot_busy[kStreams] = {false, false};
-  std::vector<void *> to_free;       // request outputs, freed when no pass is in flight
+  // device output blocks by size (powers of two), kept for reuse: a free
+  // waits for the whole device, so blocks are only freed under budget
+  // pressure; cached blocks count as used
+  std::map<uint64_t, std::vector<void *>> out_free;
+  uint64_t out_free_bytes = 0;
   std::deque<uint64_t> to_copy;      // finished on the device, result not yet in host memory
   std::deque<uint64_t> done_q;       // finished requests, in completion order (for next_done)
   std::condition_variable cv_copy;
@@ -131,18 +136,18 @@ struct peval_server {
 // residency
 // ---------------------------------------------------------------------------
 static uint64_t estimate_poly_bytes(const SPoly &sp) {
-  // resident terms + one thread layout (K <= 8, P = 16) + tables
+  // resident terms + one thread layout (K <= 16, P = 16) + tables
   uint64_t b = sp.s * (sp.w + 2ull * (sp.n - 2));
   b += (sp.s + 64) * 5 + (sp.s / 64 + 2) * 12 + sp.G * 4;
   return b + 4096;
 }
 
 // Upper bound of the scratch one slice of ts evaluations with at most c
-// chains needs (any K <= 8, P = 16): power tables, chain starts, Gamma,
+// chains needs (any K <= 16, P = 16): power tables, chain starts, Gamma,
 // Gamma', partial sums.  Used for reservations, so that every pass fits.
 static uint64_t slice_scratch_bound(const SPoly &sp, uint32_t ts, uint32_t c) {
   const uint64_t w = sp.w;
-  const uint64_t kn = sp.s + 8 * sp.G + 512;             // >= K * NT
+  const uint64_t kn = sp.s + 16 * sp.G + 1024;           // >= K * NT for K <= 16
   const uint64_t slots = (sp.s + sp.G) / 16 + 2 * sp.G + 64;  // >= nslots for K >= 1, P = 16
   const uint64_t lmax = ((uint64_t)ts + c - 1) / c;
   uint64_t b = 2 * (std::max<uint64_t>(sp.tab_total, 1) * w + 256);
@@ -195,7 +200,7 @@ static int upload_poly(const SPoly &sp, peval_poly **out, Plan **plan_out, uint6
   {
     std::lock_guard<std::mutex> lk(h->mu);
     Tuning t = choose_tuning(h, 64);
-    int rc = get_plan(h, std::min<uint32_t>(t.K, 8), kBatchP, &pl);
+    int rc = get_plan(h, t.K, kBatchP, &pl);
     if (rc != PEVAL_OK) {
       peval_destroy(h);
       return rc;
@@ -212,6 +217,40 @@ static int upload_poly(const SPoly &sp, peval_poly **out, Plan **plan_out, uint6
 // ---------------------------------------------------------------------------
 // scheduler
 // ---------------------------------------------------------------------------
+static uint64_t out_block(uint64_t bytes) {
+  uint64_t b = 65536;
+  while (b < bytes) b <<= 1;
+  return b;
+}
+
+// The request's output block goes back to the pool and its scratch
+// reservation to the budget.
+static void release_output(peval_server *S, SReq &r) {
+  if (r.d_out) {
+    S->out_free[r.out_alloc].push_back(r.d_out);
+    S->out_free_bytes += r.out_alloc;
+    r.d_out = nullptr;
+  } else {
+    S->used -= r.out_alloc;  // simulated: nothing was allocated
+  }
+  S->used -= r.reserve;
+}
+
+// Free cached output blocks, largest first, until `need` more bytes fit.
+static void trim_out_cache(peval_server *S, uint64_t need) {
+  while (S->used + need > S->budget && !S->out_free.empty()) {
+    auto it = std::prev(S->out_free.end());
+    if (it->second.empty()) {
+      S->out_free.erase(it);
+      continue;
+    }
+    (void)hipFree(it->second.back());
+    it->second.pop_back();
+    S->used -= it->first;
+    S->out_free_bytes -= it->first;
+  }
+}
+
 static void finish_request(peval_server *S, SReq &r, double t) {
   r.status = 0;
   S->done_q.push_back(r.id);
@@ -222,10 +261,7 @@ static void finish_request(peval_server *S, SReq &r, double t) {
   S->t_last_done = t;
   SPoly &sp = S->polys[r.poly];
   sp.refs--;
-  S->used -= r.out_bytes + r.reserve;
-  // hipFree waits for the whole device; defer it to a moment with no pass in flight
-  if (r.d_out) S->to_free.push_back(r.d_out);
-  r.d_out = nullptr;
+  release_output(S, r);
 }
 
 // Retire passes whose work is complete (oldest first).
@@ -274,9 +310,22 @@ static void admit(peval_server *S, std::unique_lock<std::mutex> &lk) {
     if (sp.plan) {  // resident: the reservation follows the actual thread layout
       r.reserve = 2 * (member_scratch_bytes(sp.h, *sp.plan, r.cmax, r.ts) + (uint64_t)r.cmax * sp.plan->nslots * sp.w);
     }
-    uint64_t need = r.out_bytes + r.reserve + (resident ? 0 : estimate_poly_bytes(sp));
-    if (S->used + need > S->budget) evict_for(S, need);
-    if (S->used + need > S->budget) return;  // head of line waits for memory
+    const uint64_t ob = out_block(r.out_bytes);
+    auto cached_block = [&] {
+      auto it = S->out_free.find(ob);
+      return !S->simulate && it != S->out_free.end() && !it->second.empty();
+    };
+    auto need_now = [&] { return (cached_block() ? 0 : ob) + r.reserve + (resident ? 0 : estimate_poly_bytes(sp)); };
+    if (S->used + need_now() > S->budget) trim_out_cache(S, need_now());
+    if (S->used + need_now() > S->budget) evict_for(S, need_now());
+    if (S->used + need_now() > S->budget) return;  // head of line waits for memory
+    const bool reuse = cached_block();
+    if (reuse) {
+      r.d_out = S->out_free[ob].back();
+      S->out_free[ob].pop_back();
+      S->out_free_bytes -= ob;
+    }
+    r.out_alloc = ob;
     int rc = PEVAL_OK;
     if (S->simulate) {
       rc = make_resident(S, sp);
@@ -290,8 +339,10 @@ static void admit(peval_server *S, std::unique_lock<std::mutex> &lk) {
       Plan *plan = sp.plan;
       uint64_t bytes = 0;
       if (upload) rc = upload_poly(sp, &h, &plan, &bytes);
-      if (rc == PEVAL_OK && hipMalloc(&r.d_out, std::max<uint64_t>(r.out_bytes, 256)) != hipSuccess)
+      if (rc == PEVAL_OK && !reuse && hipMalloc(&r.d_out, ob) != hipSuccess) {
+        r.d_out = nullptr;
         rc = fail(PEVAL_ENOMEM, "output");
+      }
       lk.lock();
       if (upload) {
         S->used -= estimate_poly_bytes(sp);
@@ -310,6 +361,11 @@ static void admit(peval_server *S, std::unique_lock<std::mutex> &lk) {
     }
     S->pending.pop_front();
     if (rc != PEVAL_OK) {
+      if (r.d_out) {  // a reused block goes back to the pool
+        S->out_free[ob].push_back(r.d_out);
+        S->out_free_bytes += ob;
+        r.d_out = nullptr;
+      }
       r.status = rc;
       S->done_q.push_back(r.id);
       S->rejected++;
@@ -318,7 +374,7 @@ static void admit(peval_server *S, std::unique_lock<std::mutex> &lk) {
     }
     sp.refs++;
     sp.last_used = ++S->clock;
-    S->used += r.out_bytes + r.reserve;
+    S->used += (reuse ? 0 : ob) + r.reserve;
     S->peak = std::max(S->peak, S->used);
     r.admitted = true;
     S->active.push_back(r.id);
@@ -557,7 +613,7 @@ static void copier_main(peval_server *S, int idx) {
       r.status = fail(rc, "result copy failed");
       S->done_q.push_back(r.id);
       S->polys[r.poly].refs--;
-      S->used -= r.out_bytes + r.reserve;
+      release_output(S, r);
       S->cv_done.notify_all();
       continue;
     }
@@ -583,12 +639,6 @@ static void worker_main(peval_server *S) {
       }
     }
     bool busy = !S->inflight.empty();
-    // hipFree waits for the device, so outputs are freed when it is idle, or
-    // in one go once many have piled up
-    if (!S->to_free.empty() && (!busy || S->to_free.size() >= 512)) {
-      for (void *p : S->to_free) (void)hipFree(p);
-      S->to_free.clear();
-    }
     S->cv_work.wait_for(lk, std::chrono::microseconds(busy ? 50 : 2000));
   }
 }
@@ -714,7 +764,7 @@ extern "C" int peval_server_submit(peval_server *S, uint64_t poly_id, const uint
   r.cmax = std::max<uint32_t>(r.cmax, 1);
   r.reserve = slice_scratch_bound(sp, r.ts, r.cmax) * 2;  // two passes may hold slices of it
   // a request that cannot fit even alone is refused now
-  const uint64_t alone = r.out_bytes + r.reserve + estimate_poly_bytes(sp);
+  const uint64_t alone = out_block(r.out_bytes) + r.reserve + estimate_poly_bytes(sp);
   if (alone > S->budget) {
     S->rejected++;
     return fail(PEVAL_ENOMEM, "request needs about %llu bytes, budget is %llu", (unsigned long long)alone,
@@ -866,7 +916,8 @@ extern "C" int peval_server_destroy(peval_server *S) {
   }
   for (auto &kv : S->reqs)
     if (kv.second.d_out) (void)hipFree(kv.second.d_out);
-  for (void *p : S->to_free) (void)hipFree(p);
+  for (auto &kv : S->out_free)
+    for (void *p : kv.second) (void)hipFree(p);
   for (auto &kv : S->polys)
     if (kv.second.h) peval_destroy(kv.second.h);
   for (int k = 0; k < kStreams; ++k) {
