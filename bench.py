@@ -70,6 +70,8 @@ def parse():
     ap.add_argument("--duration", type=float, default=3.0, help="served stream: seconds of arrivals")
     ap.add_argument("--pool", type=int, default=20, help="served stream: polynomials (last 20%% start cold)")
     ap.add_argument("--budget-gb", type=float, default=64.0)
+    ap.add_argument("--sweep", default="250,500,1000,4000", help="served stream: other arrival rates (paced)")
+    ap.add_argument("--tight-gb", type=float, default=2.0, help="served stream: a run under this HBM budget (0: skip)")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-smax", type=float, default=1e6)
     ap.add_argument("--tuning", default="", help="K,P,C override")
@@ -292,7 +294,7 @@ def serve_main(args):
     # each result has been consumed
     G = [srv._meta[pid][2] for pid in pids]
     wb = [4 if w.p < 2**31 else 8 for w in pool]
-    max_bytes = max(r.T * G[r.poly_index] * wb[r.poly_index] for r in reqs)
+    max_bytes = max(2048 * G[j] * wb[j] for j in range(len(pool)))  # T <= 2^11 in every stream
     n_buf = 256
     bufs = [torch.empty(max_bytes, dtype=torch.uint8, pin_memory=True).numpy() for _ in range(n_buf)]
     free_bufs = list(range(n_buf))
@@ -302,7 +304,7 @@ def serve_main(args):
         n = r.T * G[r.poly_index]
         return bufs[b][: n * wb[r.poly_index]].view(dt).reshape(r.T, G[r.poly_index])
 
-    def stream(paced: bool):
+    def stream(paced: bool, reqs=reqs, srv=srv, pids=pids):
         """Submit every request (at its arrival time if paced, else at once);
         a collector thread waits for them in order and releases them."""
         srv.reset_stats()
@@ -337,47 +339,82 @@ def serve_main(args):
             except Exception as e:  # surface it to the submitting thread
                 errors.append(e)
 
-        col = threading.Thread(target=collector)
+        col = threading.Thread(target=collector, daemon=True)
         col.start()
         t0 = time.perf_counter()
         lag = 0.0
-        for r in reqs:
-            if paced:
-                delay = r.arrival_s - (time.perf_counter() - t0)
-                if delay > 0:
-                    time.sleep(delay)
-                else:
-                    lag = max(lag, -delay)
-            t_wait = time.perf_counter()
-            while True:
+        refused = 0
+        try:
+            for r in reqs:
+                if paced:
+                    delay = r.arrival_s - (time.perf_counter() - t0)
+                    if delay > 0:
+                        time.sleep(delay)
+                    else:
+                        lag = max(lag, -delay)
+                t_wait = time.perf_counter()
+                while True:
+                    with lock:
+                        bi = free_bufs.pop() if free_bufs else None
+                    if bi is not None:
+                        break
+                    if errors:
+                        raise errors[0]
+                    if time.perf_counter() - t_wait > 120:
+                        raise RuntimeError("no result buffer came back within 120 s")
+                    time.sleep(0.0001)
                 with lock:
-                    bi = free_bufs.pop() if free_bufs else None
-                if bi is not None:
-                    break
-                if errors:
-                    raise errors[0]
-                if time.perf_counter() - t_wait > 120:
-                    raise RuntimeError("no result buffer came back within 120 s")
-                time.sleep(0.0001)
-            with lock:
-                rid = srv.submit(pids[r.poly_index], r.beta, r.T, out=out_view(r, bi))
-                owner[rid] = bi
-                n_sub[0] += 1
+                    try:
+                        rid = srv.submit(pids[r.poly_index], r.beta, r.T, out=out_view(r, bi))
+                    except PV.PevalError as e:
+                        if e.code != PV.ENOMEM:
+                            raise
+                        refused += 1          # cannot fit the budget even alone: refused at submit
+                        free_bufs.append(bi)
+                        continue
+                    owner[rid] = bi
+                    n_sub[0] += 1
+        finally:
+            finished.set()
         submit_s = time.perf_counter() - t0
-        finished.set()
-        col.join()
+        col.join(timeout=300)
+        if col.is_alive():
+            raise RuntimeError("results did not all come back within 300 s")
         if errors:
             raise errors[0]
         print(f"serve: {'paced' if paced else 'saturated'} stream done", file=sys.stderr, flush=True)
         st = srv.stats()
         st["submit_s"] = submit_s
         st["max_submit_lag_s"] = lag
+        st["refused_at_submit"] = refused
         return st
 
     te = sum(pool[r.poly_index].s * r.T for r in reqs)
     st = stream(paced=True)
     sat = stream(paced=False)
+    # the knee: the same pool at other arrival rates
+    sweep = []
+    for rate in [float(x) for x in args.sweep.split(",") if x]:
+        rq = W.serve_stream(rate, args.duration, pool)
+        sr = stream(paced=True, reqs=rq)
+        sweep.append({"rate_per_s": rate, "requests": len(rq),
+                      "offered_term_evals_per_s": sum(pool[r.poly_index].s * r.T for r in rq) / args.duration,
+                      "value": sr["term_evals"] / sr["wall_s"], "p50_ms": sr["p50_ms"], "p99_ms": sr["p99_ms"],
+                      "max_ms": sr["max_ms"]})
+        print(f"serve: rate {rate:g} done", file=sys.stderr, flush=True)
     srv.destroy()
+    # a tight HBM budget: residency by eviction and upload, admission by memory
+    tight = None
+    if args.tight_gb > 0:
+        srv2 = PV.Server(int(args.tight_gb * (1 << 30)))
+        pids2 = [srv2.add_poly(w.p, w.exps, w.coeffs) for w in pool]
+        s2 = stream(paced=True, srv=srv2, pids=pids2)
+        tight = {"budget_gb": args.tight_gb, "value": s2["term_evals"] / s2["wall_s"], "p50_ms": s2["p50_ms"],
+                 "p99_ms": s2["p99_ms"], "max_ms": s2["max_ms"], "uploads": s2["uploads"],
+                 "evictions": s2["evictions"], "hbm_peak_gb": s2["hbm_peak"] / 2**30,
+                 "completed": s2["completed"], "refused_at_submit": s2["refused_at_submit"]}
+        srv2.destroy()
+        print("serve: tight budget done", file=sys.stderr, flush=True)
 
     # the same requests (a prefix) one at a time: a plain run into device
     # memory, then the result copied to the same kind of page-locked buffer
@@ -429,6 +466,8 @@ def serve_main(args):
         "sequential_plain": {"requests": k, "value": te_seq / el_seq, "seconds": el_seq,
                              "saturated_served_over_sequential": (sat["term_evals"] / sat["wall_s"]) / (te_seq / el_seq)},
         "generate_s": gen_s,
+        "rate_sweep": sweep,
+        "tight_budget": tight,
     }
     print(json.dumps(res), flush=True)
 

@@ -762,6 +762,8 @@ extern "C" int peval_server_submit(peval_server *S, uint64_t poly_id, const uint
   r.cmax = (uint32_t)std::min<uint64_t>(std::min<uint64_t>(want, 64), r.ts);
   while (r.cmax > 1 && slice_scratch_bound(sp, r.ts, r.cmax) * 4 > S->budget) r.cmax /= 2;
   r.cmax = std::max<uint32_t>(r.cmax, 1);
+  // a tight budget takes shorter slices rather than refusing the request
+  while (r.ts > 16 && slice_scratch_bound(sp, r.ts, r.cmax) * 4 > S->budget) r.ts = std::max<uint32_t>(16, r.ts / 2);
   r.reserve = slice_scratch_bound(sp, r.ts, r.cmax) * 2;  // two passes may hold slices of it
   // a request that cannot fit even alone is refused now
   const uint64_t alone = out_block(r.out_bytes) + r.reserve + estimate_poly_bytes(sp);
