@@ -55,13 +55,17 @@ __device__ __forceinline__ uint64_t mad_wide(uint32_t a, uint32_t b, uint64_t c)
   return (uint64_t)a * b + c;
 }
 
-// floor(a * b / 2^64) from four 32x32 products.
+// floor(a * b / 2^64) from four 32x32 products: with t = a0 b1 + hi(a0 b0)
+// and u = a1 b0 + lo(t) (neither overflows 64 bits), the high word is
+// a1 b1 + hi(t) + hi(u).  Adding hi(t) inside the last multiply-add and
+// hi(u) after it needs one register copy fewer on gfx950 than summing the
+// two high words first.
 __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) {
   uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
   uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
-  uint64_t t = mad_wide(a1, b0, __umulhi(a0, b0));
-  uint64_t u = mad_wide(a0, b1, (uint32_t)t);
-  return mad_wide(a1, b1, (t >> 32) + (u >> 32));
+  uint64_t t = mad_wide(a0, b1, __umulhi(a0, b0));
+  uint64_t u = mad_wide(a1, b0, (uint32_t)t);
+  return mad_wide(a1, b1, t >> 32) + (u >> 32);
 }
 
 // ---------------------------------------------------------------------------
