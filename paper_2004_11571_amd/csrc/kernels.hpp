@@ -201,29 +201,68 @@ __device__ __forceinline__ void wave_sync() {
 
 constexpr int kEvalBlock = 256;  // 4 waves, each independent
 
-// Transposed segmented sum of one pass of np <= P evaluations staged in st:
-// lane (h, pp) walks sub-tile h (lanes h*P .. h*P+P-1) for evaluation pp,
-// emitting a reduced partial at every segment end of the wave's endmask.
+// Transposed segmented sum of one pass of np <= P evaluations staged in st.
+// The wave's endmask marks the last lane of every segment: group ends and
+// the wave's last lane.  Lane (h, pp) walks sub-tile h (lanes h*P ..
+// h*P+P-1) for evaluation pp: segments that start and end inside the
+// sub-tile are emitted at once; the open segment before the sub-tile's first
+// end (its head) and the one after its last end (its tail) are handed, through
+// the stage, to lanes (0, pp), which chain the sub-tiles: a group that spans
+// several sub-tiles of the wave leaves it as one partial.
 // partial[(slot * C + c) * Lmax + i]: the P lanes of a sub-tile write P
 // consecutive evaluations of one slot.
 template <class A, int P>
-__device__ __forceinline__ void segmented_walk(const Stage<A, P> &st, int lane, int np, uint64_t emask,
-                                               uint32_t sbase, typename A::PT *partial, uint32_t c, uint32_t C,
-                                               uint32_t Lmax, uint32_t i0, const typename A::M &m) {
+__device__ __forceinline__ void segmented_walk(Stage<A, P> &st, int lane, int np, uint64_t emask, uint32_t sbase,
+                                               typename A::PT *partial, uint32_t c, uint32_t C, uint32_t Lmax,
+                                               uint32_t i0, const typename A::M &m) {
+  constexpr int S = 64 / P;  // sub-tiles per wave
+  constexpr uint64_t kSubMask = (P == 64) ? ~0ull : ((1ull << P) - 1ull);
   const int h = lane / P, pp = lane % P;
-  if (pp >= np) return;
-  typename A::Acc sum = A::zero();
+  const bool live = pp < np;
   typename A::PT *pcol = partial + (uint64_t)c * Lmax + i0 + pp;
   const uint64_t slot_stride = (uint64_t)C * Lmax;
+  typename A::Acc head = A::zero(), sum = A::zero();
+  if (live) {
+    bool first = true;
 #pragma unroll 4
-  for (int jj = 0; jj < P; ++jj) {
-    const int src = h * P + jj;
-    A::add_walk(sum, st.get(src, pp), m);
-    if ((emask >> src) & 1ull) {
-      const uint32_t slot = sbase + (uint32_t)__popcll(emask & ((1ull << src) - 1ull));
-      pcol[slot * slot_stride] = A::reduce(sum, m);
-      sum = A::zero();
+    for (int jj = 0; jj < P; ++jj) {
+      const int src = h * P + jj;
+      A::add_walk(sum, st.get(src, pp), m);
+      if ((emask >> src) & 1ull) {
+        if (first) {
+          head = sum;
+          first = false;
+        } else {
+          const uint32_t slot = sbase + (uint32_t)__popcll(emask & ((1ull << src) - 1ull));
+          pcol[slot * slot_stride] = A::reduce(sum, m);
+        }
+        sum = A::zero();
+      }
     }
+  }
+  wave_sync();  // the staged values are read; rows h*P and h*P+1 now take head and tail
+  if (live) {
+    st.put(h * P, pp, head);
+    st.put(h * P + 1, pp, sum);
+  }
+  wave_sync();
+  if (h == 0 && live) {
+    typename A::Acc carry = A::zero();
+#pragma unroll
+    for (int hh = 0; hh < S; ++hh) {
+      const uint64_t bits = (emask >> (hh * P)) & kSubMask;
+      if (bits) {  // wave-uniform: the carried segment closes at this sub-tile's first end
+        typename A::Acc hd = st.get(hh * P, pp);
+        A::add_walk(hd, carry, m);
+        const int first_end = hh * P + (int)__builtin_ctzll(bits);
+        const uint32_t slot = sbase + (uint32_t)__popcll(emask & ((1ull << first_end) - 1ull));
+        pcol[slot * slot_stride] = A::reduce(hd, m);
+        carry = st.get(hh * P + 1, pp);
+      } else {
+        A::add_walk(carry, st.get(hh * P + 1, pp), m);
+      }
+    }
+    // the wave's last lane always ends a segment, so the final carry is empty
   }
 }
 

@@ -185,7 +185,9 @@ HostPlan build_host_plan(const std::vector<uint64_t> &grp_off, uint32_t K, uint3
     uint64_t mask = 0;
     for (uint32_t l = 0; l < 64; ++l) {
       uint64_t t = w * 64 + l;
-      bool end = (l % P == P - 1) || (t + 1 == hp.NT) || (tgrp[t] != tgrp[t + 1]);
+      // segment ends: group changes and the wave's last lane (sub-tiles of one
+      // group are merged inside the wave by the walk)
+      bool end = (l == 63) || (t + 1 == hp.NT) || (tgrp[t] != tgrp[t + 1]);
       if (end) {
         mask |= 1ull << l;
         per_group[tgrp[t]] += 1;

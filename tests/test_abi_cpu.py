@@ -90,7 +90,7 @@ def _check_layout(sizes, K, P):
     # threads of a group are contiguous and in group order
     real = grp_of_thread[grp_of_thread >= 0]
     assert (np.diff(real) >= 0).all()
-    # segment ends: group boundaries and sub-tile boundaries; slots per group contiguous
+    # segment ends: group boundaries and wave ends; slots per group contiguous
     slots = []
     last = -1
     for w in range(NW):
@@ -102,8 +102,11 @@ def _check_layout(sizes, K, P):
             last = g
             if (m >> l) & 1:
                 slots.append(g)
-            if l % P == P - 1:
-                assert (m >> l) & 1
+            if l == 63:
+                assert (m >> l) & 1          # a segment never leaves its wave open
+            elif (m >> l) & 1:
+                g2 = grp_of_thread[j + 1] if grp_of_thread[j + 1] >= 0 else len(sizes) - 1
+                assert g2 != g                # only group changes end a segment inside a wave
             if j + 1 < NT:
                 g2 = grp_of_thread[j + 1] if grp_of_thread[j + 1] >= 0 else len(sizes) - 1
                 if g2 != g:
