@@ -210,8 +210,9 @@ constexpr int kEvalBlock = 256;  // 4 waves, each independent
 // the stage, to lanes (0, pp), which chain the sub-tiles: a group that spans
 // several sub-tiles of the wave leaves it as one partial.
 // partial[(slot * C + c) * Lmax + i]: the P lanes of a sub-tile write P
-// consecutive evaluations of one slot.
-template <class A, int P>
+// consecutive evaluations of one slot.  Merge = false is the plain walk for
+// layouts whose endmask also closes every sub-tile: every end is emitted.
+template <class A, int P, bool Merge = true>
 __device__ __forceinline__ void segmented_walk(Stage<A, P> &st, int lane, int np, uint64_t emask, uint32_t sbase,
                                                typename A::PT *partial, uint32_t c, uint32_t C, uint32_t Lmax,
                                                uint32_t i0, const typename A::M &m) {
@@ -229,7 +230,7 @@ __device__ __forceinline__ void segmented_walk(Stage<A, P> &st, int lane, int np
       const int src = h * P + jj;
       A::add_walk(sum, st.get(src, pp), m);
       if ((emask >> src) & 1ull) {
-        if (first) {
+        if (Merge && first) {
           head = sum;
           first = false;
         } else {
@@ -240,6 +241,7 @@ __device__ __forceinline__ void segmented_walk(Stage<A, P> &st, int lane, int np
       }
     }
   }
+  if (!Merge) return;
   wave_sync();  // the staged values are read; rows h*P and h*P+1 now take head and tail
   if (live) {
     st.put(h * P, pp, head);

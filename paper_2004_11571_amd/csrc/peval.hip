@@ -158,7 +158,7 @@ extern "C" int peval_prof_read(double *ms, uint64_t *launches) {
 // ---------------------------------------------------------------------------
 namespace peval {
 
-HostPlan build_host_plan(const std::vector<uint64_t> &grp_off, uint32_t K, uint32_t P) {
+HostPlan build_host_plan(const std::vector<uint64_t> &grp_off, uint32_t K, uint32_t P, bool subtile_ends) {
   HostPlan hp;
   const uint64_t G = grp_off.size() - 1;
   uint64_t nt_real = 0;
@@ -186,8 +186,9 @@ HostPlan build_host_plan(const std::vector<uint64_t> &grp_off, uint32_t K, uint3
     for (uint32_t l = 0; l < 64; ++l) {
       uint64_t t = w * 64 + l;
       // segment ends: group changes and the wave's last lane (sub-tiles of one
-      // group are merged inside the wave by the walk)
-      bool end = (l == 63) || (t + 1 == hp.NT) || (tgrp[t] != tgrp[t + 1]);
+      // group are merged inside the wave by the walk), or every sub-tile end
+      // for the walk that does not merge
+      bool end = (l == 63) || (t + 1 == hp.NT) || (tgrp[t] != tgrp[t + 1]) || (subtile_ends && l % P == P - 1);
       if (end) {
         mask |= 1ull << l;
         per_group[tgrp[t]] += 1;
@@ -215,7 +216,7 @@ extern "C" int peval_layout(const uint64_t *group_sizes, uint64_t G, uint32_t K,
     if (group_sizes[g] == 0) return fail(PEVAL_EINVAL, "empty group %llu", (unsigned long long)g);
     off[g + 1] = off[g] + group_sizes[g];
   }
-  HostPlan hp = build_host_plan(off, K, P);
+  HostPlan hp = build_host_plan(off, K, P, false);
   sizes[0] = hp.NT;
   sizes[1] = hp.NW;
   sizes[2] = hp.nslots;
@@ -269,14 +270,14 @@ static void free_plan(Plan &pl) {
 }
 
 namespace peval {
-int get_plan(peval_poly *h, uint32_t K, uint32_t P, Plan **out) {
-  uint32_t key = K << 8 | P;
+int get_plan(peval_poly *h, uint32_t K, uint32_t P, Plan **out, bool subtile_ends) {
+  uint32_t key = (subtile_ends ? 1u << 16 : 0u) | K << 8 | P;
   auto it = h->plans.find(key);
   if (it != h->plans.end()) {
     *out = &it->second;
     return PEVAL_OK;
   }
-  HostPlan hp = build_host_plan(h->grp_off, K, P);
+  HostPlan hp = build_host_plan(h->grp_off, K, P, subtile_ends);
   Plan pl;
   pl.K = K;
   pl.P = P;

@@ -45,7 +45,7 @@ struct HostPlan {
   std::vector<uint32_t> slot_base;
   std::vector<uint32_t> slot_off;
 };
-HostPlan build_host_plan(const std::vector<uint64_t> &grp_off, uint32_t K, uint32_t P);
+HostPlan build_host_plan(const std::vector<uint64_t> &grp_off, uint32_t K, uint32_t P, bool subtile_ends);
 
 struct Tuning {
   uint32_t K, P, C;
@@ -97,7 +97,7 @@ struct peval_poly {
   uint16_t *d_exps = nullptr;          // (n - 2) * s tail exponents
   uint64_t resident_bytes = 0;
 
-  std::map<uint32_t, peval::Plan> plans;  // key K << 8 | P
+  std::map<uint32_t, peval::Plan> plans;  // key (sub-tile ends) << 16 | K << 8 | P
   peval::Scratch tabval, tabquot, lam, gam, gamq, partial, outbuf;
 
   uint32_t tune_K = 0, tune_P = 0, tune_C = 0;  // 0 = automatic
@@ -132,7 +132,9 @@ Tuning choose_tuning(const peval_poly *h, uint32_t T);
 bool tune_cache_lookup(const peval_poly *h, uint32_t T, Tuning *out);
 
 int ensure(Scratch &sc, size_t bytes, peval_poly *h);
-int get_plan(peval_poly *h, uint32_t K, uint32_t P, Plan **out);
+// subtile_ends: every P-lane sub-tile also ends a segment (layout of the walk
+// that does not merge sub-tiles, used by the point mode)
+int get_plan(peval_poly *h, uint32_t K, uint32_t P, Plan **out, bool subtile_ends = false);
 int check_run_args(peval_poly *h, const uint64_t *beta, uint64_t t0, uint32_t T, BetaArg *ba);
 int run_locked(peval_poly *h, const BetaArg &ba, uint64_t t0, uint32_t T, void *dev_out, hipStream_t st,
                const Tuning &tu);

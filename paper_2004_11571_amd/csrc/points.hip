@@ -141,7 +141,7 @@ int run_points_impl(peval_poly *h, const uint64_t *points, uint32_t T, void *dev
   const uint32_t ntail = h->n - 2;
   const FactorPlan &fp = h->fplan;
   Plan *pl = nullptr;
-  PEVAL_TRY(get_plan(h, K, kPointsP, &pl));
+  PEVAL_TRY(get_plan(h, K, kPointsP, &pl, true));
   auto eval = points_kernel_for<A>(K, fp.nf);
   if (!eval) return fail(PEVAL_EINVAL, "no point kernel for K=%u with %u factors", K, fp.nf);
 

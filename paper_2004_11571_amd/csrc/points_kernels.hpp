@@ -16,8 +16,10 @@
 //   points_prep_kernel   per thread slot: a_i, its quotient, packed entry
 //                        indices (once per polynomial and thread layout)
 //   points_eval_kernel   per point: the block stages the point's tables in
-//                        LDS, every thread sums its K terms; then the same
-//                        segmented walk as the power path
+//                        LDS, every thread sums its K terms; then the
+//                        segmented walk of the power path, without the
+//                        merge of sub-tiles (a pass holds only 8 points, too
+//                        few to pay for the merge)
 //
 // The thread layout, partial-sum layout and combine are those of the power
 // path, so the images come out in the same dense T x G form.
@@ -199,7 +201,7 @@ __global__ __launch_bounds__(kEvalBlock) void points_eval_kernel(PointsArgs<A> a
     }
     if (active) {
       wave_sync();
-      segmented_walk<A, P>(stage[warp], lane, np, emask, sbase, a.partial, c, a.C, a.Lmax, i0, a.m);
+      segmented_walk<A, P, false>(stage[warp], lane, np, emask, sbase, a.partial, c, a.C, a.Lmax, i0, a.m);
       wave_sync();
     }
   }
