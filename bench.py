@@ -528,14 +528,23 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    PV.prof_read()  # drop anything recorded so far
-    PV.prof_enable(True)
-    torch.cuda.synchronize()
+    # timed steps: no per-kernel events in the way
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # the same steps again with HIP events around every kernel launch, for
+    # the per-kernel times and the roofline
+    prof_steps = min(args.steps, 500)
+    PV.prof_read()  # drop anything recorded so far
+    PV.prof_enable(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(prof_steps):
+        step()
+    torch.cuda.synchronize()
+    prof_elapsed = time.perf_counter() - t1
     PV.prof_enable(False)
     kern = PV.prof_read()
 
@@ -543,7 +552,23 @@ def main():
     value = te * args.steps / elapsed
     eval_ms, eval_n = kern["eval"]
     eval_avg_s = eval_ms / max(eval_n, 1) / 1e3
-    te_per_launch = te * args.steps / max(eval_n, 1)
+    te_per_launch = te * prof_steps / max(eval_n, 1)
+    # the whole pass as one replay of a captured graph (a batch of one): no
+    # per-kernel launch cost on the host
+    graph = None
+    if not points_mode:
+        b = PV.Batch([poly], [w.T])
+        for _ in range(3):
+            b.run([w.beta], [out], stream=stream)
+        torch.cuda.synchronize()
+        gsteps = min(args.steps, 500)
+        t2 = time.perf_counter()
+        for _ in range(gsteps):
+            b.run([w.beta], [out], stream=stream)
+        torch.cuda.synchronize()
+        gel = time.perf_counter() - t2
+        b.destroy()
+        graph = {"ms_per_step": gel / gsteps * 1e3, "value": te * gsteps / gel, "steps": gsteps}
     arith = poly.arith()
     if points_mode:
         ops = points_ops(poly.elem_bytes, nf)
@@ -578,7 +603,9 @@ def main():
                    "arith": "int" if points_mode else arith,
                    "points": "uniform random in [1,p)^(n-2)" if points_mode else "powers of one base point"},
         "roofline": roof,
-        "kernels_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in kern.items()},
+        "kernels_ms_per_step": {k: v[0] / max(prof_steps, 1) for k, v in kern.items()},
+        "profiled_ms_per_step": prof_elapsed / prof_steps * 1e3,
+        "graph_replay": graph,
         "create_s": create_s,
     }
 

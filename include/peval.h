@@ -253,8 +253,9 @@ int peval_tune_load(const char *path);
  * t = t0s[j] .. t0s[j]+Ts[j]-1 (t0s may be NULL: all 1) into dev_outs[j]
  * (device, Ts[j] x G_j residues of that polynomial's width), on `stream`.
  * Results equal those of peval_run_async member by member.  Consecutive
- * runs of one batch are ordered; the call returns after enqueueing, but
- * waits for the previous run of the same batch to finish first.
+ * runs of one batch are ordered on the device (also across streams); the
+ * call returns after enqueueing and blocks only when the run table it stages
+ * (four staging buffers in rotation) still awaits its upload.
  *
  * peval_batch_info fills info[5]: members, work items, persistent blocks,
  * scratch bytes, term-evaluations per run.

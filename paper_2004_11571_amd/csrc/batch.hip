@@ -213,11 +213,16 @@ int batch_enqueue(const BatchCore &b, hipStream_t st) {
 
 using namespace peval;
 
+constexpr int kRunSlots = 4;  // run tables staged in rotation, so that runs pipeline
+
 struct peval_batch {
   BatchCore core;
   std::vector<peval_poly *> polys;
   std::vector<uint32_t> Ts;
-  BatchRun *h_run = nullptr;  // pinned staging for the run table
+  BatchRun *h_run[kRunSlots] = {};        // pinned staging for the run table
+  hipEvent_t copied[kRunSlots] = {};      // its upload has been consumed
+  bool slot_used[kRunSlots] = {};
+  int next_slot = 0;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -234,7 +239,10 @@ static void batch_free(peval_batch *b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
   if (b->done) (void)hipEventDestroy(b->done);
-  if (b->h_run) (void)hipHostFree(b->h_run);
+  for (int k = 0; k < kRunSlots; ++k) {
+    if (b->copied[k]) (void)hipEventDestroy(b->copied[k]);
+    if (b->h_run[k]) (void)hipHostFree(b->h_run[k]);
+  }
   batch_release(b->core);
   delete b;
 }
@@ -277,9 +285,13 @@ extern "C" int peval_batch_create(uint32_t count, peval_poly *const *polys, cons
   for (auto &m : mem) m.C = member_chains(*m.plan, m.T, target);
   int rc = batch_build(b->core, mem);
   if (rc != PEVAL_OK) return bail(rc);
-  if (hipHostMalloc((void **)&b->h_run, count * sizeof(BatchRun), hipHostMallocDefault) != hipSuccess)
-    return bail(fail(PEVAL_ENOMEM, "pinned staging"));
-  memset(b->h_run, 0, count * sizeof(BatchRun));
+  for (int k = 0; k < kRunSlots; ++k) {
+    if (hipHostMalloc((void **)&b->h_run[k], count * sizeof(BatchRun), hipHostMallocDefault) != hipSuccess)
+      return bail(fail(PEVAL_ENOMEM, "pinned staging"));
+    memset(b->h_run[k], 0, count * sizeof(BatchRun));
+    if (hipEventCreateWithFlags(&b->copied[k], hipEventDisableTiming) != hipSuccess)
+      return bail(fail(PEVAL_EDEVICE, "event creation"));
+  }
   if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess)
     return bail(fail(PEVAL_EDEVICE, "event creation"));
   if (b->use_graph) {
@@ -311,17 +323,25 @@ extern "C" int peval_batch_run(peval_batch *b, const uint64_t *const *betas, con
   }
   std::lock_guard<std::mutex> lk(b->mu);
   hipStream_t st = (hipStream_t)stream;
-  // the staging buffer is reused: wait until the previous upload has been consumed
-  if (b->have_done) HIP_TRY(hipEventSynchronize(b->done));
+  // staging slots rotate: only a slot whose upload (kRunSlots runs back) has
+  // not been consumed yet makes the host wait
+  const int slot = b->next_slot;
+  b->next_slot = (slot + 1) % kRunSlots;
+  if (b->slot_used[slot]) HIP_TRY(hipEventSynchronize(b->copied[slot]));
   for (uint32_t j = 0; j < count; ++j) {
-    BatchRun &r = b->h_run[j];
+    BatchRun &r = b->h_run[slot][j];
     memset(&r.beta, 0, sizeof r.beta);
     const peval_poly *h = b->polys[j];
     for (uint32_t k = 0; k + 2 < h->n; ++k) r.beta.b[k] = betas[j][k] % h->p;
     r.t0 = t0s ? t0s[j] : 1;
     r.out = dev_outs[j];
   }
-  HIP_TRY(hipMemcpyAsync(b->core.d_run, b->h_run, count * sizeof(BatchRun), hipMemcpyHostToDevice, st));
+  // runs share the device run table and scratch: a run on another stream
+  // starts after the previous one on the device, not on the host
+  if (b->have_done) HIP_TRY(hipStreamWaitEvent(st, b->done, 0));
+  HIP_TRY(hipMemcpyAsync(b->core.d_run, b->h_run[slot], count * sizeof(BatchRun), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipEventRecord(b->copied[slot], st));
+  b->slot_used[slot] = true;
   if (b->use_graph) {
     HIP_TRY(hipGraphLaunch(b->exec, st));
   } else {

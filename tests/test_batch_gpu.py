@@ -95,3 +95,31 @@ def test_batch_edge_members():
     finally:
         for q in polys:
             q.destroy()
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_runs_pipeline_across_streams(graph):
+    """Six runs enqueued back to back, alternating between two streams, with
+    no host synchronisation in between: each run's outputs equal the plain
+    runs at its own base points (runs share scratch, so they must be ordered
+    on the device)."""
+    import torch
+    ws = _mixed(12, 2e4, 3)
+    polys = [PV.Poly(w.p, w.exps, w.coeffs) for w in ws]
+    Ts = [w.T for w in ws]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    try:
+        with PV.Batch(polys, Ts, graph=graph) as b:
+            runs = []
+            for rep in range(6):
+                betas = [np.asarray((w.beta.astype(object) * (rep + 2)) % w.p, np.uint64) for w in ws]
+                outs = _outs(polys, Ts)
+                b.run(betas, outs, stream=streams[rep % 2])
+                runs.append((betas, outs))
+            torch.cuda.synchronize()
+            for rep, (betas, outs) in enumerate(runs):
+                for q, w, beta, o in zip(polys, ws, betas, outs):
+                    assert np.array_equal(_host(q, o), q.run(beta, w.T)), (rep, w.name)
+    finally:
+        for q in polys:
+            q.destroy()
