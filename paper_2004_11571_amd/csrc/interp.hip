@@ -72,7 +72,7 @@ int interp_impl(peval_poly *h, const BetaArg &beta, const void *images, uint64_t
   PEVAL_TRY(interp_setup(h));
   PEVAL_TRY(ensure(h->tabval, (size_t)std::max<uint32_t>(h->tab_total, 1) * w, h));
   PEVAL_TRY(ensure(h->tabquot, (size_t)std::max<uint32_t>(h->tab_total, 1) * w, h));
-  PEVAL_TRY(ensure(h->iscr, (size_t)6 * h->s * w, h));
+  PEVAL_TRY(ensure(h->iscr, ((size_t)7 * h->s + h->G) * w, h));
   interp_status_reset<<<1, 64, 0, st>>>(status);
   HIP_TRY(hipGetLastError());
   if (ntail) {
@@ -97,6 +97,7 @@ int interp_impl(peval_poly *h, const BetaArg &beta, const void *images, uint64_t
   a.cquot = scr + 3 * h->s;
   a.bval = scr + 4 * h->s;
   a.dval = scr + 5 * h->s;
+  a.qval = scr + 6 * h->s;
   a.task_group = h->d_task_group;
   a.task_first = h->d_task_first;
   a.ntasks = h->ntasks;
@@ -121,6 +122,8 @@ int interp_impl(peval_poly *h, const BetaArg &beta, const void *images, uint64_t
       interp_group_kernel<A, 1024><<<(unsigned)h->G, 1024, shmem, st>>>(a);
     else
       interp_group_kernel<A, 256><<<(unsigned)h->G, 256, shmem, st>>>(a);
+    HIP_TRY(hipGetLastError());
+    interp_bcoef_kernel<A><<<(unsigned)((h->ntasks + 3) / 4), 256, 0, st>>>(a);
     HIP_TRY(hipGetLastError());
   }
   {

@@ -18,7 +18,8 @@
 //                        column c laid out along the sorted terms, with
 //                        Shoup quotients
 //   interp_group_kernel  one block per group: Q by m multiplications with
-//                        (z - v_j) in LDS, then the coefficients of B and Q'
+//                        (z - v_j) in LDS
+//   interp_bcoef_kernel  over the whole chip: the coefficients of B and Q'
 //   interp_solve_kernel  per term, over the whole chip: B(v_j) and Q'(v_j)
 //                        by Horner, one inversion, the result scattered to
 //                        the caller's term order
@@ -59,6 +60,7 @@ struct InterpArgs {
   T *cval, *cquot;          // s: group image columns along the sorted terms
   T *bval;                  // s: coefficients of B per group
   T *dval;                  // s: coefficients of Q' per group
+  T *qval;                  // s + G: coefficients of Q per group (group g at grp_off[g] + g)
   const uint32_t *task_group, *task_first;  // per wave of the solve: group, first term
   uint64_t ntasks;
   uint64_t *out;            // s coefficients in the caller's order
@@ -95,11 +97,10 @@ __global__ void interp_prep_kernel(InterpArgs<A> a) {
   a.cquot[i] = shoup_quot(c, a.m);
 }
 
-// Per group (one block of BS threads): Q in LDS, then b_l and the
-// coefficients (l+1) q_{l+1} of Q', both written along the sorted terms.
-// Thread tid owns coefficients tid + r*BS, r < kInterpPer, so a group may
-// have up to kInterpPer * BS - 1 terms.  The operand of the next step (v of
-// the next root, c of the next k) is loaded one step ahead.
+// Per group (one block of BS threads): Q = prod (z - v_i) in LDS, written
+// out at the end.  Thread tid owns coefficients tid + r*BS, r < kInterpPer,
+// so a group may have up to kInterpPer * BS - 1 terms.  The next root is
+// loaded one step ahead.
 template <class A, int BS>
 __global__ __launch_bounds__(BS) void interp_group_kernel(InterpArgs<A> a) {
   using T = typename A::T;
@@ -140,29 +141,37 @@ __global__ __launch_bounds__(BS) void interp_group_kernel(InterpArgs<A> a) {
     vq = vqn;
   }
 
-  // b_l = sum_{k=0}^{m-1-l} q_{k+l+1} c_{k+1}, for l = tid + r*BS at once
-  typename A::Acc acc[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) acc[r] = A::zero();
-  T c = a.cval[base], cq = a.cquot[base];
-  for (uint32_t k = 0; k < m; ++k) {
-    const uint32_t knext = (k + 1 < m) ? k + 1 : k;
-    const T cn = a.cval[base + knext], cqn = a.cquot[base + knext];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const uint32_t l = tid + r * BS;
-      if (l + k < m) A::add(acc[r], A::mul_lazy(q[k + l + 1], c, cq, a.m));
-    }
-    c = cn;
-    cq = cqn;
+  // Q leaves LDS for the chip-wide kernels
+  T *qg = a.qval + base + g;
+  for (uint32_t k = tid; k <= m; k += BS) qg[k] = q[k];
+}
+
+// b_l = sum_{k=0}^{m-1-l} q_{k+l+1} c_{k+1} and the Q' coefficient
+// (l+1) q_{l+1}, over the whole chip: one wave per 64 consecutive l of one
+// group (the solve kernel's tasks), so c_{k+1} is wave-uniform.
+template <class A>
+__global__ __launch_bounds__(256) void interp_bcoef_kernel(InterpArgs<A> a) {
+  using T = typename A::T;
+  const uint64_t task = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+  if (task >= a.ntasks) return;  // whole waves leave together
+  const uint32_t g = __builtin_amdgcn_readfirstlane(a.task_group[task]);
+  const uint32_t l0 = __builtin_amdgcn_readfirstlane(a.task_first[task]);
+  const uint64_t base = __builtin_amdgcn_readfirstlane(a.grp_off[g]);
+  const uint32_t m = __builtin_amdgcn_readfirstlane(a.grp_off[g + 1]) - (uint32_t)base;
+  const uint32_t l = l0 + (threadIdx.x & 63);
+  const T *qg = a.qval + base + g;
+  const T *cv = a.cval + base, *cq = a.cquot + base;
+  // lanes of the wave stop at m-1-l: the longest runs first, the others idle
+  const uint32_t kend = (l < m) ? m - l : 0;  // k < m - l
+  const uint32_t kmax = m - l0;                // longest run in the wave
+  typename A::Acc acc = A::zero();
+  for (uint32_t k = 0; k < kmax; ++k) {
+    const T c = cv[k], q = (k < kend) ? qg[k + l + 1] : (T)0;
+    A::add(acc, A::mul_lazy(q, c, cq[k], a.m));
   }
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    const uint32_t l = tid + r * BS;
-    if (l < m) {
-      a.bval[base + l] = A::reduce(acc[r], a.m);
-      a.dval[base + l] = mul_mod(q[l + 1], (T)((l + 1) % a.m.p), a.m);
-    }
+  if (l < m) {
+    a.bval[base + l] = A::reduce(acc, a.m);
+    a.dval[base + l] = mul_mod(qg[l + 1], (T)((l + 1) % a.m.p), a.m);
   }
 }
 
