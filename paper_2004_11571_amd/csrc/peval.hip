@@ -450,8 +450,14 @@ extern "C" int peval_info(const peval_poly *h, peval_info_t *info) {
   info->s = h->s;
   info->G = h->G;
   uint64_t b = h->resident_bytes + h->tabval.bytes + h->tabquot.bytes + h->lam.bytes + h->gam.bytes +
-               h->gamq.bytes + h->partial.bytes + h->outbuf.bytes;
+               h->gamq.bytes + h->partial.bytes + h->outbuf.bytes + h->ptab.bytes + h->ptsbuf.bytes +
+               h->iscr.bytes;
   for (auto &kv : h->plans) b += kv.second.device_bytes;
+  for (auto &kv : h->pprep) {
+    auto pl = h->plans.find(1u << 16 | kv.first << 8 | peval::kPointsP);
+    if (pl != h->plans.end()) b += (uint64_t)kv.first * pl->second.NT * (2ull * h->w + 8);
+  }
+  if (h->d_order) b += (uint64_t)h->s * 4 + (h->G + 1) * 4 + h->G * 4 + h->ntasks * 8;
   info->device_bytes = b;
   for (uint32_t k = 0; k < h->n && k < 32; ++k) info->max_exp[k] = h->max_exp[k];
   return PEVAL_OK;

@@ -161,11 +161,15 @@ static uint32_t slice_evals(const peval_server *S, const SPoly &sp, uint32_t T) 
   return (uint32_t)std::min<double>(T, std::max(16.0, ts));
 }
 
-static void evict_for(peval_server *S, uint64_t need) {
+// Evict least recently used resident polynomials with no request in flight
+// until `need` more bytes fit; `keep` (the polynomial of the request being
+// admitted, whose residency the caller has already counted) is never chosen.
+static void evict_for(peval_server *S, uint64_t need, uint64_t keep) {
   while (S->used + need > S->budget) {
     SPoly *victim = nullptr;
     for (auto &kv : S->polys) {
       SPoly &sp = kv.second;
+      if (kv.first == keep) continue;
       if ((sp.h || (S->simulate && sp.bytes)) && sp.refs == 0 && (!victim || sp.last_used < victim->last_used))
         victim = &sp;
     }
@@ -317,7 +321,7 @@ static void admit(peval_server *S, std::unique_lock<std::mutex> &lk) {
     };
     auto need_now = [&] { return (cached_block() ? 0 : ob) + r.reserve + (resident ? 0 : estimate_poly_bytes(sp)); };
     if (S->used + need_now() > S->budget) trim_out_cache(S, need_now());
-    if (S->used + need_now() > S->budget) evict_for(S, need_now());
+    if (S->used + need_now() > S->budget) evict_for(S, need_now(), r.poly);
     if (S->used + need_now() > S->budget) return;  // head of line waits for memory
     const bool reuse = cached_block();
     if (reuse) {

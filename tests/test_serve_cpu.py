@@ -103,3 +103,33 @@ def test_completion_queue_order():
         with pytest.raises(PV.PevalError) as e:
             srv.next_done(10)
         assert e.value.code == PV.ETIMEOUT
+
+
+def test_admission_never_evicts_its_own_polynomial():
+    """A request that needs room must not evict the polynomial it is about to
+    use (the budget check has already counted that polynomial as resident):
+    a is resident and least recently used, b resident after it; the first
+    request on a that does not fit beside b must evict b, not a."""
+    budget = 6 << 20
+    qa, qb = _poly(20, 40000, n=6), _poly(21, 40000, n=6)
+    triggered = False
+    T = 1 << 14
+    while T >= 8 and not triggered:
+        with PV.Server(budget, simulate=True) as srv:
+            srv.configure(slice_work=1e6, sim_rate=1e9)
+            pa, pb = srv.add_poly(qa.p, qa.exps, qa.coeffs), srv.add_poly(qb.p, qb.exps, qb.coeffs)
+            srv.wait(srv.submit(pa, np.ones(4, np.uint64), 8), 20000)
+            srv.wait(srv.submit(pb, np.ones(4, np.uint64), 8), 20000)
+            try:
+                rid = srv.submit(pa, np.ones(4, np.uint64), T)
+            except PV.PevalError:      # larger than the budget even alone
+                T //= 2
+                continue
+            srv.wait(rid, 20000)
+            st = srv.stats()
+            assert st["hbm_peak"] <= budget
+            if st["evictions"]:
+                triggered = True
+                assert st["uploads"] == 2, st   # b was evicted; a was neither evicted nor uploaded again
+        T //= 2
+    assert triggered, "no request size needed an eviction"
