@@ -49,6 +49,31 @@ int interp_setup(peval_poly *h) {
       tf.push_back((uint32_t)j);
     }
   h->ntasks = tg.size();
+  // few groups: Q as 4 or 8 sub-products per group (one block each), merged
+  // pairwise in chip-wide levels, so that more than G blocks share the work
+  uint64_t mx = 0;
+  for (uint64_t g = 0; g < h->G; ++g) mx = std::max<uint64_t>(mx, h->grp_off[g + 1] - h->grp_off[g]);
+  h->interp_H = (mx < 256 || h->G >= 256) ? 1 : (h->G < 128 ? 8 : 4);
+  for (uint32_t lvl = 0, Hl = h->interp_H; Hl > 1; ++lvl, Hl /= 2) {
+    std::vector<uint32_t> mg, mp, mf;
+    for (uint64_t g = 0; g < h->G; ++g) {
+      const uint64_t m = h->grp_off[g + 1] - h->grp_off[g];
+      for (uint32_t j = 0; j < Hl / 2; ++j) {
+        const uint64_t deg = ((2 * j + 2) * m) / Hl - ((2 * j) * m) / Hl;  // degree of the product
+        for (uint64_t k = 0; k <= deg; k += 64) {
+          mg.push_back((uint32_t)g);
+          mp.push_back(j);
+          mf.push_back((uint32_t)k);
+        }
+      }
+    }
+    h->mt_n[lvl] = mg.size();
+    for (int q = 0; q < 3; ++q) {
+      const std::vector<uint32_t> &src = q == 0 ? mg : q == 1 ? mp : mf;
+      HIP_TRY(hipMalloc((void **)&h->d_mt[lvl][q], std::max<size_t>(src.size(), 1) * 4));
+      HIP_TRY(hipMemcpy(h->d_mt[lvl][q], src.data(), src.size() * 4, hipMemcpyHostToDevice));
+    }
+  }
   HIP_TRY(hipMalloc((void **)&h->d_task_group, std::max<size_t>(tg.size(), 1) * 4));
   HIP_TRY(hipMalloc((void **)&h->d_task_first, std::max<size_t>(tf.size(), 1) * 4));
   HIP_TRY(hipMemcpy(h->d_task_group, tg.data(), tg.size() * 4, hipMemcpyHostToDevice));
@@ -72,7 +97,9 @@ int interp_impl(peval_poly *h, const BetaArg &beta, const void *images, uint64_t
   PEVAL_TRY(interp_setup(h));
   PEVAL_TRY(ensure(h->tabval, (size_t)std::max<uint32_t>(h->tab_total, 1) * w, h));
   PEVAL_TRY(ensure(h->tabquot, (size_t)std::max<uint32_t>(h->tab_total, 1) * w, h));
-  PEVAL_TRY(ensure(h->iscr, ((size_t)7 * h->s + h->G) * w, h));
+  // m, m', c, c', b, Q' (s each), Q (s + G), and two buffers of parts with
+  // quotients that the merge levels alternate between (s + 8G, twice each)
+  PEVAL_TRY(ensure(h->iscr, ((size_t)11 * h->s + 33 * h->G) * w, h));
   interp_status_reset<<<1, 64, 0, st>>>(status);
   HIP_TRY(hipGetLastError());
   if (ntail) {
@@ -98,6 +125,13 @@ int interp_impl(peval_poly *h, const BetaArg &beta, const void *images, uint64_t
   a.bval = scr + 4 * h->s;
   a.dval = scr + 5 * h->s;
   a.qval = scr + 6 * h->s;
+  T_ *lv0 = a.qval + h->s + h->G;           // parts (values, quotients)
+  T_ *lv0q = lv0 + h->s + 8 * h->G;
+  T_ *lv1 = lv0q + h->s + 8 * h->G;         // the next level, then back to lv0
+  T_ *lv1q = lv1 + h->s + 8 * h->G;
+  a.part_val = lv0;
+  a.part_quot = lv0q;
+  a.H = h->interp_H;
   a.task_group = h->d_task_group;
   a.task_first = h->d_task_first;
   a.ntasks = h->ntasks;
@@ -113,16 +147,29 @@ int interp_impl(peval_poly *h, const BetaArg &beta, const void *images, uint64_t
     HIP_TRY(hipGetLastError());
   }
   {
-    // blocks of 256 threads hold groups of up to 8 * 256 - 1 terms; larger
-    // groups (or few groups, which then need whole CUs) take 1024
+    // blocks of 256 threads hold parts of up to 8 * 256 - 1 roots, larger
+    // parts take 1024
     const uint64_t mx = largest_group(h);
-    const size_t shmem = (mx + 1) * w;
+    const uint64_t part = (mx + a.H - 1) / a.H + 1;
+    const size_t shmem = (part + 1) * w;
+    const unsigned blocks = (unsigned)(h->G * a.H);
     ProfScope ps(st, 2);
-    if (mx >= (uint64_t)kInterpPer * 256 || h->G < 256)
-      interp_group_kernel<A, 1024><<<(unsigned)h->G, 1024, shmem, st>>>(a);
+    if (part >= (uint64_t)kInterpPer * 256)
+      interp_group_kernel<A, 1024><<<blocks, 1024, shmem, st>>>(a);
     else
-      interp_group_kernel<A, 256><<<(unsigned)h->G, 256, shmem, st>>>(a);
+      interp_group_kernel<A, 256><<<blocks, 256, shmem, st>>>(a);
     HIP_TRY(hipGetLastError());
+    T_ *in_v = lv0, *in_q = lv0q;
+    for (uint32_t lvl = 0, Hl = a.H; Hl > 1; ++lvl, Hl /= 2) {
+      const bool last = Hl == 2;
+      T_ *nv = (in_v == lv0) ? lv1 : lv0, *nq = (in_v == lv0) ? lv1q : lv0q;
+      T_ *out_v = last ? a.qval : nv, *out_q = last ? nullptr : nq;
+      interp_merge_kernel<A><<<(unsigned)((h->mt_n[lvl] + 3) / 4), 256, 0, st>>>(
+          a, in_v, in_q, out_v, out_q, Hl, h->d_mt[lvl][0], h->d_mt[lvl][1], h->d_mt[lvl][2], h->mt_n[lvl]);
+      HIP_TRY(hipGetLastError());
+      in_v = out_v;
+      in_q = out_q;
+    }
     interp_bcoef_kernel<A><<<(unsigned)((h->ntasks + 3) / 4), 256, 0, st>>>(a);
     HIP_TRY(hipGetLastError());
   }

@@ -17,8 +17,9 @@
 //   interp_prep_kernel   v_i (from the power tables) and the group's image
 //                        column c laid out along the sorted terms, with
 //                        Shoup quotients
-//   interp_group_kernel  one block per group: Q by m multiplications with
+//   interp_group_kernel  one block per part of a group: the product of its
 //                        (z - v_j) in LDS
+//   interp_merge_kernel  few groups: parts multiplied pairwise over the chip
 //   interp_bcoef_kernel  over the whole chip: the coefficients of B and Q'
 //   interp_solve_kernel  per term, over the whole chip: B(v_j) and Q'(v_j)
 //                        by Horner, one inversion, the result scattered to
@@ -61,6 +62,11 @@ struct InterpArgs {
   T *bval;                  // s: coefficients of B per group
   T *dval;                  // s: coefficients of Q' per group
   T *qval;                  // s + G: coefficients of Q per group (group g at grp_off[g] + g)
+  // Q as H sub-products per group, merged pairwise: with H_l parts per
+  // group, part h of group g sits at grp_off[g] + g*H_l + start + h, where
+  // start = (h*m)/H_l is its first root.  Values and Shoup quotients.
+  T *part_val, *part_quot;  // the H parts of the group kernel (H > 1)
+  uint32_t H;               // sub-products per group (1, 4 or 8)
   const uint32_t *task_group, *task_first;  // per wave of the solve: group, first term
   uint64_t ntasks;
   uint64_t *out;            // s coefficients in the caller's order
@@ -97,29 +103,33 @@ __global__ void interp_prep_kernel(InterpArgs<A> a) {
   a.cquot[i] = shoup_quot(c, a.m);
 }
 
-// Per group (one block of BS threads): Q = prod (z - v_i) in LDS, written
-// out at the end.  Thread tid owns coefficients tid + r*BS, r < kInterpPer,
-// so a group may have up to kInterpPer * BS - 1 terms.  The next root is
-// loaded one step ahead.
+// Per part of a group (H blocks per group): prod (z - v_i) over the part's
+// roots in LDS, written out at the end (with quotients when parts are
+// merged afterwards).  Thread tid owns coefficients tid + r*BS, r <
+// kInterpPer, so a part may have up to kInterpPer * BS - 1 roots.  The next
+// root is loaded one step ahead.
 template <class A, int BS>
 __global__ __launch_bounds__(BS) void interp_group_kernel(InterpArgs<A> a) {
   using T = typename A::T;
   constexpr int R = kInterpPer;
   extern __shared__ __align__(16) unsigned char smem[];
-  T *q = reinterpret_cast<T *>(smem);  // m + 1 coefficients
+  T *q = reinterpret_cast<T *>(smem);  // d + 1 coefficients
   const T p = (T)a.m.p;
-  const uint32_t g = a.gorder[blockIdx.x];
+  const uint32_t g = a.gorder[blockIdx.x / a.H];
+  const uint32_t h = blockIdx.x % a.H;
   const uint64_t base = a.grp_off[g];
   const uint32_t m = a.grp_off[g + 1] - (uint32_t)base;
+  const uint32_t r0 = (uint32_t)(((uint64_t)h * m) / a.H), r1 = (uint32_t)(((uint64_t)(h + 1) * m) / a.H);
+  const uint32_t d = r1 - r0;  // roots of this part (may be 0)
   const int tid = threadIdx.x;
 
-  // Q(z) = 1, then multiply by (z - v_i) for each term of the group
-  for (uint32_t k = tid; k <= m; k += BS) q[k] = (k == 0) ? (T)(1 % p) : (T)0;
+  // prod (z - v_i) over the part's roots, starting from 1
+  for (uint32_t k = tid; k <= d; k += BS) q[k] = (k == 0) ? (T)(1 % p) : (T)0;
   __syncthreads();
-  T v = a.mval[base], vq = a.mquot[base];
-  for (uint32_t i = 0; i < m; ++i) {
-    const uint32_t inext = (i + 1 < m) ? i + 1 : i;
-    const T vn = a.mval[base + inext], vqn = a.mquot[base + inext];
+  T v = d ? a.mval[base + r0] : (T)0, vq = d ? a.mquot[base + r0] : (T)0;
+  for (uint32_t i = 0; i < d; ++i) {
+    const uint32_t inext = (i + 1 < d) ? i + 1 : i;
+    const T vn = a.mval[base + r0 + inext], vqn = a.mquot[base + r0 + inext];
     T nv[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -141,9 +151,62 @@ __global__ __launch_bounds__(BS) void interp_group_kernel(InterpArgs<A> a) {
     vq = vqn;
   }
 
-  // Q leaves LDS for the chip-wide kernels
-  T *qg = a.qval + base + g;
-  for (uint32_t k = tid; k <= m; k += BS) qg[k] = q[k];
+  // the part leaves LDS: straight into Q when there is one part per group
+  const uint64_t at = base + (uint64_t)g * a.H + r0 + h;
+  T *out = (a.H == 1) ? a.qval + at : a.part_val + at;
+  T *outq = (a.H == 1) ? nullptr : a.part_quot + at;
+  for (uint32_t k = tid; k <= d; k += BS) {
+    out[k] = q[k];
+    if (outq) outq[k] = shoup_quot(q[k], a.m);
+  }
+}
+
+// One merge level: for every group, parts 2j and 2j+1 of a level with H_l
+// parts per group multiply into part j of the next level (H_l / 2 parts).  One wave per
+// 64 consecutive coefficients of one product (tasks built on the host);
+// the left operand's coefficient is wave-uniform, the right one carries its
+// Shoup quotient.
+template <class A>
+__global__ __launch_bounds__(256) void interp_merge_kernel(InterpArgs<A> a, const typename A::T *in_v,
+                                                           const typename A::T *in_q, typename A::T *out_v,
+                                                           typename A::T *out_q, uint32_t Hl,
+                                                           const uint32_t *mt_group, const uint32_t *mt_pair,
+                                                           const uint32_t *mt_first, uint64_t ntasks) {
+  using T = typename A::T;
+  const uint64_t task = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / 64;
+  if (task >= ntasks) return;  // whole waves leave together
+  const uint32_t g = __builtin_amdgcn_readfirstlane(mt_group[task]);
+  const uint32_t j = __builtin_amdgcn_readfirstlane(mt_pair[task]);
+  const uint32_t k0 = __builtin_amdgcn_readfirstlane(mt_first[task]);
+  const uint64_t base = __builtin_amdgcn_readfirstlane(a.grp_off[g]);
+  const uint32_t m = __builtin_amdgcn_readfirstlane(a.grp_off[g + 1]) - (uint32_t)base;
+  auto start = [&](uint32_t hh, uint32_t HH) { return (uint32_t)(((uint64_t)hh * m) / HH); };
+  const uint32_t ha = 2 * j, hb = 2 * j + 1;
+  const uint32_t ra = start(ha, Hl), rb = start(hb, Hl), re = start(hb + 1, Hl);
+  const uint32_t da = rb - ra, db = re - rb;
+  const T *av = in_v + base + (uint64_t)g * Hl + ra + ha;
+  const T *bv = in_v + base + (uint64_t)g * Hl + rb + hb;
+  const T *bq = in_q + base + (uint64_t)g * Hl + rb + hb;
+  const uint32_t Hn = Hl / 2;
+  const uint64_t at = base + (uint64_t)g * Hn + start(j, Hn) + j;
+  T *out = out_v + at;
+  T *outq = out_q ? out_q + at : nullptr;  // quotients only where the part is merged again
+  const uint32_t k = k0 + (threadIdx.x & 63);
+  typename A::Acc acc = A::zero();
+  // out_k = sum_i a_i b_{k-i}; the wave's 64 outputs need i in [k0-db, k0+63]
+  const uint32_t i_lo = (k0 > db) ? k0 - db : 0;
+  const uint32_t i_hi = (k0 + 63 < da) ? k0 + 63 : da;
+  for (uint32_t i = i_lo; i <= i_hi; ++i) {
+    const T ai = av[i];
+    const bool in = k >= i && k - i <= db;
+    const T b = in ? bv[k - i] : (T)0, q = in ? bq[k - i] : (T)0;
+    A::add(acc, A::mul_lazy(ai, b, q, a.m));
+  }
+  if (k <= da + db) {
+    const T r = A::reduce(acc, a.m);
+    out[k] = r;
+    if (outq) outq[k] = shoup_quot(r, a.m);
+  }
 }
 
 // b_l = sum_{k=0}^{m-1-l} q_{k+l+1} c_{k+1} and the Q' coefficient

@@ -432,6 +432,9 @@ extern "C" int peval_destroy(peval_poly *h) {
     if (h->d_gorder) (void)hipFree(h->d_gorder);
     if (h->d_task_group) (void)hipFree(h->d_task_group);
     if (h->d_task_first) (void)hipFree(h->d_task_first);
+    for (auto &lv : h->d_mt)
+      for (uint32_t *p : lv)
+        if (p) (void)hipFree(p);
     if (h->d_coeff) (void)hipFree(h->d_coeff);
     if (h->d_exps) (void)hipFree(h->d_exps);
     if (h->done) (void)hipEventDestroy(h->done);

@@ -113,6 +113,9 @@ struct peval_poly {
   uint32_t *d_order = nullptr, *d_grp_off32 = nullptr, *d_gorder = nullptr;
   uint32_t *d_task_group = nullptr, *d_task_first = nullptr;
   uint64_t ntasks = 0;
+  uint32_t interp_H = 1;                       // sub-products per group for Q
+  uint32_t *d_mt[3][3] = {};                   // merge tasks per level: group, pair, first
+  uint64_t mt_n[3] = {0, 0, 0};
   peval::Scratch iscr;
 
   hipStream_t stream = nullptr;  // for peval_run
