@@ -256,9 +256,20 @@ __global__ __launch_bounds__(256) void interp_solve_kernel(InterpArgs<A> a) {
   const T v = live ? a.mval[base + j] : (T)0, vq = live ? a.mquot[base + j] : (T)0;
   const T *bv = a.bval + base, *dv = a.dval + base;
   T b = 0, d = 0;
-  for (uint32_t l = m; l-- > 0;) {
-    b = add_mod(canon(A::mul_lazy(b, v, vq, a.m), p), bv[l], p);
-    d = add_mod(canon(A::mul_lazy(d, v, vq, a.m), p), dv[l], p);
+  if (a.m.p < (T)(~(T)0 / 3)) {
+    // 3p fits the word: the running values stay lazy in [0, 3p) (a Shoup
+    // product takes any input below 2^64 and returns below 2p)
+    for (uint32_t l = m; l-- > 0;) {
+      b = A::mul_lazy(b, v, vq, a.m) + bv[l];
+      d = A::mul_lazy(d, v, vq, a.m) + dv[l];
+    }
+    b = canon(canon(b, p), p);
+    d = canon(canon(d, p), p);
+  } else {
+    for (uint32_t l = m; l-- > 0;) {
+      b = add_mod(canon(A::mul_lazy(b, v, vq, a.m), p), bv[l], p);
+      d = add_mod(canon(A::mul_lazy(d, v, vq, a.m), p), dv[l], p);
+    }
   }
   if (!live) return;
   const T den = canon(A::mul_lazy(d, v, vq, a.m), p);
