@@ -424,6 +424,7 @@ extern "C" int peval_destroy(peval_poly *h) {
       (void)hipFree(kv.second.pa);
       (void)hipFree(kv.second.paq);
       (void)hipFree(kv.second.pidx);
+      (void)hipFree(kv.second.slot_term);
     }
     h->pprep.clear();
     release(h->iscr);
@@ -458,7 +459,7 @@ extern "C" int peval_info(const peval_poly *h, peval_info_t *info) {
   for (auto &kv : h->plans) b += kv.second.device_bytes;
   for (auto &kv : h->pprep) {
     auto pl = h->plans.find(1u << 16 | kv.first << 8 | peval::kPointsP);
-    if (pl != h->plans.end()) b += (uint64_t)kv.first * pl->second.NT * (2ull * h->w + 8);
+    if (pl != h->plans.end()) b += (uint64_t)kv.first * pl->second.NT * (2ull * h->w + 12);
   }
   if (h->d_order) b += (uint64_t)h->s * 4 + (h->G + 1) * 4 + h->G * 4 + h->ntasks * 8;
   info->device_bytes = b;

@@ -55,6 +55,7 @@ struct Tuning {
 struct PointsPrep {
   void *pa = nullptr, *paq = nullptr;
   uint64_t *pidx = nullptr;
+  uint32_t *slot_term = nullptr;
 };
 
 // HIP-event timing of one kernel launch (active while profiling is enabled).

@@ -114,6 +114,47 @@ const Mod32 &mod_for<W32>(const peval_poly *h) { return h->m32; }
 template <class A>
 using PointsFn = void (*)(PointsArgs<A>);
 
+// Which term fills each thread slot (k, j), [K][NT]: the threads of a group
+// keep the group (the segmented walk relies on it), but the group's terms
+// are sorted by their entry in the first factor table, then the second, and
+// dealt k-major over the group's threads, so that at every k neighbouring
+// lanes hold terms with close entries (few LDS bank conflicts in the
+// lookups).  0xffffffff marks padding.
+int deal_slots(peval_poly *h, uint32_t K, uint64_t NT, const FactorPlan &fp, std::vector<uint32_t> *out) {
+  const uint64_t s = h->s;
+  const uint32_t ntail = h->n - 2;
+  std::vector<uint16_t> ex((size_t)ntail * s);
+  if (!ex.empty()) HIP_TRY(hipMemcpy(ex.data(), h->d_exps, ex.size() * 2, hipMemcpyDeviceToHost));
+  auto key = [&](uint64_t i) {
+    uint32_t local[kMaxFactors] = {0, 0, 0, 0};
+    for (uint32_t d = 0; d < fp.ndig; ++d) {
+      const uint32_t e = ex[(size_t)fp.var[d] * s + i];
+      local[fp.fac[d]] += ((e >> fp.shift[d]) & fp.mask[d]) * fp.stride[d];
+    }
+    return ((uint64_t)local[0] << 32) | local[1];
+  };
+  HostPlan hp = build_host_plan(h->grp_off, K, kPointsP, true);
+  if (hp.NT != NT) return fail(PEVAL_EINVAL, "thread layout mismatch");
+  out->assign((size_t)K * NT, 0xffffffffu);
+  std::vector<std::pair<uint64_t, uint32_t>> terms;
+  uint64_t j = 0;
+  for (uint64_t g = 0; g < h->G; ++g) {
+    const uint64_t b = h->grp_off[g], e = h->grp_off[g + 1];
+    const uint64_t j0 = j;
+    while (j < NT && hp.thr_cnt[j] && hp.thr_first[j] < e) ++j;
+    const uint64_t nt = j - j0;  // ceil(m / K) threads
+    terms.clear();
+    for (uint64_t i = b; i < e; ++i) terms.emplace_back(key(i), (uint32_t)i);
+    std::stable_sort(terms.begin(), terms.end(),
+                     [](const std::pair<uint64_t, uint32_t> &x, const std::pair<uint64_t, uint32_t> &y) {
+                       return x.first < y.first;
+                     });
+    for (uint64_t q = 0; q < terms.size(); ++q)
+      (*out)[(q / nt) * NT + j0 + q % nt] = terms[q].second;
+  }
+  return PEVAL_OK;
+}
+
 template <class A>
 PointsFn<A> points_kernel_for(uint32_t K, uint32_t NF) {
 #define PEVAL_PCASE(k, f) \
@@ -147,16 +188,20 @@ int run_points_impl(peval_poly *h, const uint64_t *points, uint32_t T, void *dev
 
   auto it = h->pprep.find(K);
   if (it == h->pprep.end()) {  // per-slot coefficients, quotients and entry indices
+    std::vector<uint32_t> slot_term;
+    PEVAL_TRY(deal_slots(h, K, pl->NT, fp, &slot_term));
     PointsPrep pp;
     const uint64_t total = (uint64_t)K * pl->NT;
     HIP_TRY(hipMalloc(&pp.pa, total * w));
     HIP_TRY(hipMalloc(&pp.paq, total * w));
     HIP_TRY(hipMalloc((void **)&pp.pidx, total * sizeof(uint64_t)));
+    HIP_TRY(hipMalloc((void **)&pp.slot_term, total * sizeof(uint32_t)));
     it = h->pprep.emplace(K, pp).first;
+    HIP_TRY(hipMemcpy(pp.slot_term, slot_term.data(), total * sizeof(uint32_t), hipMemcpyHostToDevice));
     ProfScope ps(st, 1);
     points_prep_kernel<A><<<(unsigned)((total + 255) / 256), 256, 0, st>>>(
-        (const T_ *)h->d_coeff, h->d_exps, pl->d_thr_first, pl->d_thr_cnt, h->s, pl->NT, K, fp, (T_ *)pp.pa,
-        (T_ *)pp.paq, pp.pidx, m);
+        (const T_ *)h->d_coeff, h->d_exps, pp.slot_term, h->s, pl->NT, K, fp, (T_ *)pp.pa, (T_ *)pp.paq, pp.pidx,
+        m);
     HIP_TRY(hipGetLastError());
   }
   const PointsPrep &pp = it->second;

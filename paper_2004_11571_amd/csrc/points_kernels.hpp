@@ -14,7 +14,10 @@
 //
 //   points_table_kernel  factor tables for every point of the launch (HBM)
 //   points_prep_kernel   per thread slot: a_i, its quotient, packed entry
-//                        indices (once per polynomial and thread layout)
+//                        indices (once per polynomial and thread layout);
+//                        a group's terms are dealt to its slots sorted by
+//                        their table entries, k-major, so that neighbouring
+//                        lanes read neighbouring entries
 //   points_eval_kernel   per point: the block stages the point's tables in
 //                        LDS, every thread sums its K terms; then the
 //                        segmented walk of the power path, without the
@@ -110,19 +113,21 @@ __global__ void points_table_kernel(const uint64_t *points, uint32_t ntail, uint
 }
 
 // Per thread slot (k, j): coefficient, quotient and the entry index of each
-// factor; padding slots get a zero coefficient and in-range indices.
+// factor.  slot_term[k * NT + j] names the term of the slot (a term of the
+// thread's own group, in any order: the group's sum does not depend on it),
+// or 0xffffffff for padding, which gets a zero coefficient and in-range
+// indices.
 template <class A>
-__global__ void points_prep_kernel(const typename A::T *coeff, const uint16_t *exps, const uint32_t *thr_first,
-                                   const uint8_t *thr_cnt, uint64_t s, uint64_t NT, uint32_t K, FactorPlan fp,
-                                   typename A::T *pa, typename A::T *paq, uint64_t *pidx, typename A::M m) {
+__global__ void points_prep_kernel(const typename A::T *coeff, const uint16_t *exps, const uint32_t *slot_term,
+                                   uint64_t s, uint64_t NT, uint32_t K, FactorPlan fp, typename A::T *pa,
+                                   typename A::T *paq, uint64_t *pidx, typename A::M m) {
   const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (uint64_t)K * NT) return;
-  const uint32_t k = (uint32_t)(idx / NT);
-  const uint64_t j = idx - (uint64_t)k * NT;
+  const uint32_t term = slot_term[idx];
   uint32_t local[kMaxFactors] = {0, 0, 0, 0};
   typename A::T a = 0, aq = 0;
-  if (k < thr_cnt[j]) {
-    const uint64_t i = (uint64_t)thr_first[j] + k;
+  if (term != 0xffffffffu) {
+    const uint64_t i = term;
     a = coeff[i];
     aq = shoup_quot(a, m);
     for (uint32_t d = 0; d < fp.ndig; ++d) {
