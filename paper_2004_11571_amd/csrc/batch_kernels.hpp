@@ -28,14 +28,27 @@ __device__ __forceinline__ uint32_t find_poly(const uint64_t *prefix, uint32_t c
   return lo;
 }
 
+// Member of entry idx for a flattened kernel: thread 0 finds the member of
+// the block's first entry (blocks cover consecutive entries), and each thread
+// steps forward from there, rarely more than once.
+__device__ __forceinline__ uint32_t find_poly_block(const uint64_t *prefix, uint32_t count, uint64_t idx,
+                                                    uint32_t *shared_first) {
+  if (threadIdx.x == 0) shared_first[0] = find_poly(prefix, count, (uint64_t)blockIdx.x * blockDim.x);
+  __syncthreads();
+  uint32_t j = shared_first[0];
+  while (j + 1 < count && prefix[j + 1] <= idx) ++j;
+  return j;
+}
+
 __global__ void batch_reset_kernel(uint32_t *counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0;
 }
 
 __global__ void batch_power_kernel(const BatchDesc *D, const BatchRun *R, uint32_t count, const uint64_t *prefix) {
+  __shared__ uint32_t first;
   uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t j = find_poly_block(prefix, count, idx, &first);  // every thread takes part in the barrier
   if (idx >= prefix[count]) return;
-  uint32_t j = find_poly(prefix, count, idx);
   const BatchDesc &d = D[j];
   uint32_t local = (uint32_t)(idx - prefix[j]);
   if (d.w == 4)
@@ -69,9 +82,10 @@ __device__ __forceinline__ void batch_mono_one(const BatchDesc &d, uint64_t t0, 
 }
 
 __global__ void batch_mono_kernel(const BatchDesc *D, const BatchRun *R, uint32_t count, const uint64_t *prefix) {
+  __shared__ uint32_t first;
   uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t j = find_poly_block(prefix, count, idx, &first);  // every thread takes part in the barrier
   if (idx >= prefix[count]) return;
-  uint32_t j = find_poly(prefix, count, idx);
   const BatchDesc &d = D[j];
   uint64_t local = idx - prefix[j];
   if (d.w == 4) batch_mono_one<W32>(d, R[j].t0, local, d.m32);
