@@ -553,6 +553,19 @@ def main():
     eval_ms, eval_n = kern["eval"]
     eval_avg_s = eval_ms / max(eval_n, 1) / 1e3
     te_per_launch = te * prof_steps / max(eval_n, 1)
+    # the boundary's host form: peval_run into a page-locked host buffer
+    # (the rate including the device-to-host copy of the images)
+    host_out = None
+    if not points_mode:
+        hb = torch.empty((w.T, poly.G), dtype=dt, pin_memory=True).numpy().view(poly.dtype)
+        poly.run(w.beta, w.T, out=hb)
+        hsteps = min(args.steps, 200)
+        t3 = time.perf_counter()
+        for _ in range(hsteps):
+            poly.run(w.beta, w.T, out=hb)
+        hel = time.perf_counter() - t3
+        host_out = {"ms_per_step": hel / hsteps * 1e3, "value": te * hsteps / hel, "steps": hsteps,
+                    "output_MB": w.T * poly.G * poly.elem_bytes / 1e6}
     # the whole pass as one replay of a captured graph (a batch of one): no
     # per-kernel launch cost on the host
     graph = None
@@ -606,6 +619,7 @@ def main():
         "kernels_ms_per_step": {k: v[0] / max(prof_steps, 1) for k, v in kern.items()},
         "profiled_ms_per_step": prof_elapsed / prof_steps * 1e3,
         "graph_replay": graph,
+        "host_output": host_out,
         "create_s": create_s,
     }
 

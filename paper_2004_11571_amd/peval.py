@@ -175,10 +175,14 @@ class Poly:
             raise ValueError(f"beta must have n-2 = {self.n - 2} entries")
         return b
 
-    def run(self, beta, T: int) -> np.ndarray:
-        """(T, G) images b_1..b_T in host memory."""
+    def run(self, beta, T: int, out=None) -> np.ndarray:
+        """(T, G) images b_1..b_T in host memory (``out``: a C-contiguous
+        (T, G) array of the handle's dtype to fill, e.g. page-locked)."""
         b = self._beta(beta)
-        out = np.zeros((T, self.G), self.dtype)
+        if out is None:
+            out = np.zeros((T, self.G), self.dtype)
+        elif out.shape != (T, self.G) or out.dtype != self.dtype or not out.flags.c_contiguous:
+            raise ValueError(f"out must be a C-contiguous ({T}, {self.G}) {np.dtype(self.dtype).name} array")
         _check(lib().peval_run(self.handle, b.ctypes.data if b.size else None, T,
                                out.ctypes.data if out.size else None))
         return out

@@ -321,3 +321,53 @@ def test_pseudo_mersenne_refused():
             with pytest.raises(PV.PevalError) as ei:
                 h.set_arith("pm")
             assert ei.value.code == PV.EUNSUPPORTED
+
+
+def test_config4_full_size_sampled(orc):
+    """n=8, 1e7 terms, p = 2^63-25, T = 4096 (the large workload), automatic
+    tuning: whole oracle rows at the first, a middle and the last t, and
+    single coefficients spread over the table."""
+    import concurrent.futures as cf
+    w = W.config4()
+    _say("config4: generated")
+    with PV.Poly(w.p, w.exps, w.coeffs) as poly:
+        got = poly.run(w.beta, w.T)
+        _say("config4: tuning", poly.get_tuning(w.T), "G", poly.G)
+        gd, ge = poly.groups()
+    rows = [1, 2049, w.T]
+    with cf.ThreadPoolExecutor(len(rows)) as ex:
+        futs = {t: ex.submit(orc.evaluate, w.p, w.exps, w.coeffs, w.beta, 1, t, 1) for t in rows}
+        for t, f in futs.items():
+            assert np.array_equal(got[t - 1], f.result()[0]), t
+    rng = np.random.default_rng(44)
+    for _ in range(6):
+        t, g = int(rng.integers(1, w.T + 1)), int(rng.integers(0, len(gd)))
+        want = orc.entry(w.p, w.exps, w.coeffs, w.beta, t, int(gd[g]), int(ge[g]))
+        assert int(got[t - 1, g]) == want, (t, g)
+
+
+def test_batch_full_config_sampled(orc):
+    """The 256-member uneven batch of the benchmark (terms up to 1e6, T up to
+    2048, both primes) as one graph replay: members' first and last images
+    against the oracle for a spread of members."""
+    import torch
+    ws = W.batch_config(count=256)
+    polys = [PV.Poly(w.p, w.exps, w.coeffs) for w in ws]
+    Ts = [w.T for w in ws]
+    try:
+        with PV.Batch(polys, Ts) as b:
+            outs = [torch.empty((T, q.G), dtype=torch.int32 if q.elem_bytes == 4 else torch.int64, device="cuda")
+                    for q, T in zip(polys, Ts)]
+            b.run([w.beta for w in ws], outs)
+            torch.cuda.synchronize()
+            # the largest members and a few small ones
+            order = sorted(range(len(ws)), key=lambda j: -ws[j].s * ws[j].T)
+            for j in order[:3] + order[-3:] + [100, 200]:
+                w, q = ws[j], polys[j]
+                got = outs[j].cpu().numpy().view(q.dtype)
+                for t in (1, w.T):
+                    want = orc.evaluate(w.p, w.exps, w.coeffs, w.beta, 1, t, 8)[0]
+                    assert np.array_equal(got[t - 1].astype(np.uint64), want), (j, t)
+    finally:
+        for q in polys:
+            q.destroy()
