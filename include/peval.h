@@ -182,8 +182,12 @@ int peval_destroy(peval_poly *h);
 /*
  * Tuning knobs of the evaluation kernel for one handle (0 = automatic):
  *   K      terms held per thread (1, 2, 4, 8, 16)
- *   P      evaluations per pass before each coefficient reduction (8, 16, 32)
- *   C      independent evaluation chains (>= 1; chain c does t = t0+c, t0+c+C, ...)
+ *   P      evaluations per pass before each coefficient reduction (8, 16, 32;
+ *          the role of the paper's dependent evaluations T_d, Section 4.2)
+ *   C      independent evaluation chains (>= 1; chain c does t = t0+c,
+ *          t0+c+C, ...: the independent evaluations T_i of Section 4.2 and
+ *          Alg. 7, with Lambda_c = a_i m_i^{t0+c} and the common multiplier
+ *          m_i^C as in Fig. 3)
  * The results never depend on these; only speed does.
  */
 int peval_set_tuning(peval_poly *h, uint32_t K, uint32_t P, uint32_t C);
@@ -238,11 +242,13 @@ int peval_tune_save(const char *path);
 int peval_tune_load(const char *path);
 
 /*
- * Batched evaluation (many polynomials, uneven sizes, mixed moduli).
+ * Batched evaluation (many polynomials, uneven sizes, mixed moduli): the
+ * images of Section 2.1 / Eq. (1) by the matrix method of Section 2.3, for
+ * every member, in one pass.
  *
  * peval_batch_create plans one pass over `count` resident polynomials,
  * polys[j] evaluated Ts[j] times: it fixes every member's thread layout
- * (K from the tuning cache or the heuristic, at most 8; P = 16) and its
+ * (K from the tuning cache or the heuristic; P = 16) and its
  * chains so that the work items (one wave of one chain of one polynomial)
  * have similar costs, allocates all device scratch, and captures the pass
  * (power tables, monomials, a persistent evaluation kernel fed by a work
@@ -270,7 +276,8 @@ int peval_batch_info(const peval_batch *b, uint64_t *info);
 int peval_batch_destroy(peval_batch *b);
 
 /*
- * Serving: a request loop over resident polynomials.
+ * Serving: a request loop over resident polynomials; every request asks for
+ * the images b_1..b_T of Section 2.1 / Eq. (1) at its own base point.
  *
  * peval_server_create starts a scheduler thread on the current device.  The
  * server keeps polynomials resident within hbm_budget_bytes (resident term
@@ -293,7 +300,8 @@ int peval_batch_destroy(peval_batch *b);
  * b_1..b_T at beta into host_out (T x G residues of the polynomial's width;
  * G = number of distinct (x1, x2) exponent pairs), which must stay valid
  * until the request is done; a request that could not fit in the budget
- * even alone is refused with PEVAL_ENOMEM.  poll sets *done; wait blocks
+ * even alone is refused with PEVAL_ENOMEM (under a tight budget a request
+ * first gets shorter slices).  poll sets *done; wait blocks
  * (timeout_ms < 0: forever; PEVAL_ETIMEOUT when it expires); both return the
  * request's error if it failed.  next_done hands out finished requests in
  * completion order.  release forgets a finished request.
@@ -358,7 +366,8 @@ int peval_prof_read(double *ms, uint64_t *launches);
  *   thr_first[NT], thr_cnt[NT]  first term (offset in the sorted order) and
  *                               number of real terms (0..K) of each thread;
  *   endmask[NW]    bit l: lane l of the wave closes a segment (its group ends
- *                  there or its sub-tile of P lanes ends there);
+ *                  there, or it is the wave's last lane: the evaluation
+ *                  kernel merges a group's sub-tiles inside the wave);
  *   slot_base[NW]  index of the wave's first slot;
  *   slot_off[G+1]  slots of group g are slot_off[g] .. slot_off[g+1]-1.
  * Any of the array arguments may be NULL to skip it; otherwise they must hold
