@@ -77,7 +77,7 @@ def parse():
     ap.add_argument("--tuning", default="", help="K,P,C override")
     ap.add_argument("--arith", default="auto", choices=["auto", "int", "fp64", "pm"],
                     help="modular product of the evaluation kernel (fp64: the paper's Alg. 2, p < 2^50)")
-    ap.add_argument("--cpu-rows", type=int, default=96, help="oracle sample: first rows of the images")
+    ap.add_argument("--cpu-rows", type=int, default=192, help="oracle sample: first rows of the images")
     ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
