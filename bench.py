@@ -626,7 +626,7 @@ def main():
     if not args.no_cpu:
         from oracle import Oracle
         orc = Oracle()
-        rows = args.cpu_rows
+        rows = min(args.cpu_rows, w.T)
         threads = min(args.cpu_threads, rows)
         c0 = time.perf_counter()
         if points_mode:
