@@ -7,8 +7,9 @@
 //                        (the independent evaluations of Section 4.2 / Alg. 7)
 //   eval_kernel          per evaluation: coefficient reduction of the running
 //                        values, then their Hadamard product with Gamma
-//   combine_kernel       sums the partial coefficients of groups that were
-//                        split between sub-tiles and writes the dense images
+//   combine_kernel       sums the partial coefficients of groups that span
+//                        several waves (or sub-tiles, in the point mode's
+//                        layout) and writes the dense images
 //
 // Thread layout.  Terms are sorted by (x1, x2) exponents so that like
 // monomials are adjacent (Section 2.3); each group is split into runs of K
