@@ -99,10 +99,16 @@ def profile_traffic(kernel_sha: str, workload: str, kernel: str = "eval_kernel")
     return float(m_b.group(1))
 
 
-def kernel_source_sha() -> str:
+def kernel_source_sha(sources=None) -> str:
+    """Hash of the evaluation kernels' code: comments and whitespace are
+    dropped, so that only a change of the compiled code invalidates the
+    counter profiles taken on it."""
     h = hashlib.sha256()
     for f in ("kernels.hpp", "modarith.hpp", "points_kernels.hpp"):
-        h.update(open(os.path.join(ROOT, "paper_2004_11571_amd", "csrc", f), "rb").read())
+        text = sources[f] if sources else open(os.path.join(ROOT, "paper_2004_11571_amd", "csrc", f)).read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
