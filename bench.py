@@ -99,12 +99,13 @@ def profile_traffic(kernel_sha: str, workload: str, kernel: str = "eval_kernel")
     return float(m_b.group(1))
 
 
-def kernel_source_sha(sources=None) -> str:
+def kernel_source_sha(sources=None, extra=()) -> str:
     """Hash of the evaluation kernels' code: comments and whitespace are
     dropped, so that only a change of the compiled code invalidates the
-    counter profiles taken on it."""
+    counter profiles taken on it.  extra: further headers of the kernel
+    (the single-launch kernel's own)."""
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "modarith.hpp", "points_kernels.hpp"):
+    for f in ("kernels.hpp", "modarith.hpp", "points_kernels.hpp", *extra):
         text = sources[f] if sources else open(os.path.join(ROOT, "paper_2004_11571_amd", "csrc", f)).read()
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
         text = re.sub(r"//[^\n]*", " ", text)
@@ -510,6 +511,7 @@ def main():
     if args.tuning:
         poly.set_tuning(*[int(x) for x in args.tuning.split(",")])
     K, P, C = poly.get_tuning(w.T)
+    single = (K, P, C) == (0, 0, 0) and not points_mode  # one kernel for the whole run
     dt = torch.int64 if poly.elem_bytes == 8 else torch.int32
     out = torch.empty((w.T, poly.G), dtype=dt, device=dev)
     stream = torch.cuda.current_stream(dev)
@@ -594,9 +596,9 @@ def main():
         kname = "points_eval_kernel"
     else:
         ops = ALGO_OPS["fp64" if arith == "fp64" else poly.elem_bytes]
-        kname = "eval_kernel"
+        kname = "small_run_kernel" if single else "eval_kernel"
     achieved = ops * te_per_launch / eval_avg_s
-    sha = kernel_source_sha()
+    sha = kernel_source_sha(extra=("small_kernels.hpp",) if single else ())
     traffic = profile_traffic(sha, args.workload, kname)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
             "unit": "Tops/s (int32 lane-ops)", "frac": achieved / VALU_PEAK_OPS,
@@ -618,7 +620,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name + ("_random_points" if points_mode else ""), "n": w.n, "s": w.s,
                    "T": w.T, "p": w.p, "G": poly.G,
-                   "tuning": {"K": K, "P": 8 if points_mode else P, "C": C},
+                   "tuning": "single_launch" if single else {"K": K, "P": 8 if points_mode else P, "C": C},
                    "arith": "int" if points_mode else arith,
                    "points": "uniform random in [1,p)^(n-2)" if points_mode else "powers of one base point"},
         "roofline": roof,

@@ -116,6 +116,16 @@ int peval_run(peval_poly *h, const uint64_t *beta, uint32_t T, void *out);
  *          passed this call.
  * Returns once the work is enqueued.  Resuming or splitting a long run:
  * rows t0.. of a run equal a run started at t0.
+ *
+ * Small runs (s <= 8192 terms for p < 2^31, s <= 4096 otherwise, s*T <= 2^20,
+ * no group above 256 terms, power tables and one evaluation's term values
+ * within 64 KiB) take a
+ * single-launch path: one kernel builds the tables, the chain starts
+ * (Alg. 7) and every image, with one chain of consecutive evaluations per
+ * block, instead of the four kernels of the general path (Section 2.3).  It
+ * is used unless a tuning is set (peval_set_tuning), the autotuner chose a
+ * multi-kernel tuning for the shape, or the product was set explicitly
+ * (peval_set_arith with a mode other than AUTO).  Results are identical.
  */
 int peval_run_async(peval_poly *h, const uint64_t *beta, uint64_t t0, uint32_t T,
                     void *dev_out, void *stream);
@@ -218,7 +228,8 @@ int peval_set_arith(peval_poly *h, uint32_t mode);
  * (AUTO resolved). */
 int peval_get_arith(const peval_poly *h, uint32_t *mode);
 
-/* The tuning the next run with T evaluations would use. */
+/* The tuning the next run with T evaluations would use; K = P = C = 0 when
+ * it takes the single-launch path (see peval_run_async). */
 int peval_get_tuning(peval_poly *h, uint32_t T, uint32_t *K, uint32_t *P, uint32_t *C);
 
 /*
@@ -229,14 +240,17 @@ int peval_get_tuning(peval_poly *h, uint32_t T, uint32_t *K, uint32_t *P, uint32
  * half-octave grid) in a process-wide cache that every later run of a
  * matching shape uses (explicit peval_set_tuning values take precedence).
  * exhaustive = 0: coordinate search over K, then P, then C (about a dozen
- * timed runs); 1: the full grid.  Outputs (any may be NULL): the chosen
- * K, P, C and its time in ms.  Blocks until the timing runs are done.
+ * timed runs); 1: the full grid.  Where the run fits the single-launch path
+ * (with the product on AUTO) that path is timed too.  Outputs (any may be
+ * NULL): the chosen K, P, C (all 0 if the single-launch path won) and its
+ * time in ms.  Blocks until the timing runs are done.
  */
 int peval_autotune(peval_poly *h, const uint64_t *beta, uint32_t T, uint32_t exhaustive,
                    uint32_t *K, uint32_t *P, uint32_t *C, float *ms);
 
 /* Tuning cache: forget everything, or save to / merge from a text file
- * (one line per shape class: width s_class group_class T_class K P C ms). */
+ * (one line per shape class: width s_class group_class T_class K P C ms;
+ * K P C = 0 0 0 records the single-launch path). */
 int peval_tune_clear(void);
 int peval_tune_save(const char *path);
 int peval_tune_load(const char *path);

@@ -36,10 +36,12 @@ int interp_setup(peval_poly *h) {
     return h->grp_off[x + 1] - h->grp_off[x] > h->grp_off[y + 1] - h->grp_off[y];
   });
   HIP_TRY(hipMalloc((void **)&h->d_order, std::max<size_t>(h->order.size(), 1) * 4));
-  HIP_TRY(hipMalloc((void **)&h->d_grp_off32, off32.size() * 4));
+  if (!h->d_grp_off32) {
+    HIP_TRY(hipMalloc((void **)&h->d_grp_off32, off32.size() * 4));
+    HIP_TRY(hipMemcpy(h->d_grp_off32, off32.data(), off32.size() * 4, hipMemcpyHostToDevice));
+  }
   HIP_TRY(hipMalloc((void **)&h->d_gorder, std::max<size_t>(gord.size(), 1) * 4));
   HIP_TRY(hipMemcpy(h->d_order, h->order.data(), h->order.size() * 4, hipMemcpyHostToDevice));
-  HIP_TRY(hipMemcpy(h->d_grp_off32, off32.data(), off32.size() * 4, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(h->d_gorder, gord.data(), gord.size() * 4, hipMemcpyHostToDevice));
   // solve tasks: one wave per 64 consecutive terms of one group
   std::vector<uint32_t> tg, tf;

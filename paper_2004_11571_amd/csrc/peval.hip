@@ -18,6 +18,7 @@
 #include "errors.hpp"
 #include "kernels.hpp"
 #include "peval_internal.hpp"
+#include "small_kernels.hpp"
 
 using namespace peval;
 
@@ -370,6 +371,7 @@ extern "C" int peval_create(uint64_t p, uint32_t n, uint64_t s, const uint32_t *
   }
   if (s) h->grp_off.push_back(s);
   h->G = h->gd.size();
+  for (uint64_t g = 0; g < h->G; ++g) h->max_group = std::max(h->max_group, h->grp_off[g + 1] - h->grp_off[g]);
 
   // sorted structure-of-arrays: coefficients (reduced mod p) and tail exponents
   std::vector<uint8_t> coeff(s * h->w);
@@ -396,6 +398,10 @@ extern "C" int peval_create(uint64_t p, uint32_t n, uint64_t s, const uint32_t *
   if ((rc = upload(&h->d_exps, ex)) != PEVAL_OK) return bail(rc);
   h->resident_bytes = coeff.size() + ex.size() * 2;
   h->order = std::move(order);
+  if (s && s <= kSmallMaxTerms) {  // group offsets for the single-launch path
+    std::vector<uint32_t> off32(h->grp_off.begin(), h->grp_off.end());
+    if ((rc = upload(&h->d_grp_off32, off32)) != PEVAL_OK) return bail(rc);
+  }
   if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess)
     return bail(fail(PEVAL_EDEVICE, "stream creation failed"));
   if (hipEventCreateWithFlags(&h->done, hipEventDisableTiming) != hipSuccess)
@@ -461,7 +467,8 @@ extern "C" int peval_info(const peval_poly *h, peval_info_t *info) {
     auto pl = h->plans.find(1u << 16 | kv.first << 8 | peval::kPointsP);
     if (pl != h->plans.end()) b += (uint64_t)kv.first * pl->second.NT * (2ull * h->w + 12);
   }
-  if (h->d_order) b += (uint64_t)h->s * 4 + (h->G + 1) * 4 + h->G * 4 + h->ntasks * 8;
+  if (h->d_order) b += (uint64_t)h->s * 4 + h->G * 4 + h->ntasks * 8;
+  if (h->d_grp_off32) b += (h->G + 1) * 4;
   info->device_bytes = b;
   for (uint32_t k = 0; k < h->n && k < 32; ++k) info->max_exp[k] = h->max_exp[k];
   return PEVAL_OK;
@@ -513,18 +520,33 @@ Tuning heuristic_tuning(const peval_poly *h, uint32_t T) {
   return t;
 }
 
+uint32_t single_launch_L(const peval_poly *h, uint32_t T) {
+  if (!h->d_grp_off32 || T == 0 || h->s > kSmallMaxTerms || h->s * h->w > kSmallRowBytes ||
+      h->s * (uint64_t)T > kSmallMaxWork || h->max_group > kSmallMaxGroup)
+    return 0;
+  const uint64_t tab = 2ull * h->tab_total * h->w, row = h->s * (uint64_t)h->w;
+  if (tab + row > kSmallLds) return 0;
+  const uint64_t fit = (kSmallLds - tab) / row;  // evaluations whose term values fit in LDS
+  return (uint32_t)std::min<uint64_t>(fit, (T + kSmallTargetBlocks - 1) / kSmallTargetBlocks);
+}
+
 // Tuning for a run of T evaluations: explicit settings first, then the
-// autotuner's cache for this shape, then the heuristic.
+// autotuner's cache for this shape, then the heuristic.  Small runs take the
+// single-launch path unless a tuning is set, the autotuner chose a
+// multi-kernel tuning for the shape, or the product was chosen explicitly.
 Tuning choose_tuning(const peval_poly *h, uint32_t T) {
   Tuning t = heuristic_tuning(h, T);
   Tuning cached;
-  if (tune_cache_lookup(h, T, &cached)) t = cached;
+  const bool hit = tune_cache_lookup(h, T, &cached);
+  if (hit && !cached.L) t = cached;
   if (h->tune_K) t.K = h->tune_K;
   if (h->tune_P) t.P = h->tune_P;
   if (h->tune_C) t.C = h->tune_C;
   if (h->arith == 1) t.K = std::min<uint32_t>(t.K, 8);  // exact double sums of at most 8 residues
   if (T) t.C = std::min<uint32_t>(t.C, T);
   t.C = std::max<uint32_t>(t.C, 1);
+  const bool forced = h->tune_K || h->tune_P || h->tune_C;
+  if (!forced && h->arith_auto && (!hit || cached.L)) t.L = single_launch_L(h, T);
   return t;
 }
 
@@ -558,11 +580,13 @@ extern "C" int peval_set_arith(peval_poly *h, uint32_t mode) {
   std::lock_guard<std::mutex> lk(h->mu);
   if (mode == PEVAL_ARITH_PMERSENNE) {
     h->arith = 2;
+    h->arith_auto = false;
     h->mpm64 = ModPM64{h->p, (1ull << 63) - h->p, h->m64};
     if (h->w == 4) h->mpm32 = ModPM32{(uint32_t)h->p, (uint32_t)((1ull << 31) - h->p), h->m32};
     return PEVAL_OK;
   }
   h->arith = (mode == PEVAL_ARITH_FP64 || (mode == PEVAL_ARITH_AUTO && fp64_by_default(h->p))) ? 1 : 0;
+  h->arith_auto = mode == PEVAL_ARITH_AUTO;
   return PEVAL_OK;
 }
 
@@ -576,9 +600,9 @@ extern "C" int peval_get_tuning(peval_poly *h, uint32_t T, uint32_t *K, uint32_t
   if (!h || !K || !P || !C) return fail(PEVAL_EINVAL, "null argument");
   std::lock_guard<std::mutex> lk(h->mu);
   Tuning t = choose_tuning(h, T);
-  *K = t.K;
-  *P = t.P;
-  *C = t.C;
+  *K = t.L ? 0 : t.K;
+  *P = t.L ? 0 : t.P;
+  *C = t.L ? 0 : t.C;
   return PEVAL_OK;
 }
 
@@ -766,6 +790,36 @@ static int run_impl(peval_poly *h, const BetaArg &beta, uint64_t t0, uint32_t T,
   return PEVAL_OK;
 }
 
+// Single-launch path: tables, chain starts, evaluations and group sums in
+// one kernel (small runs, where the four launches would dominate).
+template <class A>
+static int run_small(peval_poly *h, const BetaArg &beta, uint64_t t0, uint32_t T, void *dev_out, hipStream_t st,
+                     uint32_t L) {
+  using T_ = typename A::T;
+  const uint64_t lds = (2ull * h->tab_total + (uint64_t)L * h->s) * sizeof(T_);
+  if (L == 0 || lds > kSmallLds || !h->d_grp_off32)
+    return fail(PEVAL_EINVAL, "single-launch path does not fit (L=%u)", L);
+  SmallArgs<A> a;
+  a.coeff = (const T_ *)h->d_coeff;
+  a.exps = h->d_exps;
+  a.grp_off = h->d_grp_off32;
+  a.out = (T_ *)dev_out;
+  a.beta = beta;
+  a.to = h->tab;
+  a.t0 = t0;
+  a.s = (uint32_t)h->s;
+  a.G = (uint32_t)h->G;
+  a.T = T;
+  a.L = L;
+  a.ntail = h->n - 2;
+  a.tab_total = h->tab_total;
+  a.m = mod_of<A>(h);
+  ProfScope ps(st, 2);
+  small_run_kernel<A><<<(T + L - 1) / L, kSmallBlock, (size_t)lds, st>>>(a);
+  HIP_TRY(hipGetLastError());
+  return PEVAL_OK;
+}
+
 namespace peval {
 
 int check_run_args(peval_poly *h, const uint64_t *beta, uint64_t t0, uint32_t T, BetaArg *ba) {
@@ -784,7 +838,9 @@ int run_locked(peval_poly *h, const BetaArg &ba, uint64_t t0, uint32_t T, void *
   HIP_TRY(hipSetDevice(h->device));
   if (h->have_done) HIP_TRY(hipStreamWaitEvent(st, h->done, 0));
   int rc;
-  if (h->w == 4)
+  if (tu.L)
+    rc = (h->w == 4) ? run_small<W32>(h, ba, t0, T, dev_out, st, tu.L) : run_small<W64>(h, ba, t0, T, dev_out, st, tu.L);
+  else if (h->w == 4)
     rc = (h->arith == 2) ? run_impl<W32, W32PM>(h, ba, t0, T, dev_out, st, tu)
                          : run_impl<W32>(h, ba, t0, T, dev_out, st, tu);
   else

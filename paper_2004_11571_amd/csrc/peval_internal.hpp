@@ -49,6 +49,7 @@ HostPlan build_host_plan(const std::vector<uint64_t> &grp_off, uint32_t K, uint3
 
 struct Tuning {
   uint32_t K, P, C;
+  uint32_t L = 0;  // > 0: the single-launch path with L evaluations per block (K, P, C unused)
 };
 
 // Per-thread-slot inputs of the point mode for one thread layout (K).
@@ -86,10 +87,12 @@ struct peval_poly {
   peval::ModPM64 mpm64{};
   peval::ModPM32 mpm32{};
   uint32_t arith = 0;  // 0: Shoup products; 1: FP64 product (Alg. 2), 2^31 <= p < 2^50; 2: pseudo-Mersenne
+  bool arith_auto = true;  // product chosen automatically (not set explicitly)
   int device = 0;
 
   std::vector<uint32_t> gd, ge;        // output columns
   std::vector<uint64_t> grp_off;       // CSR of groups over the sorted terms (G + 1)
+  uint64_t max_group = 0;              // terms of the largest group
   uint32_t max_exp[32] = {0};
   peval::TableOffsets tab{};           // power-table offsets per tail variable
   uint32_t tab_total = 0;
@@ -111,6 +114,8 @@ struct peval_poly {
 
   // interpolation (built on first use)
   std::vector<uint32_t> order;         // sorted position -> caller's term index
+  // (d_grp_off32 is uploaded at create for polynomials small enough for the
+  // single-launch path, which reads it too)
   uint32_t *d_order = nullptr, *d_grp_off32 = nullptr, *d_gorder = nullptr;
   uint32_t *d_task_group = nullptr, *d_task_first = nullptr;
   uint64_t ntasks = 0;
@@ -133,6 +138,9 @@ uint64_t padded_threads(const peval_poly *h, uint32_t K);
 uint32_t chains_for_waves(uint64_t nw, uint64_t target_waves, uint32_t T);
 Tuning heuristic_tuning(const peval_poly *h, uint32_t T);
 Tuning choose_tuning(const peval_poly *h, uint32_t T);
+// Evaluations per block of the single-launch path for T evaluations, 0 if
+// the run does not fit it.
+uint32_t single_launch_L(const peval_poly *h, uint32_t T);
 bool tune_cache_lookup(const peval_poly *h, uint32_t T, Tuning *out);
 
 int ensure(Scratch &sc, size_t bytes, peval_poly *h);

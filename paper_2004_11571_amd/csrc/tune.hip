@@ -140,13 +140,20 @@ extern "C" int peval_autotune(peval_poly *h, const uint64_t *beta, uint32_t T, u
       if (c != t2.C) PEVAL_TRY(consider(Tuning{t2.K, t2.P, c}));
     }
   }
+  // the single-launch path, where the run fits it
+  const uint32_t L = h->arith_auto ? single_launch_L(h, T) : 0;
+  if (L) {
+    Tuning t = best;
+    t.L = L;
+    PEVAL_TRY(consider(t));
+  }
   {
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune[shape_key(h, T)] = TuneEntry{best, best_ms};
   }
-  if (K) *K = best.K;
-  if (P) *P = best.P;
-  if (C) *C = best.C;
+  if (K) *K = best.L ? 0 : best.K;
+  if (P) *P = best.L ? 0 : best.P;
+  if (C) *C = best.L ? 0 : best.C;
   if (ms) *ms = best_ms;
   return PEVAL_OK;
 }
@@ -162,10 +169,12 @@ extern "C" int peval_tune_save(const char *path) {
   std::lock_guard<std::mutex> g(g_tune_mu);
   FILE *f = fopen(path, "w");
   if (!f) return fail(PEVAL_EINVAL, "cannot open %s", path);
-  fprintf(f, "# peval tuning cache: width s_class group_class T_class K P C ms\n");
-  for (auto &kv : g_tune)
+  fprintf(f, "# peval tuning cache: width s_class group_class T_class K P C ms (K P C = 0 0 0: single launch)\n");
+  for (auto &kv : g_tune) {
+    const Tuning &t = kv.second.t;
     fprintf(f, "%u %d %d %d %u %u %u %.6f\n", std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first),
-            std::get<3>(kv.first), kv.second.t.K, kv.second.t.P, kv.second.t.C, kv.second.ms);
+            std::get<3>(kv.first), t.L ? 0 : t.K, t.L ? 0 : t.P, t.L ? 0 : t.C, kv.second.ms);
+  }
   fclose(f);
   return PEVAL_OK;
 }
@@ -182,12 +191,15 @@ extern "C" int peval_tune_load(const char *path) {
     unsigned w, k, p, c;
     int sb, gb, tb;
     float ms;
-    if (sscanf(line, "%u %d %d %d %u %u %u %f", &w, &sb, &gb, &tb, &k, &p, &c, &ms) != 8 || (w != 4 && w != 8) ||
-        !valid_K(k) || !valid_P(p) || c == 0 || c > 65535) {
+    const int got = sscanf(line, "%u %d %d %d %u %u %u %f", &w, &sb, &gb, &tb, &k, &p, &c, &ms);
+    const bool single = got == 8 && k == 0 && p == 0 && c == 0;
+    if (got != 8 || (w != 4 && w != 8) || (!single && (!valid_K(k) || !valid_P(p) || c == 0 || c > 65535))) {
       rc = fail(PEVAL_EINVAL, "bad tuning line: %s", line);
       break;
     }
-    add[ShapeKey{w, sb, gb, tb}] = TuneEntry{Tuning{k, p, c}, ms};
+    Tuning t{k, p, c};
+    if (single) t.L = 1;  // recomputed for each polynomial when used
+    add[ShapeKey{w, sb, gb, tb}] = TuneEntry{t, ms};
   }
   fclose(f);
   if (rc != PEVAL_OK) return rc;

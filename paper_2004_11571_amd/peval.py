@@ -250,12 +250,14 @@ class Poly:
         _check(lib().peval_set_tuning(self.handle, K, P, C))
 
     def get_tuning(self, T: int) -> Tuple[int, int, int]:
+        """(K, P, C) of the next run of T evaluations; (0, 0, 0) for the single-launch path."""
         k, p, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
         _check(lib().peval_get_tuning(self.handle, T, ctypes.byref(k), ctypes.byref(p), ctypes.byref(c)))
         return k.value, p.value, c.value
 
     def autotune(self, beta, T: int, exhaustive: bool = False):
-        """Time candidate (K, P, C) for this polynomial and T; returns (K, P, C, ms)."""
+        """Time candidate (K, P, C) for this polynomial and T; returns (K, P, C, ms),
+        with K = P = C = 0 if the single-launch path was fastest."""
         b = self._beta(beta)
         k, pp, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
         ms = ctypes.c_float()

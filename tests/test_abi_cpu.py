@@ -142,13 +142,18 @@ def test_tune_file_validation(tmp_path):
     bad.write_text("8 10 4 20 3 16 5 0.1\n")  # K = 3 is not a kernel
     with pytest.raises(PV.PevalError):
         PV.tune_load(str(bad))
+    for partial in ("8 10 4 20 0 16 5 0.1\n", "8 10 4 20 0 0 5 0.1\n", "8 10 4 20 8 16 0 0.1\n"):
+        bad.write_text(partial)  # only K = P = C = 0 together (the single-launch path) is valid
+        with pytest.raises(PV.PevalError):
+            PV.tune_load(str(bad))
     good = tmp_path / "good.txt"
-    good.write_text("# comment\n8 10 4 20 8 16 5 0.1\n4 6 2 12 1 8 64 0.02\n")
+    good.write_text("# comment\n8 10 4 20 8 16 5 0.1\n4 6 2 12 1 8 64 0.02\n4 19 7 12 0 0 0 0.01\n")
     PV.tune_load(str(good))
     out = tmp_path / "out.txt"
     PV.tune_save(str(out))
     lines = [l for l in out.read_text().splitlines() if not l.startswith("#")]
-    assert len(lines) == 2
+    assert len(lines) == 3
+    assert "4 19 7 12 0 0 0 0.010000" in lines
     PV.tune_clear()
     PV.tune_save(str(out))
     assert [l for l in out.read_text().splitlines() if not l.startswith("#")] == []

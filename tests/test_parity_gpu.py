@@ -22,30 +22,48 @@ def _say(*a):
     print(*a, flush=True)
 
 
-def check(orc, p, exps, coeffs, beta, T, tuning=None, t0=1):
+def _run(poly, beta, T, t0):
+    if t0 == 1:
+        return poly.run(beta, T)
+    import torch
+    buf = torch.empty((T, max(poly.G, 1)), dtype=torch.int64 if poly.elem_bytes == 8 else torch.int32,
+                      device="cuda")
+    poly.run_async(beta, T, buf, t0=t0)
+    torch.cuda.synchronize()
+    return buf.cpu().numpy().view(poly.dtype)[:, :poly.G]
+
+
+def check(orc, p, exps, coeffs, beta, T, tuning=None, t0=1, single=None):
+    """Images of the HIP path against the oracle.  Without an explicit tuning
+    the default path runs (single-launch where the run fits it) and then the
+    multi-kernel path with its heuristic K and C; both must match.  single:
+    whether the default path must be the single-launch one (None: either)."""
     exps = np.ascontiguousarray(exps, np.uint32)
     coeffs = np.ascontiguousarray(coeffs, np.uint64)
     beta = np.ascontiguousarray(beta, np.uint64)
     _say(f"case p={p} s={exps.shape[0]} n={exps.shape[1]} T={T} tuning={tuning} t0={t0}")
+    runs = {}
     with PV.Poly(p, exps, coeffs) as poly:
-        if tuning:
-            poly.set_tuning(*tuning)
         gd, ge = poly.groups()
         od, oe = orc.groups(exps)
         assert np.array_equal(gd, od) and np.array_equal(ge, oe)
-        if t0 == 1:
-            got = poly.run(beta, T)
+        if tuning:
+            poly.set_tuning(*tuning)
+            runs["tuned"] = _run(poly, beta, T, t0)
         else:
-            import torch
-            buf = torch.empty((T, max(poly.G, 1)), dtype=torch.int64 if poly.elem_bytes == 8 else torch.int32,
-                              device="cuda")
-            poly.run_async(beta, T, buf, t0=t0)
-            torch.cuda.synchronize()
-            got = buf.cpu().numpy().view(poly.dtype)[:, :poly.G]
-    want = orc.evaluate(p, exps, coeffs, beta, T, t0=t0, threads=8).astype(got.dtype)
-    assert got.shape == want.shape
-    bad = np.argwhere(got != want)
-    assert bad.size == 0, f"{len(bad)} mismatches, first at {bad[:3].tolist()}"
+            is_single = poly.get_tuning(T) == (0, 0, 0)
+            if single is not None:
+                assert is_single == single, poly.get_tuning(T)
+            runs["single" if is_single else "default"] = _run(poly, beta, T, t0)
+            if is_single:
+                poly.set_tuning(0, 16, 0)  # the multi-kernel path, heuristic K and C
+                assert poly.get_tuning(T)[0] != 0
+                runs["multi"] = _run(poly, beta, T, t0)
+    want = orc.evaluate(p, exps, coeffs, beta, T, t0=t0, threads=8)
+    for name, got in runs.items():
+        assert got.shape == want.shape, name
+        bad = np.argwhere(got != want.astype(got.dtype))
+        assert bad.size == 0, f"{name}: {len(bad)} mismatches, first at {bad[:3].tolist()}"
     return got
 
 
@@ -147,6 +165,67 @@ def test_run_async_offset(orc):
     rng = np.random.default_rng(8)
     poly = W.random_small(rng, W.P63, 6, 900, 1, dmax=4)
     check(orc, W.P63, poly.exps, poly.coeffs, poly.beta, 50, t0=1000, tuning=(4, 16, 5))
+
+
+def _with_group(rng, p, size, others, n=6, dmax=10):
+    """A polynomial whose largest (x1, x2) group has exactly `size` terms."""
+    tails = W.draw_exponents(rng, size + others, n - 2, dmax, dmax, per_var=True)
+    e = np.zeros((size + others, n), np.uint32)
+    e[:, 2:] = tails
+    e[:size, :2] = [7, 3]
+    e[size:, 0] = rng.integers(0, 7, others)          # x1 degree below 7: never the big group
+    e[size:, 1] = rng.integers(0, 20, others)
+    e = np.unique(e, axis=0)
+    assert np.max(np.unique(e[:, :2], axis=0, return_counts=True)[1]) == size
+    return e, rng.integers(0, p, e.shape[0], dtype=np.uint64), rng.integers(1, p, n - 2, dtype=np.uint64)
+
+
+@pytest.mark.parametrize("p", [W.P31, W.P63])
+def test_single_launch_shapes(orc, p):
+    """The single-launch path at the edges of where it is used: several
+    evaluations per block, ragged last block, largest term count, largest
+    group, s*T at the limit, no tail variables, and just beyond each limit
+    (multi-kernel path)."""
+    rng = np.random.default_rng(11 if p == W.P31 else 12)
+    q = W.random_small(rng, p, 5, 50, 1, dmax=6)
+    check(orc, p, q.exps, q.coeffs, q.beta, 4000, single=True)          # 16 evaluations per block
+    check(orc, p, q.exps, q.coeffs, q.beta, 4001, single=True)          # ragged last block
+    s_max = 8192 if p == W.P31 else 4096                                 # 32 KiB of term values per evaluation
+    q = W.random_small(rng, p, 6, s_max, 1, dmax=10)
+    check(orc, p, q.exps, q.coeffs, q.beta, 128, single=True)
+    q = W.random_small(rng, p, 6, s_max + 1, 1, dmax=10)
+    check(orc, p, q.exps, q.coeffs, q.beta, 16, single=False)
+    q = W.random_small(rng, p, 6, 4096, 1, dmax=10)
+    check(orc, p, q.exps, q.coeffs, q.beta, 256, single=True)           # s T = 2^20
+    check(orc, p, q.exps, q.coeffs, q.beta, 257, single=False)
+    e, co, beta = _with_group(rng, p, 256, 300)
+    check(orc, p, e, co, beta, 40, single=True)
+    e, co, beta = _with_group(rng, p, 257, 300)
+    check(orc, p, e, co, beta, 40, single=False)
+    q = W.random_small(rng, p, 2, 300, 1, dmax=40)                       # n = 2: no tables
+    check(orc, p, q.exps, q.coeffs, np.zeros(0, np.uint64), 70, single=True)
+    q = W.random_small(rng, p, 4, 900, 1, dmax=10)
+    check(orc, p, q.exps, q.coeffs, q.beta, 33, t0=10**12 + 7, single=True)   # chain starts by exponentiation
+    check(orc, p, q.exps, q.coeffs, q.beta, 600, t0=2**40 + 3, single=True)
+
+
+def test_single_launch_selection():
+    """Which runs take the single-launch path, and how it is switched off."""
+    w = W.config1()
+    with PV.Poly(w.p, w.exps, w.coeffs) as poly:
+        assert poly.get_tuning(w.T) == (0, 0, 0)
+        poly.set_tuning(0, 16, 0)
+        assert poly.get_tuning(w.T)[0] in (1, 2, 4, 8, 16)
+        poly.set_tuning(0, 0, 0)
+        assert poly.get_tuning(w.T) == (0, 0, 0)
+        poly.set_arith("int")
+        assert poly.get_tuning(w.T) != (0, 0, 0)
+        poly.set_arith("auto")
+        assert poly.get_tuning(w.T) == (0, 0, 0)
+        assert poly.get_tuning((1 << 20) // w.s + 1) != (0, 0, 0)
+    big = W.random_small(np.random.default_rng(13), W.P31, 4, 9000, 1, dmax=30)
+    with PV.Poly(big.p, big.exps, big.coeffs) as poly:
+        assert poly.get_tuning(8) != (0, 0, 0)                            # s above 8192
 
 
 def test_deterministic_repeat():

@@ -32,10 +32,22 @@ def test_autotune_and_cache(tmp_path):
     PV.tune_clear()
 
 
-def test_autotune_exhaustive_small():
+def test_autotune_exhaustive_small(tmp_path):
+    """A run small enough for the single-launch path: the autotuner times it
+    too, and its choice (K = P = C = 0 for that path) survives save / load."""
+    PV.tune_clear()
     w = W.config1()
     with PV.Poly(w.p, w.exps, w.coeffs) as q:
+        assert q.get_tuning(w.T) == (0, 0, 0)
         K, P, C, ms = q.autotune(w.beta, w.T, exhaustive=True)
+        print("tuned", (K, P, C), ms, flush=True)
         assert ms > 0
+        assert (K, P, C) == (0, 0, 0) or (K in (1, 2, 4, 8, 16) and P in (8, 16, 32) and C >= 1)
+        assert q.get_tuning(w.T) == (K, P, C)
         assert np.array_equal(q.run(w.beta, w.T), Oracle().evaluate(w.p, w.exps, w.coeffs, w.beta, w.T))
+        path = str(tmp_path / "tune.txt")
+        PV.tune_save(path)
+        PV.tune_clear()
+        PV.tune_load(path)
+        assert q.get_tuning(w.T) == (K, P, C)
     PV.tune_clear()
