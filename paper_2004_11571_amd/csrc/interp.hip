@@ -149,17 +149,21 @@ int interp_impl(peval_poly *h, const BetaArg &beta, const void *images, uint64_t
     HIP_TRY(hipGetLastError());
   }
   {
-    // blocks of 256 threads hold parts of up to 8 * 256 - 1 roots, larger
-    // parts take 1024
+    // parts below 1024 roots: one wave each, in registers; larger ones one
+    // block each in LDS (256 threads up to 8 * 256 - 1 roots, else 1024)
     const uint64_t mx = largest_group(h);
     const uint64_t part = (mx + a.H - 1) / a.H + 1;
     const size_t shmem = (part + 1) * w;
     const unsigned blocks = (unsigned)(h->G * a.H);
     ProfScope ps(st, 2);
-    if (part >= (uint64_t)kInterpPer * 256)
+    if (part - 1 < (uint64_t)kWaveGroupSlots * 64) {  // every part has fewer than 1024 roots
+      const uint32_t nparts = (uint32_t)(h->G * a.H);
+      interp_wave_group_kernel<A, kWaveGroupSlots><<<(nparts + 3) / 4, 256, 0, st>>>(a, nparts);
+    } else if (part >= (uint64_t)kInterpPer * 256) {
       interp_group_kernel<A, 1024><<<blocks, 1024, shmem, st>>>(a);
-    else
+    } else {
       interp_group_kernel<A, 256><<<blocks, 256, shmem, st>>>(a);
+    }
     HIP_TRY(hipGetLastError());
     T_ *in_v = lv0, *in_q = lv0q;
     for (uint32_t lvl = 0, Hl = a.H; Hl > 1; ++lvl, Hl /= 2) {

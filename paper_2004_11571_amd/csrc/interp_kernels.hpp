@@ -18,7 +18,9 @@
 //                        column c laid out along the sorted terms, with
 //                        Shoup quotients
 //   interp_group_kernel  one block per part of a group: the product of its
-//                        (z - v_j) in LDS
+//                        (z - v_j) in LDS (parts of 1024 roots or more)
+//   interp_wave_group_kernel  the same product, one wave per part, in
+//                        registers (parts below 1024 roots)
 //   interp_merge_kernel  few groups: parts multiplied pairwise over the chip
 //   interp_bcoef_kernel  over the whole chip: the coefficients of B and Q'
 //   interp_solve_kernel  per term, over the whole chip: B(v_j) and Q'(v_j)
@@ -161,6 +163,110 @@ __global__ __launch_bounds__(BS) void interp_group_kernel(InterpArgs<A> a) {
   }
 }
 
+// Lane l receives lane l - 1's value, lane 0 lane 63's (DPP wave rotation).
+__device__ __forceinline__ uint32_t wave_ror1(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x13C, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint64_t wave_ror1(uint64_t x) {
+  return ((uint64_t)wave_ror1((uint32_t)(x >> 32)) << 32) | wave_ror1((uint32_t)x);
+}
+// Lane l's value for the whole wave (l wave-uniform).
+__device__ __forceinline__ uint32_t read_lane(uint32_t x, uint32_t l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)x, (int)l);
+}
+__device__ __forceinline__ uint64_t read_lane(uint64_t x, uint32_t l) {
+  return ((uint64_t)read_lane((uint32_t)(x >> 32), l) << 32) | read_lane((uint32_t)x, l);
+}
+
+constexpr int kWaveGroupSlots = 16;  // parts of up to 16 * 64 - 1 roots in one wave
+
+// Steps i_begin .. i_end - 1 of the wave product below, all with RA slots
+// holding coefficients: straight-line code over the slots, so that the
+// slots' independent products interleave.
+template <class A, int RA, int RMAX>
+__device__ __forceinline__ void wave_group_steps(typename A::T (&q)[RMAX], uint32_t i_begin, uint32_t i_end,
+                                                 typename A::T &vbuf, typename A::T &qbuf, const typename A::T *mv,
+                                                 const typename A::T *mq, uint32_t d, int lane,
+                                                 const typename A::M &m) {
+  using T = typename A::T;
+  const T p = (T)m.p;
+  for (uint32_t i = i_begin; i < i_end; ++i) {
+    if ((i & 63) == 0) {  // the next 64 roots, one per lane
+      const uint32_t j = i + lane;
+      vbuf = (j < d) ? mv[j] : (T)0;
+      qbuf = (j < d) ? mq[j] : (T)0;
+    }
+    const T v = read_lane(vbuf, i & 63), vq = read_lane(qbuf, i & 63);
+    T rot[RA];
+#pragma unroll
+    for (int r = 0; r < RA; ++r) rot[r] = wave_ror1(q[r]);
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      const T lo = (lane == 0) ? (r ? rot[r - 1] : (T)0) : rot[r];
+      q[r] = sub_mod(lo, canon(A::mul_lazy(q[r], v, vq, m), p), p);
+    }
+  }
+}
+
+template <class A, int RA, int RMAX>
+__device__ __forceinline__ void wave_group_chunk(uint32_t ra, typename A::T (&q)[RMAX], uint32_t i_begin,
+                                                 uint32_t i_end, typename A::T &vbuf, typename A::T &qbuf,
+                                                 const typename A::T *mv, const typename A::T *mq, uint32_t d,
+                                                 int lane, const typename A::M &m) {
+  if constexpr (RA <= RMAX) {
+    if (ra == RA)
+      wave_group_steps<A, RA, RMAX>(q, i_begin, i_end, vbuf, qbuf, mv, mq, d, lane, m);
+    else
+      wave_group_chunk<A, RA + 1, RMAX>(ra, q, i_begin, i_end, vbuf, qbuf, mv, mq, d, lane, m);
+  }
+}
+
+// The same product with one wave per part and the coefficients in
+// registers: coefficient k sits in lane k % 64 of slot k / 64.  Multiplying
+// by (z - v) is q'_k = q_{k-1} - v q_k; every q_{k-1} comes from the
+// neighbouring lane by a wave rotation (lane 0 takes lane 63 of the slot
+// below), so a step uses no LDS and no barrier, and only the slots that
+// already hold coefficients are updated (ra = (i + 1) / 64 + 1 of them at
+// step i, constant over runs of 64 steps).  Parts are taken largest group
+// first, one wave each.
+template <class A, int RMAX>
+__global__ __launch_bounds__(256) void interp_wave_group_kernel(InterpArgs<A> a, uint32_t nparts) {
+  using T = typename A::T;
+  const uint32_t part = (blockIdx.x * 256 + threadIdx.x) / 64;
+  if (part >= nparts) return;  // whole waves leave together
+  const int lane = threadIdx.x & 63;
+  const T p = (T)a.m.p;
+  const uint32_t g = __builtin_amdgcn_readfirstlane(a.gorder[part / a.H]);
+  const uint32_t h = part % a.H;
+  const uint64_t base = __builtin_amdgcn_readfirstlane(a.grp_off[g]);
+  const uint32_t m = __builtin_amdgcn_readfirstlane(a.grp_off[g + 1]) - (uint32_t)base;
+  const uint32_t r0 = (uint32_t)(((uint64_t)h * m) / a.H), r1 = (uint32_t)(((uint64_t)(h + 1) * m) / a.H);
+  const uint32_t d = r1 - r0;  // roots of this part, d < RMAX * 64 (checked on the host)
+
+  T q[RMAX];
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r) q[r] = (r == 0 && lane == 0) ? (T)(1 % p) : (T)0;
+  const T *mv = a.mval + base + r0, *mq = a.mquot + base + r0;
+  T vbuf = 0, qbuf = 0;  // roots i0 .. i0 + 63, one per lane, taken by lane reads
+  for (uint32_t c = 0; c < (uint32_t)RMAX; ++c) {  // steps with c + 1 slots
+    const uint32_t ib = c ? 64 * c - 1 : 0, ie = min(d, 64 * c + 63);
+    if (ib >= ie) break;
+    wave_group_chunk<A, 1, RMAX>(c + 1, q, ib, ie, vbuf, qbuf, mv, mq, d, lane, a.m);
+  }
+
+  const uint64_t at = base + (uint64_t)g * a.H + r0 + h;
+  T *out = (a.H == 1) ? a.qval + at : a.part_val + at;
+  T *outq = (a.H == 1) ? nullptr : a.part_quot + at;
+#pragma unroll
+  for (int r = 0; r < RMAX; ++r) {
+    const uint32_t k = (uint32_t)r * 64 + lane;
+    if (k <= d) {
+      out[k] = q[r];
+      if (outq) outq[k] = shoup_quot(q[r], a.m);
+    }
+  }
+}
+
 // One merge level: for every group, parts 2j and 2j+1 of a level with H_l
 // parts per group multiply into part j of the next level (H_l / 2 parts).  One wave per
 // 64 consecutive coefficients of one product (tasks built on the host);
@@ -196,11 +302,23 @@ __global__ __launch_bounds__(256) void interp_merge_kernel(InterpArgs<A> a, cons
   // out_k = sum_i a_i b_{k-i}; the wave's 64 outputs need i in [k0-db, k0+63]
   const uint32_t i_lo = (k0 > db) ? k0 - db : 0;
   const uint32_t i_hi = (k0 + 63 < da) ? k0 + 63 : da;
-  for (uint32_t i = i_lo; i <= i_hi; ++i) {
-    const T ai = av[i];
+  // four steps per iteration, their loads issued together
+  uint32_t i = i_lo;
+  for (; i + 3 <= i_hi; i += 4) {
+    T b[4], q[4];
+#pragma unroll
+    for (uint32_t u = 0; u < 4; ++u) {
+      const bool in = k >= i + u && k - (i + u) <= db;
+      b[u] = in ? bv[k - (i + u)] : (T)0;
+      q[u] = in ? bq[k - (i + u)] : (T)0;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < 4; ++u) A::add(acc, A::mul_lazy(av[i + u], b[u], q[u], a.m));
+  }
+  for (; i <= i_hi; ++i) {
     const bool in = k >= i && k - i <= db;
     const T b = in ? bv[k - i] : (T)0, q = in ? bq[k - i] : (T)0;
-    A::add(acc, A::mul_lazy(ai, b, q, a.m));
+    A::add(acc, A::mul_lazy(av[i], b, q, a.m));
   }
   if (k <= da + db) {
     const T r = A::reduce(acc, a.m);
@@ -228,9 +346,18 @@ __global__ __launch_bounds__(256) void interp_bcoef_kernel(InterpArgs<A> a) {
   const uint32_t kend = (l < m) ? m - l : 0;  // k < m - l
   const uint32_t kmax = m - l0;                // longest run in the wave
   typename A::Acc acc = A::zero();
-  for (uint32_t k = 0; k < kmax; ++k) {
-    const T c = cv[k], q = (k < kend) ? qg[k + l + 1] : (T)0;
-    A::add(acc, A::mul_lazy(q, c, cq[k], a.m));
+  // four steps per iteration, their loads issued together
+  uint32_t k = 0;
+  for (; k + 4 <= kmax; k += 4) {
+    T qv[4];
+#pragma unroll
+    for (uint32_t u = 0; u < 4; ++u) qv[u] = (k + u < kend) ? qg[k + u + l + 1] : (T)0;
+#pragma unroll
+    for (uint32_t u = 0; u < 4; ++u) A::add(acc, A::mul_lazy(qv[u], cv[k + u], cq[k + u], a.m));
+  }
+  for (; k < kmax; ++k) {
+    const T q = (k < kend) ? qg[k + l + 1] : (T)0;
+    A::add(acc, A::mul_lazy(q, cv[k], cq[k], a.m));
   }
   if (l < m) {
     a.bval[base + l] = A::reduce(acc, a.m);
@@ -266,10 +393,14 @@ __global__ __launch_bounds__(256) void interp_solve_kernel(InterpArgs<A> a) {
     b = canon(canon(b, p), p);
     d = canon(canon(d, p), p);
   } else {
+    // 3p does not fit: one conditional subtraction per step keeps the
+    // running values in [0, 2p), still a valid Shoup input
     for (uint32_t l = m; l-- > 0;) {
-      b = add_mod(canon(A::mul_lazy(b, v, vq, a.m), p), bv[l], p);
-      d = add_mod(canon(A::mul_lazy(d, v, vq, a.m), p), dv[l], p);
+      b = canon(A::mul_lazy(b, v, vq, a.m), p) + bv[l];
+      d = canon(A::mul_lazy(d, v, vq, a.m), p) + dv[l];
     }
+    b = canon(b, p);
+    d = canon(d, p);
   }
   if (!live) return;
   const T den = canon(A::mul_lazy(d, v, vq, a.m), p);
