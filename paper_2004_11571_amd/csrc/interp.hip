@@ -51,8 +51,10 @@ int interp_setup(peval_poly *h) {
       tf.push_back((uint32_t)j);
     }
   h->ntasks = tg.size();
-  // few groups: Q as 4 or 8 sub-products per group (one block each), merged
-  // pairwise in chip-wide levels, so that more than G blocks share the work
+  // few groups: Q as 4 or 8 sub-products per group (one wave or block
+  // each), merged pairwise in chip-wide levels, so that more than G waves
+  // share the work (two sub-products for 256-2047 groups measured no faster:
+  // the merge costs what the shorter products save)
   uint64_t mx = 0;
   for (uint64_t g = 0; g < h->G; ++g) mx = std::max<uint64_t>(mx, h->grp_off[g + 1] - h->grp_off[g]);
   h->interp_H = (mx < 256 || h->G >= 256) ? 1 : (h->G < 128 ? 8 : 4);

@@ -70,6 +70,26 @@ def test_round_trip(orc, p):
     assert np.array_equal(got, coeffs)
 
 
+@pytest.mark.parametrize("d12,per_group,H", [(11, 300, 4), (20, 290, 1)])
+def test_round_trip_sub_products(d12, per_group, H):
+    """Group counts that split Q into H sub-products per group (merged
+    pairwise afterwards): 144 groups -> 4, 441 -> 1."""
+    p = W.P63
+    rng = np.random.default_rng(d12)
+    G = (d12 + 1) ** 2
+    exps = support(rng, p, 6, G * per_group, d12, 5)
+    sizes = group_sizes(exps)
+    assert len(sizes) == G and sizes.max() >= 256
+    coeffs = rng.integers(0, p, size=exps.shape[0], dtype=np.uint64)
+    beta = rng.integers(1, p, size=4, dtype=np.uint64)
+    T = int(sizes.max())
+    _say(f"sub-products case G={G} s={exps.shape[0]} T={T} H={H}")
+    with PV.Poly(p, exps, coeffs) as h:
+        images = h.run(beta, T)
+        got = h.interpolate(beta, images)
+    assert np.array_equal(got, coeffs)
+
+
 def test_largest_group(orc):
     """One group of 8191 terms (the largest supported), x3 exponents 0..8190."""
     p = W.P63
