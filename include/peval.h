@@ -265,8 +265,9 @@ int peval_tune_load(const char *path);
  * (K from the tuning cache or the heuristic; P = 16) and its
  * chains so that the work items (one wave of one chain of one polynomial)
  * have similar costs, allocates all device scratch, and captures the pass
- * (power tables, monomials, a persistent evaluation kernel fed by a work
- * queue in decreasing item cost, combine) into a hipGraph unless flags has
+ * (power tables, monomials, persistent evaluation kernels fed by work
+ * queues in decreasing item cost, one for the 64-bit members and one for
+ * the 32-bit ones, combine) into a hipGraph unless flags has
  * PEVAL_BATCH_NO_GRAPH.  The handles must outlive the batch.
  *
  * peval_batch_run evaluates polys[j] at betas[j] (n_j - 2 values each) for
@@ -277,8 +278,8 @@ int peval_tune_load(const char *path);
  * call returns after enqueueing and blocks only when the run table it stages
  * (four staging buffers in rotation) still awaits its upload.
  *
- * peval_batch_info fills info[5]: members, work items, persistent blocks,
- * scratch bytes, term-evaluations per run.
+ * peval_batch_info fills info[5]: members, work items, persistent blocks
+ * (both evaluation kernels), scratch bytes, term-evaluations per run.
  */
 typedef struct peval_batch peval_batch;
 #define PEVAL_BATCH_NO_GRAPH 1u

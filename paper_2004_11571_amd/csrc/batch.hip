@@ -25,19 +25,31 @@ void batch_release(BatchCore &b) {
   b.arena = nullptr;
 }
 
-int batch_persistent_blocks(int *blocks) {
-  static int cached = 0;
+// Blocks that fill the chip with each evaluation kernel (64-bit, 32-bit).
+static int persistent_blocks(int blocks[2]) {
+  static int cached[2] = {0, 0};
   static std::mutex mu;
   std::lock_guard<std::mutex> lk(mu);
-  if (!cached) {
-    int dev = 0, per_cu = 0;
+  if (!cached[0]) {
+    int dev = 0, per_cu64 = 0, per_cu32 = 0;
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipGetDeviceProperties(&prop, dev));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_eval_kernel, kEvalBlock, 0));
-    cached = std::max(1, per_cu) * prop.multiProcessorCount;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu64, batch_eval_kernel<W64>, kEvalBlock, 0));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu32, batch_eval_kernel<W32>, kEvalBlock, 0));
+    cached[0] = std::max(1, per_cu64) * prop.multiProcessorCount;
+    cached[1] = std::max(1, per_cu32) * prop.multiProcessorCount;
   }
-  *blocks = cached;
+  blocks[0] = cached[0];
+  blocks[1] = cached[1];
+  return PEVAL_OK;
+}
+
+int batch_set_blocks(BatchCore &b) {
+  int bl[2];
+  PEVAL_TRY(persistent_blocks(bl));
+  const uint64_t n[2] = {b.n_items64, (uint64_t)b.n_items - b.n_items64};
+  for (int k = 0; k < 2; ++k) b.eval_blocks[k] = (int)std::min<uint64_t>((uint64_t)bl[k], (n[k] + 3) / 4);
   return PEVAL_OK;
 }
 
@@ -133,9 +145,16 @@ void batch_plan(BatchCore &b, const std::vector<BatchMember> &mem, void *arena, 
   uint64_t n_items = 0;
   for (uint32_t j = 0; j < count; ++j) n_items += (uint64_t)b.descs[j].C * b.descs[j].NW;
   items.reserve(n_items);
-  for (uint32_t j : order)
-    for (uint32_t c = 0; c < b.descs[j].C; ++c)
-      for (uint64_t wv = 0; wv < b.descs[j].NW; ++wv) items.push_back(BatchItem{j, (uint32_t)wv, c, 0});
+  // the 64-bit members' items first, then the 32-bit ones (one queue and
+  // one evaluation kernel per width), each in decreasing cost
+  for (uint32_t width : {8u, 4u}) {
+    for (uint32_t j : order) {
+      if (b.descs[j].w != width) continue;
+      for (uint32_t c = 0; c < b.descs[j].C; ++c)
+        for (uint64_t wv = 0; wv < b.descs[j].NW; ++wv) items.push_back(BatchItem{j, (uint32_t)wv, c, 0});
+    }
+    if (width == 8) b.n_items64 = (uint32_t)items.size();
+  }
   b.n_items = (uint32_t)items.size();
   b.tab_total = ptab[count];
   b.mono_total = pmono[count];
@@ -181,9 +200,7 @@ int batch_build(BatchCore &b, const std::vector<BatchMember> &mem) {
   HIP_TRY(hipMalloc(&blob, b.blob_bytes));
   batch_bind(b, blob);
   HIP_TRY(hipMemcpy(blob, b.image.data(), b.blob_bytes, hipMemcpyHostToDevice));
-  PEVAL_TRY(batch_persistent_blocks(&b.eval_blocks));
-  b.eval_blocks = (int)std::min<uint64_t>((uint64_t)b.eval_blocks, std::max<uint64_t>(1, (b.n_items + 3) / 4));
-  return PEVAL_OK;
+  return batch_set_blocks(b);
 }
 
 // Kernels of one batched pass (the run table must already be on the device).
@@ -198,8 +215,13 @@ int batch_enqueue(const BatchCore &b, hipStream_t st) {
     batch_mono_kernel<<<(unsigned)((b.mono_total + 255) / 256), 256, 0, st>>>(b.d_desc, b.d_run, b.count, b.d_pmono);
     HIP_TRY(hipGetLastError());
   }
-  if (b.n_items) {
-    batch_eval_kernel<<<b.eval_blocks, kEvalBlock, 0, st>>>(b.d_desc, b.d_items, b.n_items, b.d_counter);
+  if (b.n_items64) {
+    batch_eval_kernel<W64><<<b.eval_blocks[0], kEvalBlock, 0, st>>>(b.d_desc, b.d_items, b.n_items64, b.d_counter);
+    HIP_TRY(hipGetLastError());
+  }
+  if (b.n_items > b.n_items64) {
+    batch_eval_kernel<W32><<<b.eval_blocks[1], kEvalBlock, 0, st>>>(b.d_desc, b.d_items + b.n_items64,
+                                                                     b.n_items - b.n_items64, b.d_counter + 1);
     HIP_TRY(hipGetLastError());
   }
   if (b.out_total) {  // out_total counts combine tiles
@@ -356,7 +378,7 @@ extern "C" int peval_batch_info(const peval_batch *b, uint64_t *info) {
   if (!b || !info) return fail(PEVAL_EINVAL, "null argument");
   info[0] = b->core.count;
   info[1] = b->core.n_items;
-  info[2] = (uint64_t)b->core.eval_blocks;
+  info[2] = (uint64_t)b->core.eval_blocks[0] + (uint64_t)b->core.eval_blocks[1];
   info[3] = b->core.scratch_bytes;
   uint64_t te = 0;
   for (uint32_t j = 0; j < b->core.count; ++j) te += b->polys[j]->s * (uint64_t)b->Ts[j];

@@ -40,8 +40,8 @@ __device__ __forceinline__ uint32_t find_poly_block(const uint64_t *prefix, uint
   return j;
 }
 
-__global__ void batch_reset_kernel(uint32_t *counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0;
+__global__ void batch_reset_kernel(uint32_t *counter) {  // the two work queues
+  if (blockIdx.x == 0 && threadIdx.x < 2) counter[threadIdx.x] = 0;
 }
 
 __global__ void batch_power_kernel(const BatchDesc *D, const BatchRun *R, uint32_t count, const uint64_t *prefix) {
@@ -113,13 +113,24 @@ __device__ __forceinline__ void batch_eval_item(const BatchDesc &d, const BatchI
   eval_wave<A, K, kBatchP>(a, it.wave, it.chain, *reinterpret_cast<Stage<A, kBatchP> *>(lds), lane);
 }
 
-constexpr size_t kStageBytes = sizeof(Stage<W64, kBatchP>) > sizeof(Stage<W32, kBatchP>)
-                                   ? sizeof(Stage<W64, kBatchP>)
-                                   : sizeof(Stage<W32, kBatchP>);
+template <class A>
+__device__ __forceinline__ const typename A::M &member_mod(const BatchDesc &d);
+template <>
+__device__ __forceinline__ const Mod32 &member_mod<W32>(const BatchDesc &d) { return d.m32; }
+template <>
+__device__ __forceinline__ const Mod64 &member_mod<W64>(const BatchDesc &d) { return d.m64; }
 
-__global__ __launch_bounds__(kEvalBlock) void batch_eval_kernel(const BatchDesc *D, const BatchItem *items,
+// Persistent evaluation over the work queue of the members of one residue
+// width (one kernel per width, so that each gets the registers and LDS of
+// its own widest variant rather than those of the 64-bit one).  The 64-bit
+// kernel is held to three waves per SIMD, as the single-polynomial kernel
+// runs: its few spills sit outside the evaluation passes, and three waves
+// measured faster than the two that its unbounded register count allows.
+template <class A>
+__global__ __launch_bounds__(kEvalBlock, sizeof(typename A::T) == 8 ? 3 : 4) void batch_eval_kernel(
+    const BatchDesc *D, const BatchItem *items,
                                                                 uint32_t n_items, uint32_t *counter) {
-  __shared__ __align__(16) unsigned char stage[kEvalBlock / 64][kStageBytes];
+  __shared__ __align__(16) unsigned char stage[kEvalBlock / 64][sizeof(Stage<A, kBatchP>)];
   const int lane = threadIdx.x & 63;
   const int warp = threadIdx.x >> 6;
   void *lds = stage[warp];
@@ -130,22 +141,14 @@ __global__ __launch_bounds__(kEvalBlock) void batch_eval_kernel(const BatchDesc 
     if (next >= n_items) break;  // every wave reaches this once the queue is drained
     const BatchItem it = items[next];
     const BatchDesc &d = D[it.poly];
-    if (d.w == 4) {
-      switch (d.K) {
-        case 1: batch_eval_item<W32, 1>(d, it, lds, lane, d.m32); break;
-        case 2: batch_eval_item<W32, 2>(d, it, lds, lane, d.m32); break;
-        case 4: batch_eval_item<W32, 4>(d, it, lds, lane, d.m32); break;
-        case 8: batch_eval_item<W32, 8>(d, it, lds, lane, d.m32); break;
-        default: batch_eval_item<W32, 16>(d, it, lds, lane, d.m32); break;
-      }
-    } else {
-      switch (d.K) {
-        case 1: batch_eval_item<W64, 1>(d, it, lds, lane, d.m64); break;
-        case 2: batch_eval_item<W64, 2>(d, it, lds, lane, d.m64); break;
-        case 4: batch_eval_item<W64, 4>(d, it, lds, lane, d.m64); break;
-        case 8: batch_eval_item<W64, 8>(d, it, lds, lane, d.m64); break;
-        default: batch_eval_item<W64, 16>(d, it, lds, lane, d.m64); break;
-      }
+    if (d.w != sizeof(typename A::T)) continue;  // never planned so; skipped rather than misread
+    const typename A::M &m = member_mod<A>(d);
+    switch (d.K) {
+      case 1: batch_eval_item<A, 1>(d, it, lds, lane, m); break;
+      case 2: batch_eval_item<A, 2>(d, it, lds, lane, m); break;
+      case 4: batch_eval_item<A, 4>(d, it, lds, lane, m); break;
+      case 8: batch_eval_item<A, 8>(d, it, lds, lane, m); break;
+      default: batch_eval_item<A, 16>(d, it, lds, lane, m); break;
     }
   }
 }

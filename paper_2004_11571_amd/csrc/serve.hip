@@ -528,10 +528,8 @@ static bool launch_pass_impl(peval_server *S, std::unique_lock<std::mutex> &lk) 
         break;
       }
       batch_bind(core, blob);
-      int bl = 0;
-      batch_persistent_blocks(&bl);
-      core.eval_blocks = (int)std::min<uint64_t>((uint64_t)bl, std::max<uint64_t>(1, (core.n_items + 3) / 4));
-      launch_rc = batch_enqueue(core, st);
+      launch_rc = batch_set_blocks(core);
+      if (launch_rc == PEVAL_OK) launch_rc = batch_enqueue(core, st);
       if (launch_rc == PEVAL_OK && hipEventRecord(S->ev[slot], st) != hipSuccess)
         launch_rc = fail(PEVAL_EDEVICE, "event record");
     } while (false);
