@@ -9,7 +9,7 @@ timing (its data is resident in HBM when the timed region starts).
 Default workload: n = 6 variables, 1e6 distinct terms, x1/x2 degree <= 40,
 x3..x6 total degree <= 20, p = 2^63 - 25, T = 1024 evaluations.
 
-Prints one JSON line (see the design doc for the roofline definition).
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -482,8 +482,8 @@ def serve_main(args):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
-                          "design note (DESIGN.md), not implemented"}), flush=True)
+        print(json.dumps({"error": "runs on one GPU only: sharding over several GPUs is described "
+                          "in the design notes, not implemented"}), flush=True)
         sys.exit(2)
 
     if args.workload == "batch":

@@ -48,7 +48,7 @@ enum {
     PEVAL_EINVAL = -1,        /* bad argument (null pointer, size, range) */
     PEVAL_ENOMEM = -2,        /* host or device allocation failed */
     PEVAL_EDEVICE = -3,       /* HIP runtime or kernel error */
-    PEVAL_EUNSUPPORTED = -4,  /* valid input outside what this build supports */
+    PEVAL_EUNSUPPORTED = -4,  /* valid input outside what the library supports */
     PEVAL_EBUSY = -5,         /* resource temporarily unavailable (server) */
     PEVAL_ETIMEOUT = -6,      /* wait ended before completion */
     PEVAL_ESINGULAR = -7      /* interpolation: a group's system has no unique solution */
