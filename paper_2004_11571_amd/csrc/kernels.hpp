@@ -82,12 +82,23 @@ struct MonoArgs {
 };
 
 // off: power-table offsets per tail variable (read through a pointer so that
-// a dynamically indexed copy never lands in scratch memory)
+// a dynamically indexed copy never lands in scratch memory).
+// idx enumerates tiles of 64 threads x K slots, the slot k of a tile
+// changing every 64 indices: the lanes of a wave store 64 consecutive
+// threads' values of one slot (coalesced, [k][thread] layout), and the few
+// consecutive blocks that cover one tile read all K terms of its threads, so
+// every cache line of term data is fetched once.  (With idx = k NT + j the
+// waves of slot k read one term in K, and the term data came from HBM about
+// K times over.)  NT is a multiple of 64 and K a power of two.
 template <class A>
 __device__ __forceinline__ void monomial_entry(const MonoArgs<A> &a, const uint32_t *off, uint64_t idx) {
   using T = typename A::T;
-  uint32_t k = (uint32_t)(idx / a.NT);
-  uint64_t j = idx - (uint64_t)k * a.NT;
+  const uint32_t sh = 6 + __builtin_ctz(a.K);  // log2(64 K)
+  const uint64_t tile = idx >> sh;
+  const uint32_t r = (uint32_t)(idx & ((1ull << sh) - 1));
+  const uint32_t k = r >> 6;
+  const uint64_t j = (tile << 6) + (r & 63);
+  const uint64_t pos = (uint64_t)k * a.NT + j;  // slot (k, j) in the [k][thread] arrays
   const uint64_t NTK = (uint64_t)a.K * a.NT;
   // canonical value, or its double image when the evaluation uses Alg. 2
   auto out = [&](T v) -> T {
@@ -97,9 +108,9 @@ __device__ __forceinline__ void monomial_entry(const MonoArgs<A> &a, const uint3
     return v;
   };
   if (k >= a.thr_cnt[j]) {  // padding: a zero term stays zero (0.0 has the same bits)
-    for (uint32_t c = 0; c < a.C; ++c) a.lam[c * NTK + idx] = 0;
-    a.gam[idx] = 0;
-    a.gamq[idx] = 0;
+    for (uint32_t c = 0; c < a.C; ++c) a.lam[c * NTK + pos] = 0;
+    a.gam[pos] = 0;
+    a.gamq[pos] = 0;
     return;
   }
   const uint64_t i = (uint64_t)a.thr_first[j] + k;
@@ -121,15 +132,15 @@ __device__ __forceinline__ void monomial_entry(const MonoArgs<A> &a, const uint3
     T mt = pow_mod(mi, a.t0, a.m);
     lam = A::mul_lazy(a.coeff[i], mt, shoup_quot(mt, a.m), a.m);
   }
-  a.lam[idx] = out(lam);
+  a.lam[pos] = out(lam);
   for (uint32_t c = 1; c < a.C; ++c) {
     lam = A::mul_lazy(lam, mi, mq, a.m);
-    a.lam[c * NTK + idx] = out(lam);
+    a.lam[c * NTK + pos] = out(lam);
   }
   // Gamma = m_i^C, the multiplier of every chain
   T g = (a.C == 1) ? mi : pow_mod(mi, (uint64_t)a.C, a.m);
-  a.gam[idx] = out(g);
-  a.gamq[idx] = shoup_quot(g, a.m);
+  a.gam[pos] = out(g);
+  a.gamq[pos] = shoup_quot(g, a.m);
 }
 
 template <class A>
