@@ -95,9 +95,11 @@ extern "C" int peval_autotune(peval_poly *h, const uint64_t *beta, uint32_t T, u
   std::lock_guard<std::mutex> lk(h->mu);
   PEVAL_TRY(ensure(h->outbuf, (size_t)T * h->G * h->w, h));
 
+  // the FP64 product sums at most 8 doubles per thread exactly: K <= 8
+  const uint32_t kmax = (h->arith == 1) ? 8u : 16u;
   std::vector<uint32_t> Ks;
   for (uint32_t k : {1u, 2u, 4u, 8u, 16u})
-    if (k == 1 || padded_threads(h, k) * k * 2 <= h->s * 3) Ks.push_back(k);
+    if (k <= kmax && (k == 1 || padded_threads(h, k) * k * 2 <= h->s * 3)) Ks.push_back(k);
   const uint32_t Ps[] = {8, 16, 32};
   const uint64_t targets[] = {2048, 4096, 8192, 16384};
   auto chains = [&](uint32_t k, uint64_t target) {
@@ -106,6 +108,7 @@ extern "C" int peval_autotune(peval_poly *h, const uint64_t *beta, uint32_t T, u
   };
 
   Tuning best = heuristic_tuning(h, T);
+  best.K = std::min(best.K, kmax);
   float best_ms = 1e30f;
   auto consider = [&](Tuning t) -> int {
     float m = 0;

@@ -51,3 +51,21 @@ def test_autotune_exhaustive_small(tmp_path):
         PV.tune_load(path)
         assert q.get_tuning(w.T) == (K, P, C)
     PV.tune_clear()
+
+
+@pytest.mark.parametrize("exhaustive", [False, True])
+def test_autotune_fp64_product(exhaustive):
+    """A modulus below 2^50 takes the FP64 product by default, whose kernels
+    exist only for K <= 8: the autotuner keeps to those and the result stays
+    exact."""
+    PV.tune_clear()
+    w = W.make_poly(W.config_seed(2, 8), W.P50, 6, 30000, 48, 40, 20)
+    with PV.Poly(w.p, w.exps, w.coeffs) as q:
+        assert q.arith() == "fp64"
+        K, P, C, ms = q.autotune(w.beta, w.T, exhaustive=exhaustive)
+        print("fp64 tuned", (K, P, C), ms, flush=True)
+        assert ms > 0
+        assert (K, P, C) == (0, 0, 0) or K <= 8
+        got = q.run(w.beta, w.T)
+    assert np.array_equal(got, Oracle().evaluate(w.p, w.exps, w.coeffs, w.beta, w.T, threads=8))
+    PV.tune_clear()
