@@ -212,7 +212,8 @@ int batch_enqueue(const BatchCore &b, hipStream_t st) {
     HIP_TRY(hipGetLastError());
   }
   if (b.mono_total) {
-    batch_mono_kernel<<<(unsigned)((b.mono_total + 255) / 256), 256, 0, st>>>(b.d_desc, b.d_run, b.count, b.d_pmono);
+    const uint32_t xchunk = (uint32_t)(((b.mono_total + 255) / 256 + kXcds - 1) / kXcds);
+    batch_mono_kernel<<<kXcds * xchunk, 256, 0, st>>>(b.d_desc, b.d_run, b.count, b.d_pmono, xchunk);
     HIP_TRY(hipGetLastError());
   }
   if (b.n_items64) {

@@ -32,8 +32,8 @@ __device__ __forceinline__ uint32_t find_poly(const uint64_t *prefix, uint32_t c
 // the block's first entry (blocks cover consecutive entries), and each thread
 // steps forward from there, rarely more than once.
 __device__ __forceinline__ uint32_t find_poly_block(const uint64_t *prefix, uint32_t count, uint64_t idx,
-                                                    uint32_t *shared_first) {
-  if (threadIdx.x == 0) shared_first[0] = find_poly(prefix, count, (uint64_t)blockIdx.x * blockDim.x);
+                                                    uint64_t block_first, uint32_t *shared_first) {
+  if (threadIdx.x == 0) shared_first[0] = find_poly(prefix, count, block_first);
   __syncthreads();
   uint32_t j = shared_first[0];
   while (j + 1 < count && prefix[j + 1] <= idx) ++j;
@@ -46,8 +46,9 @@ __global__ void batch_reset_kernel(uint32_t *counter) {  // the two work queues
 
 __global__ void batch_power_kernel(const BatchDesc *D, const BatchRun *R, uint32_t count, const uint64_t *prefix) {
   __shared__ uint32_t first;
-  uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t j = find_poly_block(prefix, count, idx, &first);  // every thread takes part in the barrier
+  const uint64_t block_first = (uint64_t)blockIdx.x * blockDim.x;
+  const uint64_t idx = block_first + threadIdx.x;
+  uint32_t j = find_poly_block(prefix, count, idx, block_first, &first);  // every thread takes part in the barrier
   if (idx >= prefix[count]) return;
   const BatchDesc &d = D[j];
   uint32_t local = (uint32_t)(idx - prefix[j]);
@@ -81,10 +82,14 @@ __device__ __forceinline__ void batch_mono_one(const BatchDesc &d, uint64_t t0, 
   monomial_entry<A>(a, d.to.off, local);
 }
 
-__global__ void batch_mono_kernel(const BatchDesc *D, const BatchRun *R, uint32_t count, const uint64_t *prefix) {
+// Blocks renumbered per XCD as in monomial_kernel (xchunk logical blocks per
+// XCD, grid 8 xchunk).
+__global__ void batch_mono_kernel(const BatchDesc *D, const BatchRun *R, uint32_t count, const uint64_t *prefix,
+                                  uint32_t xchunk) {
   __shared__ uint32_t first;
-  uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  uint32_t j = find_poly_block(prefix, count, idx, &first);  // every thread takes part in the barrier
+  const uint64_t block_first = xcd_logical_block(xchunk) * blockDim.x;
+  const uint64_t idx = block_first + threadIdx.x;
+  uint32_t j = find_poly_block(prefix, count, idx, block_first, &first);  // every thread takes part in the barrier
   if (idx >= prefix[count]) return;
   const BatchDesc &d = D[j];
   uint64_t local = idx - prefix[j];

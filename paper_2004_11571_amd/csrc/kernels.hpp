@@ -36,6 +36,16 @@ struct TableOffsets {
   uint32_t off[kMaxTail + 1];  // entries of variable k are off[k] .. off[k+1]-1
 };
 
+// Workgroups are dealt to the eight XCDs in turn (block b runs on XCD b % 8),
+// and each XCD has its own L2.  A kernel whose neighbouring blocks read the
+// same cache lines renumbers its blocks so that XCD x runs the consecutive
+// logical blocks x chunk .. x chunk + chunk - 1: its grid has 8 chunk blocks,
+// and logical blocks past the end return.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint64_t xcd_logical_block(uint32_t chunk) {
+  return (uint64_t)(blockIdx.x % kXcds) * chunk + blockIdx.x / kXcds;
+}
+
 // ---------------------------------------------------------------------------
 // A2: tables of powers beta_k^j (value and Shoup quotient)
 // ---------------------------------------------------------------------------
@@ -78,6 +88,7 @@ struct MonoArgs {
   uint64_t t0;
   uint32_t ntail, K, C;
   uint32_t as_double;           // store canonical values as doubles (for the FP64 product)
+  uint32_t xchunk;              // logical blocks per XCD (grid = 8 xchunk blocks of 256)
   typename A::M m;
 };
 
@@ -143,9 +154,11 @@ __device__ __forceinline__ void monomial_entry(const MonoArgs<A> &a, const uint3
   a.gamq[pos] = shoup_quot(g, a.m);
 }
 
+// The blocks of one tile of slots (K / 4 blocks for K >= 4) share their
+// term data's cache lines, so they are kept on one XCD.
 template <class A>
 __global__ void monomial_kernel(MonoArgs<A> a) {
-  uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t idx = xcd_logical_block(a.xchunk) * blockDim.x + threadIdx.x;
   if (idx >= (uint64_t)a.K * a.NT) return;
   monomial_entry<A>(a, a.to.off, idx);
 }
