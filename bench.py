@@ -99,6 +99,17 @@ def profile_traffic(kernel_sha: str, workload: str, kernel: str = "eval_kernel")
     return float(m_b.group(1))
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def kernel_source_sha(sources=None, extra=()) -> str:
     """Hash of the evaluation kernels' code: comments and whitespace are
     dropped, so that only a change of the compiled code invalidates the
@@ -642,10 +653,22 @@ def main():
         else:
             ref = orc.evaluate(w.p, w.exps, w.coeffs, w.beta, rows, t0=1, threads=threads)
         csec = time.perf_counter() - c0
+        # one thread on a few images: the per-core rate (comparable with the
+        # paper's single-core timings)
+        rows1 = min(8, rows)
+        c1 = time.perf_counter()
+        if points_mode:
+            orc.evaluate_points(w.p, w.exps, w.coeffs, pts[:rows1], threads=1)
+        else:
+            orc.evaluate(w.p, w.exps, w.coeffs, w.beta, rows1, t0=1, threads=1)
+        csec1 = time.perf_counter() - c1
         res["cpu_baseline"] = {"value": w.s * rows / csec, "unit": "term-evals/s", "cores": threads,
                                "kind": "oracle", "seconds": csec,
                                "sample": f"the first {rows} images of the same polynomial (all {w.s} terms), "
-                                         f"{threads} threads over the points"}
+                                         f"{threads} threads over the points",
+                               "single_thread_value": w.s * rows1 / csec1,
+                               "single_thread_sample": f"the first {rows1} images, one thread",
+                               "cpu_model": cpu_model(), "host_threads": os.cpu_count()}
         res["parity_sample"] = bool(np.array_equal(got[:rows].astype(np.uint64), ref))
     poly.destroy()
     print(json.dumps(res), flush=True)
