@@ -62,10 +62,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="config2",
-                    choices=["config1", "config2", "config2_p31", "config4", "paper_table2", "batch", "serve",
-                             "config2_points", "config2_p31_points", "paper_table2_points",
-                             "config2_interp", "paper_table2_interp"])
+    ap.add_argument("--workload", default="n6_s1e6_p63_T1024",
+                    choices=["n4_s1e3_p31_T64", "n6_s1e6_p63_T1024", "n6_s1e6_p31_T1024", "n8_s1e7_p63_T4096",
+                             "paper_table2", "batch", "serve",
+                             "n6_s1e6_p63_T1024_points", "n6_s1e6_p31_T1024_points", "paper_table2_points",
+                             "n6_s1e6_p63_T1024_interp", "paper_table2_interp"])
     ap.add_argument("--rate", type=float, default=2000.0, help="served stream: mean arrivals per second")
     ap.add_argument("--duration", type=float, default=3.0, help="served stream: seconds of arrivals")
     ap.add_argument("--pool", type=int, default=20, help="served stream: polynomials (last 20%% start cold)")
@@ -136,7 +137,7 @@ def interp_main(args):
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     base = args.workload[: -len("_interp")]
-    w = {"config2": W.config2, "paper_table2": W.paper_table2}[base]()
+    w = {"n6_s1e6_p63_T1024": W.n6_s1e6_p63_T1024, "paper_table2": W.paper_table2}[base]()
     _, sizes = np.unique(w.exps[:, :2], axis=0, return_counts=True)
     T = int(sizes.max())
     poly = PV.Poly(w.p, w.exps, w.coeffs)
@@ -215,7 +216,7 @@ def batch_main(args):
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     t_gen = time.time()
-    ws = W.batch_config(count=args.batch_count, s_max=args.batch_smax)
+    ws = W.uneven_batch(count=args.batch_count, s_max=args.batch_smax)
     gen_s = time.time() - t_gen
     t_c = time.time()
     polys = [PV.Poly(w.p, w.exps, w.coeffs) for w in ws]
@@ -513,8 +514,8 @@ def main():
     dev = torch.device("cuda:0")
     points_mode = args.workload.endswith("_points")
     base = args.workload[: -len("_points")] if points_mode else args.workload
-    w = {"config1": W.config1, "config2": W.config2, "config2_p31": W.config2_p31,
-         "config4": W.config4, "paper_table2": W.paper_table2}[base]()
+    w = {"n4_s1e3_p31_T64": W.n4_s1e3_p31_T64, "n6_s1e6_p63_T1024": W.n6_s1e6_p63_T1024, "n6_s1e6_p31_T1024": W.n6_s1e6_p31_T1024,
+         "n8_s1e7_p63_T4096": W.n8_s1e7_p63_T4096, "paper_table2": W.paper_table2}[base]()
     t_gen = time.time()
     poly = PV.Poly(w.p, w.exps, w.coeffs)
     create_s = time.time() - t_gen

@@ -37,8 +37,9 @@ P50 = (1 << 50) - 27         # largest prime below 2^50
 SEED_BASE = 2004115710
 
 
-def config_seed(config: int, instance: int = 0) -> int:
-    return SEED_BASE + 1000 * config + instance
+def workload_seed(stream: int, instance: int = 0) -> int:
+    """Seed of one input stream (a workload shape or a draw of points) and instance."""
+    return SEED_BASE + 1000 * stream + instance
 
 
 @dataclasses.dataclass
@@ -158,26 +159,26 @@ def make_poly(seed: int, p: int, n: int, s: int, T: int, d12: int, dr: int,
 
 
 # ---------------------------------------------------------------------------
-# Named configurations
+# Named workloads (each named for its shape)
 # ---------------------------------------------------------------------------
 
-def config1(instance: int = 0) -> Poly:
+def n4_s1e3_p31_T64(instance: int = 0) -> Poly:
     """n=4, 1000 distinct terms, every exponent uniform in [0,10], p=2^31-1, T=64."""
-    return make_poly(config_seed(1, instance), P31, 4, 1000, 64, 10, 10, per_var=True,
+    return make_poly(workload_seed(1, instance), P31, 4, 1000, 64, 10, 10, per_var=True,
                      name="n4_s1e3_p31_T64")
 
 
-def config2(instance: int = 0) -> Poly:
+def n6_s1e6_p63_T1024(instance: int = 0) -> Poly:
     """n=6, 1e6 distinct terms, x1,x2 degree <= 40, x3..x6 total degree <= 20,
     p=2^63-25, T=1024."""
-    return make_poly(config_seed(2, instance), P63, 6, 1_000_000, 1024, 40, 20,
+    return make_poly(workload_seed(2, instance), P63, 6, 1_000_000, 1024, 40, 20,
                      name="n6_s1e6_p63_T1024")
 
 
-def config2_p31(instance: int = 0) -> Poly:
-    """The 1e6-term shape of config2 with the 31-bit prime 2^31-1 (32-bit
+def n6_s1e6_p31_T1024(instance: int = 0) -> Poly:
+    """The 1e6-term shape of n6_s1e6_p63_T1024 with the 31-bit prime 2^31-1 (32-bit
     residues)."""
-    return make_poly(config_seed(2, 500 + instance), P31, 6, 1_000_000, 1024, 40, 20,
+    return make_poly(workload_seed(2, 500 + instance), P31, 6, 1_000_000, 1024, 40, 20,
                      name="n6_s1e6_p31_T1024")
 
 
@@ -187,22 +188,22 @@ def paper_table2(instance: int = 0) -> Poly:
     T = 1e4 evaluations, 64-bit integers with a prime below 2^50 (the FP64
     product of Alg. 2 needs p <= 50 bits).  The exponent distribution is not
     given in the paper: per-variable uniform in [0, 10] here."""
-    return make_poly(config_seed(6, instance), P50, 6, 500_000, 10_000, 10, 10, per_var=True,
+    return make_poly(workload_seed(6, instance), P50, 6, 500_000, 10_000, 10, 10, per_var=True,
                      name="n6_s5e5_d10_p50_T1e4")
 
 
-def config4(instance: int = 0) -> Poly:
+def n8_s1e7_p63_T4096(instance: int = 0) -> Poly:
     """n=8, 1e7 distinct terms, x1,x2 degree <= 60, x3..x8 total degree <= 30,
     p=2^63-25, T=4096."""
-    return make_poly(config_seed(4, instance), P63, 8, 10_000_000, 4096, 60, 30,
+    return make_poly(workload_seed(4, instance), P63, 8, 10_000_000, 4096, 60, 30,
                      name="n8_s1e7_p63_T4096")
 
 
-def batch_config(count: int = 256, instance: int = 0, s_max: float = 1e6,
+def uneven_batch(count: int = 256, instance: int = 0, s_max: float = 1e6,
                  t_log2: tuple = (5, 11)) -> List[Poly]:
     """Uneven batch: n ~ U{4..8}, s log-uniform in [1e3, s_max], T log-uniform
     in [2^5, 2^11], p in {2^31-1, 2^63-25} with probability 1/2 each."""
-    rng = np.random.default_rng(config_seed(3, instance))
+    rng = np.random.default_rng(workload_seed(3, instance))
     polys = []
     for j in range(count):
         n = int(rng.integers(4, 9))
@@ -218,7 +219,7 @@ def batch_config(count: int = 256, instance: int = 0, s_max: float = 1e6,
 def random_points(poly: Poly, T: int = 0, instance: int = 0) -> np.ndarray:
     """T points (x3..xn) drawn uniformly from [1, p)^(n-2), for the point
     mode (Zippel's random points, Section 2.1); T defaults to poly.T."""
-    rng = np.random.default_rng(config_seed(7, instance))
+    rng = np.random.default_rng(workload_seed(7, instance))
     T = T or poly.T
     return rng.integers(1, poly.p, size=(T, poly.n - 2), dtype=np.uint64)
 
@@ -236,7 +237,7 @@ def serve_stream(rate_per_s: float, duration_s: float, pool: List[Poly], instanc
     """Poisson arrivals; each request picks a polynomial from ``pool`` and a
     fresh base point.  The first ``new_fraction`` of the pool is treated as
     not yet resident by the caller."""
-    rng = np.random.default_rng(config_seed(5, instance))
+    rng = np.random.default_rng(workload_seed(5, instance))
     t = 0.0
     reqs = []
     while True:
@@ -253,7 +254,7 @@ def serve_stream(rate_per_s: float, duration_s: float, pool: List[Poly], instanc
 def serve_pool(count: int, instance: int = 0, s_max: float = 5e6) -> List[Poly]:
     """Polynomials for the served stream: n ~ U{4..8}, s log-uniform in
     [1e3, s_max], p in {2^31-1, 2^63-25}."""
-    rng = np.random.default_rng(config_seed(5, 100 + instance))
+    rng = np.random.default_rng(workload_seed(5, 100 + instance))
     pool = []
     for j in range(count):
         n = int(rng.integers(4, 9))

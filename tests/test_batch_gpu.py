@@ -25,7 +25,7 @@ def _host(q, buf):
 
 
 def _mixed(count, s_max, seed):
-    return W.batch_config(count=count, instance=seed, s_max=s_max, t_log2=(0, 9))
+    return W.uneven_batch(count=count, instance=seed, s_max=s_max, t_log2=(0, 9))
 
 
 @pytest.mark.parametrize("graph", [True, False])

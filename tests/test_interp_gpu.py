@@ -155,7 +155,7 @@ def test_async_and_order(orc):
 
 def test_full_size_round_trip():
     """The 1e6-term workload: its 1024 images give back all 1e6 coefficients."""
-    w = W.config2()
+    w = W.n6_s1e6_p63_T1024()
     T = int(group_sizes(w.exps).max())
     assert T <= w.T
     with PV.Poly(w.p, w.exps, w.coeffs) as h:

@@ -67,8 +67,8 @@ def check(orc, p, exps, coeffs, beta, T, tuning=None, t0=1, single=None):
     return got
 
 
-def test_config1_full(orc):
-    w = W.config1()
+def test_n4_s1e3_full(orc):
+    w = W.n4_s1e3_p31_T64()
     check(orc, w.p, w.exps, w.coeffs, w.beta, w.T)
 
 
@@ -118,7 +118,7 @@ def test_edge_all_groups_distinct(orc):
 
 
 def test_edge_T_values(orc):
-    w = W.config1()
+    w = W.n4_s1e3_p31_T64()
     for T in (1, 2, 15, 16, 17, 97):
         check(orc, w.p, w.exps, w.coeffs, w.beta, T)
 
@@ -160,7 +160,7 @@ def test_edge_empty(orc):
 
 
 def test_run_async_offset(orc):
-    w = W.config1()
+    w = W.n4_s1e3_p31_T64()
     check(orc, w.p, w.exps, w.coeffs, w.beta, 20, t0=40)
     rng = np.random.default_rng(8)
     poly = W.random_small(rng, W.P63, 6, 900, 1, dmax=4)
@@ -211,7 +211,7 @@ def test_single_launch_shapes(orc, p):
 
 def test_single_launch_selection():
     """Which runs take the single-launch path, and how it is switched off."""
-    w = W.config1()
+    w = W.n4_s1e3_p31_T64()
     with PV.Poly(w.p, w.exps, w.coeffs) as poly:
         assert poly.get_tuning(w.T) == (0, 0, 0)
         poly.set_tuning(0, 16, 0)
@@ -229,7 +229,7 @@ def test_single_launch_selection():
 
 
 def test_deterministic_repeat():
-    w = W.config1()
+    w = W.n4_s1e3_p31_T64()
     with PV.Poly(w.p, w.exps, w.coeffs) as poly:
         a = poly.run(w.beta, 64)
         for _ in range(3):
@@ -264,15 +264,15 @@ def _sampled_rows(orc, w, rows, got):
         assert np.array_equal(got[t - 1].astype(np.uint64), want), f"row t={t}"
 
 
-def test_config2_full_size_sampled(orc):
+def test_n6_s1e6_full_size_sampled(orc):
     """n=6, 1e6 terms, p = 2^63-25, T = 1024, automatic tuning (the benchmark
     configuration); full oracle rows at a few t."""
     import concurrent.futures as cf
-    w = W.config2()
-    _say("config2: generated")
+    w = W.n6_s1e6_p63_T1024()
+    _say("n6_s1e6_p63_T1024: generated")
     with PV.Poly(w.p, w.exps, w.coeffs) as poly:
         got = poly.run(w.beta, w.T)
-        _say("config2: tuning", poly.get_tuning(w.T), "G", poly.G)
+        _say("n6_s1e6_p63_T1024: tuning", poly.get_tuning(w.T), "G", poly.G)
         gd, ge = poly.groups()
     rows = [1, 2, 5, 6, 513, w.T - 1, w.T]
     with cf.ThreadPoolExecutor(len(rows)) as ex:
@@ -280,7 +280,7 @@ def test_config2_full_size_sampled(orc):
         for t, f in futs.items():
             want = f.result()[0]
             assert np.array_equal(got[t - 1], want), f"row t={t}"
-    _say("config2: rows ok")
+    _say("n6_s1e6_p63_T1024: rows ok")
 
 
 def test_single_hip_runtime():
@@ -402,16 +402,16 @@ def test_pseudo_mersenne_refused():
             assert ei.value.code == PV.EUNSUPPORTED
 
 
-def test_config4_full_size_sampled(orc):
+def test_n8_s1e7_full_size_sampled(orc):
     """n=8, 1e7 terms, p = 2^63-25, T = 4096 (the large workload), automatic
     tuning: whole oracle rows at the first, a middle and the last t, and
     single coefficients spread over the table."""
     import concurrent.futures as cf
-    w = W.config4()
-    _say("config4: generated")
+    w = W.n8_s1e7_p63_T4096()
+    _say("n8_s1e7_p63_T4096: generated")
     with PV.Poly(w.p, w.exps, w.coeffs) as poly:
         got = poly.run(w.beta, w.T)
-        _say("config4: tuning", poly.get_tuning(w.T), "G", poly.G)
+        _say("n8_s1e7_p63_T4096: tuning", poly.get_tuning(w.T), "G", poly.G)
         gd, ge = poly.groups()
     rows = [1, 2049, w.T]
     with cf.ThreadPoolExecutor(len(rows)) as ex:
@@ -425,12 +425,12 @@ def test_config4_full_size_sampled(orc):
         assert int(got[t - 1, g]) == want, (t, g)
 
 
-def test_batch_full_config_sampled(orc):
+def test_batch_full_size_sampled(orc):
     """The 256-member uneven batch of the benchmark (terms up to 1e6, T up to
     2048, both primes) as one graph replay: members' first and last images
     against the oracle for a spread of members."""
     import torch
-    ws = W.batch_config(count=256)
+    ws = W.uneven_batch(count=256)
     polys = [PV.Poly(w.p, w.exps, w.coeffs) for w in ws]
     Ts = [w.T for w in ws]
     try:

@@ -171,7 +171,7 @@ def test_points_unsupported():
 
 def test_points_full_size_sampled(orc):
     """The 1e6-term workload at 1024 random points: sampled rows against the oracle."""
-    w = W.config2()
+    w = W.n6_s1e6_p63_T1024()
     rng = np.random.default_rng(2004)
     pts = rng.integers(1, w.p, size=(w.T, w.n - 2), dtype=np.uint64)
     with PV.Poly(w.p, w.exps, w.coeffs) as h:

@@ -12,7 +12,7 @@ pytestmark = pytest.mark.gpu
 def test_autotune_and_cache(tmp_path):
     orc = Oracle()
     PV.tune_clear()
-    w = W.make_poly(W.config_seed(2, 7), W.P63, 6, 20000, 64, 40, 20)
+    w = W.make_poly(W.workload_seed(2, 7), W.P63, 6, 20000, 64, 40, 20)
     with PV.Poly(w.p, w.exps, w.coeffs) as q:
         heur = q.get_tuning(w.T)
         K, P, C, ms = q.autotune(w.beta, w.T)
@@ -36,7 +36,7 @@ def test_autotune_exhaustive_small(tmp_path):
     """A run small enough for the single-launch path: the autotuner times it
     too, and its choice (K = P = C = 0 for that path) survives save / load."""
     PV.tune_clear()
-    w = W.config1()
+    w = W.n4_s1e3_p31_T64()
     with PV.Poly(w.p, w.exps, w.coeffs) as q:
         assert q.get_tuning(w.T) == (0, 0, 0)
         K, P, C, ms = q.autotune(w.beta, w.T, exhaustive=True)
@@ -59,7 +59,7 @@ def test_autotune_fp64_product(exhaustive):
     exist only for K <= 8: the autotuner keeps to those and the result stays
     exact."""
     PV.tune_clear()
-    w = W.make_poly(W.config_seed(2, 8), W.P50, 6, 30000, 48, 40, 20)
+    w = W.make_poly(W.workload_seed(2, 8), W.P50, 6, 30000, 48, 40, 20)
     with PV.Poly(w.p, w.exps, w.coeffs) as q:
         assert q.arith() == "fp64"
         K, P, C, ms = q.autotune(w.beta, w.T, exhaustive=exhaustive)

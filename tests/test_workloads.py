@@ -10,8 +10,8 @@ def _distinct(exps):
     return np.unique(exps, axis=0).shape[0] == exps.shape[0]
 
 
-def test_config1_shape_and_bounds():
-    p = W.config1()
+def test_n4_s1e3_shape_and_bounds():
+    p = W.n4_s1e3_p31_T64()
     assert (p.n, p.s, p.T, p.p) == (4, 1000, 64, W.P31)
     assert p.exps.dtype == np.uint32 and p.exps.max() <= 10
     assert _distinct(p.exps)
@@ -19,10 +19,10 @@ def test_config1_shape_and_bounds():
 
 
 def test_reproducible():
-    a, b = W.config1(), W.config1()
+    a, b = W.n4_s1e3_p31_T64(), W.n4_s1e3_p31_T64()
     assert np.array_equal(a.exps, b.exps) and np.array_equal(a.coeffs, b.coeffs)
     assert np.array_equal(a.beta, b.beta)
-    c = W.config1(instance=1)
+    c = W.n4_s1e3_p31_T64(instance=1)
     assert not np.array_equal(a.coeffs, c.coeffs)
 
 
@@ -42,8 +42,8 @@ def test_raise_dr_makes_room():
     assert W.raise_dr(1000, 8, 40, 20) == 20
 
 
-def test_batch_config_small():
-    polys = W.batch_config(count=6, s_max=3e3)
+def test_uneven_batch_small():
+    polys = W.uneven_batch(count=6, s_max=3e3)
     assert len(polys) == 6
     for q in polys:
         assert 4 <= q.n <= 8 and 1000 <= q.s <= 3000 and 32 <= q.T <= 2048
