@@ -279,6 +279,7 @@ static void retire(peval_server *S) {
       if (q == hipErrorNotReady) return;
       if (q != hipSuccess) {
         S->err = fail(PEVAL_EDEVICE, "pass failed: %s", hipGetErrorString(q));
+        S->cv_done.notify_all();  // waiters return the error instead of waiting on
         return;
       }
       float ms = 0;
@@ -536,6 +537,7 @@ static bool launch_pass_impl(peval_server *S, std::unique_lock<std::mutex> &lk) 
     lk.lock();
     if (launch_rc != PEVAL_OK) {
       S->err = launch_rc;
+      S->cv_done.notify_all();  // waiters return the error instead of waiting on
       return false;
     }
   }
@@ -756,8 +758,6 @@ extern "C" int peval_server_submit(peval_server *S, uint64_t poly_id, const uint
   r.out_bytes = (uint64_t)T * sp.G * sp.w;
   r.t_submit = now_s();
   r.ts = slice_evals(S, sp, T);
-  // chains: enough for the device when the request runs alone, within 1/4
-  // of the budget for its scratch reservation
   // chains: enough to fill the device when the request runs alone (about
   // 8192 waves at 8 terms per thread), within 1/4 of the budget
   const uint64_t want = (8192ull * 512 + sp.s + 8 * sp.G - 1) / (sp.s + 8 * sp.G);
