@@ -26,9 +26,36 @@ const Mod64 &mod_for<W64>(const peval_poly *h) { return h->m64; }
 template <>
 const Mod32 &mod_for<W32>(const peval_poly *h) { return h->m32; }
 
-// Device copies of the sort order and group structure (first call only).
+static void free_interp_arrays(peval_poly *h) {
+  uint32_t **arrays[] = {&h->d_order, &h->d_gorder, &h->d_task_group, &h->d_task_first};
+  for (uint32_t **a : arrays) {
+    if (*a) (void)hipFree(*a);
+    *a = nullptr;
+  }
+  for (auto &lvl : h->d_mt)
+    for (uint32_t *&a : lvl) {
+      if (a) (void)hipFree(a);
+      a = nullptr;
+    }
+}
+
+static int interp_setup_once(peval_poly *h);
+
+// Device copies of the sort order and group structure (first complete call
+// only; a setup that failed half way is undone and tried again next time).
 int interp_setup(peval_poly *h) {
-  if (h->d_order) return PEVAL_OK;
+  if (h->interp_ready) return PEVAL_OK;
+  free_interp_arrays(h);
+  const int rc = interp_setup_once(h);
+  if (rc != PEVAL_OK) {
+    free_interp_arrays(h);
+    return rc;
+  }
+  h->interp_ready = true;
+  return PEVAL_OK;
+}
+
+static int interp_setup_once(peval_poly *h) {
   std::vector<uint32_t> off32(h->G + 1), gord(h->G);
   for (uint64_t g = 0; g <= h->G; ++g) off32[g] = (uint32_t)h->grp_off[g];
   std::iota(gord.begin(), gord.end(), 0u);
@@ -36,9 +63,14 @@ int interp_setup(peval_poly *h) {
     return h->grp_off[x + 1] - h->grp_off[x] > h->grp_off[y + 1] - h->grp_off[y];
   });
   HIP_TRY(hipMalloc((void **)&h->d_order, std::max<size_t>(h->order.size(), 1) * 4));
-  if (!h->d_grp_off32) {
-    HIP_TRY(hipMalloc((void **)&h->d_grp_off32, off32.size() * 4));
-    HIP_TRY(hipMemcpy(h->d_grp_off32, off32.data(), off32.size() * 4, hipMemcpyHostToDevice));
+  if (!h->d_grp_off32) {  // (uploaded at create for small polynomials)
+    uint32_t *d = nullptr;
+    HIP_TRY(hipMalloc((void **)&d, off32.size() * 4));
+    if (hipMemcpy(d, off32.data(), off32.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+      (void)hipFree(d);
+      return fail(PEVAL_EDEVICE, "group offsets upload");
+    }
+    h->d_grp_off32 = d;
   }
   HIP_TRY(hipMalloc((void **)&h->d_gorder, std::max<size_t>(gord.size(), 1) * 4));
   HIP_TRY(hipMemcpy(h->d_order, h->order.data(), h->order.size() * 4, hipMemcpyHostToDevice));

@@ -117,6 +117,7 @@ struct peval_poly {
   // (d_grp_off32 is uploaded at create for polynomials small enough for the
   // single-launch path, which reads it too)
   uint32_t *d_order = nullptr, *d_grp_off32 = nullptr, *d_gorder = nullptr;
+  bool interp_ready = false;           // every interpolation array below is in place
   uint32_t *d_task_group = nullptr, *d_task_first = nullptr;
   uint64_t ntasks = 0;
   uint32_t interp_H = 1;                       // sub-products per group for Q

@@ -192,12 +192,20 @@ int run_points_impl(peval_poly *h, const uint64_t *points, uint32_t T, void *dev
     PEVAL_TRY(deal_slots(h, K, pl->NT, fp, &slot_term));
     PointsPrep pp;
     const uint64_t total = (uint64_t)K * pl->NT;
-    HIP_TRY(hipMalloc(&pp.pa, total * w));
-    HIP_TRY(hipMalloc(&pp.paq, total * w));
-    HIP_TRY(hipMalloc((void **)&pp.pidx, total * sizeof(uint64_t)));
-    HIP_TRY(hipMalloc((void **)&pp.slot_term, total * sizeof(uint32_t)));
+    const bool ok = hipMalloc(&pp.pa, total * w) == hipSuccess && hipMalloc(&pp.paq, total * w) == hipSuccess &&
+                    hipMalloc((void **)&pp.pidx, total * sizeof(uint64_t)) == hipSuccess &&
+                    hipMalloc((void **)&pp.slot_term, total * sizeof(uint32_t)) == hipSuccess &&
+                    hipMemcpy(pp.slot_term, slot_term.data(), total * sizeof(uint32_t), hipMemcpyHostToDevice) ==
+                        hipSuccess;
+    if (!ok) {  // nothing half-built stays behind
+      (void)hipFree(pp.pa);
+      (void)hipFree(pp.paq);
+      (void)hipFree(pp.pidx);
+      (void)hipFree(pp.slot_term);
+      (void)hipGetLastError();
+      return fail(PEVAL_ENOMEM, "point-mode slot arrays of %llu slots", (unsigned long long)total);
+    }
     it = h->pprep.emplace(K, pp).first;
-    HIP_TRY(hipMemcpy(pp.slot_term, slot_term.data(), total * sizeof(uint32_t), hipMemcpyHostToDevice));
     ProfScope ps(st, 1);
     points_prep_kernel<A><<<(unsigned)((total + 255) / 256), 256, 0, st>>>(
         (const T_ *)h->d_coeff, h->d_exps, pp.slot_term, h->s, pl->NT, K, fp, (T_ *)pp.pa, (T_ *)pp.paq, pp.pidx,
