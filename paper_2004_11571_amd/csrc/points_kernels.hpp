@@ -19,7 +19,8 @@
 //                        their table entries, k-major, so that neighbouring
 //                        lanes read neighbouring entries
 //   points_eval_kernel   per point: the block stages the point's tables in
-//                        LDS, every thread sums its K terms; then the
+//                        LDS (the next point's already on their way in
+//                        registers), every thread sums its K terms; then the
 //                        segmented walk of the power path, without the
 //                        merge of sub-tiles (a pass holds only 8 points, too
 //                        few to pay for the merge)
@@ -39,6 +40,12 @@ constexpr int kPointsP = 8;          // points per pass of the segmented walk
 constexpr int kMaxFactors = 4;
 constexpr int kMaxDigits = 2 * kMaxTail;
 constexpr uint32_t kPointsTableBytes = 32768;  // LDS for one point's tables
+// 16-byte pieces per thread of the next point's tables prefetched into
+// registers: four for 64-bit residues (tables up to 16 KiB; measured 10%
+// faster on the 1e6-term workload), none for 32-bit ones, whose kernels lose
+// a wave per SIMD to the extra registers and measured slower with them
+template <class T>
+constexpr int points_prefetch() { return sizeof(T) == 8 ? 4 : 0; }
 
 // How a term's tail monomial is split into factor-table lookups.
 struct FactorPlan {
@@ -151,6 +158,8 @@ __global__ void points_prep_kernel(const typename A::T *coeff, const uint16_t *e
   pidx[idx] = packed;
 }
 
+
+
 template <class A, int K, int NF>
 __global__ __launch_bounds__(kEvalBlock) void points_eval_kernel(PointsArgs<A> a) {
   using T = typename A::T;
@@ -178,6 +187,28 @@ __global__ __launch_bounds__(kEvalBlock) void points_eval_kernel(PointsArgs<A> a
   const uint32_t L = (c < a.T) ? (a.T - 1 - c) / a.C + 1 : 0;  // points of chain c
   const uint32_t nvec = a.E * 2 * (uint32_t)sizeof(T) / 16;       // 16-byte pieces of one point's tables
 
+  // The first PRE x 256 pieces of the next point's tables are loaded into
+  // registers while the current point is evaluated, so the HBM/L2 latency of
+  // the copy overlaps the arithmetic; pieces beyond that are copied after the
+  // barrier as they come.  Loads are unconditional at clamped indices
+  // (nvec >= 1); the pieces past nvec are never stored.  (Held in named
+  // variables: an indexed array here was kept in scratch memory.)
+  constexpr int PRE = points_prefetch<T>();
+  uint4 p0 = make_uint4(0, 0, 0, 0), p1 = p0, p2 = p0, p3 = p0;
+  const uint32_t last = nvec - 1;
+  const uint32_t u0 = min(threadIdx.x, last), u1 = min(threadIdx.x + kEvalBlock, last);
+  const uint32_t u2 = min(threadIdx.x + 2 * kEvalBlock, last), u3 = min(threadIdx.x + 3 * kEvalBlock, last);
+  static_assert(PRE == 0 || PRE == 4, "prefetch of 0 or 4 pieces per thread");
+  auto prefetch = [&](const uint4 *src) {
+    if constexpr (PRE == 4) {
+      p0 = src[u0];
+      p1 = src[u1];
+      p2 = src[u2];
+      p3 = src[u3];
+    }
+  };
+  if (L) prefetch(reinterpret_cast<const uint4 *>(a.tables + (uint64_t)c * a.E * 2));
+
   for (uint32_t i0 = 0; i0 < L; i0 += P) {
     const int np = (L - i0 < (uint32_t)P) ? (int)(L - i0) : P;
 #pragma unroll 1
@@ -185,8 +216,20 @@ __global__ __launch_bounds__(kEvalBlock) void points_eval_kernel(PointsArgs<A> a
       const uint64_t t = (uint64_t)c + (uint64_t)(i0 + q) * a.C;
       const uint4 *src = reinterpret_cast<const uint4 *>(a.tables + t * a.E * 2);
       __syncthreads();  // the previous point's tables are no longer read
-      for (uint32_t u = threadIdx.x; u < nvec; u += kEvalBlock) reinterpret_cast<uint4 *>(tab)[u] = src[u];
+      {
+        uint4 *t4 = reinterpret_cast<uint4 *>(tab);
+        const uint32_t u = threadIdx.x;
+        if constexpr (PRE == 4) {
+          if (u < nvec) t4[u] = p0;
+          if (u + kEvalBlock < nvec) t4[u + kEvalBlock] = p1;
+          if (u + 2 * kEvalBlock < nvec) t4[u + 2 * kEvalBlock] = p2;
+          if (u + 3 * kEvalBlock < nvec) t4[u + 3 * kEvalBlock] = p3;
+        }
+      }
+      for (uint32_t u = threadIdx.x + PRE * kEvalBlock; u < nvec; u += kEvalBlock)
+        reinterpret_cast<uint4 *>(tab)[u] = src[u];
       __syncthreads();
+      if (i0 + q + 1 < L) prefetch(reinterpret_cast<const uint4 *>(a.tables + (t + a.C) * a.E * 2));
       if (active) {
         typename A::Acc acc = A::zero();
 #pragma unroll
