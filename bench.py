@@ -43,10 +43,10 @@ HBM_PEAK = 8.0e12
 #   = 4; x*w - q*p (sub, sub-with-borrow) = 2; 96-bit lazy sum (add, 2x
 #   add-with-carry) = 3; total 18.
 #   32-bit residues: mul_hi, mul_lo, mul_lo, sub = 4; 64-bit lazy sum = 2.
-#   FP64 product (Alg. 2, p < 2^50): mul, fma, mul, floor, fma, add = 6,
-#   and two corrections (compare, add, 64-bit select as two 32-bit selects:
-#   4 each) = 8; the double sum (add) = 1; total 15.
-ALGO_OPS = {8: 18, 4: 6, "fp64": 15}
+#   FP64 product (Alg. 2, p < 2^50, signed running values): mul, fma, mul,
+#   floor, fma, add = 6, and one correction (compare, subtract, 64-bit
+#   select as two 32-bit selects) = 4; the double sum (add) = 1; total 11.
+ALGO_OPS = {8: 18, 4: 6, "fp64": 11}
 # Point mode (arbitrary points): a term's contribution takes one lazy Shoup
 # product per factor table (NF - 1 for the monomial, one for the
 # coefficient) plus the lazy sum: NF * 15 + 3 ops (64-bit residues; the
@@ -628,7 +628,7 @@ def main():
         # one AVX-512 core = 3.54e9 term-evals/s); other configurations have no
         # published number
         "vs_baseline": (value / (5e9 / 1.411)) if args.workload == "paper_table2" else None,
-        "dtype": "u64" if poly.elem_bytes == 8 else "u32",
+        "dtype": "f64" if arith == "fp64" and not points_mode else ("u64" if poly.elem_bytes == 8 else "u32"),
         "data": "synthetic",
         "config": {"workload": w.name + ("_random_points" if points_mode else ""), "n": w.n, "s": w.s,
                    "T": w.T, "p": w.p, "G": poly.G,

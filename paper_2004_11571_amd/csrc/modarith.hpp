@@ -300,10 +300,16 @@ struct ModF64 {
   Mod64 m;    // integer constants, for the output conversion
 };
 
-// Alg. 2: x, y in [0, p), p < 2^50.  h + l = x*y exactly (FMA error-free
-// product), c is the quotient up to one, g the remainder up to p, and the
-// two tests of the algorithm bring g into [0, p).
-__device__ __forceinline__ double alg2_mul(double x, double y, double p, double u) {
+// Alg. 2 (p < 2^50): h + l = x*y exactly (FMA error-free product), c the
+// quotient up to one, g the remainder.  As printed the algorithm takes x, y
+// in [0, p) and applies two corrections (g >= p, g < 0).  Here x may be
+// negative, |x| < p, with 0 <= y < p: the error-free product and the
+// quotient estimate work unchanged (|x y| < p^2 still bounds the estimate's
+// error by one), so g = x y - c p is exact and lies in (-p, 2p), and one
+// conditional subtraction brings it into (-p, p), which is again a valid x.
+// Running values kept in (-p, p) thus save the second correction of every
+// product; they are made canonical once per coefficient sum (fp_reduce).
+__device__ __forceinline__ double alg2_mul_signed(double x, double y, double p, double u) {
 #pragma clang fp contract(off)
   double h = x * y;
   double l = __builtin_fma(x, y, -h);
@@ -311,9 +317,7 @@ __device__ __forceinline__ double alg2_mul(double x, double y, double p, double 
   double c = __builtin_floor(b);
   double d = __builtin_fma(-c, p, h);
   double g = d + l;
-  g = (g >= p) ? g - p : g;
-  g = (g < 0.0) ? g + p : g;
-  return g;
+  return (g >= p) ? g - p : g;
 }
 
 // Alg. 3: x, y in [0, p).
@@ -323,8 +327,8 @@ __device__ __forceinline__ double alg3_add(double x, double y, double p) {
   return (s >= p) ? s - p : s;
 }
 
-// An exact integer s in [0, 2^53) reduced into [0, p) (quotient from 1/p,
-// remainder by one FMA, then the same two corrections as Alg. 2).
+// An exact integer s with |s| < 2^53 reduced into [0, p) (quotient from
+// 1/p, remainder by one FMA, then the same two corrections as Alg. 2).
 __device__ __forceinline__ double fp_reduce(double s, double p, double u) {
 #pragma clang fp contract(off)
   double c = __builtin_floor(s * u);
@@ -342,9 +346,10 @@ __device__ __forceinline__ uint64_t fp_to_u64(double v) {
   return ((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo;
 }
 
-// Running values in [0, p) as doubles; a thread sums at most 8 of them
-// (< 2^53, exact) before reducing, and partial sums travel as canonical
-// uint64 residues (shared with the 64-bit integer path).
+// Running values in (-p, p) as doubles (alg2_mul_signed); a thread sums at
+// most 8 of them (|sum| < 2^53, exact) before reducing to [0, p), and
+// partial sums travel as canonical uint64 residues (shared with the 64-bit
+// integer path).
 struct WF64 {
   using T = double;
   using PT = uint64_t;
@@ -359,7 +364,7 @@ struct WF64 {
   __device__ static __forceinline__ void add_walk(Acc &a, const Acc &b, const M &m) { a.s = alg3_add(a.s, b.s, m.p); }
   __device__ static __forceinline__ PT reduce(const Acc &a, const M &) { return fp_to_u64(a.s); }
   __device__ static __forceinline__ Acc stage(const Acc &a, const M &m) { return Acc{fp_reduce(a.s, m.p, m.u)}; }
-  __device__ static __forceinline__ T mul_lazy(T x, T w, T, const M &m) { return alg2_mul(x, w, m.p, m.u); }
+  __device__ static __forceinline__ T mul_lazy(T x, T w, T, const M &m) { return alg2_mul_signed(x, w, m.p, m.u); }
 };
 
 }  // namespace peval

@@ -1,0 +1,133 @@
+"""The FP64 product's range argument (Section 3.1, Alg. 2 and 3), checked on
+the host with exact arithmetic.
+
+The FP64 policy keeps running values signed: the left operand x of Alg. 2
+lies in (-p, p), the right one y (a power of a monomial value) in [0, p),
+and a single correction (g >= p gives g - p) is applied.  The claim is that
+g = x y - c p is exact and lies in (-p, 2p), so the corrected value is
+congruent to x y and lies in (-p, p) again; and that a sum of at most 8
+such values (|s| < 2^53) is brought into [0, p) by the quotient-and-FMA step
+with both corrections.
+
+Each IEEE operation is modelled with Python floats (round to nearest, ties
+to even, as the device runs) and each FMA as the exact rational result
+rounded once (int / int true division is correctly rounded).  These are
+properties of the mathematics the kernels rely on, not a copy of a kernel;
+a wrong bound (a too-wide operand range, a missing correction, a p beyond
+2^50) fails here.
+"""
+import math
+import random
+from fractions import Fraction
+
+import pytest
+
+
+def fma(a: float, b: float, c: float) -> float:
+    exact = Fraction(a) * Fraction(b) + Fraction(c)
+    return exact.numerator / exact.denominator
+
+
+def alg2_signed(x: float, y: float, p: float, u: float):
+    h = x * y
+    l = fma(x, y, -h)
+    b = h * u
+    c = float(math.floor(b))
+    d = fma(-c, p, h)
+    g = d + l
+    return g, c, (g - p if g >= p else g)
+
+
+def reduce_sum(s: float, p: float, u: float) -> float:
+    c = float(math.floor(s * u))
+    r = fma(-c, p, s)
+    r = r - p if r >= p else r
+    return r + p if r < 0.0 else r
+
+
+# The last modulus is a 50-bit odd one whose double reciprocal lies well
+# below 1/p (relative error -1.1e-16): there the quotient estimate can fall
+# short by one and the correction fires.  For p = 2^50 - 27 it never does on
+# random operands, since fl(1/p) is accurate to about 2^-100.
+P_LOW_RECIP = 1123934916484611
+MODULI = [2**31 + 11, 2**40 - 87, 2**49 + 9, 2**50 - 27, 2**50 - 1, P_LOW_RECIP]
+
+
+def _operands(p: int, rng: random.Random):
+    edge_x = [-(p - 1), -(p - 2), -(p // 2), -1, 0, 1, p // 2, p - 2, p - 1]
+    edge_y = [0, 1, 2, p // 2, p // 2 + 1, p - 2, p - 1]
+    for x in edge_x:
+        for y in edge_y:
+            yield x, y
+    for _ in range(3000):
+        yield rng.randrange(-(p - 1), p), rng.randrange(0, p)
+    # operands near the top of the range, where the quotient estimate is tightest
+    for _ in range(1000):
+        yield rng.choice((-1, 1)) * (p - 1 - rng.randrange(1 << 20)), p - 1 - rng.randrange(1 << 20)
+
+
+@pytest.mark.parametrize("p", MODULI)
+def test_signed_product_exact_and_in_range(p):
+    rng = random.Random(p)
+    pf, u = float(p), 1.0 / float(p)
+    for x, y in _operands(p, rng):
+        g, c, r = alg2_signed(float(x), float(y), pf, u)
+        assert g == x * y - int(c) * p, (x, y)          # remainder exact
+        assert -p < g < 2 * p, (x, y)                     # before the correction
+        assert -p < r < p and (int(r) - x * y) % p == 0, (x, y)  # after it: a valid left operand again
+
+
+@pytest.mark.parametrize("p", MODULI)
+def test_chain_of_signed_products(p):
+    """A running value kept signed over a long chain stays congruent to the
+    exact power product and never leaves (-p, p)."""
+    rng = random.Random(p + 1)
+    pf, u = float(p), 1.0 / float(p)
+    for _ in range(20):
+        lam = rng.randrange(0, p)
+        gamma = rng.randrange(0, p)
+        x, want = float(lam), lam
+        for _ in range(200):
+            x = alg2_signed(x, float(gamma), pf, u)[2]
+            want = want * gamma % p
+            assert -p < x < p and (int(x) - want) % p == 0
+
+
+@pytest.mark.parametrize("p", MODULI)
+def test_sum_of_eight_reduced(p):
+    rng = random.Random(p + 2)
+    pf, u = float(p), 1.0 / float(p)
+    cases = [[-(p - 1)] * 8, [p - 1] * 8, [0] * 8, [-(p - 1), p - 1] * 4, [p - 1] * 7 + [-1]]
+    cases += [[rng.randrange(-(p - 1), p) for _ in range(rng.randrange(1, 9))] for _ in range(3000)]
+    for vals in cases:
+        s = 0.0
+        for v in vals:
+            s += float(v)
+        assert s == sum(vals)                             # the thread's sum is exact
+        r = reduce_sum(s, pf, u)
+        assert 0 <= r < p and r == sum(vals) % p, vals
+
+
+def test_correction_fires():
+    """An operand pair for which g lands in [p, 2p): the one correction is
+    needed, and it brings the value back into (-p, p)."""
+    p = P_LOW_RECIP
+    x, y = 726220303110107, 618400639462378
+    g, c, r = alg2_signed(float(x), float(y), float(p), 1.0 / float(p))
+    assert g >= p and g == x * y - int(c) * p
+    assert -p < r < p and (int(r) - x * y) % p == 0
+
+
+def test_checks_catch_planted_mistakes():
+    """The checks above are sharp enough to see a broken argument: near
+    p = 2^53 (outside the policy's p < 2^50) the remainder stops being
+    exact."""
+    rng = random.Random(7)
+    p = 2**53 - 111
+    pf, u = float(p), 1.0 / float(p)
+    inexact = 0
+    for _ in range(500):
+        x, y = -(p - 1 - rng.randrange(1 << 20)), p - 1 - rng.randrange(1 << 20)
+        g, c, _ = alg2_signed(float(x), float(y), pf, u)
+        inexact += g != x * y - int(c) * p
+    assert inexact > 0

@@ -298,7 +298,13 @@ def test_single_hip_runtime():
 P40 = (1 << 40) - 87   # prime below 2^40
 
 
-@pytest.mark.parametrize("p", [P_SMALL_W8, P40, W.P50, (1 << 50) - 1 - 2 * 12345])
+# 50-bit odd modulus whose double reciprocal lies well below 1/p: the
+# quotient estimate of Alg. 2 falls short by one now and then, so the
+# product's correction is taken on the device (about 2e-5 of products).
+P_LOW_RECIP = 1123934916484611
+
+
+@pytest.mark.parametrize("p", [P_SMALL_W8, P40, W.P50, (1 << 50) - 1 - 2 * 12345, P_LOW_RECIP])
 @pytest.mark.parametrize("K", [1, 2, 4, 8])
 @pytest.mark.parametrize("P", [8, 16, 32])
 def test_fp64_product_path(orc, p, K, P):
@@ -328,6 +334,20 @@ def test_fp64_offsets_and_edges(orc):
         for beta in (poly.beta, np.ones(3, np.uint64), np.asarray([0, p - 1, 2], np.uint64)):
             assert np.array_equal(q.run(beta, 9), orc.evaluate(p, poly.exps, poly.coeffs, beta, 9))
     check(orc, p, poly.exps, poly.coeffs, poly.beta, 30, t0=500)
+
+
+@pytest.mark.parametrize("p", [W.P50, P_LOW_RECIP])
+def test_fp64_many_products(orc, p):
+    """2e4 terms x 400 rows (8e6 products) under the FP64 product at its
+    widest K, every image against the oracle."""
+    rng = np.random.default_rng(p % 1013)
+    poly = W.random_small(rng, p, 7, 20000, 1, dmax=8)
+    want = orc.evaluate(p, poly.exps, poly.coeffs, poly.beta, 400, threads=8)
+    with PV.Poly(p, poly.exps, poly.coeffs) as q:
+        q.set_arith("fp64")
+        for tun in ((8, 16, 0), (8, 32, 3)):
+            q.set_tuning(*tun)
+            assert np.array_equal(q.run(poly.beta, 400), want), tun
 
 
 def test_fp64_mode_limits():
@@ -423,6 +443,25 @@ def test_n8_s1e7_full_size_sampled(orc):
         t, g = int(rng.integers(1, w.T + 1)), int(rng.integers(0, len(gd)))
         want = orc.entry(w.p, w.exps, w.coeffs, w.beta, t, int(gd[g]), int(ge[g]))
         assert int(got[t - 1, g]) == want, (t, g)
+
+
+def test_table2_full_size_sampled(orc):
+    """The paper's Table 2 shape (n = 6, 5e5 terms, p = 2^50-27, T = 1e4)
+    under automatic tuning, which takes the FP64 product: whole oracle rows
+    at the first, a middle and the last t."""
+    import concurrent.futures as cf
+    w = W.paper_table2()
+    _say("paper_table2: generated")
+    with PV.Poly(w.p, w.exps, w.coeffs) as poly:
+        got = poly.run(w.beta, w.T)
+        _say("paper_table2: tuning", poly.get_tuning(w.T), "arith", poly.arith(), "G", poly.G)
+        assert poly.arith() == "fp64"
+    rows = [1, 2, 5001, w.T]
+    with cf.ThreadPoolExecutor(len(rows)) as ex:
+        futs = {t: ex.submit(orc.evaluate, w.p, w.exps, w.coeffs, w.beta, 1, t, 1) for t in rows}
+        for t, f in futs.items():
+            assert np.array_equal(got[t - 1], f.result()[0]), t
+    _say("paper_table2: rows ok")
 
 
 def test_batch_full_size_sampled(orc):
