@@ -266,9 +266,12 @@ int peval_tune_load(const char *path);
  * chains so that the work items (one wave of one chain of one polynomial)
  * have similar costs, allocates all device scratch, and captures the pass
  * (power tables, monomials, persistent evaluation kernels fed by work
- * queues in decreasing item cost, one for the 64-bit members and one for
- * the 32-bit ones, combine) into a hipGraph unless flags has
- * PEVAL_BATCH_NO_GRAPH.  The handles must outlive the batch.
+ * queues in decreasing item cost, one for each kind of member: 64-bit
+ * residues with the integer product, 64-bit residues with the FP64 product
+ * (members whose arithmetic resolves to it when the batch is created), and
+ * 32-bit residues; combine) into a hipGraph unless flags has
+ * PEVAL_BATCH_NO_GRAPH.  The handles must outlive the batch; a later
+ * peval_set_arith on a member does not change the batch.
  *
  * peval_batch_run evaluates polys[j] at betas[j] (n_j - 2 values each) for
  * t = t0s[j] .. t0s[j]+Ts[j]-1 (t0s may be NULL: all 1) into dev_outs[j]
@@ -279,7 +282,7 @@ int peval_tune_load(const char *path);
  * (four staging buffers in rotation) still awaits its upload.
  *
  * peval_batch_info fills info[5]: members, work items, persistent blocks
- * (both evaluation kernels), scratch bytes, term-evaluations per run.
+ * (all evaluation kernels), scratch bytes, term-evaluations per run.
  */
 typedef struct peval_batch peval_batch;
 #define PEVAL_BATCH_NO_GRAPH 1u

@@ -25,32 +25,42 @@ void batch_release(BatchCore &b) {
   b.arena = nullptr;
 }
 
-// Blocks that fill the chip with each evaluation kernel (64-bit, 32-bit).
-static int persistent_blocks(int blocks[2]) {
-  static int cached[2] = {0, 0};
+// Blocks that fill the chip with each kind's evaluation kernel.
+static int persistent_blocks(int blocks[kKinds]) {
+  static int cached[kKinds] = {};
   static std::mutex mu;
   std::lock_guard<std::mutex> lk(mu);
   if (!cached[0]) {
-    int dev = 0, per_cu64 = 0, per_cu32 = 0;
+    int dev = 0, per_cu[kKinds] = {};
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipGetDeviceProperties(&prop, dev));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu64, batch_eval_kernel<W64>, kEvalBlock, 0));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu32, batch_eval_kernel<W32>, kEvalBlock, 0));
-    cached[0] = std::max(1, per_cu64) * prop.multiProcessorCount;
-    cached[1] = std::max(1, per_cu32) * prop.multiProcessorCount;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[kKindW64], batch_eval_kernel<W64>, kEvalBlock, 0));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[kKindF64], batch_eval_kernel<WF64>, kEvalBlock, 0));
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[kKindW32], batch_eval_kernel<W32>, kEvalBlock, 0));
+    for (int k = 0; k < kKinds; ++k) cached[k] = std::max(1, per_cu[k]) * prop.multiProcessorCount;
   }
-  blocks[0] = cached[0];
-  blocks[1] = cached[1];
+  for (int k = 0; k < kKinds; ++k) blocks[k] = cached[k];
   return PEVAL_OK;
 }
 
 int batch_set_blocks(BatchCore &b) {
-  int bl[2];
+  int bl[kKinds];
   PEVAL_TRY(persistent_blocks(bl));
-  const uint64_t n[2] = {b.n_items64, (uint64_t)b.n_items - b.n_items64};
-  for (int k = 0; k < 2; ++k) b.eval_blocks[k] = (int)std::min<uint64_t>((uint64_t)bl[k], (n[k] + 3) / 4);
+  for (int k = 0; k < kKinds; ++k) {
+    const uint64_t n = (uint64_t)b.kind_first[k + 1] - b.kind_first[k];
+    b.eval_blocks[k] = (int)std::min<uint64_t>((uint64_t)bl[k], (n + 3) / 4);
+  }
   return PEVAL_OK;
+}
+
+// The product a member's evaluations take: that of its handle when the
+// batch is planned (FP64 where the handle's arithmetic resolves to it and
+// the plan keeps K <= 8, so that a thread's sum of doubles stays exact;
+// the Shoup product, exact for every p, otherwise).
+static uint32_t member_kind(const peval_poly *h, uint32_t K) {
+  if (h->w == 4) return kKindW32;
+  return (h->arith == 1 && K <= 8) ? kKindF64 : kKindW64;
 }
 
 // Bytes of device scratch one member needs (power tables, chain starts,
@@ -101,6 +111,7 @@ void batch_plan(BatchCore &b, const std::vector<BatchMember> &mem, void *arena, 
     BatchDesc &d = b.descs[j];
     const size_t w = h->w;
     d.w = h->w;
+    d.kind = member_kind(h, pl.K);
     d.ntail = h->n - 2;
     d.K = pl.K;
     d.C = mem[j].C;
@@ -113,6 +124,7 @@ void batch_plan(BatchCore &b, const std::vector<BatchMember> &mem, void *arena, 
     d.G = h->G;
     d.m64 = h->m64;
     d.m32 = h->m32;
+    d.mf = h->mf;
     d.to = h->tab;
     d.tab_total = h->tab_total;
     d.coeff = h->d_coeff;
@@ -145,16 +157,17 @@ void batch_plan(BatchCore &b, const std::vector<BatchMember> &mem, void *arena, 
   uint64_t n_items = 0;
   for (uint32_t j = 0; j < count; ++j) n_items += (uint64_t)b.descs[j].C * b.descs[j].NW;
   items.reserve(n_items);
-  // the 64-bit members' items first, then the 32-bit ones (one queue and
-  // one evaluation kernel per width), each in decreasing cost
-  for (uint32_t width : {8u, 4u}) {
+  // items grouped by kind (one queue and one evaluation kernel per kind),
+  // each group in decreasing cost
+  for (uint32_t kind = 0; kind < kKinds; ++kind) {
+    b.kind_first[kind] = (uint32_t)items.size();
     for (uint32_t j : order) {
-      if (b.descs[j].w != width) continue;
+      if (b.descs[j].kind != kind) continue;
       for (uint32_t c = 0; c < b.descs[j].C; ++c)
         for (uint64_t wv = 0; wv < b.descs[j].NW; ++wv) items.push_back(BatchItem{j, (uint32_t)wv, c, 0});
     }
-    if (width == 8) b.n_items64 = (uint32_t)items.size();
   }
+  b.kind_first[kKinds] = (uint32_t)items.size();
   b.n_items = (uint32_t)items.size();
   b.tab_total = ptab[count];
   b.mono_total = pmono[count];
@@ -216,13 +229,17 @@ int batch_enqueue(const BatchCore &b, hipStream_t st) {
     batch_mono_kernel<<<kXcds * xchunk, 256, 0, st>>>(b.d_desc, b.d_run, b.count, b.d_pmono, xchunk);
     HIP_TRY(hipGetLastError());
   }
-  if (b.n_items64) {
-    batch_eval_kernel<W64><<<b.eval_blocks[0], kEvalBlock, 0, st>>>(b.d_desc, b.d_items, b.n_items64, b.d_counter);
-    HIP_TRY(hipGetLastError());
-  }
-  if (b.n_items > b.n_items64) {
-    batch_eval_kernel<W32><<<b.eval_blocks[1], kEvalBlock, 0, st>>>(b.d_desc, b.d_items + b.n_items64,
-                                                                     b.n_items - b.n_items64, b.d_counter + 1);
+  for (uint32_t kind = 0; kind < kKinds; ++kind) {
+    const uint32_t first = b.kind_first[kind], n = b.kind_first[kind + 1] - first;
+    if (!n) continue;
+    const BatchItem *it = b.d_items + first;
+    uint32_t *ctr = b.d_counter + kind;
+    if (kind == kKindW64)
+      batch_eval_kernel<W64><<<b.eval_blocks[kind], kEvalBlock, 0, st>>>(b.d_desc, it, n, ctr);
+    else if (kind == kKindF64)
+      batch_eval_kernel<WF64><<<b.eval_blocks[kind], kEvalBlock, 0, st>>>(b.d_desc, it, n, ctr);
+    else
+      batch_eval_kernel<W32><<<b.eval_blocks[kind], kEvalBlock, 0, st>>>(b.d_desc, it, n, ctr);
     HIP_TRY(hipGetLastError());
   }
   if (b.out_total) {  // out_total counts combine tiles
@@ -379,7 +396,8 @@ extern "C" int peval_batch_info(const peval_batch *b, uint64_t *info) {
   if (!b || !info) return fail(PEVAL_EINVAL, "null argument");
   info[0] = b->core.count;
   info[1] = b->core.n_items;
-  info[2] = (uint64_t)b->core.eval_blocks[0] + (uint64_t)b->core.eval_blocks[1];
+  info[2] = 0;
+  for (int k = 0; k < kKinds; ++k) info[2] += (uint64_t)b->core.eval_blocks[k];
   info[3] = b->core.scratch_bytes;
   uint64_t te = 0;
   for (uint32_t j = 0; j < b->core.count; ++j) te += b->polys[j]->s * (uint64_t)b->Ts[j];

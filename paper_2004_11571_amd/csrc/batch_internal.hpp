@@ -21,8 +21,8 @@ struct BatchMember {
 struct BatchCore {
   uint32_t count = 0;
   uint32_t n_items = 0;
-  uint32_t n_items64 = 0;    // items of 64-bit members, first in the item list
-  int eval_blocks[2] = {0, 0};  // persistent blocks: 64-bit members, 32-bit members
+  uint32_t kind_first[kKinds + 1] = {};  // items of kind k: kind_first[k] .. kind_first[k+1]-1
+  int eval_blocks[kKinds] = {};          // persistent blocks of each kind's evaluation kernel
   uint64_t tab_total = 0, mono_total = 0, out_total = 0;
   size_t scratch_bytes = 0;
   std::vector<BatchDesc> descs;
@@ -54,7 +54,7 @@ void batch_bind(BatchCore &b, void *d_blob);
 int batch_build(BatchCore &b, const std::vector<BatchMember> &mem);
 int batch_enqueue(const BatchCore &b, hipStream_t st);
 void batch_release(BatchCore &b);
-// Persistent blocks of the two evaluation kernels for this batch's items.
+// Persistent blocks of the evaluation kernels for this batch's items.
 int batch_set_blocks(BatchCore &b);
 
 }  // namespace peval

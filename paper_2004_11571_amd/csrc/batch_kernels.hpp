@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "batch_types.hpp"
 #include "kernels.hpp"
 
@@ -40,8 +42,8 @@ __device__ __forceinline__ uint32_t find_poly_block(const uint64_t *prefix, uint
   return j;
 }
 
-__global__ void batch_reset_kernel(uint32_t *counter) {  // the two work queues
-  if (blockIdx.x == 0 && threadIdx.x < 2) counter[threadIdx.x] = 0;
+__global__ void batch_reset_kernel(uint32_t *counter) {  // the work queues, one per kind
+  if (blockIdx.x == 0 && threadIdx.x < kKinds) counter[threadIdx.x] = 0;
 }
 
 __global__ void batch_power_kernel(const BatchDesc *D, const BatchRun *R, uint32_t count, const uint64_t *prefix) {
@@ -77,7 +79,7 @@ __device__ __forceinline__ void batch_mono_one(const BatchDesc &d, uint64_t t0, 
   a.ntail = d.ntail;
   a.K = d.K;
   a.C = d.C;
-  a.as_double = 0;
+  a.as_double = d.kind == kKindF64;  // FP64 members take chain starts and Gamma as doubles
   a.m = m;
   monomial_entry<A>(a, d.to.off, local);
 }
@@ -107,7 +109,7 @@ __device__ __forceinline__ void batch_eval_item(const BatchDesc &d, const BatchI
   a.gamq = (const T *)d.gamq;
   a.endmask = d.endmask;
   a.slot_base = d.slot_base;
-  a.partial = (T *)d.partial;
+  a.partial = (typename A::PT *)d.partial;  // partial sums as canonical integer residues
   a.NT = d.NT;
   a.NW = d.NW;
   a.nslots = d.nslots;
@@ -124,17 +126,23 @@ template <>
 __device__ __forceinline__ const Mod32 &member_mod<W32>(const BatchDesc &d) { return d.m32; }
 template <>
 __device__ __forceinline__ const Mod64 &member_mod<W64>(const BatchDesc &d) { return d.m64; }
+template <>
+__device__ __forceinline__ const ModF64 &member_mod<WF64>(const BatchDesc &d) { return d.mf; }
 
-// Persistent evaluation over the work queue of the members of one residue
-// width (one kernel per width, so that each gets the registers and LDS of
-// its own widest variant rather than those of the 64-bit one).  The 64-bit
-// kernel is held to three waves per SIMD, as the single-polynomial kernel
-// runs: its few spills sit outside the evaluation passes, and three waves
+template <class A>
+constexpr uint32_t policy_kind() {
+  return std::is_same<A, W32>::value ? kKindW32 : std::is_same<A, WF64>::value ? kKindF64 : kKindW64;
+}
+
+// Persistent evaluation over the work queue of the members of one kind (one
+// kernel per kind, so that each gets the registers and LDS of its own
+// widest variant rather than those of the 64-bit one).  The 64-bit kernels
+// are held to three waves per SIMD, as the single-polynomial kernel runs:
+// its few spills sit outside the evaluation passes, and three waves
 // measured faster than the two that its unbounded register count allows.
 template <class A>
 __global__ __launch_bounds__(kEvalBlock, sizeof(typename A::T) == 8 ? 3 : 4) void batch_eval_kernel(
-    const BatchDesc *D, const BatchItem *items,
-                                                                uint32_t n_items, uint32_t *counter) {
+    const BatchDesc *D, const BatchItem *items, uint32_t n_items, uint32_t *counter) {
   __shared__ __align__(16) unsigned char stage[kEvalBlock / 64][sizeof(Stage<A, kBatchP>)];
   const int lane = threadIdx.x & 63;
   const int warp = threadIdx.x >> 6;
@@ -146,14 +154,18 @@ __global__ __launch_bounds__(kEvalBlock, sizeof(typename A::T) == 8 ? 3 : 4) voi
     if (next >= n_items) break;  // every wave reaches this once the queue is drained
     const BatchItem it = items[next];
     const BatchDesc &d = D[it.poly];
-    if (d.w != sizeof(typename A::T)) continue;  // never planned so; skipped rather than misread
+    if (d.kind != policy_kind<A>()) continue;  // never planned so; skipped rather than misread
     const typename A::M &m = member_mod<A>(d);
     switch (d.K) {
       case 1: batch_eval_item<A, 1>(d, it, lds, lane, m); break;
       case 2: batch_eval_item<A, 2>(d, it, lds, lane, m); break;
       case 4: batch_eval_item<A, 4>(d, it, lds, lane, m); break;
       case 8: batch_eval_item<A, 8>(d, it, lds, lane, m); break;
-      default: batch_eval_item<A, 16>(d, it, lds, lane, m); break;
+      default:
+        // the FP64 product sums at most 8 doubles exactly: its members are
+        // planned with K <= 8
+        if constexpr (!std::is_same<A, WF64>::value) batch_eval_item<A, 16>(d, it, lds, lane, m);
+        break;
     }
   }
 }

@@ -200,16 +200,20 @@ def n8_s1e7_p63_T4096(instance: int = 0) -> Poly:
 
 
 def uneven_batch(count: int = 256, instance: int = 0, s_max: float = 1e6,
-                 t_log2: tuple = (5, 11)) -> List[Poly]:
+                 t_log2: tuple = (5, 11), moduli: tuple = None) -> List[Poly]:
     """Uneven batch: n ~ U{4..8}, s log-uniform in [1e3, s_max], T log-uniform
-    in [2^5, 2^11], p in {2^31-1, 2^63-25} with probability 1/2 each."""
+    in [2^5, 2^11], p in {2^31-1, 2^63-25} with probability 1/2 each (or
+    uniform over ``moduli`` when given)."""
     rng = np.random.default_rng(workload_seed(3, instance))
     polys = []
     for j in range(count):
         n = int(rng.integers(4, 9))
         s = int(round(10 ** rng.uniform(3, math.log10(s_max))))
         T = int(round(2 ** rng.uniform(*t_log2)))
-        p = P31 if rng.random() < 0.5 else P63
+        if moduli is None:
+            p = P31 if rng.random() < 0.5 else P63
+        else:
+            p = int(moduli[min(int(rng.random() * len(moduli)), len(moduli) - 1)])
         dr = raise_dr(s, n, 40, 20)
         seed = int(rng.integers(0, 2**62))
         polys.append(make_poly(seed, p, n, s, T, 40, dr, name=f"batch{j}"))

@@ -51,6 +51,37 @@ def test_batch_equals_plain_runs(graph):
             q.destroy()
 
 
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_fp64_members(graph):
+    """Members with 2^31 <= p < 2^50 take the FP64 product in the batch as in
+    their plain runs (a third queue and kernel), mixed with 32- and 64-bit
+    integer members; one such member forced to the integer product."""
+    import torch
+    orc = Oracle()
+    ws = W.uneven_batch(count=18, instance=5, s_max=2e4, t_log2=(0, 9), moduli=(W.P31, W.P50, W.P63))
+    polys = [PV.Poly(w.p, w.exps, w.coeffs) for w in ws]
+    fp = [j for j, w in enumerate(ws) if w.p == W.P50]
+    assert len(fp) >= 3 and all(polys[j].arith() == "fp64" for j in fp)
+    polys[fp[0]].set_arith("int")
+    Ts = [w.T for w in ws]
+    try:
+        with PV.Batch(polys, Ts, graph=graph) as b:
+            outs = _outs(polys, Ts)
+            for rep in range(2):
+                betas = [np.asarray((w.beta.astype(object) * (rep + 2)) % w.p, np.uint64) for w in ws]
+                b.run(betas, outs, stream=torch.cuda.current_stream())
+                torch.cuda.synchronize()
+                for j, (q, w, beta, o) in enumerate(zip(polys, ws, betas, outs)):
+                    got = _host(q, o)
+                    assert np.array_equal(got, q.run(beta, w.T)), (rep, j, w.p)
+                    if j in fp:
+                        want = orc.evaluate(w.p, w.exps, w.coeffs, beta, w.T, threads=8)
+                        assert np.array_equal(got.astype(np.uint64), want), (rep, j)
+    finally:
+        for q in polys:
+            q.destroy()
+
+
 def test_batch_against_oracle_and_offsets():
     import torch
     orc = Oracle()

@@ -14,13 +14,13 @@ from paper_2004_11571_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def _pool(seed, count, s_max):
+def _pool(seed, count, s_max, moduli=(W.P63, W.P31)):
     rng = np.random.default_rng(seed)
     out = []
     for j in range(count):
         n = int(rng.integers(4, 9))
         s = int(round(10 ** rng.uniform(3, np.log10(s_max))))
-        p = W.P31 if j % 2 else W.P63
+        p = moduli[j % len(moduli)]
         out.append(W.make_poly(int(rng.integers(0, 2**62)), p, n, s, 1, 40, W.raise_dr(s, n, 40, 20)))
     return out
 
@@ -85,6 +85,29 @@ def test_served_tight_budget_and_oracle():
     want = _alone(pool, reqs)
     for g, w_ in zip(got, want):
         assert np.array_equal(g, w_)
+
+
+def test_served_fp64_members():
+    """Polynomials with 2^31 <= p < 2^50 are served with the FP64 product
+    (their own queue in each pass) beside 32- and 64-bit integer ones."""
+    pool = _pool(5, 6, 3e4, moduli=(W.P31, W.P50, W.P63))
+    reqs = _requests(pool, 30, 6, t_max=400)
+    orc = Oracle()
+    with PV.Server(4 << 30) as srv:
+        srv.configure(slice_work=5e6)
+        pids = [srv.add_poly(w.p, w.exps, w.coeffs) for w in pool]
+        rids = [srv.submit(pids[j], beta, T) for j, beta, T in reqs]
+        got = [srv.wait(r, 60000) for r in rids]
+    want = _alone(pool, reqs)
+    for k, (g, w_) in enumerate(zip(got, want)):
+        assert np.array_equal(g, w_), f"request {k}"
+    checked = 0
+    for (j, beta, T), g in zip(reqs, got):
+        w = pool[j]
+        if w.p == W.P50 and checked < 5:
+            assert np.array_equal(g.astype(np.uint64), orc.evaluate(w.p, w.exps, w.coeffs, beta, T, threads=8))
+            checked += 1
+    assert checked == 5
 
 
 def test_concurrent_submitters():
