@@ -39,20 +39,21 @@ HBM_PEAK = 8.0e12
 # 32x32->64 multiply-add, a 32-bit add/sub with carry, a three-input add or a
 # 64-bit add each count once):
 #   64-bit residues: high half of x*w' (mul_hi + 3 mad_u64_u32 + one 64-bit
-#   add) = 5; low half of x*w (mad + 2 mul_lo + add3) = 4; low half of q*p
-#   = 4; x*w - q*p (sub, sub-with-borrow) = 2; 96-bit lazy sum (add, 2x
-#   add-with-carry) = 3; total 18.
+#   add) = 5; the remainder x*w - q*p mod 2^64 as x*w + q*(2^64 - p) (four
+#   cross-product mads into one pair, a 64-bit shift, two mads) = 7; the
+#   lazy sum (the value's two 32-bit halves into two 64-bit sums, one mad
+#   each) = 2; total 14.
 #   32-bit residues: mul_hi, mul_lo, mul_lo, sub = 4; 64-bit lazy sum = 2.
 #   FP64 product (Alg. 2, p < 2^50, signed running values): mul, fma, mul,
 #   floor, fma, add = 6, and one correction (compare, subtract, 64-bit
 #   select as two 32-bit selects) = 4; the double sum (add) = 1; total 11.
-ALGO_OPS = {8: 18, 4: 6, "fp64": 11}
+ALGO_OPS = {8: 14, 4: 6, "fp64": 11}
 # Point mode (arbitrary points): a term's contribution takes one lazy Shoup
 # product per factor table (NF - 1 for the monomial, one for the
-# coefficient) plus the lazy sum: NF * 15 + 3 ops (64-bit residues; the
-# product alone is 18 - 3 = 15), NF * 4 + 2 (32-bit residues).
+# coefficient) plus the lazy sum: NF * 12 + 2 ops (64-bit residues; the
+# product alone is 14 - 2 = 12), NF * 4 + 2 (32-bit residues).
 def points_ops(w: int, nf: int) -> int:
-    return nf * 15 + 3 if w == 8 else nf * 4 + 2
+    return nf * 12 + 2 if w == 8 else nf * 4 + 2
 # Algorithmic HBM bytes per run: resident term data read once (coefficient
 # and n-2 16-bit exponents per term) plus the dense output written once.
 
@@ -165,11 +166,11 @@ def interp_main(args):
     # algorithmic work: per group of m terms, 3 m^2 modular multiply-adds
     # (Q, the b_l, and the two Horner evaluations) plus the Fermat inversion
     # of each term (2 log2 p products, each with its quotient computed: 2),
-    # each priced as one lazy Shoup product and sum (18 ops, 64-bit
-    # residues; 6 for 32-bit)
+    # each priced as one lazy Shoup product and sum (ALGO_OPS: 14 ops,
+    # 64-bit residues; 6 for 32-bit)
     bits = int(w.p).bit_length()
     mac = float((3 * sizes.astype(np.float64) ** 2).sum() + 4 * bits * w.s)
-    ops = mac * (18 if poly.elem_bytes == 8 else 6)
+    ops = mac * ALGO_OPS[poly.elem_bytes]
     achieved = ops / solve_s
     ok = int(status.item()) == 0 and bool(np.array_equal(out.cpu().numpy().view(np.uint64), w.coeffs))
     res = {

@@ -136,12 +136,12 @@ constexpr uint32_t policy_kind() {
 
 // Persistent evaluation over the work queue of the members of one kind (one
 // kernel per kind, so that each gets the registers and LDS of its own
-// widest variant rather than those of the 64-bit one).  The 64-bit kernels
-// are held to three waves per SIMD, as the single-polynomial kernel runs:
-// its few spills sit outside the evaluation passes, and three waves
-// measured faster than the two that its unbounded register count allows.
+// widest variant rather than those of the 64-bit one).  The 64-bit integer
+// kernel runs two waves per SIMD: held to three it spilled some 20
+// registers at item boundaries and measured 1-3% slower.
 template <class A>
-__global__ __launch_bounds__(kEvalBlock, sizeof(typename A::T) == 8 ? 3 : 4) void batch_eval_kernel(
+__global__ __launch_bounds__(kEvalBlock, (std::is_same<A, W64>::value ? 2 : (sizeof(typename A::T) == 8 ? 3 : 4)))
+void batch_eval_kernel(
     const BatchDesc *D, const BatchItem *items, uint32_t n_items, uint32_t *counter) {
   __shared__ __align__(16) unsigned char stage[kEvalBlock / 64][sizeof(Stage<A, kBatchP>)];
   const int lane = threadIdx.x & 63;

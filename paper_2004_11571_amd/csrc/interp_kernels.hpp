@@ -298,7 +298,7 @@ __global__ __launch_bounds__(256) void interp_merge_kernel(InterpArgs<A> a, cons
   T *out = out_v + at;
   T *outq = out_q ? out_q + at : nullptr;  // quotients only where the part is merged again
   const uint32_t k = k0 + (threadIdx.x & 63);
-  typename A::Acc acc = A::zero();
+  typename A::Sum acc = A::sum_zero();
   // out_k = sum_i a_i b_{k-i}; the wave's 64 outputs need i in [k0-db, k0+63]
   const uint32_t i_lo = (k0 > db) ? k0 - db : 0;
   const uint32_t i_hi = (k0 + 63 < da) ? k0 + 63 : da;
@@ -313,15 +313,15 @@ __global__ __launch_bounds__(256) void interp_merge_kernel(InterpArgs<A> a, cons
       q[u] = in ? bq[k - (i + u)] : (T)0;
     }
 #pragma unroll
-    for (uint32_t u = 0; u < 4; ++u) A::add(acc, A::mul_lazy(av[i + u], b[u], q[u], a.m));
+    for (uint32_t u = 0; u < 4; ++u) A::sum_add(acc, A::mul_lazy(av[i + u], b[u], q[u], a.m));
   }
   for (; i <= i_hi; ++i) {
     const bool in = k >= i && k - i <= db;
     const T b = in ? bv[k - i] : (T)0, q = in ? bq[k - i] : (T)0;
-    A::add(acc, A::mul_lazy(av[i], b, q, a.m));
+    A::sum_add(acc, A::mul_lazy(av[i], b, q, a.m));
   }
   if (k <= da + db) {
-    const T r = A::reduce(acc, a.m);
+    const T r = A::reduce(A::stage(acc, a.m), a.m);
     out[k] = r;
     if (outq) outq[k] = shoup_quot(r, a.m);
   }
@@ -345,7 +345,7 @@ __global__ __launch_bounds__(256) void interp_bcoef_kernel(InterpArgs<A> a) {
   // lanes of the wave stop at m-1-l: the longest runs first, the others idle
   const uint32_t kend = (l < m) ? m - l : 0;  // k < m - l
   const uint32_t kmax = m - l0;                // longest run in the wave
-  typename A::Acc acc = A::zero();
+  typename A::Sum acc = A::sum_zero();
   // four steps per iteration, their loads issued together
   uint32_t k = 0;
   for (; k + 4 <= kmax; k += 4) {
@@ -353,14 +353,14 @@ __global__ __launch_bounds__(256) void interp_bcoef_kernel(InterpArgs<A> a) {
 #pragma unroll
     for (uint32_t u = 0; u < 4; ++u) qv[u] = (k + u < kend) ? qg[k + u + l + 1] : (T)0;
 #pragma unroll
-    for (uint32_t u = 0; u < 4; ++u) A::add(acc, A::mul_lazy(qv[u], cv[k + u], cq[k + u], a.m));
+    for (uint32_t u = 0; u < 4; ++u) A::sum_add(acc, A::mul_lazy(qv[u], cv[k + u], cq[k + u], a.m));
   }
   for (; k < kmax; ++k) {
     const T q = (k < kend) ? qg[k + l + 1] : (T)0;
-    A::add(acc, A::mul_lazy(q, cv[k], cq[k], a.m));
+    A::sum_add(acc, A::mul_lazy(q, cv[k], cq[k], a.m));
   }
   if (l < m) {
-    a.bval[base + l] = A::reduce(acc, a.m);
+    a.bval[base + l] = A::reduce(A::stage(acc, a.m), a.m);
     a.dval[base + l] = mul_mod(qg[l + 1], (T)((l + 1) % a.m.p), a.m);
   }
 }

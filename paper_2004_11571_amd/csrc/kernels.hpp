@@ -318,10 +318,10 @@ __device__ __forceinline__ void eval_wave(const EvalArgs<A> &a, uint64_t wave, u
     // P evaluations: reduce (sum the running values), then multiply by Gamma
 #pragma unroll 1
     for (int q = 0; q < np; ++q) {
-      typename A::Acc acc = A::zero();
+      typename A::Sum acc = A::sum_zero();
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        A::add(acc, lam[k]);
+        A::sum_add(acc, lam[k]);
         lam[k] = A::mul_lazy(lam[k], g[k], gq[k], a.m);
       }
       st.put(lane, q, A::stage(acc, a.m));

@@ -23,8 +23,11 @@
 // w' = (-r) * p^{-1} mod 2^64 (exact division by multiplication with the
 // inverse of p modulo 2^64; Jebelean 1993).
 //
-// The integer code is plain 32/64-bit C; hipcc selects v_mad_u64_u32 /
-// v_mul_hi_u32 / v_mul_lo_u32 for it.  The paper's FP64 product (Alg. 2,
+// The integer code is plain 32/64-bit C, for which hipcc selects
+// v_mad_u64_u32 / v_mul_hi_u32 / v_mul_lo_u32, except two short
+// arithmetic-only sequences written in assembly (the remainder of the
+// 64-bit product and the per-thread sum of 64-bit values), whose C forms
+// the compiler expands into longer code.  The paper's FP64 product (Alg. 2,
 // p < 2^50) is kept as a second policy so that both can be measured on the
 // same kernel.
 #pragma once
@@ -73,9 +76,31 @@ __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) {
 // ---------------------------------------------------------------------------
 
 // x * w mod p in [0, 2p), for any x < 2^64, w < p, wq = floor(w 2^64 / p).
+// The remainder x w - q p (mod 2^64) is formed as x w + q n with
+// n = 2^64 - p, by multiply-adds only: the four 32x32 cross products that
+// reach the high word are accumulated in one 64-bit pair (only its low 32
+// bits count), shifted up by 32 and used as the addend of x0 w0, then
+// q0 n0 is added; every step wraps modulo 2^64, which is what is wanted.
+// That is 7 instructions, written into x's own registers, against 10 for
+// the two 64-bit low products and the subtraction.  It is written out in
+// assembly (arithmetic only) because the compiler turns the same steps in
+// C back into 64x64-bit multiply expansions.
 __device__ __forceinline__ uint64_t shoup_mul(uint64_t x, uint64_t w, uint64_t wq, uint64_t p) {
-  uint64_t q = mulhi64(x, wq);
-  return x * w - q * p;
+  const uint64_t q = mulhi64(x, wq);
+  const uint64_t n = 0 - p;
+  const uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32), w0 = (uint32_t)w, w1 = (uint32_t)(w >> 32);
+  const uint32_t q0 = (uint32_t)q, q1 = (uint32_t)(q >> 32), n0 = (uint32_t)n, n1 = (uint32_t)(n >> 32);
+  uint64_t h, carry;  // carry: the unused carry-out mask each v_mad_u64_u32 writes
+  asm("v_mad_u64_u32 %1, %2, %4, %5, 0\n\t"    // h  = x1 w0
+      "v_mad_u64_u32 %1, %2, %3, %6, %1\n\t"   // h += x0 w1
+      "v_mad_u64_u32 %1, %2, %7, %8, %1\n\t"   // h += q1 n0
+      "v_mad_u64_u32 %1, %2, %9, %10, %1\n\t"  // h += q0 n1
+      "v_lshlrev_b64 %1, 32, %1\n\t"           // h <<= 32
+      "v_mad_u64_u32 %0, %2, %3, %5, %1\n\t"   // x  = x0 w0 + h
+      "v_mad_u64_u32 %0, %2, %9, %8, %0"         // x += q0 n0
+      : "+v"(x), "=&v"(h), "=&s"(carry)
+      : "v"(x0), "v"(x1), "v"(w0), "v"(w1), "v"(q1), "v"(n0), "v"(q0), "v"(n1));
+  return x;
 }
 
 __device__ __forceinline__ uint64_t canon(uint64_t x, uint64_t p) {  // [0, 2p) -> [0, p)
@@ -196,7 +221,25 @@ struct W64 {
   __device__ static __forceinline__ T reduce(const Acc &a, const M &m) {
     return reduce96(((uint64_t)a.w1 << 32) | a.w0, a.w2, m);
   }
-  __device__ static __forceinline__ Acc stage(const Acc &a, const M &) { return a; }
+  // A thread's sum over its terms: the low and high 32-bit halves of the
+  // values are summed separately in 64 bits (value = lo + hi 2^32), one
+  // multiply-add by 1 each and no carry chain; exact for up to 2^32 values.
+  // It becomes a 96-bit Acc once per row (stage).
+  struct Sum {
+    uint64_t lo, hi;
+  };
+  __device__ static __forceinline__ Sum sum_zero() { return Sum{0, 0}; }
+  __device__ static __forceinline__ void sum_add(Sum &s, T x) {
+    uint64_t carry;
+    asm("v_mad_u64_u32 %0, %2, %3, 1, %0\n\t"
+        "v_mad_u64_u32 %1, %2, %4, 1, %1"
+        : "+v"(s.lo), "+v"(s.hi), "=&s"(carry)
+        : "v"((uint32_t)x), "v"((uint32_t)(x >> 32)));
+  }
+  __device__ static __forceinline__ Acc stage(const Sum &s, const M &) {
+    const uint64_t t = (s.lo >> 32) + (uint32_t)s.hi;
+    return Acc{(uint32_t)s.lo, (uint32_t)t, (uint32_t)(s.hi >> 32) + (uint32_t)(t >> 32)};
+  }
   __device__ static __forceinline__ void add_walk(Acc &a, const Acc &b, const M &) { add(a, b); }
   __device__ static __forceinline__ T mul_lazy(T x, T w, T wq, const M &m) {
     return shoup_mul(x, w, wq, m.p);
@@ -216,6 +259,9 @@ struct W32 {
   __device__ static __forceinline__ void add(Acc &a, T x) { a.v += x; }
   __device__ static __forceinline__ void add(Acc &a, const Acc &b) { a.v += b.v; }
   __device__ static __forceinline__ T reduce(const Acc &a, const M &m) { return reduce64(a.v, m); }
+  using Sum = Acc;  // a thread's sum over its terms
+  __device__ static __forceinline__ Sum sum_zero() { return zero(); }
+  __device__ static __forceinline__ void sum_add(Sum &s, T x) { add(s, x); }
   __device__ static __forceinline__ Acc stage(const Acc &a, const M &) { return a; }
   __device__ static __forceinline__ void add_walk(Acc &a, const Acc &b, const M &) { add(a, b); }
   __device__ static __forceinline__ T mul_lazy(T x, T w, T wq, const M &m) {
@@ -259,7 +305,10 @@ struct W64PM {
   __device__ static __forceinline__ Acc zero() { return W64::zero(); }
   __device__ static __forceinline__ void add(Acc &a, T x) { W64::add(a, x); }
   __device__ static __forceinline__ T reduce(const Acc &a, const M &m) { return W64::reduce(a, m.m); }
-  __device__ static __forceinline__ Acc stage(const Acc &a, const M &) { return a; }
+  using Sum = W64::Sum;
+  __device__ static __forceinline__ Sum sum_zero() { return W64::sum_zero(); }
+  __device__ static __forceinline__ void sum_add(Sum &s, T x) { W64::sum_add(s, x); }
+  __device__ static __forceinline__ Acc stage(const Sum &s, const M &m) { return W64::stage(s, m.m); }
   __device__ static __forceinline__ void add_walk(Acc &a, const Acc &b, const M &) { W64::add(a, b); }
   __device__ static __forceinline__ T mul_lazy(T x, T w, T, const M &m) { return pm63_mul_lazy(x, w, m.c); }
 };
@@ -285,6 +334,9 @@ struct W32PM {
   __device__ static __forceinline__ Acc zero() { return W32::zero(); }
   __device__ static __forceinline__ void add(Acc &a, T x) { W32::add(a, x); }
   __device__ static __forceinline__ T reduce(const Acc &a, const M &m) { return W32::reduce(a, m.m); }
+  using Sum = Acc;
+  __device__ static __forceinline__ Sum sum_zero() { return zero(); }
+  __device__ static __forceinline__ void sum_add(Sum &s, T x) { add(s, x); }
   __device__ static __forceinline__ Acc stage(const Acc &a, const M &) { return a; }
   __device__ static __forceinline__ void add_walk(Acc &a, const Acc &b, const M &) { W32::add(a, b); }
   __device__ static __forceinline__ T mul_lazy(T x, T w, T, const M &m) { return pm31_mul_lazy(x, w, m.c); }
@@ -360,6 +412,9 @@ struct WF64 {
   static constexpr int bytes = 8;
   __device__ static __forceinline__ Acc zero() { return Acc{0.0}; }
   __device__ static __forceinline__ void add(Acc &a, T x) { a.s += x; }
+  using Sum = Acc;  // a thread's sum over its terms (at most 8, exact)
+  __device__ static __forceinline__ Sum sum_zero() { return zero(); }
+  __device__ static __forceinline__ void sum_add(Sum &s, T x) { add(s, x); }
   // both canonical (staged values and walk sums): Alg. 3
   __device__ static __forceinline__ void add_walk(Acc &a, const Acc &b, const M &m) { a.s = alg3_add(a.s, b.s, m.p); }
   __device__ static __forceinline__ PT reduce(const Acc &a, const M &) { return fp_to_u64(a.s); }

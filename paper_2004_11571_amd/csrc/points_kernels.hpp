@@ -231,7 +231,7 @@ __global__ __launch_bounds__(kEvalBlock) void points_eval_kernel(PointsArgs<A> a
       __syncthreads();
       if (i0 + q + 1 < L) prefetch(reinterpret_cast<const uint4 *>(a.tables + (t + a.C) * a.E * 2));
       if (active) {
-        typename A::Acc acc = A::zero();
+        typename A::Sum acc = A::sum_zero();
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           const uint64_t x = ix[k];
@@ -242,7 +242,7 @@ __global__ __launch_bounds__(kEvalBlock) void points_eval_kernel(PointsArgs<A> a
             load_entry(tab, (uint32_t)(x >> (16 * f)) & 0xffff, tv, tq);
             mv = A::mul_lazy(mv, tv, tq, a.m);
           }
-          A::add(acc, A::mul_lazy(mv, av[k], aq[k], a.m));
+          A::sum_add(acc, A::mul_lazy(mv, av[k], aq[k], a.m));
         }
         stage[warp].put(lane, q, A::stage(acc, a.m));
       }
