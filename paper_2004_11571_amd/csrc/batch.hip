@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstring>
 #include <mutex>
 #include <numeric>
@@ -77,10 +78,14 @@ size_t member_scratch_bytes(const peval_poly *h, const Plan &pl, uint32_t C, uin
 }
 
 // Chains for one member so that its work items cost about target_cost
-// term-evaluations each.
+// term-evaluations each, but no more than keep each chain's start (about
+// 2 log2 T + 2 products per term in the monomial kernel) below a quarter of
+// its rows: a lone large member otherwise got so many chains that its
+// chain starts cost as much as its evaluations.
 uint32_t member_chains(const Plan &pl, uint32_t T, double target_cost) {
   double per_chain_full = 64.0 * pl.K * T;  // one wave, one chain over all T
   double c = std::ceil(per_chain_full / std::max(target_cost, 1.0));
+  c = std::min(c, std::floor(T / (4.0 * (2.0 * std::log2(std::max<double>(T, 2.0)) + 2.0))));
   c = std::min<double>(std::max(c, 1.0), std::min<uint32_t>(T, 256));
   return (uint32_t)c;
 }
