@@ -38,8 +38,9 @@ HBM_PEAK = 8.0e12
 # each gfx950 integer instruction of the shortest sequence as one op (a
 # 32x32->64 multiply-add, a 32-bit add/sub with carry, a three-input add or a
 # 64-bit add each count once):
-#   64-bit residues: high half of x*w' (mul_hi + 3 mad_u64_u32 + one 64-bit
-#   add) = 5; the remainder x*w - q*p mod 2^64 as x*w + q*(2^64 - p) (four
+#   64-bit residues: high half of x*w' (mul_hi + 3 mad_u64_u32, the middle
+#   one's carry-out turned into the last one's addend by one select) = 5;
+#   the remainder x*w - q*p mod 2^64 as x*w + q*(2^64 - p) (four
 #   cross-product mads into one pair, a 64-bit shift, two mads) = 7; the
 #   lazy sum (the value's two 32-bit halves into two 64-bit sums, one mad
 #   each) = 2; total 14.

@@ -24,10 +24,10 @@
 // inverse of p modulo 2^64; Jebelean 1993).
 //
 // The integer code is plain 32/64-bit C, for which hipcc selects
-// v_mad_u64_u32 / v_mul_hi_u32 / v_mul_lo_u32, except two short
-// arithmetic-only sequences written in assembly (the remainder of the
-// 64-bit product and the per-thread sum of 64-bit values), whose C forms
-// the compiler expands into longer code.  The paper's FP64 product (Alg. 2,
+// v_mad_u64_u32 / v_mul_hi_u32 / v_mul_lo_u32, except short
+// arithmetic-only sequences written in assembly (the high word and the
+// remainder of the 64-bit product, and the per-thread sum of 64-bit
+// values), whose C forms the compiler expands into longer code.  The paper's FP64 product (Alg. 2,
 // p < 2^50) is kept as a second policy so that both can be measured on the
 // same kernel.
 #pragma once
@@ -58,17 +58,29 @@ __device__ __forceinline__ uint64_t mad_wide(uint32_t a, uint32_t b, uint64_t c)
   return (uint64_t)a * b + c;
 }
 
-// floor(a * b / 2^64) from four 32x32 products: with t = a0 b1 + hi(a0 b0)
-// and u = a1 b0 + lo(t) (neither overflows 64 bits), the high word is
-// a1 b1 + hi(t) + hi(u).  Adding hi(t) inside the last multiply-add and
-// hi(u) after it needs one register copy fewer on gfx950 than summing the
-// two high words first.
+// floor(a * b / 2^64) from four 32x32 products.  With t = a0 b1 + hi(a0 b0)
+// (below 2^64), u = a1 b0 + t is at most 65 bits and floor(u / 2^32) =
+// hi(a1 b0 + lo(t)) + hi(t), so the high word is a1 b1 + floor(u / 2^32).
+// One multiply-add forms u modulo 2^64 and writes its 65th bit to the carry
+// mask it always produces; the addend (hi(u), carry) of the last
+// multiply-add is then one copy and one select.  That is 6 instructions
+// against 8 for adding hi(t) and hi(u) separately, each of which needs an
+// (x, 0) register pair built by a copy.  Assembly (arithmetic only) keeps
+// the carry mask, with the two wait states gfx950 needs between a vector
+// write of a mask and its read, which the compiler does not see.
 __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) {
-  uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
-  uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
-  uint64_t t = mad_wide(a0, b1, __umulhi(a0, b0));
-  uint64_t u = mad_wide(a1, b0, (uint32_t)t);
-  return mad_wide(a1, b1, t >> 32) + (u >> 32);
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  const uint64_t t = mad_wide(a0, b1, __umulhi(a0, b0));
+  uint64_t u, carry, unused, q;
+  uint32_t cbit;
+  asm("v_mad_u64_u32 %0, %1, %3, %4, %5\n\t"   // u = a1 b0 + t (mod 2^64), carry = bit 64
+      "s_nop 1\n\t"
+      "v_cndmask_b32 %2, 0, 1, %1"               // cbit = carry
+      : "=&v"(u), "=&s"(carry), "=v"(cbit) : "v"(a1), "v"(b0), "v"(t));
+  const uint64_t s = ((uint64_t)cbit << 32) | (uint32_t)(u >> 32);  // floor(u / 2^32)
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(q), "=s"(unused) : "v"(a1), "v"(b1), "v"(s));
+  return q;
 }
 
 // ---------------------------------------------------------------------------
@@ -76,30 +88,41 @@ __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) {
 // ---------------------------------------------------------------------------
 
 // x * w mod p in [0, 2p), for any x < 2^64, w < p, wq = floor(w 2^64 / p).
-// The remainder x w - q p (mod 2^64) is formed as x w + q n with
-// n = 2^64 - p, by multiply-adds only: the four 32x32 cross products that
-// reach the high word are accumulated in one 64-bit pair (only its low 32
-// bits count), shifted up by 32 and used as the addend of x0 w0, then
-// q0 n0 is added; every step wraps modulo 2^64, which is what is wanted.
-// That is 7 instructions, written into x's own registers, against 10 for
-// the two 64-bit low products and the subtraction.  It is written out in
-// assembly (arithmetic only) because the compiler turns the same steps in
-// C back into 64x64-bit multiply expansions.
+// q = floor(x wq / 2^64) as in mulhi64, and the remainder x w - q p
+// (mod 2^64) formed as x w + q n with n = 2^64 - p, by multiply-adds only:
+// the four 32x32 cross products that reach the high word are accumulated in
+// one 64-bit pair (only its low 32 bits count), shifted up by 32 and used as
+// the addend of x0 w0, then q0 n0 is added; every step wraps modulo 2^64,
+// which is what is wanted.  The remainder takes 7 instructions, written
+// into x's own registers (10 for the two 64-bit low products and the
+// subtraction); the two cross products that do not involve q fill the two
+// wait states between the carry mask of the quotient's middle multiply-add
+// and its read.  Written in assembly (arithmetic only) because the compiler
+// turns the same steps in C back into 64x64-bit multiply expansions.
 __device__ __forceinline__ uint64_t shoup_mul(uint64_t x, uint64_t w, uint64_t wq, uint64_t p) {
-  const uint64_t q = mulhi64(x, wq);
   const uint64_t n = 0 - p;
   const uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32), w0 = (uint32_t)w, w1 = (uint32_t)(w >> 32);
-  const uint32_t q0 = (uint32_t)q, q1 = (uint32_t)(q >> 32), n0 = (uint32_t)n, n1 = (uint32_t)(n >> 32);
-  uint64_t h, carry;  // carry: the unused carry-out mask each v_mad_u64_u32 writes
-  asm("v_mad_u64_u32 %1, %2, %4, %5, 0\n\t"    // h  = x1 w0
-      "v_mad_u64_u32 %1, %2, %3, %6, %1\n\t"   // h += x0 w1
-      "v_mad_u64_u32 %1, %2, %7, %8, %1\n\t"   // h += q1 n0
-      "v_mad_u64_u32 %1, %2, %9, %10, %1\n\t"  // h += q0 n1
-      "v_lshlrev_b64 %1, 32, %1\n\t"           // h <<= 32
-      "v_mad_u64_u32 %0, %2, %3, %5, %1\n\t"   // x  = x0 w0 + h
-      "v_mad_u64_u32 %0, %2, %9, %8, %0"         // x += q0 n0
-      : "+v"(x), "=&v"(h), "=&s"(carry)
-      : "v"(x0), "v"(x1), "v"(w0), "v"(w1), "v"(q1), "v"(n0), "v"(q0), "v"(n1));
+  const uint32_t y0 = (uint32_t)wq, y1 = (uint32_t)(wq >> 32), n0 = (uint32_t)n, n1 = (uint32_t)(n >> 32);
+  const uint64_t t = mad_wide(x0, y1, __umulhi(x0, y0));
+  uint64_t u, h, carry, unused, q;
+  uint32_t cbit;
+  asm("v_mad_u64_u32 %[u], %[c], %[x1], %[y0], %[t]\n\t"  // u = x1 y0 + t (mod 2^64), c = bit 64
+      "v_mad_u64_u32 %[h], %[z], %[x1], %[w0], 0\n\t"     // h = x1 w0
+      "v_mad_u64_u32 %[h], %[z], %[x0], %[w1], %[h]\n\t"  // h += x0 w1
+      "v_cndmask_b32 %[cb], 0, 1, %[c]"                     // cbit = c
+      : [u] "=&v"(u), [h] "=&v"(h), [c] "=&s"(carry), [cb] "=v"(cbit), [z] "=&s"(unused)
+      : [x1] "v"(x1), [y0] "v"(y0), [t] "v"(t), [w0] "v"(w0), [x0] "v"(x0), [w1] "v"(w1));
+  const uint64_t s = ((uint64_t)cbit << 32) | (uint32_t)(u >> 32);  // floor((x1 y0 + t) / 2^32)
+  asm("v_mad_u64_u32 %[q], %[z], %[x1], %[y1], %[s]"                // q = x1 y1 + s
+      : [q] "=v"(q), [z] "=s"(unused) : [x1] "v"(x1), [y1] "v"(y1), [s] "v"(s));
+  const uint32_t q0 = (uint32_t)q, q1 = (uint32_t)(q >> 32);
+  asm("v_mad_u64_u32 %[h], %[z], %[q1], %[n0], %[h]\n\t"  // h += q1 n0
+      "v_mad_u64_u32 %[h], %[z], %[q0], %[n1], %[h]\n\t"  // h += q0 n1
+      "v_lshlrev_b64 %[h], 32, %[h]\n\t"                  // h <<= 32
+      "v_mad_u64_u32 %[x], %[z], %[x0], %[w0], %[h]\n\t"  // x = x0 w0 + h
+      "v_mad_u64_u32 %[x], %[z], %[q0], %[n0], %[x]"        // x += q0 n0
+      : [x] "+v"(x), [h] "+v"(h), [z] "=&s"(unused)
+      : [q1] "v"(q1), [n0] "v"(n0), [q0] "v"(q0), [n1] "v"(n1), [x0] "v"(x0), [w0] "v"(w0));
   return x;
 }
 

@@ -160,8 +160,13 @@ __global__ void points_prep_kernel(const typename A::T *coeff, const uint16_t *e
 
 
 
+// Three waves per SIMD where the registers allow it without more than a
+// couple of spills (every variant but K = 16 with three or four factor
+// tables): the table gathers from LDS need the latency hiding, and the
+// K = 16, NF = 2 variant would otherwise take a few registers more than
+// three waves allow (two waves: 15% slower on 1e6 terms x 1024 points).
 template <class A, int K, int NF>
-__global__ __launch_bounds__(kEvalBlock) void points_eval_kernel(PointsArgs<A> a) {
+__global__ __launch_bounds__(kEvalBlock, ((K == 16 && NF > 2) ? 2 : 3)) void points_eval_kernel(PointsArgs<A> a) {
   using T = typename A::T;
   constexpr int P = kPointsP;
   extern __shared__ __align__(16) unsigned char smem[];
