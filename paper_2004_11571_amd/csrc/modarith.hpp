@@ -383,7 +383,8 @@ struct ModF64 {
 // error by one), so g = x y - c p is exact and lies in (-p, 2p), and one
 // conditional subtraction brings it into (-p, p), which is again a valid x.
 // Running values kept in (-p, p) thus save the second correction of every
-// product; they are made canonical once per coefficient sum (fp_reduce).
+// product; sums of them are folded (fp_fold) and made canonical only when a
+// partial coefficient leaves the kernel.
 __device__ __forceinline__ double alg2_mul_signed(double x, double y, double p, double u) {
 #pragma clang fp contract(off)
   double h = x * y;
@@ -395,22 +396,17 @@ __device__ __forceinline__ double alg2_mul_signed(double x, double y, double p, 
   return (g >= p) ? g - p : g;
 }
 
-// Alg. 3: x, y in [0, p).
-__device__ __forceinline__ double alg3_add(double x, double y, double p) {
+// An exact integer s with |s| < 2^53 folded to s - rint(s / p) p: congruent
+// to s and within p/2 + 2^-30 p of zero (for p >= 2^31 the quotient
+// estimate from 1/p is off by less than 2^-30), so |result| < p; exact,
+// since the result is an integer below 2^53.  Rounding the quotient to
+// nearest instead of down (as Alg. 2 does) leaves no correction step.  The
+// sums of the FP64 policy (a thread's terms, the walks between threads) use
+// it in place of Alg. 3's conditional subtraction, and stay signed.
+__device__ __forceinline__ double fp_fold(double s, double p, double u) {
 #pragma clang fp contract(off)
-  double s = x + y;
-  return (s >= p) ? s - p : s;
-}
-
-// An exact integer s with |s| < 2^53 reduced into [0, p) (quotient from
-// 1/p, remainder by one FMA, then the same two corrections as Alg. 2).
-__device__ __forceinline__ double fp_reduce(double s, double p, double u) {
-#pragma clang fp contract(off)
-  double c = __builtin_floor(s * u);
-  double r = __builtin_fma(-c, p, s);
-  r = (r >= p) ? r - p : r;
-  r = (r < 0.0) ? r + p : r;
-  return r;
+  const double c = __builtin_rint(s * u);
+  return __builtin_fma(-c, p, s);
 }
 
 // Exact integer in [0, 2^53) held in a double -> uint64.
@@ -422,9 +418,9 @@ __device__ __forceinline__ uint64_t fp_to_u64(double v) {
 }
 
 // Running values in (-p, p) as doubles (alg2_mul_signed); a thread sums at
-// most 8 of them (|sum| < 2^53, exact) before reducing to [0, p), and
-// partial sums travel as canonical uint64 residues (shared with the 64-bit
-// integer path).
+// most 8 of them (|sum| < 2^53, exact) and folds the sum into (-p, p); the
+// walks add two folded values (|sum| < 2p) and fold again; partial sums
+// leave as canonical uint64 residues (shared with the 64-bit integer path).
 struct WF64 {
   using T = double;
   using PT = uint64_t;
@@ -438,10 +434,14 @@ struct WF64 {
   using Sum = Acc;  // a thread's sum over its terms (at most 8, exact)
   __device__ static __forceinline__ Sum sum_zero() { return zero(); }
   __device__ static __forceinline__ void sum_add(Sum &s, T x) { add(s, x); }
-  // both canonical (staged values and walk sums): Alg. 3
-  __device__ static __forceinline__ void add_walk(Acc &a, const Acc &b, const M &m) { a.s = alg3_add(a.s, b.s, m.p); }
-  __device__ static __forceinline__ PT reduce(const Acc &a, const M &) { return fp_to_u64(a.s); }
-  __device__ static __forceinline__ Acc stage(const Acc &a, const M &m) { return Acc{fp_reduce(a.s, m.p, m.u)}; }
+  // staged values and walk sums: folded, in (-p, p)
+  __device__ static __forceinline__ void add_walk(Acc &a, const Acc &b, const M &m) {
+    a.s = fp_fold(a.s + b.s, m.p, m.u);
+  }
+  __device__ static __forceinline__ PT reduce(const Acc &a, const M &m) {
+    return fp_to_u64(a.s < 0.0 ? a.s + m.p : a.s);
+  }
+  __device__ static __forceinline__ Acc stage(const Acc &a, const M &m) { return Acc{fp_fold(a.s, m.p, m.u)}; }
   __device__ static __forceinline__ T mul_lazy(T x, T w, T, const M &m) { return alg2_mul_signed(x, w, m.p, m.u); }
 };
 

@@ -6,8 +6,9 @@ lies in (-p, p), the right one y (a power of a monomial value) in [0, p),
 and a single correction (g >= p gives g - p) is applied.  The claim is that
 g = x y - c p is exact and lies in (-p, 2p), so the corrected value is
 congruent to x y and lies in (-p, p) again; and that a sum of at most 8
-such values (|s| < 2^53) is brought into [0, p) by the quotient-and-FMA step
-with both corrections.
+such values (|s| < 2^53) is folded by s - rint(s u) p into (-p, p) with no
+correction, as is the sum of two folded values in the walks between
+threads, and that one conditional addition makes a folded value canonical.
 
 Each IEEE operation is modelled with Python floats (round to nearest, ties
 to even, as the device runs) and each FMA as the exact rational result
@@ -38,10 +39,12 @@ def alg2_signed(x: float, y: float, p: float, u: float):
     return g, c, (g - p if g >= p else g)
 
 
-def reduce_sum(s: float, p: float, u: float) -> float:
-    c = float(math.floor(s * u))
-    r = fma(-c, p, s)
-    r = r - p if r >= p else r
+def fold(s: float, p: float, u: float) -> float:
+    c = float(round(s * u))  # Python's round: to nearest, ties to even, as v_rndne_f64
+    return fma(-c, p, s)
+
+
+def canonical(r: float, p: float) -> float:
     return r + p if r < 0.0 else r
 
 
@@ -94,7 +97,7 @@ def test_chain_of_signed_products(p):
 
 
 @pytest.mark.parametrize("p", MODULI)
-def test_sum_of_eight_reduced(p):
+def test_sum_of_eight_folded(p):
     rng = random.Random(p + 2)
     pf, u = float(p), 1.0 / float(p)
     cases = [[-(p - 1)] * 8, [p - 1] * 8, [0] * 8, [-(p - 1), p - 1] * 4, [p - 1] * 7 + [-1]]
@@ -104,8 +107,27 @@ def test_sum_of_eight_reduced(p):
         for v in vals:
             s += float(v)
         assert s == sum(vals)                             # the thread's sum is exact
-        r = reduce_sum(s, pf, u)
-        assert 0 <= r < p and r == sum(vals) % p, vals
+        r = fold(s, pf, u)
+        assert r == int(r) and -p < r < p and (int(r) - sum(vals)) % p == 0, vals
+        assert abs(r) <= p / 2 + p * 2.0**-30              # rounded quotient: within p/2 of zero
+        c = canonical(r, pf)
+        assert 0 <= c < p and c == sum(vals) % p
+
+
+@pytest.mark.parametrize("p", MODULI)
+def test_walk_of_folded_values(p):
+    """The walks between threads add two folded values and fold again: a
+    long walk stays in (-p, p) and congruent to the exact sum."""
+    rng = random.Random(p + 3)
+    pf, u = float(p), 1.0 / float(p)
+    for _ in range(40):
+        acc, want = 0.0, 0
+        for _ in range(200):
+            v = fold(float(rng.randrange(-(8 * (p - 1)), 8 * p)), pf, u)
+            want += int(v)
+            acc = fold(acc + v, pf, u)
+            assert -p < acc < p and (int(acc) - want) % p == 0
+        assert canonical(acc, pf) == want % p
 
 
 def test_correction_fires():
