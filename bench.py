@@ -45,10 +45,10 @@ HBM_PEAK = 8.0e12
 #   lazy sum (the value's two 32-bit halves into two 64-bit sums, one mad
 #   each) = 2; total 14.
 #   32-bit residues: mul_hi, mul_lo, mul_lo, sub = 4; 64-bit lazy sum = 2.
-#   FP64 product (Alg. 2, p < 2^50, signed running values): mul, fma, mul,
-#   floor, fma, add = 6, and one correction (compare, subtract, 64-bit
-#   select as two 32-bit selects) = 4; the double sum (add) = 1; total 11.
-ALGO_OPS = {8: 14, 4: 6, "fp64": 11}
+#   FP64 product (Alg. 2, p < 2^50, signed running values, the quotient
+#   rounded to nearest so that no correction follows): mul, fma, mul,
+#   rint, fma, add = 6; the double sum (add) = 1; total 7.
+ALGO_OPS = {8: 14, 4: 6, "fp64": 7}
 # Point mode (arbitrary points): a term's contribution takes one lazy Shoup
 # product per factor table (NF - 1 for the monomial, one for the
 # coefficient) plus the lazy sum: NF * 12 + 2 ops (64-bit residues; the

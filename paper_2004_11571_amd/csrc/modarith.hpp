@@ -375,25 +375,25 @@ struct ModF64 {
   Mod64 m;    // integer constants, for the output conversion
 };
 
-// Alg. 2 (p < 2^50): h + l = x*y exactly (FMA error-free product), c the
-// quotient up to one, g the remainder.  As printed the algorithm takes x, y
-// in [0, p) and applies two corrections (g >= p, g < 0).  Here x may be
-// negative, |x| < p, with 0 <= y < p: the error-free product and the
-// quotient estimate work unchanged (|x y| < p^2 still bounds the estimate's
-// error by one), so g = x y - c p is exact and lies in (-p, 2p), and one
-// conditional subtraction brings it into (-p, p), which is again a valid x.
-// Running values kept in (-p, p) thus save the second correction of every
-// product; sums of them are folded (fp_fold) and made canonical only when a
-// partial coefficient leaves the kernel.
+// Alg. 2 (p < 2^50): h + l = x*y exactly (FMA error-free product), c a
+// quotient estimate from the precomputed 1/p, g = x y - c p the remainder.
+// As printed, the algorithm takes x, y in [0, p), rounds the estimate down
+// and applies two corrections (g >= p, g < 0) to land in [0, p).  Here x
+// may be negative, |x| < p, with 0 <= y < p, and the estimate is rounded to
+// nearest: h u differs from x y / p by at most 3/8 (relative errors of
+// 2^-53 in h, in 1/p and in the product, on a quotient below 2^50), so
+// |x y / p - c| <= 7/8 and g lies in (-7p/8, 7p/8) -- again a valid x, with
+// no correction step.  g is exact: d = h - c p is an integer below 2^53 and
+// d + l = x y - c p.  Running values thus stay signed; sums of them are
+// folded (fp_fold) and made canonical only when a partial coefficient
+// leaves the kernel.
 __device__ __forceinline__ double alg2_mul_signed(double x, double y, double p, double u) {
 #pragma clang fp contract(off)
-  double h = x * y;
-  double l = __builtin_fma(x, y, -h);
-  double b = h * u;
-  double c = __builtin_floor(b);
-  double d = __builtin_fma(-c, p, h);
-  double g = d + l;
-  return (g >= p) ? g - p : g;
+  const double h = x * y;
+  const double l = __builtin_fma(x, y, -h);
+  const double c = __builtin_rint(h * u);
+  const double d = __builtin_fma(-c, p, h);
+  return d + l;
 }
 
 // An exact integer s with |s| < 2^53 folded to s - rint(s / p) p: congruent

@@ -3,9 +3,10 @@ the host with exact arithmetic.
 
 The FP64 policy keeps running values signed: the left operand x of Alg. 2
 lies in (-p, p), the right one y (a power of a monomial value) in [0, p),
-and a single correction (g >= p gives g - p) is applied.  The claim is that
-g = x y - c p is exact and lies in (-p, 2p), so the corrected value is
-congruent to x y and lies in (-p, p) again; and that a sum of at most 8
+and the quotient estimate c is rounded to nearest instead of down.  The
+claim is that g = x y - c p is exact and lies within 7p/8 of zero, so with
+no correction step it is congruent to x y and lies in (-p, p) again; and
+that a sum of at most 8
 such values (|s| < 2^53) is folded by s - rint(s u) p into (-p, p) with no
 correction, as is the sum of two folded values in the walks between
 threads, and that one conditional addition makes a folded value canonical.
@@ -14,7 +15,7 @@ Each IEEE operation is modelled with Python floats (round to nearest, ties
 to even, as the device runs) and each FMA as the exact rational result
 rounded once (int / int true division is correctly rounded).  These are
 properties of the mathematics the kernels rely on, not a copy of a kernel;
-a wrong bound (a too-wide operand range, a missing correction, a p beyond
+a wrong bound (a quotient rounded down with no correction, a p beyond
 2^50) fails here.
 """
 import math
@@ -29,14 +30,15 @@ def fma(a: float, b: float, c: float) -> float:
     return exact.numerator / exact.denominator
 
 
-def alg2_signed(x: float, y: float, p: float, u: float):
+def alg2_signed(x: float, y: float, p: float, u: float, quotient=round):
+    """Returns (g, c): the remainder and the quotient estimate.  round:
+    Python's round on a float, to nearest with ties to even (v_rndne_f64)."""
     h = x * y
     l = fma(x, y, -h)
     b = h * u
-    c = float(math.floor(b))
+    c = float(quotient(b))
     d = fma(-c, p, h)
-    g = d + l
-    return g, c, (g - p if g >= p else g)
+    return d + l, c
 
 
 def fold(s: float, p: float, u: float) -> float:
@@ -49,9 +51,9 @@ def canonical(r: float, p: float) -> float:
 
 
 # The last modulus is a 50-bit odd one whose double reciprocal lies well
-# below 1/p (relative error -1.1e-16): there the quotient estimate can fall
-# short by one and the correction fires.  For p = 2^50 - 27 it never does on
-# random operands, since fl(1/p) is accurate to about 2^-100.
+# below 1/p (relative error -1.1e-16): there a quotient rounded down can
+# fall short by one (for p = 2^50 - 27 it never does on random operands,
+# since fl(1/p) is accurate to about 2^-100).
 P_LOW_RECIP = 1123934916484611
 MODULI = [2**31 + 11, 2**40 - 87, 2**49 + 9, 2**50 - 27, 2**50 - 1, P_LOW_RECIP]
 
@@ -74,10 +76,9 @@ def test_signed_product_exact_and_in_range(p):
     rng = random.Random(p)
     pf, u = float(p), 1.0 / float(p)
     for x, y in _operands(p, rng):
-        g, c, r = alg2_signed(float(x), float(y), pf, u)
-        assert g == x * y - int(c) * p, (x, y)          # remainder exact
-        assert -p < g < 2 * p, (x, y)                     # before the correction
-        assert -p < r < p and (int(r) - x * y) % p == 0, (x, y)  # after it: a valid left operand again
+        g, c = alg2_signed(float(x), float(y), pf, u)
+        assert g == x * y - int(c) * p, (x, y)            # remainder exact
+        assert abs(g) <= 7 * p / 8, (x, y)                # a valid left operand again, no correction
 
 
 @pytest.mark.parametrize("p", MODULI)
@@ -91,7 +92,7 @@ def test_chain_of_signed_products(p):
         gamma = rng.randrange(0, p)
         x, want = float(lam), lam
         for _ in range(200):
-            x = alg2_signed(x, float(gamma), pf, u)[2]
+            x = alg2_signed(x, float(gamma), pf, u)[0]
             want = want * gamma % p
             assert -p < x < p and (int(x) - want) % p == 0
 
@@ -130,14 +131,17 @@ def test_walk_of_folded_values(p):
         assert canonical(acc, pf) == want % p
 
 
-def test_correction_fires():
-    """An operand pair for which g lands in [p, 2p): the one correction is
-    needed, and it brings the value back into (-p, p)."""
+def test_quotient_rounded_down_needs_a_correction():
+    """An operand pair for which a quotient rounded down (as Alg. 2 is
+    printed) falls short and leaves g in [p, 2p): the rounded-to-nearest
+    estimate the kernels use lands within 7p/8 of zero there too."""
     p = P_LOW_RECIP
     x, y = 726220303110107, 618400639462378
-    g, c, r = alg2_signed(float(x), float(y), float(p), 1.0 / float(p))
-    assert g >= p and g == x * y - int(c) * p
-    assert -p < r < p and (int(r) - x * y) % p == 0
+    pf, u = float(p), 1.0 / float(p)
+    g_floor, c = alg2_signed(float(x), float(y), pf, u, quotient=math.floor)
+    assert g_floor >= p and g_floor == x * y - int(c) * p
+    g, c = alg2_signed(float(x), float(y), pf, u)
+    assert abs(g) <= 7 * p / 8 and g == x * y - int(c) * p
 
 
 def test_checks_catch_planted_mistakes():
@@ -150,6 +154,6 @@ def test_checks_catch_planted_mistakes():
     inexact = 0
     for _ in range(500):
         x, y = -(p - 1 - rng.randrange(1 << 20)), p - 1 - rng.randrange(1 << 20)
-        g, c, _ = alg2_signed(float(x), float(y), pf, u)
+        g, c = alg2_signed(float(x), float(y), pf, u)
         inexact += g != x * y - int(c) * p
     assert inexact > 0
