@@ -52,8 +52,11 @@ ALGO_OPS = {8: 14, 4: 6, "fp64": 7}
 # Point mode (arbitrary points): a term's contribution takes one lazy Shoup
 # product per factor table (NF - 1 for the monomial, one for the
 # coefficient) plus the lazy sum: NF * 12 + 2 ops (64-bit residues; the
-# product alone is 14 - 2 = 12), NF * 4 + 2 (32-bit residues).
-def points_ops(w: int, nf: int) -> int:
+# product alone is 14 - 2 = 12), NF * 4 + 2 (32-bit residues), NF * 6 + 1
+# (the FP64 product).
+def points_ops(w: int, nf: int, arith: str = "int") -> int:
+    if arith == "fp64":
+        return nf * 6 + 1
     return nf * 12 + 2 if w == 8 else nf * 4 + 2
 # Algorithmic HBM bytes per run: resident term data read once (coefficient
 # and n-2 16-bit exponents per term) plus the dense output written once.
@@ -606,7 +609,7 @@ def main():
         graph = {"ms_per_step": gel / gsteps * 1e3, "value": te * gsteps / gel, "steps": gsteps}
     arith = poly.arith()
     if points_mode:
-        ops = points_ops(poly.elem_bytes, nf)
+        ops = points_ops(poly.elem_bytes, nf, arith)
         kname = "points_eval_kernel"
     else:
         ops = ALGO_OPS["fp64" if arith == "fp64" else poly.elem_bytes]
@@ -630,12 +633,12 @@ def main():
         # one AVX-512 core = 3.54e9 term-evals/s); other configurations have no
         # published number
         "vs_baseline": (value / (5e9 / 1.411)) if args.workload == "paper_table2" else None,
-        "dtype": "f64" if arith == "fp64" and not points_mode else ("u64" if poly.elem_bytes == 8 else "u32"),
+        "dtype": "f64" if arith == "fp64" else ("u64" if poly.elem_bytes == 8 else "u32"),
         "data": "synthetic",
         "config": {"workload": w.name + ("_random_points" if points_mode else ""), "n": w.n, "s": w.s,
                    "T": w.T, "p": w.p, "G": poly.G,
                    "tuning": "single_launch" if single else {"K": K, "P": 8 if points_mode else P, "C": C},
-                   "arith": "int" if points_mode else arith,
+                   "arith": arith,
                    "points": "uniform random in [1,p)^(n-2)" if points_mode else "powers of one base point"},
         "roofline": roof,
         "kernels_ms_per_step": {k: v[0] / max(prof_steps, 1) for k, v in kern.items()},

@@ -205,11 +205,15 @@ int peval_set_tuning(peval_poly *h, uint32_t K, uint32_t P, uint32_t C);
 /*
  * Modular product of the evaluation kernel.  PEVAL_ARITH_INT: Shoup's
  * precomputed-quotient product on 32-bit limbs, for every p.
- * PEVAL_ARITH_FP64: the paper's FP64-FMA product (Alg. 2, with Alg. 3 for
- * the additions), allowed for 2^31 <= p < 2^50; terms per thread are capped
- * at 8 (exact double sums).  PEVAL_ARITH_AUTO (the default at create):
- * FP64 for 2^31 <= p < 2^50, where it is faster on gfx950, integer
- * otherwise.  Results are identical; only speed differs.
+ * PEVAL_ARITH_FP64: the paper's FP64-FMA product (Alg. 2) on signed running
+ * values with its quotient estimate rounded to nearest (no correction step)
+ * and sums folded the same way, allowed for 2^31 <= p < 2^50; terms per
+ * thread are capped at 8 (exact double sums).  PEVAL_ARITH_AUTO (the
+ * default at create): FP64 for 2^31 <= p < 2^50, where it is faster on
+ * gfx950, integer otherwise.  The choice applies to the power mode, the
+ * point mode and batches created afterwards (peval_batch_create, the
+ * server); the single-launch path of small runs and interpolation use the
+ * integer product.  Results are identical; only speed differs.
  */
 #define PEVAL_ARITH_AUTO 0u
 #define PEVAL_ARITH_INT 1u

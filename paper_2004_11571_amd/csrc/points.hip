@@ -110,6 +110,8 @@ template <>
 const Mod64 &mod_for<W64>(const peval_poly *h) { return h->m64; }
 template <>
 const Mod32 &mod_for<W32>(const peval_poly *h) { return h->m32; }
+template <>
+const ModF64 &mod_for<WF64>(const peval_poly *h) { return h->mf; }
 
 template <class A>
 using PointsFn = void (*)(PointsArgs<A>);
@@ -164,7 +166,9 @@ PointsFn<A> points_kernel_for(uint32_t K, uint32_t NF) {
   PEVAL_PCASES(2)
   PEVAL_PCASES(4)
   PEVAL_PCASES(8)
-  PEVAL_PCASES(16)
+  if constexpr (!std::is_same<A, WF64>::value) {  // FP64: a thread sums at most 8 doubles exactly
+    PEVAL_PCASES(16)
+  }
 #undef PEVAL_PCASES
 #undef PEVAL_PCASE
   return nullptr;
@@ -173,20 +177,27 @@ PointsFn<A> points_kernel_for(uint32_t K, uint32_t NF) {
 constexpr size_t kPointsPartialBudget = (size_t)2 << 30;  // partial sums per launch
 constexpr size_t kPointsTablesBudget = (size_t)256 << 20;  // factor tables per launch
 
-template <class A>
+// A: integer policy of the tables, slot arrays, partial sums and output;
+// E: policy of the evaluation kernel (A itself, or the FP64 product on
+// 64-bit residues, whose tables and coefficients are written as doubles).
+template <class A, class E = A>
 int run_points_impl(peval_poly *h, const uint64_t *points, uint32_t T, void *dev_out, hipStream_t st,
                     uint32_t K, uint32_t C) {
   using T_ = typename A::T;
+  using TE = typename E::T;
+  constexpr bool fp64 = std::is_same<E, WF64>::value;
+  static_assert(sizeof(TE) == sizeof(T_), "the FP64 product runs on 64-bit residues");
   const auto &m = mod_for<A>(h);
   const size_t w = sizeof(T_);
   const uint32_t ntail = h->n - 2;
   const FactorPlan &fp = h->fplan;
   Plan *pl = nullptr;
   PEVAL_TRY(get_plan(h, K, kPointsP, &pl, true));
-  auto eval = points_kernel_for<A>(K, fp.nf);
+  auto eval = points_kernel_for<E>(K, fp.nf);
   if (!eval) return fail(PEVAL_EINVAL, "no point kernel for K=%u with %u factors", K, fp.nf);
 
-  auto it = h->pprep.find(K);
+  const uint32_t prep_key = K | (fp64 ? 0x100u : 0u);  // slot arrays differ by product
+  auto it = h->pprep.find(prep_key);
   if (it == h->pprep.end()) {  // per-slot coefficients, quotients and entry indices
     std::vector<uint32_t> slot_term;
     PEVAL_TRY(deal_slots(h, K, pl->NT, fp, &slot_term));
@@ -205,11 +216,11 @@ int run_points_impl(peval_poly *h, const uint64_t *points, uint32_t T, void *dev
       (void)hipGetLastError();
       return fail(PEVAL_ENOMEM, "point-mode slot arrays of %llu slots", (unsigned long long)total);
     }
-    it = h->pprep.emplace(K, pp).first;
+    it = h->pprep.emplace(prep_key, pp).first;
     ProfScope ps(st, 1);
     points_prep_kernel<A><<<(unsigned)((total + 255) / 256), 256, 0, st>>>(
         (const T_ *)h->d_coeff, h->d_exps, pp.slot_term, h->s, pl->NT, K, fp, (T_ *)pp.pa, (T_ *)pp.paq, pp.pidx,
-        m);
+        m, fp64 ? 1u : 0u);
     HIP_TRY(hipGetLastError());
   }
   const PointsPrep &pp = it->second;
@@ -221,7 +232,7 @@ int run_points_impl(peval_poly *h, const uint64_t *points, uint32_t T, void *dev
   if (tc < T && tc > C) tc = tc / C * C;
   PEVAL_TRY(ensure(h->ptab, (size_t)tc * fp.E * 2 * w, h));
   PEVAL_TRY(ensure(h->partial, (size_t)((tc + C - 1) / C) * C * pl->nslots * w, h));
-  const size_t shmem = (kEvalBlock / 64) * sizeof(Stage<A, kPointsP>) + (size_t)fp.E * 2 * w;
+  const size_t shmem = (kEvalBlock / 64) * sizeof(Stage<E, kPointsP>) + (size_t)fp.E * 2 * w;
 
   for (uint64_t done = 0; done < T; done += tc) {
     const uint32_t Tc = (uint32_t)std::min<uint64_t>(tc, T - done);
@@ -231,25 +242,25 @@ int run_points_impl(peval_poly *h, const uint64_t *points, uint32_t T, void *dev
       const uint64_t total = (uint64_t)Tc * fp.E;
       ProfScope ps(st, 0);
       points_table_kernel<A><<<(unsigned)((total + 255) / 256), 256, 0, st>>>(
-          points + done * ntail, ntail, Tc, fp, (T_ *)h->ptab.ptr, m);
+          points + done * ntail, ntail, Tc, fp, (T_ *)h->ptab.ptr, m, fp64 ? 1u : 0u);
       HIP_TRY(hipGetLastError());
     }
     {
-      PointsArgs<A> a;
-      a.pa = (const T_ *)pp.pa;
-      a.paq = (const T_ *)pp.paq;
+      PointsArgs<E> a;
+      a.pa = (const TE *)pp.pa;
+      a.paq = (const TE *)pp.paq;
       a.pidx = pp.pidx;
-      a.tables = (const T_ *)h->ptab.ptr;
+      a.tables = (const TE *)h->ptab.ptr;
       a.endmask = pl->d_endmask;
       a.slot_base = pl->d_slot_base;
-      a.partial = (T_ *)h->partial.ptr;
+      a.partial = (typename E::PT *)h->partial.ptr;
       a.NT = pl->NT;
       a.NW = pl->NW;
       a.C = Cc;
       a.T = Tc;
       a.Lmax = Lmax;
       a.E = fp.E;
-      a.m = m;
+      a.m = mod_for<E>(h);
       dim3 grid((unsigned)((pl->NW + 3) / 4), Cc);
       ProfScope ps(st, 2);
       eval<<<grid, kEvalBlock, shmem, st>>>(a);
@@ -280,6 +291,7 @@ int run_points_impl(peval_poly *h, const uint64_t *points, uint32_t T, void *dev
 Tuning points_tuning(peval_poly *h, uint32_t T) {
   Tuning t = heuristic_tuning(h, T);
   if (h->tune_K) t.K = h->tune_K;
+  if (h->arith == 1) t.K = std::min<uint32_t>(t.K, 8);  // FP64 product: exact sums of at most 8 doubles
   t.P = kPointsP;
   const uint64_t nw = (padded_threads(h, t.K) + 63) / 64;
   t.C = h->tune_C ? h->tune_C : chains_for_waves(nw, 8192, T);
@@ -298,8 +310,9 @@ int points_locked(peval_poly *h, const uint64_t *points_dev, uint32_t T, void *d
     return fail(PEVAL_EUNSUPPORTED, "point mode: the tail degrees need too many factor tables");
   if (h->have_done) HIP_TRY(hipStreamWaitEvent(st, h->done, 0));
   const Tuning tu = points_tuning(h, T);
-  int rc = (h->w == 4) ? run_points_impl<W32>(h, points_dev, T, dev_out, st, tu.K, tu.C)
-                       : run_points_impl<W64>(h, points_dev, T, dev_out, st, tu.K, tu.C);
+  int rc = (h->w == 4)       ? run_points_impl<W32>(h, points_dev, T, dev_out, st, tu.K, tu.C)
+           : (h->arith == 1) ? run_points_impl<W64, WF64>(h, points_dev, T, dev_out, st, tu.K, tu.C)
+                             : run_points_impl<W64>(h, points_dev, T, dev_out, st, tu.K, tu.C);
   if (rc != PEVAL_OK) return rc;
   HIP_TRY(hipEventRecord(h->done, st));
   h->have_done = true;

@@ -73,6 +73,11 @@ __device__ __forceinline__ void load_entry(const uint64_t *tab, uint32_t off, ui
   v = ((uint64_t)x.y << 32) | x.x;
   q = ((uint64_t)x.w << 32) | x.z;
 }
+// FP64 product: the entry's value as a double (its second half is unused)
+__device__ __forceinline__ void load_entry(const double *tab, uint32_t off, double &v, double &q) {
+  v = *reinterpret_cast<const double *>(reinterpret_cast<const unsigned char *>(tab) + off);
+  q = 0.0;
+}
 template <class T>
 __device__ __forceinline__ T load_value(const T *tab, uint32_t off) {
   return *reinterpret_cast<const T *>(reinterpret_cast<const unsigned char *>(tab) + off);
@@ -93,10 +98,11 @@ struct PointsArgs {
 };
 
 // One table entry for launch-local point t: the product over the factor's
-// digits of x_var^(digit << shift), with its Shoup quotient.
+// digits of x_var^(digit << shift), with its Shoup quotient; or, for the
+// FP64 product (as_double), the value as a double and 0.
 template <class A>
 __global__ void points_table_kernel(const uint64_t *points, uint32_t ntail, uint32_t T, FactorPlan fp,
-                                    typename A::T *tables, typename A::M m) {
+                                    typename A::T *tables, typename A::M m, uint32_t as_double) {
   using T_ = typename A::T;
   const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (uint64_t)T * fp.E) return;
@@ -115,6 +121,13 @@ __global__ void points_table_kernel(const uint64_t *points, uint32_t ntail, uint
       v = mul_mod(v, pow_mod(x, (uint64_t)digit << fp.shift[d], m), m);
     }
   }  // entries past the last factor (padding to an even count) hold 1
+  if constexpr (sizeof(T_) == 8) {
+    if (as_double) {
+      tables[2 * idx] = (T_)__double_as_longlong((double)v);
+      tables[2 * idx + 1] = 0;
+      return;
+    }
+  }
   tables[2 * idx] = v;
   tables[2 * idx + 1] = shoup_quot(v, m);
 }
@@ -124,10 +137,11 @@ __global__ void points_table_kernel(const uint64_t *points, uint32_t ntail, uint
 // thread's own group, in any order: the group's sum does not depend on it),
 // or 0xffffffff for padding, which gets a zero coefficient and in-range
 // indices.
+// as_double: the coefficient as a double and no quotient (FP64 product).
 template <class A>
 __global__ void points_prep_kernel(const typename A::T *coeff, const uint16_t *exps, const uint32_t *slot_term,
                                    uint64_t s, uint64_t NT, uint32_t K, FactorPlan fp, typename A::T *pa,
-                                   typename A::T *paq, uint64_t *pidx, typename A::M m) {
+                                   typename A::T *paq, uint64_t *pidx, typename A::M m, uint32_t as_double) {
   const uint64_t idx = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (uint64_t)K * NT) return;
   const uint32_t term = slot_term[idx];
@@ -137,6 +151,12 @@ __global__ void points_prep_kernel(const typename A::T *coeff, const uint16_t *e
     const uint64_t i = term;
     a = coeff[i];
     aq = shoup_quot(a, m);
+    if constexpr (sizeof(a) == 8) {
+      if (as_double) {
+        a = (typename A::T)__double_as_longlong((double)a);
+        aq = 0;
+      }
+    }
     for (uint32_t d = 0; d < fp.ndig; ++d) {
       const uint32_t e = exps[(uint64_t)fp.var[d] * s + i];
       const uint32_t digit = (e >> fp.shift[d]) & fp.mask[d];

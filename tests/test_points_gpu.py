@@ -179,3 +179,60 @@ def test_points_full_size_sampled(orc):
     rows = [0, 1, 511, 1023]
     want = orc.evaluate_points(w.p, w.exps, w.coeffs, pts[rows], threads=16)
     assert np.array_equal(got[rows], want)
+
+
+# 50-bit odd modulus whose double reciprocal lies well below 1/p (the FP64
+# product's quotient estimate is least accurate there)
+P_LOW_RECIP = 1123934916484611
+
+
+@pytest.mark.parametrize("p", [P_SMALL_W8, W.P50, P_LOW_RECIP])
+@pytest.mark.parametrize("K", [1, 2, 4, 8, 16])
+def test_points_fp64_product(orc, p, K):
+    """2^31 <= p < 2^50 takes the FP64 product by default (K capped at 8);
+    the integer product on the same handle agrees, with runs alternating so
+    that each product's slot arrays are prepared once and kept apart."""
+    rng = np.random.default_rng(p % 1009 + K)
+    poly = W.random_small(rng, p, 6, 3000, 1, dmax=7)
+    poly.exps[:900, :2] = [3, 2]  # one group over several waves
+    poly.exps = np.unique(poly.exps, axis=0)
+    poly.coeffs = rng.integers(0, p, size=poly.exps.shape[0], dtype=np.uint64)
+    exps = np.ascontiguousarray(poly.exps, np.uint32)
+    pts = random_points(rng, p, 37, 4)
+    want = orc.evaluate_points(p, exps, poly.coeffs, pts, threads=8)
+    with PV.Poly(p, exps, poly.coeffs) as h:
+        assert h.arith() == "fp64"
+        h.set_tuning(K, 0, 3)
+        for mode in ("auto", "int", "fp64", "int"):
+            h.set_arith(mode)
+            got = h.run_points(pts)
+            assert np.array_equal(got.astype(np.uint64), want), (mode, K)
+
+
+@pytest.mark.parametrize("tail", [[30], [20] * 4, [300], [65535, 3]])
+def test_points_fp64_factor_shapes(orc, tail):
+    """FP64 product with one to four factor tables and digit-split variables."""
+    p = W.P50
+    rng = np.random.default_rng(len(tail) * 31 + tail[0])
+    s, m = 700, len(tail)
+    exps = np.zeros((s, m + 2), np.uint32)
+    exps[:, :2] = rng.integers(0, 12, size=(s, 2))
+    for v, d in enumerate(tail):
+        exps[:, 2 + v] = rng.integers(0, d + 1, size=s)
+    exps[0, 2:] = tail
+    exps = np.unique(exps, axis=0)
+    coeffs = rng.integers(0, p, size=exps.shape[0], dtype=np.uint64)
+    check_points(orc, p, exps, coeffs, random_points(rng, p, 23, m))
+
+
+def test_points_table2_shape_sampled(orc):
+    """The paper's Table 2 shape (5e5 terms, p = 2^50 - 27) at 1e4 random
+    points with the FP64 product: sampled rows against the oracle."""
+    w = W.paper_table2()
+    pts = W.random_points(w)
+    with PV.Poly(w.p, w.exps, w.coeffs) as h:
+        assert h.arith() == "fp64"
+        got = h.run_points(pts)
+    rows = [0, 1, 4999, w.T - 1]
+    want = orc.evaluate_points(w.p, w.exps, w.coeffs, pts[rows], threads=16)
+    assert np.array_equal(got[rows].astype(np.uint64), want)
