@@ -171,10 +171,14 @@ def interp_main(args):
     # (Q, the b_l, and the two Horner evaluations) plus the Fermat inversion
     # of each term (2 log2 p products, each with its quotient computed: 2),
     # each priced as one lazy Shoup product and sum (ALGO_OPS: 14 ops,
-    # 64-bit residues; 6 for 32-bit)
+    # 64-bit residues; 6 for 32-bit); under the FP64 product the two Horner
+    # evaluations (2 m^2 steps) take its product, an addition and a fold
+    # per step (6 + 1 + 3 ops)
     bits = int(w.p).bit_length()
-    mac = float((3 * sizes.astype(np.float64) ** 2).sum() + 4 * bits * w.s)
-    ops = mac * ALGO_OPS[poly.elem_bytes]
+    m2 = float((sizes.astype(np.float64) ** 2).sum())
+    mac = 3 * m2 + 4 * bits * w.s
+    horner_ops = 10 if poly.arith() == "fp64" else ALGO_OPS[poly.elem_bytes]
+    ops = (m2 + 4 * bits * w.s) * ALGO_OPS[poly.elem_bytes] + 2 * m2 * horner_ops
     achieved = ops / solve_s
     ok = int(status.item()) == 0 and bool(np.array_equal(out.cpu().numpy().view(np.uint64), w.coeffs))
     res = {

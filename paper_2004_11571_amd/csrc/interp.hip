@@ -177,6 +177,8 @@ int interp_impl(peval_poly *h, const BetaArg &beta, const void *images, uint64_t
   a.G = h->G;
   a.ntail = ntail;
   a.m = m;
+  a.fp64 = (sizeof(T_) == 8 && h->arith == 1) ? 1u : 0u;  // the handle's product resolves to FP64
+  a.mf = h->mf;
   {
     ProfScope ps(st, 1);
     interp_prep_kernel<A><<<(unsigned)((h->s + 255) / 256), 256, 0, st>>>(a);

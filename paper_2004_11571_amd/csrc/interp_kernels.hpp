@@ -76,6 +76,11 @@ struct InterpArgs {
   uint64_t s, G;
   uint32_t ntail;
   typename A::M m;
+  // 64-bit residues with 2^31 <= p < 2^50 and the handle's product FP64:
+  // B's and Q''s coefficients are stored as doubles and the solve's Horner
+  // steps use the FP64 product (0 otherwise)
+  uint32_t fp64;
+  ModF64 mf;
 };
 
 template <class A>
@@ -360,8 +365,16 @@ __global__ __launch_bounds__(256) void interp_bcoef_kernel(InterpArgs<A> a) {
     A::sum_add(acc, A::mul_lazy(q, cv[k], cq[k], a.m));
   }
   if (l < m) {
-    a.bval[base + l] = A::reduce(A::stage(acc, a.m), a.m);
-    a.dval[base + l] = mul_mod(qg[l + 1], (T)((l + 1) % a.m.p), a.m);
+    T bl = A::reduce(A::stage(acc, a.m), a.m);
+    T dl = mul_mod(qg[l + 1], (T)((l + 1) % a.m.p), a.m);
+    if constexpr (sizeof(T) == 8) {
+      if (a.fp64) {  // canonical residues below 2^50: exact as doubles
+        bl = (T)__double_as_longlong((double)bl);
+        dl = (T)__double_as_longlong((double)dl);
+      }
+    }
+    a.bval[base + l] = bl;
+    a.dval[base + l] = dl;
   }
 }
 
@@ -383,7 +396,21 @@ __global__ __launch_bounds__(256) void interp_solve_kernel(InterpArgs<A> a) {
   const T v = live ? a.mval[base + j] : (T)0, vq = live ? a.mquot[base + j] : (T)0;
   const T *bv = a.bval + base, *dv = a.dval + base;
   T b = 0, d = 0;
-  if (a.m.p < (T)(~(T)0 / 3)) {
+  if (a.fp64) {  // set for 64-bit residues only
+    // FP64 product (Alg. 2, quotient rounded to nearest): a running value
+    // in (-p, p) times v gives one within 7p/8 of zero, plus a coefficient
+    // in [0, p) below 2p in magnitude, folded back within p/2 of zero
+    // (exact integers throughout); made canonical at the end
+    const double pf = a.mf.p, uf = a.mf.u, vf = (double)v;
+    const double *bvf = reinterpret_cast<const double *>(bv), *dvf = reinterpret_cast<const double *>(dv);
+    double bf = 0.0, df = 0.0;
+    for (uint32_t l = m; l-- > 0;) {
+      bf = fp_fold(alg2_mul_signed(bf, vf, pf, uf) + bvf[l], pf, uf);
+      df = fp_fold(alg2_mul_signed(df, vf, pf, uf) + dvf[l], pf, uf);
+    }
+    b = (T)fp_to_u64(bf < 0.0 ? bf + pf : bf);
+    d = (T)fp_to_u64(df < 0.0 ? df + pf : df);
+  } else if (a.m.p < (T)(~(T)0 / 3)) {
     // 3p fits the word: the running values stay lazy in [0, 3p) (a Shoup
     // product takes any input below 2^64 and returns below 2p)
     for (uint32_t l = m; l-- > 0;) {

@@ -172,3 +172,24 @@ def test_table2_shape_round_trip():
         images = h.run(w.beta, T)
         got = h.interpolate(w.beta, images)
     assert np.array_equal(got, w.coeffs)
+
+
+@pytest.mark.parametrize("p", [(1 << 31) + 11, W.P50])
+def test_fp64_and_integer_solve_agree(orc, p):
+    """2^31 <= p < 2^50: the solve's Horner steps take the FP64 product by
+    default; forcing the integer product on the same handle gives the same
+    coefficients, and both round-trip the evaluation."""
+    rng = np.random.default_rng(p % 991)
+    exps = support(rng, p, 6, 6000, 6, 5)
+    coeffs = rng.integers(0, p, size=exps.shape[0], dtype=np.uint64)
+    beta = rng.integers(1, p, size=4, dtype=np.uint64)
+    T = int(group_sizes(exps).max())
+    with PV.Poly(p, exps, coeffs) as h:
+        assert h.arith() == "fp64"
+        images = h.run(beta, T)
+        got_fp = h.interpolate(beta, images)
+        h.set_arith("int")
+        got_int = h.interpolate(beta, images)
+        h.set_arith("auto")
+        again = h.interpolate(beta, images)
+    assert np.array_equal(got_fp, coeffs) and np.array_equal(got_int, coeffs) and np.array_equal(again, coeffs)
