@@ -44,20 +44,22 @@ HBM_PEAK = 8.0e12
 #   cross-product mads into one pair, a 64-bit shift, two mads) = 7; the
 #   lazy sum (the value's two 32-bit halves into two 64-bit sums, one mad
 #   each) = 2; total 14.
-#   32-bit residues: mul_hi, mul_lo, mul_lo, sub = 4; 64-bit lazy sum = 2.
+#   32-bit residues: mul_hi, and the remainder as the low word of
+#   x*w + q*(2^32 - p) by two mads = 3; the lazy 64-bit sum by one mad = 1;
+#   total 4.
 #   FP64 product (Alg. 2, p < 2^50, signed running values, the quotient
 #   rounded to nearest so that no correction follows): mul, fma, mul,
 #   rint, fma, add = 6; the double sum (add) = 1; total 7.
-ALGO_OPS = {8: 14, 4: 6, "fp64": 7}
+ALGO_OPS = {8: 14, 4: 4, "fp64": 7}
 # Point mode (arbitrary points): a term's contribution takes one lazy Shoup
 # product per factor table (NF - 1 for the monomial, one for the
 # coefficient) plus the lazy sum: NF * 12 + 2 ops (64-bit residues; the
-# product alone is 14 - 2 = 12), NF * 4 + 2 (32-bit residues), NF * 6 + 1
+# product alone is 14 - 2 = 12), NF * 3 + 1 (32-bit residues), NF * 6 + 1
 # (the FP64 product).
 def points_ops(w: int, nf: int, arith: str = "int") -> int:
     if arith == "fp64":
         return nf * 6 + 1
-    return nf * 12 + 2 if w == 8 else nf * 4 + 2
+    return nf * 12 + 2 if w == 8 else nf * 3 + 1
 # Algorithmic HBM bytes per run: resident term data read once (coefficient
 # and n-2 16-bit exponents per term) plus the dense output written once.
 
@@ -171,7 +173,7 @@ def interp_main(args):
     # (Q, the b_l, and the two Horner evaluations) plus the Fermat inversion
     # of each term (2 log2 p products, each with its quotient computed: 2),
     # each priced as one lazy Shoup product and sum (ALGO_OPS: 14 ops,
-    # 64-bit residues; 6 for 32-bit); under the FP64 product the two Horner
+    # 64-bit residues; 4 for 32-bit); under the FP64 product the two Horner
     # evaluations (2 m^2 steps) take its product, an addition and a fold
     # per step (6 + 1 + 3 ops)
     bits = int(w.p).bit_length()

@@ -172,9 +172,19 @@ __device__ __forceinline__ uint64_t pow_mod(uint64_t base, uint64_t e, const Mod
 // 32-bit residues (3 <= p < 2^31)
 // ---------------------------------------------------------------------------
 
+// x * w mod p in [0, 2p) for p < 2^31, any x < 2^32, wq = floor(w 2^32 / p):
+// the remainder x w - q p (mod 2^32) as the low word of x w + q (2^32 - p),
+// two multiply-adds (against two multiplies and a subtraction); each in an
+// assembly statement of its own (arithmetic only), so that the result may
+// take the registers of x and the compiler cannot fold them back into
+// 32-bit multiplies.
 __device__ __forceinline__ uint32_t shoup_mul(uint32_t x, uint32_t w, uint32_t wq, uint32_t p) {
-  uint32_t q = __umulhi(x, wq);
-  return x * w - q * p;
+  const uint32_t q = __umulhi(x, wq);
+  const uint32_t n = 0u - p;
+  uint64_t t, r, carry;  // carry: the unused carry-out mask of each v_mad_u64_u32
+  asm("v_mad_u64_u32 %0, %1, %2, %3, 0" : "=v"(t), "=s"(carry) : "v"(x), "v"(w));
+  asm("v_mad_u64_u32 %0, %1, %2, %3, %4" : "=v"(r), "=s"(carry) : "v"(q), "v"(n), "v"(t));
+  return (uint32_t)r;
 }
 
 __device__ __forceinline__ uint32_t canon(uint32_t x, uint32_t p) {
@@ -284,7 +294,11 @@ struct W32 {
   __device__ static __forceinline__ T reduce(const Acc &a, const M &m) { return reduce64(a.v, m); }
   using Sum = Acc;  // a thread's sum over its terms
   __device__ static __forceinline__ Sum sum_zero() { return zero(); }
-  __device__ static __forceinline__ void sum_add(Sum &s, T x) { add(s, x); }
+  // one multiply-add by 1 into the 64-bit sum (no carry chain)
+  __device__ static __forceinline__ void sum_add(Sum &s, T x) {
+    uint64_t carry;
+    asm("v_mad_u64_u32 %0, %1, %2, 1, %0" : "+v"(s.v), "=s"(carry) : "v"(x));
+  }
   __device__ static __forceinline__ Acc stage(const Acc &a, const M &) { return a; }
   __device__ static __forceinline__ void add_walk(Acc &a, const Acc &b, const M &) { add(a, b); }
   __device__ static __forceinline__ T mul_lazy(T x, T w, T wq, const M &m) {
@@ -359,7 +373,7 @@ struct W32PM {
   __device__ static __forceinline__ T reduce(const Acc &a, const M &m) { return W32::reduce(a, m.m); }
   using Sum = Acc;
   __device__ static __forceinline__ Sum sum_zero() { return zero(); }
-  __device__ static __forceinline__ void sum_add(Sum &s, T x) { add(s, x); }
+  __device__ static __forceinline__ void sum_add(Sum &s, T x) { W32::sum_add(s, x); }
   __device__ static __forceinline__ Acc stage(const Acc &a, const M &) { return a; }
   __device__ static __forceinline__ void add_walk(Acc &a, const Acc &b, const M &) { W32::add(a, b); }
   __device__ static __forceinline__ T mul_lazy(T x, T w, T, const M &m) { return pm31_mul_lazy(x, w, m.c); }
