@@ -332,11 +332,13 @@ __device__ __forceinline__ void eval_wave(const EvalArgs<A> &a, uint64_t wave, u
   }
 }
 
-// Three waves per SIMD: the 64-bit K = 16 variants need a few registers
-// more than that allows (two spilled, outside the evaluation passes), and
-// two waves hide the latency of the stage and walk less well.
+// Three waves per SIMD for P <= 16: the 64-bit K = 16 variants need a few
+// registers more than that allows (two spilled, outside the evaluation
+// passes), and two waves hide the latency of the stage and walk less well.
+// With P = 32 the stages alone hold a block's LDS to one or two blocks per
+// CU, so a register bound would only cost spills.
 template <class A, int K, int P>
-__global__ __launch_bounds__(kEvalBlock, 3) void eval_kernel(EvalArgs<A> a) {
+__global__ __launch_bounds__(kEvalBlock, (P <= 16 ? 3 : 1)) void eval_kernel(EvalArgs<A> a) {
   __shared__ Stage<A, P> stage[kEvalBlock / 64];
   const int lane = threadIdx.x & 63;
   const int warp = threadIdx.x >> 6;
