@@ -175,12 +175,16 @@ def interp_main(args):
     # each priced as one lazy Shoup product and sum (ALGO_OPS: 14 ops,
     # 64-bit residues; 4 for 32-bit); under the FP64 product the two Horner
     # evaluations (2 m^2 steps) take its product, an addition and a fold
-    # per step (6 + 1 + 3 ops)
+    # per step (6 + 1 + 3 ops), and the b_l sums (m^2 / 2) its product, an
+    # addition, a quarter of a fold and the conversion of q (6 + 1 + 1 + 3)
     bits = int(w.p).bit_length()
     m2 = float((sizes.astype(np.float64) ** 2).sum())
     mac = 3 * m2 + 4 * bits * w.s
-    horner_ops = 10 if poly.arith() == "fp64" else ALGO_OPS[poly.elem_bytes]
-    ops = (m2 + 4 * bits * w.s) * ALGO_OPS[poly.elem_bytes] + 2 * m2 * horner_ops
+    fp = poly.arith() == "fp64"
+    horner_ops = 10 if fp else ALGO_OPS[poly.elem_bytes]
+    bsum_ops = 11 if fp else ALGO_OPS[poly.elem_bytes]
+    ops = ((m2 / 2 + 4 * bits * w.s) * ALGO_OPS[poly.elem_bytes] + (m2 / 2) * bsum_ops
+           + 2 * m2 * horner_ops)
     achieved = ops / solve_s
     ok = int(status.item()) == 0 and bool(np.array_equal(out.cpu().numpy().view(np.uint64), w.coeffs))
     res = {

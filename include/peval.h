@@ -211,9 +211,10 @@ int peval_set_tuning(peval_poly *h, uint32_t K, uint32_t P, uint32_t C);
  * thread are capped at 8 (exact double sums).  PEVAL_ARITH_AUTO (the
  * default at create): FP64 for 2^31 <= p < 2^50, where it is faster on
  * gfx950, integer otherwise.  The choice applies to the power mode, the
- * point mode, the Horner steps of interpolation, and batches created
- * afterwards (peval_batch_create, the server); the single-launch path of
- * small runs and interpolation's other kernels use the integer product.
+ * point mode, interpolation's b_l sums and Horner steps, and batches
+ * created afterwards (peval_batch_create, the server); the single-launch
+ * path of small runs and interpolation's product of (z - v) factors use the
+ * integer product.
  * Results are identical; only speed differs.
  */
 #define PEVAL_ARITH_AUTO 0u

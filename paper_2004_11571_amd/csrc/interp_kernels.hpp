@@ -106,8 +106,11 @@ __global__ void interp_prep_kernel(InterpArgs<A> a) {
   }
   const uint64_t k = i - a.grp_off[lo];
   const T c = (T)reduce64((uint64_t)a.images[k * a.G + lo], a.m);
-  a.cval[i] = c;
   a.cquot[i] = shoup_quot(c, a.m);
+  a.cval[i] = c;
+  if constexpr (sizeof(T) == 8) {
+    if (a.fp64) a.cval[i] = (T)__double_as_longlong((double)c);  // read only by the b_l sums
+  }
 }
 
 // Per part of a group (H blocks per group): prod (z - v_i) over the part's
@@ -350,6 +353,34 @@ __global__ __launch_bounds__(256) void interp_bcoef_kernel(InterpArgs<A> a) {
   // lanes of the wave stop at m-1-l: the longest runs first, the others idle
   const uint32_t kend = (l < m) ? m - l : 0;  // k < m - l
   const uint32_t kmax = m - l0;                // longest run in the wave
+  if (a.fp64) {  // set for 64-bit residues only
+    // FP64 product (Alg. 2, quotient rounded to nearest): q (an integer
+    // residue, converted) times c (stored as a double) lands within 7p/8 of
+    // zero; four of them added to a folded sum stay below 4p, folded again
+    const double pf = a.mf.p, uf = a.mf.u;
+    const double *cvf = reinterpret_cast<const double *>(cv);
+    double accf = 0.0;
+    uint32_t k = 0;
+    for (; k + 4 <= kmax; k += 4) {
+      T qv[4];
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u) qv[u] = (k + u < kend) ? qg[k + u + l + 1] : (T)0;
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u) accf += alg2_mul_signed((double)qv[u], cvf[k + u], pf, uf);
+      accf = fp_fold(accf, pf, uf);
+    }
+    for (; k < kmax; ++k) {
+      const T q = (k < kend) ? qg[k + l + 1] : (T)0;
+      accf = fp_fold(accf + alg2_mul_signed((double)q, cvf[k], pf, uf), pf, uf);
+    }
+    if (l < m) {
+      const double bl = accf < 0.0 ? accf + pf : accf;  // canonical, as the solve reads it
+      const T dl = mul_mod(qg[l + 1], (T)((l + 1) % a.m.p), a.m);
+      a.bval[base + l] = (T)__double_as_longlong(bl);
+      a.dval[base + l] = (T)__double_as_longlong((double)dl);
+    }
+    return;
+  }
   typename A::Sum acc = A::sum_zero();
   // four steps per iteration, their loads issued together
   uint32_t k = 0;
@@ -365,16 +396,8 @@ __global__ __launch_bounds__(256) void interp_bcoef_kernel(InterpArgs<A> a) {
     A::sum_add(acc, A::mul_lazy(q, cv[k], cq[k], a.m));
   }
   if (l < m) {
-    T bl = A::reduce(A::stage(acc, a.m), a.m);
-    T dl = mul_mod(qg[l + 1], (T)((l + 1) % a.m.p), a.m);
-    if constexpr (sizeof(T) == 8) {
-      if (a.fp64) {  // canonical residues below 2^50: exact as doubles
-        bl = (T)__double_as_longlong((double)bl);
-        dl = (T)__double_as_longlong((double)dl);
-      }
-    }
-    a.bval[base + l] = bl;
-    a.dval[base + l] = dl;
+    a.bval[base + l] = A::reduce(A::stage(acc, a.m), a.m);
+    a.dval[base + l] = mul_mod(qg[l + 1], (T)((l + 1) % a.m.p), a.m);
   }
 }
 
