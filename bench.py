@@ -6,8 +6,9 @@ combine) for one resident polynomial and one base point, i.e. one
 ``peval_run_async`` of T evaluations.  The polynomial is ingested once before
 timing (its data is resident in HBM when the timed region starts).
 
-Default workload: n = 6 variables, 1e6 distinct terms, x1/x2 degree <= 40,
-x3..x6 total degree <= 20, p = 2^63 - 25, T = 1024 evaluations.
+Default workload: the largest single polynomial, n = 8 variables, 1e7
+distinct terms, x1/x2 degree <= 60, x3..x8 total degree <= 30,
+p = 2^63 - 25, T = 4096 evaluations.
 
 Prints one JSON line.
 """
@@ -67,9 +68,10 @@ def points_ops(w: int, nf: int, arith: str = "int") -> int:
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="n6_s1e6_p63_T1024",
+    ap.add_argument("--steps", type=int, default=0,
+                    help="timed steps (0: enough for about 2 s of timed work, at least 20)")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="n8_s1e7_p63_T4096",
                     choices=["n4_s1e3_p31_T64", "n6_s1e6_p63_T1024", "n6_s1e6_p31_T1024", "n8_s1e7_p63_T4096",
                              "paper_table2", "batch", "serve",
                              "n6_s1e6_p63_T1024_points", "n6_s1e6_p31_T1024_points", "paper_table2_points",
@@ -85,7 +87,9 @@ def parse():
     ap.add_argument("--tuning", default="", help="K,P,C override")
     ap.add_argument("--arith", default="auto", choices=["auto", "int", "fp64", "pm"],
                     help="modular product of the evaluation kernel (fp64: the paper's Alg. 2, p < 2^50)")
-    ap.add_argument("--cpu-rows", type=int, default=192, help="oracle sample: first rows of the images")
+    ap.add_argument("--cpu-rows", type=int, default=0,
+                    help="oracle sample: images checked (half the first rows, half the last; "
+                         "0: about 1.6e8 term-evaluations of oracle work)")
     ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -154,6 +158,7 @@ def interp_main(args):
     status = torch.zeros(1, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream(dev)
     poly.run_async(w.beta, T, img, stream=stream)
+    args.steps = args.steps or 200
     for _ in range(args.warmup):
         poly.interpolate_async(w.beta, T, img, out, status, stream=stream)
     torch.cuda.synchronize()
@@ -244,8 +249,8 @@ def batch_main(args):
     stream = torch.cuda.current_stream()
     b = PV.Batch(polys, Ts, graph=True)
     info = b.info()
-    steps = max(1, args.steps // 100)
-    warm = max(1, args.warmup // 10)
+    steps = args.steps or 20
+    warm = max(1, args.warmup)
     for _ in range(warm):
         b.run(betas, outs, stream=stream)
     torch.cuda.synchronize()
@@ -563,31 +568,44 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # timed steps: no per-kernel events in the way
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
+    if not args.steps:  # about 2 s of timed work, at least 20 steps
+        t_est = time.perf_counter()
         step()
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    # the same steps again with HIP events around every kernel launch, for
-    # the per-kernel times and the roofline
-    prof_steps = min(args.steps, 500)
+        torch.cuda.synchronize()
+        args.steps = int(min(5000, max(20, 2.0 / max(time.perf_counter() - t_est, 1e-6))))
+    # timed steps.  The library records a HIP event pair around every kernel
+    # launch on the launch stream (the per-kernel times and the roofline come
+    # from these same steps), and one torch event per step on the same stream
+    # gives the spread of the step times.
     PV.prof_read()  # drop anything recorded so far
     PV.prof_enable(True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for _ in range(prof_steps):
+    t0 = time.perf_counter()
+    marks[0].record(stream)
+    for i in range(args.steps):
         step()
+        marks[i + 1].record(stream)
     torch.cuda.synchronize()
-    prof_elapsed = time.perf_counter() - t1
+    elapsed = time.perf_counter() - t0
     PV.prof_enable(False)
     kern = PV.prof_read()
+    step_ms = sorted(marks[i].elapsed_time(marks[i + 1]) for i in range(args.steps))
+    spread = {"min": step_ms[0], "median": step_ms[len(step_ms) // 2], "max": step_ms[-1]}
+    # the same steps without the per-kernel events (host cost of the events)
+    ust = min(args.steps, 500)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(ust):
+        step()
+    torch.cuda.synchronize()
+    unprof_ms = (time.perf_counter() - t1) / ust * 1e3
 
     te = w.s * w.T
     value = te * args.steps / elapsed
     eval_ms, eval_n = kern["eval"]
     eval_avg_s = eval_ms / max(eval_n, 1) / 1e3
-    te_per_launch = te * prof_steps / max(eval_n, 1)
+    te_per_launch = te * args.steps / max(eval_n, 1)
     # the boundary's host form: peval_run into a page-locked host buffer
     # (the rate including the device-to-host copy of the images)
     host_out = None
@@ -627,10 +645,17 @@ def main():
     achieved = ops * te_per_launch / eval_avg_s
     sha = kernel_source_sha(extra=("small_kernels.hpp",) if single else ())
     traffic = profile_traffic(sha, args.workload, kname)
+    # algorithmic HBM bytes of one step: the resident term data read once
+    # (coefficient and n-2 16-bit exponents per term) and the images written
+    # once; against the HBM peak they give the step's bandwidth fraction
+    algo_bytes = w.s * (poly.elem_bytes + 2 * (w.n - 2)) + w.T * poly.G * poly.elem_bytes
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
             "unit": "Tops/s (int32 lane-ops)", "frac": achieved / VALU_PEAK_OPS,
             "traffic": traffic, "kernel": kname, "ops_per_term_eval": ops,
-            "eval_launch_ms": eval_avg_s * 1e3, "kernel_source_sha256": sha}
+            "eval_launch_ms": eval_avg_s * 1e3, "kernel_source_sha256": sha,
+            "hbm_algorithmic_bytes_per_step": algo_bytes,
+            "hbm_frac": algo_bytes / (elapsed / args.steps) / HBM_PEAK,
+            "traffic_frac": (traffic / eval_avg_s / HBM_PEAK) if traffic else None}
     if points_mode:
         roof["factor_tables"] = {"nf": nf, "entries_per_point": E}
 
@@ -651,8 +676,9 @@ def main():
                    "arith": arith,
                    "points": "uniform random in [1,p)^(n-2)" if points_mode else "powers of one base point"},
         "roofline": roof,
-        "kernels_ms_per_step": {k: v[0] / max(prof_steps, 1) for k, v in kern.items()},
-        "profiled_ms_per_step": prof_elapsed / prof_steps * 1e3,
+        "kernels_ms_per_step": {k: v[0] / max(args.steps, 1) for k, v in kern.items()},
+        "step_ms_spread": spread,
+        "unprofiled_ms_per_step": unprof_ms,
         "graph_replay": graph,
         "host_output": host_out,
         "create_s": create_s,
@@ -661,17 +687,24 @@ def main():
     if not args.no_cpu:
         from oracle import Oracle
         orc = Oracle()
-        rows = min(args.cpu_rows, w.T)
+        # the sample: half the images from the start of the run, half from its
+        # end (the last rows come from the far end of every chain)
+        rows = min(args.cpu_rows or max(8, int(round(1.6e8 / max(w.s, 1)))), w.T)
+        head = (rows + 1) // 2
+        tail_t0 = w.T - (rows - head) + 1
         threads = min(args.cpu_threads, rows)
         c0 = time.perf_counter()
         if points_mode:
-            ref = orc.evaluate_points(w.p, w.exps, w.coeffs, pts[:rows], threads=threads)
+            ref = np.concatenate([orc.evaluate_points(w.p, w.exps, w.coeffs, pts[:head], threads=threads),
+                                  orc.evaluate_points(w.p, w.exps, w.coeffs, pts[tail_t0 - 1:], threads=threads)])
         else:
-            ref = orc.evaluate(w.p, w.exps, w.coeffs, w.beta, rows, t0=1, threads=threads)
+            ref = np.concatenate([orc.evaluate(w.p, w.exps, w.coeffs, w.beta, head, t0=1, threads=threads),
+                                  orc.evaluate(w.p, w.exps, w.coeffs, w.beta, rows - head, t0=tail_t0,
+                                               threads=threads)])
         csec = time.perf_counter() - c0
         # one thread on a few images: the per-core rate (comparable with the
         # paper's single-core timings)
-        rows1 = min(8, rows)
+        rows1 = min(2, rows)
         c1 = time.perf_counter()
         if points_mode:
             orc.evaluate_points(w.p, w.exps, w.coeffs, pts[:rows1], threads=1)
@@ -680,12 +713,14 @@ def main():
         csec1 = time.perf_counter() - c1
         res["cpu_baseline"] = {"value": w.s * rows / csec, "unit": "term-evals/s", "cores": threads,
                                "kind": "oracle", "seconds": csec,
-                               "sample": f"the first {rows} images of the same polynomial (all {w.s} terms), "
-                                         f"{threads} threads over the points",
+                               "sample": f"images 1..{head} and {tail_t0}..{w.T} of the same polynomial "
+                                         f"(all {w.s} terms), {threads} threads over the points",
                                "single_thread_value": w.s * rows1 / csec1,
                                "single_thread_sample": f"the first {rows1} images, one thread",
                                "cpu_model": cpu_model(), "host_threads": os.cpu_count()}
-        res["parity_sample"] = bool(np.array_equal(got[:rows].astype(np.uint64), ref))
+        sel = np.r_[0:head, tail_t0 - 1:w.T]
+        res["parity_sample"] = bool(np.array_equal(got[sel].astype(np.uint64), ref))
+        res["parity_rows"] = int(rows)
     poly.destroy()
     print(json.dumps(res), flush=True)
 
