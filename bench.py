@@ -73,7 +73,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="n8_s1e7_p63_T4096",
                     choices=["n4_s1e3_p31_T64", "n6_s1e6_p63_T1024", "n6_s1e6_p31_T1024", "n8_s1e7_p63_T4096",
-                             "paper_table2", "batch", "serve",
+                             "paper_table2", "batch", "serve", "modarith",
                              "n6_s1e6_p63_T1024_points", "n6_s1e6_p31_T1024_points", "paper_table2_points",
                              "n6_s1e6_p63_T1024_interp", "paper_table2_interp"])
     ap.add_argument("--rate", type=float, default=2000.0, help="served stream: mean arrivals per second")
@@ -134,6 +134,60 @@ def kernel_source_sha(sources=None, extra=()) -> str:
         text = re.sub(r"//[^\n]*", " ", text)
         h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
+
+# Microbenchmark kinds (include/peval_testing.h): product forms, with the
+# modulus each is measured at and its counted operations per product and
+# addition; then single instructions.
+MB_PRODUCTS = [("shoup64", 0, (1 << 63) - 25, 14), ("shoup32", 1, (1 << 31) - 1, 4),
+               ("fp64_alg2_rounded", 2, (1 << 50) - 27, 7), ("pseudo_mersenne63", 3, (1 << 63) - 25, None),
+               ("pseudo_mersenne31", 4, (1 << 31) - 1, None)]
+MB_INSNS = [("v_add_u32", 16), ("v_mul_lo_u32", 17), ("v_mul_hi_u32", 18), ("v_mad_u64_u32", 19),
+            ("v_fma_f64", 20)]
+MB_BLOCKS = 256 * 8   # eight 256-thread workgroups per CU
+
+
+def bench_product(kind: int, p: int, target_ms: float = 80.0):
+    """(work per second, ms) of one microbenchmark kind, its iteration count
+    scaled so that the timed launch takes about target_ms."""
+    import ctypes
+
+    from paper_2004_11571_amd import peval as PV
+    L = PV.lib()
+    ms, work = ctypes.c_double(), ctypes.c_double()
+    iters = 64
+    for _ in range(4):
+        PV._check(L.peval_bench_product(kind, p, iters, MB_BLOCKS, ctypes.byref(ms), ctypes.byref(work)))
+        if ms.value >= 0.5 * target_ms:
+            break
+        iters = int(min(1 << 24, iters * max(2.0, target_ms / max(ms.value, 1e-3))))
+    return work.value / (ms.value / 1e3), ms.value
+
+
+def modarith_main(args):
+    """Modular products at full occupancy (every thread 16 running values, 8
+    for the FP64 product, each added into the thread's sum and multiplied by
+    its fixed multiplier per iteration) and the issue rates of the
+    instructions they are built from; rates per CU per clock at 2.4 GHz."""
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    per_clk = 256 * 2.4e9
+    products = {}
+    for name, kind, p, ops in MB_PRODUCTS:
+        rate, ms = bench_product(kind, p)
+        products[name] = {"p": p, "products_per_s": rate, "per_cu_per_clock": rate / per_clk,
+                          "lane_cycles_per_product": 64 * per_clk / rate, "ms": ms,
+                          "counted_ops": ops, "frac_of_valu_peak": (rate * ops / VALU_PEAK_OPS) if ops else None}
+    insns = {}
+    for name, kind in MB_INSNS:
+        rate, ms = bench_product(kind, 0)
+        insns[name] = {"lane_ops_per_s": rate, "per_cu_per_clock": rate / per_clk, "ms": ms}
+    best = products["shoup64"]["products_per_s"]
+    res = {"metric": "modular products with additions per second (full occupancy)", "value": best,
+           "unit": "products/s", "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": products["shoup64"]["ms"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+           "config": {"workload": "modarith_microbenchmark", "blocks": MB_BLOCKS, "threads_per_block": 256},
+           "products": products, "instructions": insns}
+    print(json.dumps(res), flush=True)
 
 
 def interp_main(args):
@@ -522,6 +576,8 @@ def main():
         return batch_main(args)
     if args.workload == "serve":
         return serve_main(args)
+    if args.workload == "modarith":
+        return modarith_main(args)
     if args.workload.endswith("_interp"):
         return interp_main(args)
 
@@ -658,6 +714,14 @@ def main():
             "traffic_frac": (traffic / eval_avg_s / HBM_PEAK) if traffic else None}
     if points_mode:
         roof["factor_tables"] = {"nf": nf, "entries_per_point": E}
+    else:
+        # the same product and sum alone at full occupancy (microbenchmark):
+        # the rate of the evaluation loop without its stage, walk and memory
+        mb_kind = {"fp64": 2, "pm": 3 if poly.elem_bytes == 8 else 4}.get(arith, 0 if poly.elem_bytes == 8 else 1)
+        mb_rate, _ = bench_product(mb_kind, w.p, target_ms=40.0)
+        roof["measured_product_ceiling"] = {"kind": [k for k in MB_PRODUCTS if k[1] == mb_kind][0][0],
+                                            "products_per_s": mb_rate,
+                                            "frac": te_per_launch / eval_avg_s / mb_rate}
 
     got = out.cpu().numpy().view(poly.dtype)
     res = {

@@ -355,6 +355,10 @@ int peval_server_configure(peval_server *srv, double slice_work, double pass_wor
                            double sim_rate);
 int peval_server_add_poly(peval_server *srv, uint64_t p, uint32_t n, uint64_t s, const uint32_t *exponents,
                           const uint64_t *coeffs, uint64_t *poly_id);
+/* The registered polynomial's modulus, sizes and output shape (G columns of
+ * elem_bytes, the layout submit writes); device_bytes is its resident size,
+ * 0 while it is not resident. */
+int peval_server_poly_info(peval_server *srv, uint64_t poly_id, peval_info_t *info);
 int peval_server_remove_poly(peval_server *srv, uint64_t poly_id);
 int peval_server_submit(peval_server *srv, uint64_t poly_id, const uint64_t *beta, uint32_t T, void *host_out,
                         uint64_t *req_id);

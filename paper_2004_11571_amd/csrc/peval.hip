@@ -64,7 +64,8 @@ extern "C" const char *peval_last_error(void) { return last_error_slot().c_str()
 // ---------------------------------------------------------------------------
 typedef unsigned __int128 u128;
 
-static Mod64 make_mod64(uint64_t p) {
+namespace peval {
+Mod64 make_mod64(uint64_t p) {
   Mod64 m;
   m.p = p;
   uint64_t inv = p;  // Newton iteration for p^{-1} mod 2^64 (p odd)
@@ -76,7 +77,7 @@ static Mod64 make_mod64(uint64_t p) {
   return m;
 }
 
-static Mod32 make_mod32(uint32_t p) {
+Mod32 make_mod32(uint32_t p) {
   Mod32 m;
   m.p = p;
   uint32_t inv = p;
@@ -87,6 +88,7 @@ static Mod32 make_mod32(uint32_t p) {
   m.oneq = (uint32_t)((1ull << 32) / p);
   return m;
 }
+}  // namespace peval
 
 // Automatic choice of the product (measured on the paper's own workload,
 // 5e5 terms x 1e4 evaluations with a 50-bit prime: the evaluation kernel

@@ -133,6 +133,11 @@ struct peval_poly {
 
 namespace peval {
 
+// Per-modulus constants of the integer products (host, exact 128-bit
+// arithmetic): p^{-1} mod 2^w, 2^w mod p and the Shoup quotients.
+Mod64 make_mod64(uint64_t p);
+Mod32 make_mod32(uint32_t p);
+
 bool valid_K(uint32_t K);
 bool valid_P(uint32_t P);
 uint64_t padded_threads(const peval_poly *h, uint32_t K);

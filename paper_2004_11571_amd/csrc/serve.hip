@@ -724,6 +724,24 @@ extern "C" int peval_server_add_poly(peval_server *S, uint64_t p, uint32_t n, ui
   return PEVAL_OK;
 }
 
+extern "C" int peval_server_poly_info(peval_server *S, uint64_t poly_id, peval_info_t *info) {
+  if (!S || !info) return fail(PEVAL_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  auto it = S->polys.find(poly_id);
+  if (it == S->polys.end()) return fail(PEVAL_EINVAL, "unknown polynomial");
+  const SPoly &sp = it->second;
+  memset(info, 0, sizeof *info);
+  info->p = sp.p;
+  info->n = sp.n;
+  info->elem_bytes = sp.w;
+  info->s = sp.s;
+  info->G = sp.G;
+  info->device_bytes = sp.h ? sp.bytes : 0;
+  for (uint32_t k = 0; k < sp.n && k < 32; ++k)
+    for (uint64_t i = 0; i < sp.s; ++i) info->max_exp[k] = std::max(info->max_exp[k], sp.exps[i * sp.n + k]);
+  return PEVAL_OK;
+}
+
 extern "C" int peval_server_remove_poly(peval_server *S, uint64_t poly_id) {
   if (!S) return fail(PEVAL_EINVAL, "null server");
   std::lock_guard<std::mutex> lk(S->mu);

@@ -80,6 +80,7 @@ def lib() -> ctypes.CDLL:
         "peval_server_configure": ([vp, ctypes.c_double, ctypes.c_double, u32, ctypes.c_double], i32),
         "peval_server_add_poly": ([vp, u64, u32, u64, vp, vp, ctypes.POINTER(u64)], i32),
         "peval_server_remove_poly": ([vp, u64], i32),
+        "peval_server_poly_info": ([vp, u64, ctypes.POINTER(_Info)], i32),
         "peval_server_submit": ([vp, u64, vp, u32, vp, ctypes.POINTER(u64)], i32),
         "peval_server_poll": ([vp, u64, ctypes.POINTER(ctypes.c_int)], i32),
         "peval_server_wait": ([vp, u64, ctypes.c_int64], i32),
@@ -95,6 +96,9 @@ def lib() -> ctypes.CDLL:
         "peval_tune_clear": ([], i32),
         "peval_tune_save": ([ctypes.c_char_p], i32),
         "peval_tune_load": ([ctypes.c_char_p], i32),
+        "peval_test_arith": ([u32, u64, u64, vp, vp, vp, vp], i32),
+        "peval_bench_product": ([u32, u64, u32, u32, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(ctypes.c_double)], i32),
         "peval_strerror": ([i32], ctypes.c_char_p),
         "peval_last_error": ([], ctypes.c_char_p),
     }
@@ -361,9 +365,16 @@ class Server:
         pid = ctypes.c_uint64()
         _check(lib().peval_server_add_poly(self._s, p, n, s, exps.ctypes.data if s else None,
                                            coeffs.ctypes.data if s else None, ctypes.byref(pid)))
-        G = len({(int(a), int(b)) for a, b in exps[:, :2].tolist()}) if s else 0
-        self._meta[pid.value] = (p, n, G)
+        inf = self.poly_info(pid.value)
+        self._meta[pid.value] = (inf["p"], inf["n"], inf["G"])
         return pid.value
+
+    def poly_info(self, pid: int) -> dict:
+        """Modulus, sizes and output columns G of a registered polynomial."""
+        inf = _Info()
+        _check(lib().peval_server_poly_info(self._s, pid, ctypes.byref(inf)))
+        return {"p": inf.p, "n": inf.n, "elem_bytes": inf.elem_bytes, "s": inf.s, "G": inf.G,
+                "device_bytes": inf.device_bytes, "max_exp": list(inf.max_exp)[: inf.n]}
 
     def remove_poly(self, pid: int):
         _check(lib().peval_server_remove_poly(self._s, pid))

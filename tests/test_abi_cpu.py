@@ -210,3 +210,20 @@ def test_interpolate_null_arguments():
     assert L.peval_interpolate(None, None, 1, None, None) == PV.EINVAL
     assert L.peval_interpolate_async(None, None, 1, None, None, None, None) == PV.EINVAL
     assert L.peval_strerror(PV.ESINGULAR) == b"singular system"
+
+
+def test_testing_entries_validate_before_any_device_call():
+    L = PV.lib()
+    top_mul32, top_alg2, top_pm63 = 16, 8, 12
+    assert L.peval_test_arith(top_mul32, (1 << 31) + 11, 0, None, None, None, None) == PV.EINVAL
+    assert L.peval_test_arith(top_alg2, (1 << 50) + 1, 0, None, None, None, None) == PV.EINVAL
+    assert L.peval_test_arith(top_alg2, (1 << 31) - 1, 0, None, None, None, None) == PV.EINVAL
+    assert L.peval_test_arith(top_pm63, (1 << 63) - (1 << 21) + 1, 0, None, None, None, None) == PV.EINVAL
+    assert L.peval_test_arith(99, 101, 0, None, None, None, None) == PV.EINVAL
+    assert L.peval_test_arith(0, 101, 5, None, None, None, None) == PV.EINVAL   # null arrays
+    assert L.peval_test_arith(0, 101, 0, None, None, None, None) == PV.OK       # empty: nothing to do
+    ms, work = ctypes.c_double(), ctypes.c_double()
+    assert L.peval_bench_product(7, 101, 1, 1, ctypes.byref(ms), ctypes.byref(work)) == PV.EINVAL
+    assert L.peval_bench_product(0, 100, 1, 1, ctypes.byref(ms), ctypes.byref(work)) == PV.EINVAL
+    assert L.peval_bench_product(1, (1 << 31) + 11, 1, 1, ctypes.byref(ms), ctypes.byref(work)) == PV.EINVAL
+    assert L.peval_bench_product(16, 0, 0, 1, ctypes.byref(ms), ctypes.byref(work)) == PV.EINVAL

@@ -133,3 +133,23 @@ def test_admission_never_evicts_its_own_polynomial():
                 assert st["uploads"] == 2, st   # b was evicted; a was neither evicted nor uploaded again
         T //= 2
     assert triggered, "no request size needed an eviction"
+
+
+def test_poly_info_reports_the_library_group_count():
+    """The binding takes the output shape from the library (no second
+    definition of the group count): G is the number of distinct (x1, x2)
+    pairs, the width follows p, and nothing is resident before a request."""
+    with PV.Server(1 << 30, simulate=True) as srv:
+        for seed, p, s, n in ((11, W.P63, 3000, 6), (12, W.P31, 700, 4), (13, W.P50, 1, 3)):
+            q = _poly(seed, s, n=n, p=p)
+            pid = srv.add_poly(q.p, q.exps, q.coeffs)
+            inf = srv.poly_info(pid)
+            want_G = len(np.unique(q.exps[:, :2], axis=0))
+            assert inf["G"] == want_G and srv._meta[pid] == (p, n, want_G)
+            assert inf["s"] == s and inf["n"] == n and inf["p"] == p
+            assert inf["elem_bytes"] == (4 if p < 2**31 else 8)
+            assert inf["device_bytes"] == 0
+            assert inf["max_exp"] == [int(x) for x in q.exps.max(axis=0)]
+        with pytest.raises(PV.PevalError) as e:
+            srv.poly_info(10**9)
+        assert e.value.code == PV.EINVAL
