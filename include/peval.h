@@ -131,6 +131,38 @@ int peval_run_async(peval_poly *h, const uint64_t *beta, uint64_t t0, uint32_t T
                     void *dev_out, void *stream);
 
 /*
+ * peval_run_async without any device allocation, for callers that cannot
+ * allocate device memory while they run (code under HIP graph capture, tight
+ * serving loops, hosts that forbid hipMalloc after setup).
+ *
+ * Same arguments, results and ordering as peval_run_async.  The run's
+ * scratch (power tables, chain starts, Gamma and its quotients, partial
+ * sums) is carved from one fixed region of 128 MiB per GPU, held by the
+ * library from its first use on that GPU until the process ends; fewer
+ * chains, or more launches over shorter stretches of T, are used when the
+ * tuning's scratch would not fit (results are the same).  It calls no
+ * hipMalloc, hipFree or other allocating routine, and records no timing
+ * events (peval_prof_enable does not see its kernels).
+ *
+ * Limits and errors:
+ *   - PEVAL_EUNSUPPORTED when even one chain does not fit the region
+ *     (about 3 s residues of elem_bytes plus the tables and one row of
+ *     partial sums: roughly s <= 5e6 terms for p >= 2^31, 1e7 below);
+ *   - PEVAL_EUNSUPPORTED when the handle has no thread layout yet for the
+ *     run's tuning (K, P): a layout is device memory of the handle, made
+ *     once by the first peval_run or peval_run_async with that tuning (the
+ *     single-launch path of small runs needs none).
+ * Sharing: every call on one GPU uses that GPU's one region.  Calls on the
+ * same handle are ordered on the device as with peval_run_async; calls on
+ * different handles whose device work overlaps (other streams, no ordering
+ * by the caller) race on the region and give wrong results.  Nothing in the
+ * region needs clearing between calls (every entry is written before it is
+ * read within a call).
+ */
+int peval_run_async_noalloc(peval_poly *h, const uint64_t *beta, uint64_t t0, uint32_t T,
+                            void *dev_out, void *stream);
+
+/*
  * Images at T arbitrary points instead of the powers of one base point
  * (paper, Section 2.1: the random points of Zippel's method; the cost of
  * evaluating at unrelated points is O(nT(d+s)), Section 2.3):

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <new>
 #include <numeric>
@@ -112,8 +113,12 @@ uint64_t g_prof_n[4] = {0, 0, 0, 0};
 }  // namespace
 
 namespace peval {
+static thread_local int t_prof_off = 0;
+ProfOff::ProfOff() { ++t_prof_off; }
+ProfOff::~ProfOff() { --t_prof_off; }
+
 ProfScope::ProfScope(hipStream_t s, int k) : st(s), kind(k) {
-  if (!g_prof.load()) return;
+  if (!g_prof.load() || t_prof_off) return;
   if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
     a = b = nullptr;
     return;
@@ -273,8 +278,17 @@ static void free_plan(Plan &pl) {
 }
 
 namespace peval {
+static uint32_t plan_key(uint32_t K, uint32_t P, bool subtile_ends) {
+  return (subtile_ends ? 1u << 16 : 0u) | K << 8 | P;
+}
+
+Plan *find_plan(peval_poly *h, uint32_t K, uint32_t P, bool subtile_ends) {
+  auto it = h->plans.find(plan_key(K, P, subtile_ends));
+  return it == h->plans.end() ? nullptr : &it->second;
+}
+
 int get_plan(peval_poly *h, uint32_t K, uint32_t P, Plan **out, bool subtile_ends) {
-  uint32_t key = (subtile_ends ? 1u << 16 : 0u) | K << 8 | P;
+  uint32_t key = plan_key(K, P, subtile_ends);
   auto it = h->plans.find(key);
   if (it != h->plans.end()) {
     *out = &it->second;
@@ -689,39 +703,88 @@ static constexpr size_t kPartialBudget = (size_t)2 << 30;  // bytes of partial s
 // the evaluation kernel (A itself, or the FP64 product on 64-bit residues).
 template <class A, class E = A>
 static int run_impl(peval_poly *h, const BetaArg &beta, uint64_t t0, uint32_t T, void *dev_out,
-                    hipStream_t st, const Tuning &tu) {
+                    hipStream_t st, const Tuning &tu, const FixedScratch *fixed) {
   using T_ = typename A::T;
   const auto &m = mod_of<A>(h);
   constexpr bool fp = std::is_same<E, WF64>::value;
   constexpr bool pm = std::is_same<E, W64PM>::value || std::is_same<E, W32PM>::value;
   const uint32_t ntail = h->n - 2;
-  const uint32_t K = tu.K, P = pm ? 16 : tu.P, C = tu.C;
+  const uint32_t K = tu.K, P = pm ? 16 : tu.P;
+  uint32_t C = tu.C;
   Plan *pl = nullptr;
-  PEVAL_TRY(get_plan(h, K, P, &pl));
-  const size_t w = sizeof(T_);
-
-  // A2: power tables
-  PEVAL_TRY(ensure(h->tabval, (size_t)std::max<uint32_t>(h->tab_total, 1) * w, h));
-  PEVAL_TRY(ensure(h->tabquot, (size_t)std::max<uint32_t>(h->tab_total, 1) * w, h));
-  if (ntail) {
-    ProfScope ps(st, 0);
-    uint32_t blocks = (h->tab_total + 255) / 256;
-    power_table_kernel<A><<<blocks, 256, 0, st>>>(beta, h->tab, ntail, h->tab_total, (T_ *)h->tabval.ptr,
-                                                  (T_ *)h->tabquot.ptr, m);
-    HIP_TRY(hipGetLastError());
+  if (fixed) {
+    pl = find_plan(h, K, P);
+    if (!pl)
+      return fail(PEVAL_EUNSUPPORTED,
+                  "no thread layout for K=%u P=%u on this handle yet (a peval_run_async with this tuning makes it)",
+                  K, P);
+  } else {
+    PEVAL_TRY(get_plan(h, K, P, &pl));
   }
+  const size_t w = sizeof(T_);
+  auto eval = Dispatch<E>::eval(K, P);
+  if (!eval) return fail(PEVAL_EINVAL, "no kernel for K=%u P=%u", K, P);
 
   // T is processed in chunks so that the partial sums stay within budget
-  uint64_t tc = std::max<uint64_t>(1, kPartialBudget / std::max<uint64_t>(1, pl->nslots * w));
+  const size_t tab_bytes = (size_t)std::max<uint32_t>(h->tab_total, 1) * w;
+  const size_t chain_bytes = (size_t)K * pl->NT * w;  // chain starts of one chain; also Gamma, Gamma'
+  const size_t row_bytes = (size_t)pl->nslots * w;    // partial sums of one evaluation
+  uint64_t tc = std::max<uint64_t>(1, kPartialBudget / std::max<size_t>(1, row_bytes));
+  void *tabval, *tabquot, *lam, *gam, *gamq, *partial;
+  uint64_t fit_rows = 0;  // rows of partial sums that fit the caller's region
+  if (fixed) {
+    // everything in the caller's region: tables, Gamma, Gamma', then as many
+    // chains as fit beside at least one row of partial sums, then the rows
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t head = 2 * up(tab_bytes) + 2 * up(chain_bytes);
+    if (head + up(chain_bytes) + up(row_bytes) + 256 > fixed->bytes)
+      return fail(PEVAL_EUNSUPPORTED,
+                  "run needs at least %zu bytes of scratch (%zu available): %llu terms are too many",
+                  head + up(chain_bytes) + up(row_bytes) + 256, fixed->bytes, (unsigned long long)h->s);
+    const uint64_t cfit = (fixed->bytes - head - up(row_bytes) - 256) / std::max<size_t>(chain_bytes, 1);
+    C = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(C, cfit));
+    unsigned char *b = fixed->base;
+    tabval = b;
+    tabquot = b + up(tab_bytes);
+    gam = b + 2 * up(tab_bytes);
+    gamq = b + 2 * up(tab_bytes) + up(chain_bytes);
+    lam = b + head;
+    const size_t lam_end = head + up((size_t)C * chain_bytes);
+    partial = b + lam_end;
+    fit_rows = (fixed->bytes - lam_end) / std::max<size_t>(row_bytes, 1);  // >= 1 by the choice of C
+    tc = std::min<uint64_t>(tc, fit_rows);
+  }
   tc = std::min<uint64_t>(tc, (uint64_t)C * kCombineTile * 32768);  // keeps grid.z of the combine in range
   tc = std::min<uint64_t>(tc, T);
   if (tc < T && tc > C) tc = tc / C * C;
-  PEVAL_TRY(ensure(h->lam, (size_t)C * K * pl->NT * w, h));
-  PEVAL_TRY(ensure(h->gam, (size_t)K * pl->NT * w, h));
-  PEVAL_TRY(ensure(h->gamq, (size_t)K * pl->NT * w, h));
-  PEVAL_TRY(ensure(h->partial, (size_t)((tc + C - 1) / C) * C * pl->nslots * w, h));
-  auto eval = Dispatch<E>::eval(K, P);
-  if (!eval) return fail(PEVAL_EINVAL, "no kernel for K=%u P=%u", K, P);
+  if (fixed) {
+    // a chunk of x evaluations on min(C, x) chains fills whole rounds of rows
+    const uint64_t cc = std::min<uint64_t>(C, tc), rows = (tc + cc - 1) / cc * cc;
+    if (rows > fit_rows) tc = fit_rows >= C ? fit_rows / C * C : fit_rows;
+  }
+  if (!fixed) {
+    PEVAL_TRY(ensure(h->tabval, tab_bytes, h));
+    PEVAL_TRY(ensure(h->tabquot, tab_bytes, h));
+    PEVAL_TRY(ensure(h->lam, (size_t)C * chain_bytes, h));
+    PEVAL_TRY(ensure(h->gam, chain_bytes, h));
+    PEVAL_TRY(ensure(h->gamq, chain_bytes, h));
+    PEVAL_TRY(ensure(h->partial, (size_t)((tc + C - 1) / C) * C * row_bytes, h));
+    tabval = h->tabval.ptr;
+    tabquot = h->tabquot.ptr;
+    lam = h->lam.ptr;
+    gam = h->gam.ptr;
+    gamq = h->gamq.ptr;
+    partial = h->partial.ptr;
+  }
+
+  // A2: power tables
+  if (ntail) {
+    ProfScope ps(st, 0);
+    uint32_t blocks = (h->tab_total + 255) / 256;
+    power_table_kernel<A><<<blocks, 256, 0, st>>>(beta, h->tab, ntail, h->tab_total, (T_ *)tabval,
+                                                  (T_ *)tabquot, m);
+    HIP_TRY(hipGetLastError());
+  }
 
   for (uint64_t done = 0; done < T; done += tc) {
     const uint32_t Tc = (uint32_t)std::min<uint64_t>(tc, T - done);
@@ -730,14 +793,14 @@ static int run_impl(peval_poly *h, const BetaArg &beta, uint64_t t0, uint32_t T,
       MonoArgs<A> ma;
       ma.coeff = (const T_ *)h->d_coeff;
       ma.exps = h->d_exps;
-      ma.tval = (const T_ *)h->tabval.ptr;
-      ma.tquot = (const T_ *)h->tabquot.ptr;
+      ma.tval = (const T_ *)tabval;
+      ma.tquot = (const T_ *)tabquot;
       ma.to = h->tab;
       ma.thr_first = pl->d_thr_first;
       ma.thr_cnt = pl->d_thr_cnt;
-      ma.lam = (T_ *)h->lam.ptr;
-      ma.gam = (T_ *)h->gam.ptr;
-      ma.gamq = (T_ *)h->gamq.ptr;
+      ma.lam = (T_ *)lam;
+      ma.gam = (T_ *)gam;
+      ma.gamq = (T_ *)gamq;
       ma.s = h->s;
       ma.NT = pl->NT;
       ma.t0 = t0 + done;
@@ -755,12 +818,12 @@ static int run_impl(peval_poly *h, const BetaArg &beta, uint64_t t0, uint32_t T,
     {  // A4-A6: evaluations
       using TE = typename E::T;
       EvalArgs<E> ea;
-      ea.lam = (const TE *)h->lam.ptr;
-      ea.gam = (const TE *)h->gam.ptr;
-      ea.gamq = (const TE *)h->gamq.ptr;
+      ea.lam = (const TE *)lam;
+      ea.gam = (const TE *)gam;
+      ea.gamq = (const TE *)gamq;
       ea.endmask = pl->d_endmask;
       ea.slot_base = pl->d_slot_base;
-      ea.partial = (typename E::PT *)h->partial.ptr;
+      ea.partial = (typename E::PT *)partial;
       ea.NT = pl->NT;
       ea.NW = pl->NW;
       ea.nslots = pl->nslots;
@@ -775,7 +838,7 @@ static int run_impl(peval_poly *h, const BetaArg &beta, uint64_t t0, uint32_t T,
     }
     {  // A7: combine
       CombineArgs<A> ca;
-      ca.partial = (const T_ *)h->partial.ptr;
+      ca.partial = (const T_ *)partial;
       ca.slot_off = pl->d_slot_off;
       ca.out = (T_ *)dev_out + done * h->G;
       ca.G = h->G;
@@ -837,19 +900,19 @@ int check_run_args(peval_poly *h, const uint64_t *beta, uint64_t t0, uint32_t T,
 
 // Enqueue one run on stream st (handle lock held by the caller).
 int run_locked(peval_poly *h, const BetaArg &ba, uint64_t t0, uint32_t T, void *dev_out, hipStream_t st,
-               const Tuning &tu) {
+               const Tuning &tu, const FixedScratch *fixed) {
   HIP_TRY(hipSetDevice(h->device));
   if (h->have_done) HIP_TRY(hipStreamWaitEvent(st, h->done, 0));
   int rc;
   if (tu.L)
     rc = (h->w == 4) ? run_small<W32>(h, ba, t0, T, dev_out, st, tu.L) : run_small<W64>(h, ba, t0, T, dev_out, st, tu.L);
   else if (h->w == 4)
-    rc = (h->arith == 2) ? run_impl<W32, W32PM>(h, ba, t0, T, dev_out, st, tu)
-                         : run_impl<W32>(h, ba, t0, T, dev_out, st, tu);
+    rc = (h->arith == 2) ? run_impl<W32, W32PM>(h, ba, t0, T, dev_out, st, tu, fixed)
+                         : run_impl<W32>(h, ba, t0, T, dev_out, st, tu, fixed);
   else
-    rc = (h->arith == 1)   ? run_impl<W64, WF64>(h, ba, t0, T, dev_out, st, tu)
-         : (h->arith == 2) ? run_impl<W64, W64PM>(h, ba, t0, T, dev_out, st, tu)
-                           : run_impl<W64>(h, ba, t0, T, dev_out, st, tu);
+    rc = (h->arith == 1)   ? run_impl<W64, WF64>(h, ba, t0, T, dev_out, st, tu, fixed)
+         : (h->arith == 2) ? run_impl<W64, W64PM>(h, ba, t0, T, dev_out, st, tu, fixed)
+                           : run_impl<W64>(h, ba, t0, T, dev_out, st, tu, fixed);
   if (rc != PEVAL_OK) return rc;
   HIP_TRY(hipEventRecord(h->done, st));
   h->have_done = true;
@@ -866,6 +929,50 @@ extern "C" int peval_run_async(peval_poly *h, const uint64_t *beta, uint64_t t0,
   if (!dev_out) return fail(PEVAL_EINVAL, "null output");
   std::lock_guard<std::mutex> lk(h->mu);
   return run_locked(h, ba, t0, T, dev_out, (hipStream_t)stream, choose_tuning(h, T));
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free entry point
+// ---------------------------------------------------------------------------
+// One fixed scratch region per GPU for peval_run_async_noalloc.  In host code
+// `scratch` only names the symbol; its device address comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+static constexpr size_t kNoAllocScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+std::mutex g_scratch_mu;
+std::map<int, unsigned char *> g_scratch_addr;  // device -> address of its copy of `scratch`
+}  // namespace
+
+// Address of the current device's scratch (device `dev` must be current).
+static int scratch_address(int dev, unsigned char **out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_addr.find(dev);
+  if (it == g_scratch_addr.end()) {
+    void *ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(PEVAL_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    it = g_scratch_addr.emplace(dev, (unsigned char *)ptr).first;
+  }
+  *out = it->second;
+  return PEVAL_OK;
+}
+
+extern "C" int peval_run_async_noalloc(peval_poly *h, const uint64_t *beta, uint64_t t0, uint32_t T,
+                                       void *dev_out, void *stream) {
+  BetaArg ba;
+  PEVAL_TRY(check_run_args(h, beta, t0, T, &ba));
+  if (T == 0 || h->G == 0) return PEVAL_OK;
+  if (!dev_out) return fail(PEVAL_EINVAL, "null output");
+  std::lock_guard<std::mutex> lk(h->mu);
+  HIP_TRY(hipSetDevice(h->device));
+  FixedScratch fx;
+  PEVAL_TRY(scratch_address(h->device, &fx.base));
+  fx.bytes = kNoAllocScratchBytes;
+  ProfOff no_events;
+  return run_locked(h, ba, t0, T, dev_out, (hipStream_t)stream, choose_tuning(h, T), &fx);
 }
 
 extern "C" int peval_run(peval_poly *h, const uint64_t *beta, uint32_t T, void *out) {

@@ -35,6 +35,14 @@ struct Scratch {
   size_t bytes = 0;
 };
 
+// A caller-provided region that a run carves all of its scratch from (power
+// tables, chain starts, Gamma and its quotients, partial sums) instead of
+// the handle's grow-on-demand buffers; nothing is allocated.
+struct FixedScratch {
+  unsigned char *base = nullptr;
+  size_t bytes = 0;
+};
+
 // Host-side layout computation (pure C++; also used by the CPU tests through
 // peval_debug_plan).
 struct HostPlan {
@@ -67,6 +75,12 @@ struct ProfScope {
   hipEvent_t a = nullptr, b = nullptr;
   ProfScope(hipStream_t s, int k);
   ~ProfScope();
+};
+// Timing is off for the calling thread while a ProfOff is alive (the
+// allocation-free entry point creates no events).
+struct ProfOff {
+  ProfOff();
+  ~ProfOff();
 };
 
 // Factor tables of the point mode from the per-variable degree bounds of the
@@ -153,8 +167,13 @@ int ensure(Scratch &sc, size_t bytes, peval_poly *h);
 // subtile_ends: every P-lane sub-tile also ends a segment (layout of the walk
 // that does not merge sub-tiles, used by the point mode)
 int get_plan(peval_poly *h, uint32_t K, uint32_t P, Plan **out, bool subtile_ends = false);
+// The existing layout of (K, P), or null (never builds one).
+Plan *find_plan(peval_poly *h, uint32_t K, uint32_t P, bool subtile_ends = false);
 int check_run_args(peval_poly *h, const uint64_t *beta, uint64_t t0, uint32_t T, BetaArg *ba);
+// fixed: carve the run's scratch from this region (no allocation; the chains
+// C of tu are lowered and T is split into chunks as needed to fit), else the
+// handle's own buffers, grown on demand.
 int run_locked(peval_poly *h, const BetaArg &ba, uint64_t t0, uint32_t T, void *dev_out, hipStream_t st,
-               const Tuning &tu);
+               const Tuning &tu, const FixedScratch *fixed = nullptr);
 
 }  // namespace peval

@@ -62,6 +62,7 @@ def lib() -> ctypes.CDLL:
         "peval_groups": ([vp, vp, vp], i32),
         "peval_run": ([vp, vp, u32, vp], i32),
         "peval_run_async": ([vp, vp, u64, u32, vp, vp], i32),
+        "peval_run_async_noalloc": ([vp, vp, u64, u32, vp, vp], i32),
         "peval_run_points": ([vp, vp, u32, vp], i32),
         "peval_run_points_async": ([vp, vp, u32, vp, vp], i32),
         "peval_points_factors": ([u32, u32, vp, vp, vp], i32),
@@ -196,6 +197,14 @@ class Poly:
         b = self._beta(beta)
         _check(lib().peval_run_async(self.handle, b.ctypes.data if b.size else None, t0, T,
                                      _ptr(dev_out), _stream(stream)))
+
+    def run_async_noalloc(self, beta, T: int, dev_out, t0: int = 1, stream=None):
+        """run_async without device allocation: the scratch is the library's
+        fixed per-GPU region (the handle needs a thread layout for the run's
+        tuning, made by an earlier run_async)."""
+        b = self._beta(beta)
+        _check(lib().peval_run_async_noalloc(self.handle, b.ctypes.data if b.size else None, t0, T,
+                                             _ptr(dev_out), _stream(stream)))
 
     def _points(self, points):
         pts = np.ascontiguousarray(points, dtype=np.uint64)
