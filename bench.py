@@ -78,7 +78,12 @@ def parse():
                              "n6_s1e6_p63_T1024_interp", "paper_table2_interp"])
     ap.add_argument("--rate", type=float, default=2000.0, help="served stream: mean arrivals per second")
     ap.add_argument("--duration", type=float, default=3.0, help="served stream: seconds of arrivals")
-    ap.add_argument("--pool", type=int, default=20, help="served stream: polynomials (last 20%% start cold)")
+    ap.add_argument("--pool", type=int, default=20, help="served stream: resident polynomials")
+    ap.add_argument("--new-fraction", type=float, default=0.1,
+                    help="served stream: share of requests for a polynomial the server has not seen")
+    ap.add_argument("--oracle-requests", type=int, default=24, help="served stream: requests checked by the oracle")
+    ap.add_argument("--oracle-max-work", type=float, default=1e8,
+                    help="served stream: largest s*T of a request in the oracle sample")
     ap.add_argument("--budget-gb", type=float, default=64.0)
     ap.add_argument("--sweep", default="250,500,1000,4000", help="served stream: other arrival rates (paced)")
     ap.add_argument("--tight-gb", type=float, default=2.0, help="served stream: a run under this HBM budget (0: skip)")
@@ -359,9 +364,33 @@ def batch_main(args):
     print(json.dumps(res), flush=True)
 
 
+class PinnedSlots:
+    """Page-locked host memory carved into one result buffer per request
+    (chunks of 1 GiB), so that every served result is still there when the
+    stream has ended."""
+
+    def __init__(self, sizes, chunk=1 << 30):
+        import torch
+        self.chunks, self.where = [], []
+        used = chunk
+        for nb in sizes:
+            nb = (nb + 255) & ~255
+            if used + nb > chunk:
+                self.chunks.append(torch.empty(max(chunk, nb), dtype=torch.uint8, pin_memory=True).numpy())
+                used = 0
+            self.where.append((len(self.chunks) - 1, used))
+            used += nb
+
+    def view(self, i, nbytes):
+        c, off = self.where[i]
+        return self.chunks[c][off:off + nbytes]
+
+
 def serve_main(args):
-    """Poisson stream of evaluation requests against the server; p50/p99
-    latency and throughput, then the same requests one at a time."""
+    """Poisson stream of evaluation requests against the server (about 10%
+    of them for polynomials it has not seen before); p50/p99 latency and
+    throughput; every served result compared with the same request run
+    alone; an oracle-checked sample; then the same requests one at a time."""
     import threading
 
     import torch
@@ -373,43 +402,56 @@ def serve_main(args):
     t_gen = time.time()
     pool = W.serve_pool(args.pool)
     reqs = W.serve_stream(args.rate, args.duration, pool)
+    new_coeffs = W.serve_new_polys(reqs, pool, args.new_fraction)
     gen_s = time.time() - t_gen
-    n_cold = max(1, args.pool // 5)
+    print(f"serve: {len(pool)} pool polynomials, {len(reqs)} requests, {len(new_coeffs)} for new polynomials "
+          f"({gen_s:.1f} s to generate)", file=sys.stderr, flush=True)
+    wb = [4 if w.p < 2**31 else 8 for w in pool]
+    dts = [np.uint32 if b == 4 else np.uint64 for b in wb]
+
     srv = PV.Server(int(args.budget_gb * (1 << 30)))
     pids = [srv.add_poly(w.p, w.exps, w.coeffs) for w in pool]
-    # resident part of the pool: one warm-up request each
-    for j in range(len(pool) - n_cold):
+    G = [srv.poly_info(pid)["G"] for pid in pids]
+    for j in range(len(pool)):  # the pool is resident before the stream: one request each
         rid = srv.submit(pids[j], pool[j].beta, 64)
         srv.wait(rid, 600000)
         srv.release(rid)
-    print(f"serve: pool ready ({len(pool)} polynomials, {len(reqs)} requests)", file=sys.stderr, flush=True)
-    # client-side result buffers: a pool of page-locked buffers reused after
-    # each result has been consumed
-    G = [srv._meta[pid][2] for pid in pids]
-    wb = [4 if w.p < 2**31 else 8 for w in pool]
+
+    def register_new(s):
+        """The stream's new polynomials, registered (host copies) but not
+        resident: each is uploaded when its request is admitted."""
+        t0 = time.perf_counter()
+        m = {i: s.add_poly(pool[reqs[i].poly_index].p, pool[reqs[i].poly_index].exps, c)
+             for i, c in new_coeffs.items()}
+        return m, time.perf_counter() - t0
+
+    def nbytes(r):
+        return r.T * G[r.poly_index] * wb[r.poly_index]
+
+    def as_image(r, buf):
+        return buf[: nbytes(r)].view(dts[r.poly_index]).reshape(r.T, G[r.poly_index])
+
+    # client-side buffers: a pool of page-locked buffers reused once a result
+    # has been consumed, or one buffer per request (the verified run)
     max_bytes = max(2048 * G[j] * wb[j] for j in range(len(pool)))  # T <= 2^11 in every stream
     n_buf = 256
     bufs = [torch.empty(max_bytes, dtype=torch.uint8, pin_memory=True).numpy() for _ in range(n_buf)]
-    free_bufs = list(range(n_buf))
 
-    def out_view(r, b):
-        dt = np.uint32 if wb[r.poly_index] == 4 else np.uint64
-        n = r.T * G[r.poly_index]
-        return bufs[b][: n * wb[r.poly_index]].view(dt).reshape(r.T, G[r.poly_index])
-
-    def stream(paced: bool, reqs=reqs, srv=srv, pids=pids):
-        """Submit every request (at its arrival time if paced, else at once);
-        a collector thread waits for them in order and releases them."""
+    def stream(paced, reqs=reqs, srv=srv, new_pid=None, keep=None):
+        """Submit every request (at its arrival time if paced, else at once)
+        into a free buffer (or its own slot of `keep`); a collector thread
+        takes results in completion order, releases them and drops each new
+        polynomial once its request is done."""
+        new_pid = new_pid or {}
         srv.reset_stats()
         lock = threading.Lock()
         owner = {}
+        free_bufs = list(range(n_buf))
         n_sub = [0]
         finished = threading.Event()
-
         errors = []
 
         def collector():
-            # consume results in completion order (small requests finish first)
             n_done = 0
             try:
                 while True:
@@ -425,10 +467,12 @@ def serve_main(args):
                     srv.wait(rid, 0)  # raises if the request failed
                     srv.release(rid)
                     with lock:
-                        bi = owner.pop(rid, None)
+                        i, bi = owner.pop(rid)
                         if bi is not None:
                             free_bufs.append(bi)
-                            n_done += 1
+                        n_done += 1
+                    if i in new_pid:
+                        srv.remove_poly(new_pid[i])
             except Exception as e:  # surface it to the submitting thread
                 errors.append(e)
 
@@ -438,34 +482,40 @@ def serve_main(args):
         lag = 0.0
         refused = 0
         try:
-            for r in reqs:
+            for i, r in enumerate(reqs):
                 if paced:
                     delay = r.arrival_s - (time.perf_counter() - t0)
                     if delay > 0:
                         time.sleep(delay)
                     else:
                         lag = max(lag, -delay)
-                t_wait = time.perf_counter()
-                while True:
-                    with lock:
-                        bi = free_bufs.pop() if free_bufs else None
-                    if bi is not None:
-                        break
-                    if errors:
-                        raise errors[0]
-                    if time.perf_counter() - t_wait > 120:
-                        raise RuntimeError("no result buffer came back within 120 s")
-                    time.sleep(0.0001)
+                if keep is not None:
+                    bi, out = None, as_image(r, keep.view(i, nbytes(r)))
+                else:
+                    t_wait = time.perf_counter()
+                    while True:
+                        with lock:
+                            bi = free_bufs.pop() if free_bufs else None
+                        if bi is not None:
+                            break
+                        if errors:
+                            raise errors[0]
+                        if time.perf_counter() - t_wait > 120:
+                            raise RuntimeError("no result buffer came back within 120 s")
+                        time.sleep(0.0001)
+                    out = as_image(r, bufs[bi])
+                pid = new_pid.get(i, pids[r.poly_index])
                 with lock:
                     try:
-                        rid = srv.submit(pids[r.poly_index], r.beta, r.T, out=out_view(r, bi))
+                        rid = srv.submit(pid, r.beta, r.T, out=out)
                     except PV.PevalError as e:
                         if e.code != PV.ENOMEM:
                             raise
                         refused += 1          # cannot fit the budget even alone: refused at submit
-                        free_bufs.append(bi)
+                        if bi is not None:
+                            free_bufs.append(bi)
                         continue
-                    owner[rid] = bi
+                    owner[rid] = (i, bi)
                     n_sub[0] += 1
         finally:
             finished.set()
@@ -475,7 +525,6 @@ def serve_main(args):
             raise RuntimeError("results did not all come back within 300 s")
         if errors:
             raise errors[0]
-        print(f"serve: {'paced' if paced else 'saturated'} stream done", file=sys.stderr, flush=True)
         st = srv.stats()
         st["submit_s"] = submit_s
         st["max_submit_lag_s"] = lag
@@ -483,9 +532,15 @@ def serve_main(args):
         return st
 
     te = sum(pool[r.poly_index].s * r.T for r in reqs)
-    st = stream(paced=True)
-    sat = stream(paced=False)
-    # the knee: the same pool at other arrival rates
+    # the verified run: paced, every result kept
+    keep = PinnedSlots([nbytes(r) for r in reqs])
+    new_pid, reg_s = register_new(srv)
+    st = stream(paced=True, new_pid=new_pid, keep=keep)
+    print(f"serve: paced stream done ({st['uploads']} uploads)", file=sys.stderr, flush=True)
+    new_pid, _ = register_new(srv)
+    sat = stream(paced=False, new_pid=new_pid)
+    print("serve: saturated stream done", file=sys.stderr, flush=True)
+    # the knee: the pool alone at other arrival rates
     sweep = []
     for rate in [float(x) for x in args.sweep.split(",") if x]:
         rq = W.serve_stream(rate, args.duration, pool)
@@ -500,8 +555,11 @@ def serve_main(args):
     tight = None
     if args.tight_gb > 0:
         srv2 = PV.Server(int(args.tight_gb * (1 << 30)))
-        pids2 = [srv2.add_poly(w.p, w.exps, w.coeffs) for w in pool]
-        s2 = stream(paced=True, srv=srv2, pids=pids2)
+        pids_save = list(pids)
+        pids[:] = [srv2.add_poly(w.p, w.exps, w.coeffs) for w in pool]
+        new_pid2, _ = register_new(srv2)
+        s2 = stream(paced=True, srv=srv2, new_pid=new_pid2)
+        pids[:] = pids_save
         tight = {"budget_gb": args.tight_gb, "value": s2["term_evals"] / s2["wall_s"], "p50_ms": s2["p50_ms"],
                  "p99_ms": s2["p99_ms"], "max_ms": s2["max_ms"], "uploads": s2["uploads"],
                  "evictions": s2["evictions"], "hbm_peak_gb": s2["hbm_peak"] / 2**30,
@@ -509,24 +567,73 @@ def serve_main(args):
         srv2.destroy()
         print("serve: tight budget done", file=sys.stderr, flush=True)
 
-    # the same requests (a prefix) one at a time: a plain run into device
-    # memory, then the result copied to the same kind of page-locked buffer
+    # the same requests one at a time: a plain run into device memory (a new
+    # polynomial is created first and destroyed after), then the result
+    # copied to the same kind of page-locked buffer
     hs = [PV.Poly(w.p, w.exps, w.coeffs) for w in pool]
     dev = torch.empty(max_bytes, dtype=torch.uint8, device="cuda")
+    dev2 = torch.empty(max_bytes, dtype=torch.uint8, device="cuda")
     pin = torch.from_numpy(bufs[0])
     for j, h in enumerate(hs):
         h.run_async(pool[j].beta, 16, dev)
     torch.cuda.synchronize()
-    k = len(reqs)
-    t1 = time.perf_counter()
-    te_seq = 0
-    for r in reqs[:k]:
-        nb = r.T * G[r.poly_index] * wb[r.poly_index]
+
+    def alone(i, r):
+        w = pool[r.poly_index]
+        if i in new_coeffs:
+            h = PV.Poly(w.p, w.exps, new_coeffs[i])
+            h.run_async(r.beta, r.T, dev)
+            return h
         hs[r.poly_index].run_async(r.beta, r.T, dev)
-        pin[:nb].copy_(dev[:nb])
-        te_seq += pool[r.poly_index].s * r.T
+        return None
+
+    t1 = time.perf_counter()
+    for i, r in enumerate(reqs):
+        h = alone(i, r)
+        pin[: nbytes(r)].copy_(dev[: nbytes(r)])
+        if h is not None:
+            h.destroy()
     torch.cuda.synchronize()
     el_seq = time.perf_counter() - t1
+    print("serve: sequential plain runs done", file=sys.stderr, flush=True)
+
+    # alone vs in the mix: every element of every served result of the
+    # verified run against the same request run alone (compared on the device)
+    v0 = time.perf_counter()
+    mismatch = []
+    for i, r in enumerate(reqs):
+        h = alone(i, r)
+        nb = nbytes(r)
+        dev2[:nb].copy_(torch.from_numpy(keep.view(i, nb)), non_blocking=True)
+        if not torch.equal(dev[:nb], dev2[:nb]):
+            mismatch.append(i)
+        if h is not None:
+            h.destroy()
+    verify_s = time.perf_counter() - v0
+    print(f"serve: alone vs mix checked ({len(mismatch)} differ)", file=sys.stderr, flush=True)
+    # the oracle on a seeded sample of the verified run's requests (both kinds)
+    from oracle import Oracle
+    orc = Oracle()
+    rng = np.random.default_rng(W.workload_seed(5, 300))
+    small = [i for i, r in enumerate(reqs) if pool[r.poly_index].s * r.T <= args.oracle_max_work]
+    small_new = [i for i in small if i in new_coeffs]
+    small_old = [i for i in small if i not in new_coeffs]
+    n_new = min(len(small_new), args.oracle_requests // 4)
+    pick = sorted(list(rng.choice(small_new, n_new, replace=False)) +
+                  list(rng.choice(small_old, min(len(small_old), args.oracle_requests - n_new), replace=False)))
+    o0 = time.perf_counter()
+    ok = 0
+    o_te = 0
+    for i in pick:
+        r = reqs[i]
+        w = pool[r.poly_index]
+        want = orc.evaluate(w.p, w.exps, new_coeffs.get(i, w.coeffs), r.beta, r.T, threads=args.cpu_threads)
+        ok += int(np.array_equal(as_image(r, keep.view(i, nbytes(r))).astype(np.uint64), want))
+        o_te += w.s * r.T
+    oracle_s = time.perf_counter() - o0
+    print(f"serve: oracle sample {ok}/{len(pick)}", file=sys.stderr, flush=True)
+    for h in hs:
+        h.destroy()
     # device -> page-locked host bandwidth, for context (results must cross it)
     big = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
     hb = torch.empty(1 << 30, dtype=torch.uint8, pin_memory=True)
@@ -538,25 +645,32 @@ def serve_main(args):
     torch.cuda.synchronize()
     d2h_gbps = 3 * (1 << 30) / (time.perf_counter() - tb) / 1e9
     del big, hb
-    for h in hs:
-        h.destroy()
+    te_seq = sum(pool[r.poly_index].s * r.T for r in reqs)
     res = {
         "metric": METRIC, "value": st["term_evals"] / st["wall_s"], "unit": "term-evals/s", "n_gpus": 1,
-        "steps": len(reqs), "warmup": len(pool) - n_cold, "ms_per_step": st["mean_ms"],
+        "steps": len(reqs), "warmup": len(pool), "ms_per_step": st["mean_ms"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32+u64", "data": "synthetic",
-        "config": {"workload": f"served_poisson{args.rate:g}_s1e3-5e6_T64-2048_p31p63",
+        "config": {"workload": f"served_poisson{args.rate:g}_s1e3-5e6_T64-2048_p31p63_new{args.new_fraction:g}",
                    "rate_per_s": args.rate, "duration_s": args.duration, "requests": len(reqs),
-                   "pool": len(pool), "cold_polys": n_cold, "budget_gb": args.budget_gb,
+                   "pool": len(pool), "new_poly_requests": len(new_coeffs), "budget_gb": args.budget_gb,
                    "offered_term_evals_per_s": te / args.duration},
         "latency_ms": {"p50": st["p50_ms"], "p99": st["p99_ms"], "max": st["max_ms"], "mean": st["mean_ms"]},
         "server": st,
+        "new_poly_registration_s": reg_s,
+        "alone_vs_mix": {"requests": len(reqs), "identical": len(reqs) - len(mismatch),
+                         "first_mismatches": mismatch[:10], "seconds": verify_s,
+                         "how": "every element of every served result against the same request run alone "
+                                "(peval_run_async; a new polynomial created for it), compared on the device"},
+        "alone_vs_mix_identical": not mismatch,
+        "oracle_sample": {"n": len(pick), "ok": ok, "new_poly_requests": n_new, "term_evals": o_te,
+                          "seconds": oracle_s, "threads": args.cpu_threads,
+                          "selection": f"seeded, among requests with s*T <= {args.oracle_max_work:.0e}"},
         "saturated": {"value": sat["term_evals"] / sat["wall_s"], "p50_ms": sat["p50_ms"], "p99_ms": sat["p99_ms"],
-                      "passes": sat["passes"], "slices": sat["slices"], "host_pass_s": sat["host_pass_s"],
-                      "gpu_pass_s": sat["gpu_pass_s"],
-                      "wall_s": sat["wall_s"]},
+                      "passes": sat["passes"], "slices": sat["slices"], "uploads": sat["uploads"],
+                      "host_pass_s": sat["host_pass_s"], "gpu_pass_s": sat["gpu_pass_s"], "wall_s": sat["wall_s"]},
         "d2h_pinned_GBps": d2h_gbps,
-        "output_GB": sum(r.T * G[r.poly_index] * wb[r.poly_index] for r in reqs) / 1e9,
-        "sequential_plain": {"requests": k, "value": te_seq / el_seq, "seconds": el_seq,
+        "output_GB": sum(nbytes(r) for r in reqs) / 1e9,
+        "sequential_plain": {"requests": len(reqs), "value": te_seq / el_seq, "seconds": el_seq,
                              "saturated_served_over_sequential": (sat["term_evals"] / sat["wall_s"]) / (te_seq / el_seq)},
         "generate_s": gen_s,
         "rate_sweep": sweep,

@@ -13,6 +13,7 @@
 #include <new>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <type_traits>
 #include <vector>
 
@@ -320,6 +321,25 @@ int get_plan(peval_poly *h, uint32_t K, uint32_t P, Plan **out, bool subtile_end
 // ---------------------------------------------------------------------------
 // create / destroy / info
 // ---------------------------------------------------------------------------
+// Host threads for an ingest pass over n terms: one per 2^16 terms, at most 8.
+static unsigned ingest_threads(uint64_t n) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(std::min(hw, 8u), n >> 16));
+}
+
+// fn(lo, hi, t) over nt contiguous ranges of [0, n), range t on thread t.
+template <class F>
+static void par_ranges(uint64_t n, unsigned nt, F &&fn) {
+  if (nt <= 1) {
+    fn(0, n, 0u);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (unsigned t = 1; t < nt; ++t) th.emplace_back([&fn, n, nt, t] { fn(n * t / nt, n * (t + 1) / nt, t); });
+  fn(0, n / nt, 0u);
+  for (auto &x : th) x.join();
+}
+
 extern "C" int peval_create(uint64_t p, uint32_t n, uint64_t s, const uint32_t *exponents,
                             const uint64_t *coeffs, peval_poly **out) {
   if (!out) return fail(PEVAL_EINVAL, "out is NULL");
@@ -330,9 +350,18 @@ extern "C" int peval_create(uint64_t p, uint32_t n, uint64_t s, const uint32_t *
   if (s && (!exponents || !coeffs)) return fail(PEVAL_EINVAL, "null exponents or coefficients");
   if (s >= (1ull << 32) - 64) return fail(PEVAL_EUNSUPPORTED, "s >= 2^32 terms");
   const uint32_t ntail = n - 2;
+  const unsigned nt = ingest_threads(s);
   uint32_t maxe[32] = {0};
-  for (uint64_t i = 0; i < s; ++i)
-    for (uint32_t k = 0; k < n; ++k) maxe[k] = std::max(maxe[k], exponents[i * n + k]);
+  {
+    std::vector<uint32_t> part((size_t)nt * 32, 0);
+    par_ranges(s, nt, [&](uint64_t lo, uint64_t hi, unsigned t) {
+      uint32_t *mx = &part[(size_t)t * 32];
+      for (uint64_t i = lo; i < hi; ++i)
+        for (uint32_t k = 0; k < n; ++k) mx[k] = std::max(mx[k], exponents[i * n + k]);
+    });
+    for (unsigned t = 0; t < nt; ++t)
+      for (uint32_t k = 0; k < n; ++k) maxe[k] = std::max(maxe[k], part[(size_t)t * 32 + k]);
+  }
   for (uint32_t k = 2; k < n; ++k)
     if (maxe[k] > 65535)
       return fail(PEVAL_EUNSUPPORTED, "exponent of x%u is %u > 65535", k + 1, maxe[k]);
@@ -359,50 +388,76 @@ extern "C" int peval_create(uint64_t p, uint32_t n, uint64_t s, const uint32_t *
   h->tab_total = off;
 
   // A1: sort terms by (d, e) descending so that like monomials are adjacent
+  // (stable: terms of one group keep their input order)
   std::vector<uint32_t> order(s);
-  std::iota(order.begin(), order.end(), 0u);
   auto key = [&](uint64_t i) { return ((uint64_t)exponents[i * n] << 32) | exponents[i * n + 1]; };
   const uint64_t ext0 = (uint64_t)maxe[0] + 1, ext1 = (uint64_t)maxe[1] + 1;
   if (s && ext0 <= (1ull << 24) && ext1 <= (1ull << 24) && ext0 * ext1 <= (1ull << 24)) {
-    // counting sort over the dense (d, e) grid
+    // counting sort over the dense (d, e) grid, bin 0 = the largest key; each
+    // thread counts its range, then scatters it after the earlier ranges'
+    // terms of the same bin
     const uint64_t span = ext0 * ext1;
-    std::vector<uint32_t> cnt(span + 1, 0);
+    const unsigned ns = span * nt <= (1ull << 22) ? nt : 1;  // per-thread counts stay small
     auto dense = [&](uint64_t i) {
       return (uint64_t)(maxe[0] - exponents[i * n]) * ext1 + (maxe[1] - exponents[i * n + 1]);
     };
-    for (uint64_t i = 0; i < s; ++i) cnt[dense(i) + 1]++;
-    for (uint64_t b = 0; b < span; ++b) cnt[b + 1] += cnt[b];
-    for (uint64_t i = 0; i < s; ++i) order[cnt[dense(i)]++] = (uint32_t)i;
-  } else {
-    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return key(a) > key(b); });
-  }
-  h->grp_off.push_back(0);
-  for (uint64_t r = 0; r < s; ++r) {
-    uint64_t k = key(order[r]);
-    if (r == 0 || k != key(order[r - 1])) {
-      if (r) h->grp_off.push_back(r);
-      h->gd.push_back((uint32_t)(k >> 32));
-      h->ge.push_back((uint32_t)k);
+    std::vector<uint32_t> cnt((size_t)ns * span, 0);
+    par_ranges(s, ns, [&](uint64_t lo, uint64_t hi, unsigned t) {
+      uint32_t *c = &cnt[(size_t)t * span];
+      for (uint64_t i = lo; i < hi; ++i) c[dense(i)]++;
+    });
+    h->grp_off.push_back(0);
+    uint64_t run = 0;
+    for (uint64_t b = 0; b < span; ++b) {
+      const uint64_t start = run;
+      for (unsigned t = 0; t < ns; ++t) {
+        const uint32_t c = cnt[(size_t)t * span + b];
+        cnt[(size_t)t * span + b] = (uint32_t)run;
+        run += c;
+      }
+      if (run > start) {  // a group: bin b holds terms
+        h->gd.push_back((uint32_t)(maxe[0] - b / ext1));
+        h->ge.push_back((uint32_t)(maxe[1] - b % ext1));
+        h->grp_off.push_back(run);
+      }
     }
+    par_ranges(s, ns, [&](uint64_t lo, uint64_t hi, unsigned t) {
+      uint32_t *c = &cnt[(size_t)t * span];
+      for (uint64_t i = lo; i < hi; ++i) order[c[dense(i)]++] = (uint32_t)i;
+    });
+  } else {
+    std::iota(order.begin(), order.end(), 0u);
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t a, uint32_t b) { return key(a) > key(b); });
+    h->grp_off.push_back(0);
+    for (uint64_t r = 0; r < s; ++r) {
+      uint64_t k = key(order[r]);
+      if (r == 0 || k != key(order[r - 1])) {
+        if (r) h->grp_off.push_back(r);
+        h->gd.push_back((uint32_t)(k >> 32));
+        h->ge.push_back((uint32_t)k);
+      }
+    }
+    if (s) h->grp_off.push_back(s);
   }
-  if (s) h->grp_off.push_back(s);
   h->G = h->gd.size();
   for (uint64_t g = 0; g < h->G; ++g) h->max_group = std::max(h->max_group, h->grp_off[g + 1] - h->grp_off[g]);
 
   // sorted structure-of-arrays: coefficients (reduced mod p) and tail exponents
   std::vector<uint8_t> coeff(s * h->w);
   std::vector<uint16_t> ex((size_t)ntail * s);
-  for (uint64_t r = 0; r < s; ++r) {
-    uint64_t i = order[r];
-    uint64_t a = coeffs[i] % p;
-    if (h->w == 4) {
-      uint32_t a32 = (uint32_t)a;
-      memcpy(&coeff[r * 4], &a32, 4);
-    } else {
-      memcpy(&coeff[r * 8], &a, 8);
+  par_ranges(s, nt, [&](uint64_t lo, uint64_t hi, unsigned) {
+    for (uint64_t r = lo; r < hi; ++r) {
+      uint64_t i = order[r];
+      uint64_t a = coeffs[i] % p;
+      if (h->w == 4) {
+        uint32_t a32 = (uint32_t)a;
+        memcpy(&coeff[r * 4], &a32, 4);
+      } else {
+        memcpy(&coeff[r * 8], &a, 8);
+      }
+      for (uint32_t k = 0; k < ntail; ++k) ex[(size_t)k * s + r] = (uint16_t)exponents[i * n + 2 + k];
     }
-    for (uint32_t k = 0; k < ntail; ++k) ex[(size_t)k * s + r] = (uint16_t)exponents[i * n + 2 + k];
-  }
+  });
 
   int rc = PEVAL_OK;
   auto bail = [&](int code) {

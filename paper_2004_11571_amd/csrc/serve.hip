@@ -41,6 +41,7 @@ struct SPoly {
   uint32_t n = 0, w = 8;
   uint64_t s = 0, G = 0;
   uint64_t tab_total = 0;      // power-table entries (sum of tail degrees + 1)
+  uint32_t max_exp[32] = {0};  // largest exponent of each variable
   std::vector<uint32_t> exps;  // host copy for re-upload after eviction
   std::vector<uint64_t> coeffs;
   peval_poly *h = nullptr;     // resident handle (null when not resident)
@@ -49,6 +50,7 @@ struct SPoly {
   uint64_t last_used = 0;
   uint32_t refs = 0;           // admitted requests using it
   bool removed = false;
+  bool uploading = false;      // queued for (or in) an upload by an uploader thread
 };
 
 struct SReq {
@@ -77,6 +79,7 @@ struct Pass {
 };
 
 constexpr int kStreams = 2;
+constexpr int kUploaders = 2;  // threads making polynomials resident (each ingest is multi-threaded itself)
 
 }  // namespace
 
@@ -128,6 +131,15 @@ struct peval_server {
   std::deque<uint64_t> done_q;       // finished requests, in completion order (for next_done)
   std::condition_variable cv_copy;
   std::vector<std::thread> copiers;
+  // uploads and frees off the scheduler thread: polynomials to make resident
+  // (in admission order), and evicted handles and trimmed output blocks to
+  // release (hipFree waits for the device, so it never runs under the lock
+  // or on the scheduler thread)
+  std::deque<uint64_t> upload_q;
+  std::vector<peval_poly *> reclaim_h;
+  std::vector<void *> reclaim_blocks;
+  std::condition_variable cv_upload;
+  std::vector<std::thread> uploaders;
   hipStream_t copy_sts[4] = {nullptr, nullptr, nullptr, nullptr};
   int err = PEVAL_OK;                // sticky device error
 };
@@ -174,7 +186,10 @@ static void evict_for(peval_server *S, uint64_t need, uint64_t keep) {
         victim = &sp;
     }
     if (!victim) return;
-    if (victim->h) peval_destroy(victim->h);
+    if (victim->h) {  // released by an uploader thread; its bytes count as free now
+      S->reclaim_h.push_back(victim->h);
+      S->cv_upload.notify_one();
+    }
     victim->h = nullptr;
     victim->plan = nullptr;
     S->used -= victim->bytes;
@@ -248,7 +263,8 @@ static void trim_out_cache(peval_server *S, uint64_t need) {
       S->out_free.erase(it);
       continue;
     }
-    (void)hipFree(it->second.back());
+    S->reclaim_blocks.push_back(it->second.back());  // freed by an uploader thread
+    S->cv_upload.notify_one();
     it->second.pop_back();
     S->used -= it->first;
     S->out_free_bytes -= it->first;
@@ -311,7 +327,8 @@ static void admit(peval_server *S, std::unique_lock<std::mutex> &lk) {
   while (!S->pending.empty()) {
     SReq &r = S->reqs[S->pending.front()];
     SPoly &sp = S->polys[r.poly];
-    const bool resident = sp.h || (S->simulate && sp.bytes);
+    // a polynomial being uploaded already holds its estimated bytes
+    const bool resident = sp.h || (S->simulate && sp.bytes) || sp.uploading;
     if (sp.plan) {  // resident: the reservation follows the actual thread layout
       r.reserve = 2 * (member_scratch_bytes(sp.h, *sp.plan, r.cmax, r.ts) + (uint64_t)r.cmax * sp.plan->nslots * sp.w);
     }
@@ -335,33 +352,21 @@ static void admit(peval_server *S, std::unique_lock<std::mutex> &lk) {
     if (S->simulate) {
       rc = make_resident(S, sp);
     } else {
+      if (!resident) {  // an uploader thread makes it resident; passes skip the request until then
+        sp.uploading = true;
+        S->used += estimate_poly_bytes(sp);  // held while uploading
+        S->upload_q.push_back(r.poly);
+        S->cv_upload.notify_one();
+      }
       // the request stays at the head of `pending` meanwhile, which keeps its
       // polynomial from being removed
-      const bool upload = !sp.h;
-      if (upload) S->used += estimate_poly_bytes(sp);  // held while uploading
-      lk.unlock();
-      peval_poly *h = sp.h;
-      Plan *plan = sp.plan;
-      uint64_t bytes = 0;
-      if (upload) rc = upload_poly(sp, &h, &plan, &bytes);
-      if (rc == PEVAL_OK && !reuse && hipMalloc(&r.d_out, ob) != hipSuccess) {
-        r.d_out = nullptr;
-        rc = fail(PEVAL_ENOMEM, "output");
-      }
-      lk.lock();
-      if (upload) {
-        S->used -= estimate_poly_bytes(sp);
-        if (rc == PEVAL_OK || h) {
-          sp.h = h;
-          sp.plan = plan;
-          sp.bytes = bytes;
-          S->used += bytes;
-          S->uploads++;
-          // exact reservation now that the layout is known (never above the bound)
-          if (plan)
-            r.reserve = std::min<uint64_t>(
-                r.reserve, 2 * (member_scratch_bytes(h, *plan, r.cmax, r.ts) + (uint64_t)r.cmax * plan->nslots * sp.w));
+      if (!reuse) {
+        lk.unlock();
+        if (hipMalloc(&r.d_out, ob) != hipSuccess) {
+          r.d_out = nullptr;
+          rc = fail(PEVAL_ENOMEM, "output");
         }
+        lk.lock();
       }
     }
     S->pending.pop_front();
@@ -408,6 +413,7 @@ static bool launch_pass_impl(peval_server *S, std::unique_lock<std::mutex> &lk) 
   for (uint64_t rid : S->active) {
     const SReq &r = S->reqs[rid];
     if (r.t_next > r.T) continue;
+    if (!S->simulate && !S->polys[r.poly].h) continue;  // its upload has not finished
     cand.emplace_back((double)S->polys[r.poly].s * (r.T - r.t_next + 1), rid);
   }
   if (cand.empty()) return false;
@@ -632,6 +638,77 @@ static void copier_main(peval_server *S, int idx) {
   }
 }
 
+// Uploads of polynomials for admitted requests, and the frees of evicted
+// handles and trimmed output blocks.
+static void uploader_main(peval_server *S) {
+  (void)hipSetDevice(S->device);
+  std::unique_lock<std::mutex> lk(S->mu);
+  while (true) {
+    S->cv_upload.wait(lk, [&] {
+      return S->stop || !S->upload_q.empty() || !S->reclaim_h.empty() || !S->reclaim_blocks.empty();
+    });
+    if (!S->reclaim_h.empty() || !S->reclaim_blocks.empty()) {
+      std::vector<peval_poly *> hs;
+      std::vector<void *> bs;
+      hs.swap(S->reclaim_h);
+      bs.swap(S->reclaim_blocks);
+      lk.unlock();
+      for (peval_poly *h : hs) peval_destroy(h);
+      for (void *b : bs) (void)hipFree(b);
+      lk.lock();
+      continue;
+    }
+    if (S->stop) break;
+    const uint64_t pid = S->upload_q.front();
+    S->upload_q.pop_front();
+    // an admitted request holds the polynomial (refs > 0), so it stays
+    // registered; its inputs never change after add_poly
+    SPoly &sp = S->polys[pid];
+    lk.unlock();
+    peval_poly *h = nullptr;
+    Plan *plan = nullptr;
+    uint64_t bytes = 0;
+    int rc = upload_poly(sp, &h, &plan, &bytes);
+    lk.lock();
+    S->used -= estimate_poly_bytes(sp);
+    sp.uploading = false;
+    if (rc == PEVAL_OK) {
+      sp.h = h;
+      sp.plan = plan;
+      sp.bytes = bytes;
+      S->used += bytes;
+      S->peak = std::max(S->peak, S->used);
+      S->uploads++;
+      // exact reservations now that the layout is known (never above the bound)
+      for (uint64_t rid : S->active) {
+        SReq &r = S->reqs[rid];
+        if (r.poly != pid) continue;
+        const uint64_t exact =
+            std::min<uint64_t>(r.reserve, 2 * (member_scratch_bytes(h, *plan, r.cmax, r.ts) +
+                                               (uint64_t)r.cmax * plan->nslots * sp.w));
+        S->used -= r.reserve - exact;
+        r.reserve = exact;
+      }
+    } else {  // every admitted request of the polynomial fails with the upload's error
+      for (size_t j = 0; j < S->active.size();) {
+        SReq &r = S->reqs[S->active[j]];
+        if (r.poly != pid) {
+          ++j;
+          continue;
+        }
+        S->active.erase(S->active.begin() + j);
+        r.status = rc;
+        S->done_q.push_back(r.id);
+        S->rejected++;
+        sp.refs--;
+        release_output(S, r);
+      }
+      S->cv_done.notify_all();
+    }
+    S->cv_work.notify_one();
+  }
+}
+
 static void worker_main(peval_server *S) {
   if (!S->simulate) (void)hipSetDevice(S->device);
   std::unique_lock<std::mutex> lk(S->mu);
@@ -672,8 +749,10 @@ extern "C" int peval_server_create(uint64_t hbm_budget_bytes, uint32_t flags, pe
   }
   S->t_start = now_s();
   S->worker = std::thread(worker_main, S);
-  if (!S->simulate)
+  if (!S->simulate) {
     for (int k = 0; k < 4; ++k) S->copiers.emplace_back(copier_main, S, k);
+    for (int k = 0; k < kUploaders; ++k) S->uploaders.emplace_back(uploader_main, S);
+  }
   *out = S;
   return PEVAL_OK;
 }
@@ -700,22 +779,29 @@ extern "C" int peval_server_add_poly(peval_server *S, uint64_t p, uint32_t n, ui
   sp.n = n;
   sp.s = s;
   sp.w = p < (1ull << 31) ? 4 : 8;
+  for (uint64_t i = 0; i < s; ++i)
+    for (uint32_t k = 0; k < n; ++k) sp.max_exp[k] = std::max(sp.max_exp[k], exponents[i * n + k]);
+  for (uint32_t k = 2; k < n; ++k) {
+    if (sp.max_exp[k] > 65535) return fail(PEVAL_EUNSUPPORTED, "tail exponent > 65535");
+    sp.tab_total += sp.max_exp[k] + 1;
+  }
   sp.exps.assign(exponents, exponents + s * n);
   sp.coeffs.assign(coeffs, coeffs + s);
-  for (uint64_t i = 0; i < s; ++i)
-    for (uint32_t k = 2; k < n; ++k)
-      if (exponents[i * n + k] > 65535) return fail(PEVAL_EUNSUPPORTED, "tail exponent > 65535");
-  {
-    std::vector<uint32_t> mx(n, 0);
-    for (uint64_t i = 0; i < s; ++i)
-      for (uint32_t k = 2; k < n; ++k) mx[k] = std::max(mx[k], exponents[i * n + k]);
-    for (uint32_t k = 2; k < n; ++k) sp.tab_total += mx[k] + 1;
-  }
   {  // number of output columns (distinct (x1, x2) exponents)
-    std::vector<uint64_t> keys(s);
-    for (uint64_t i = 0; i < s; ++i) keys[i] = ((uint64_t)exponents[i * n] << 32) | exponents[i * n + 1];
-    std::sort(keys.begin(), keys.end());
-    sp.G = (uint64_t)(std::unique(keys.begin(), keys.end()) - keys.begin());
+    const uint64_t ext0 = (uint64_t)sp.max_exp[0] + 1, ext1 = (uint64_t)sp.max_exp[1] + 1;
+    if (s && ext0 * ext1 <= (1ull << 26)) {
+      std::vector<uint8_t> seen(ext0 * ext1, 0);
+      for (uint64_t i = 0; i < s; ++i) {
+        uint8_t &f = seen[(uint64_t)exponents[i * n] * ext1 + exponents[i * n + 1]];
+        sp.G += f ^ 1;
+        f = 1;
+      }
+    } else {
+      std::vector<uint64_t> keys(s);
+      for (uint64_t i = 0; i < s; ++i) keys[i] = ((uint64_t)exponents[i * n] << 32) | exponents[i * n + 1];
+      std::sort(keys.begin(), keys.end());
+      sp.G = (uint64_t)(std::unique(keys.begin(), keys.end()) - keys.begin());
+    }
   }
   std::lock_guard<std::mutex> lk(S->mu);
   sp.id = S->next_id++;
@@ -737,8 +823,7 @@ extern "C" int peval_server_poly_info(peval_server *S, uint64_t poly_id, peval_i
   info->s = sp.s;
   info->G = sp.G;
   info->device_bytes = sp.h ? sp.bytes : 0;
-  for (uint32_t k = 0; k < sp.n && k < 32; ++k)
-    for (uint64_t i = 0; i < sp.s; ++i) info->max_exp[k] = std::max(info->max_exp[k], sp.exps[i * sp.n + k]);
+  std::copy(sp.max_exp, sp.max_exp + 32, info->max_exp);
   return PEVAL_OK;
 }
 
@@ -750,7 +835,15 @@ extern "C" int peval_server_remove_poly(peval_server *S, uint64_t poly_id) {
   if (it->second.refs) return fail(PEVAL_EBUSY, "polynomial has requests in flight");
   for (uint64_t rid : S->pending)
     if (S->reqs[rid].poly == poly_id) return fail(PEVAL_EBUSY, "polynomial has queued requests");
-  if (it->second.h) peval_destroy(it->second.h);
+  if (it->second.uploading) return fail(PEVAL_EBUSY, "polynomial is being uploaded");
+  if (it->second.h) {
+    if (S->simulate) {
+      peval_destroy(it->second.h);
+    } else {
+      S->reclaim_h.push_back(it->second.h);
+      S->cv_upload.notify_one();
+    }
+  }
   S->used -= it->second.bytes;
   S->polys.erase(it);
   return PEVAL_OK;
@@ -932,6 +1025,14 @@ extern "C" int peval_server_destroy(peval_server *S) {
   if (S->worker.joinable()) S->worker.join();
   for (auto &t : S->copiers)
     if (t.joinable()) t.join();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->cv_upload.notify_all();
+  }
+  for (auto &t : S->uploaders)
+    if (t.joinable()) t.join();
+  for (peval_poly *h : S->reclaim_h) peval_destroy(h);
+  for (void *b : S->reclaim_blocks) (void)hipFree(b);
   if (!S->simulate) {
     for (int k = 0; k < kStreams; ++k)
       if (S->st[k]) (void)hipStreamSynchronize(S->st[k]);

@@ -387,8 +387,12 @@ class Server:
 
     def remove_poly(self, pid: int):
         _check(lib().peval_server_remove_poly(self._s, pid))
+        self._meta.pop(pid, None)
 
     def submit(self, pid: int, beta, T: int, out: Optional[np.ndarray] = None) -> int:
+        if pid not in self._meta:  # not registered (or removed): the library refuses it
+            rid = ctypes.c_uint64()
+            _check(lib().peval_server_submit(self._s, pid, None, T, None, ctypes.byref(rid)))
         p, n, G = self._meta[pid]
         if out is None:
             out = np.zeros((T, G), out_dtype(p))

@@ -237,10 +237,9 @@ class Request:
 
 
 def serve_stream(rate_per_s: float, duration_s: float, pool: List[Poly], instance: int = 0,
-                 new_fraction: float = 0.1, t_log2: tuple = (6, 11)) -> List[Request]:
-    """Poisson arrivals; each request picks a polynomial from ``pool`` and a
-    fresh base point.  The first ``new_fraction`` of the pool is treated as
-    not yet resident by the caller."""
+                 t_log2: tuple = (6, 11)) -> List[Request]:
+    """Poisson arrivals; each request picks a polynomial from ``pool``
+    uniformly, T log-uniform in 2^t_log2 and a fresh base point."""
     rng = np.random.default_rng(workload_seed(5, instance))
     t = 0.0
     reqs = []
@@ -253,6 +252,21 @@ def serve_stream(rate_per_s: float, duration_s: float, pool: List[Poly], instanc
         beta = rng.integers(1, pool[j].p, size=pool[j].n - 2, dtype=np.uint64)
         reqs.append(Request(arrival_s=t, poly_index=j, T=T, beta=beta))
     return reqs
+
+
+def serve_new_polys(reqs: List[Request], pool: List[Poly], fraction: float = 0.1,
+                    instance: int = 0) -> dict:
+    """About ``fraction`` of the requests ask for a polynomial that the server
+    has not seen before the stream: the exponent rows of the request's pool
+    member with fresh coefficients, uniform in [0, p).  Returns
+    {request index: coefficients}."""
+    rng = np.random.default_rng(workload_seed(5, 200 + instance))
+    out = {}
+    for i, r in enumerate(reqs):
+        if rng.random() < fraction:
+            w = pool[r.poly_index]
+            out[i] = rng.integers(0, w.p, size=w.s, dtype=np.uint64)
+    return out
 
 
 def serve_pool(count: int, instance: int = 0, s_max: float = 5e6) -> List[Poly]:

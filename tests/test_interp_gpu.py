@@ -31,10 +31,18 @@ def group_sizes(exps):
     return cnt
 
 
+# With p = 101 a group of dozens of terms has two equal monomial values at
+# every beta (there are only 100 non-zero residues), so its system is always
+# singular: there the two larger shapes keep a handful of terms per group.
+SMALL_P_SHAPE = {(5, 800, 3, 6): (5, 48, 3, 6), (8, 500, 4, 3): (8, 75, 4, 3)}
+
+
 @pytest.mark.parametrize("p", [101, 65537, W.P31, (1 << 31) + 11, W.P50, W.P63])
 @pytest.mark.parametrize("shape", [(3, 300, 2, 60), (5, 800, 3, 6), (8, 500, 4, 3), (2, 40, 6, 0)])
 def test_parity_arbitrary_images(orc, p, shape):
     """Any image values determine one coefficient vector; GPU == oracle."""
+    if p == 101:
+        shape = SMALL_P_SHAPE.get(shape, shape)
     n, s, d12, dmax = shape
     rng = np.random.default_rng(p % 1009 + n)
     exps = support(rng, p, n, s, d12, dmax)

@@ -130,3 +130,63 @@ def test_concurrent_submitters():
             t.join()
     for g, w_ in zip(got, want):
         assert np.array_equal(g, w_)
+
+
+def test_served_at_stream_sizes():
+    """The served stream's sizes: terms up to 5e6, T up to 2048, 31- and
+    63-bit primes, and a tenth of the requests for polynomials the server has
+    not seen (registered just before, uploaded at admission, removed after).
+    Every result equals the request run alone (stops at the first
+    mismatch); a few small ones are checked by the oracle."""
+    sizes = [5_000_000, 1_200_000, 300_000, 40_000, 3_000]
+    rng = np.random.default_rng(11)
+    pool = []
+    for j, s in enumerate(sizes):
+        n = int(rng.integers(4, 9))
+        p = (W.P63, W.P31)[j % 2]
+        pool.append(W.make_poly(int(rng.integers(0, 2**62)), p, n, s, 1, 40, W.raise_dr(s, n, 40, 20)))
+    reqs = []
+    for k in range(60):
+        j = int(rng.integers(0, len(pool)))
+        T = int(round(2 ** rng.uniform(6, 11)))
+        beta = rng.integers(1, pool[j].p, size=pool[j].n - 2, dtype=np.uint64)
+        fresh = rng.integers(0, pool[j].p, size=pool[j].s, dtype=np.uint64) if k % 10 == 3 else None
+        reqs.append((j, beta, T, fresh))
+    print("case served stream sizes:", [(w.s, w.n) for w in pool], flush=True)
+    with PV.Server(64 << 30) as srv:
+        pids = [srv.add_poly(w.p, w.exps, w.coeffs) for w in pool]
+        rids, new_ids = [], []
+        for j, beta, T, fresh in reqs:
+            pid = pids[j] if fresh is None else srv.add_poly(pool[j].p, pool[j].exps, fresh)
+            rids.append(srv.submit(pid, beta, T))
+            new_ids.append(None if fresh is None else pid)
+        got = [srv.wait(r, 120000) for r in rids]
+        for pid in new_ids:
+            if pid is not None:
+                srv.remove_poly(pid)
+        st = srv.stats()
+        print("stats", st, flush=True)
+    assert st["completed"] == len(reqs) and st["rejected"] == 0
+    used = len({j for j, _, _, f in reqs if f is None})
+    assert st["uploads"] >= used + sum(f is not None for *_, f in reqs)
+    hs = [PV.Poly(w.p, w.exps, w.coeffs) for w in pool]
+    try:
+        for k, ((j, beta, T, fresh), g) in enumerate(zip(reqs, got)):
+            if fresh is None:
+                want = hs[j].run(beta, T)
+            else:
+                with PV.Poly(pool[j].p, pool[j].exps, fresh) as h:
+                    want = h.run(beta, T)
+            assert np.array_equal(g, want), f"request {k}: poly {j} (s={pool[j].s}) T={T} new={fresh is not None}"
+    finally:
+        for h in hs:
+            h.destroy()
+    orc = Oracle()
+    checked = 0
+    for k, (j, beta, T, fresh) in enumerate(reqs):
+        w = pool[j]
+        if w.s * T <= 2e7 and checked < 4:
+            coeffs = w.coeffs if fresh is None else fresh
+            assert np.array_equal(got[k].astype(np.uint64), orc.evaluate(w.p, w.exps, coeffs, beta, T, threads=8))
+            checked += 1
+    assert checked >= 2
