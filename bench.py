@@ -89,6 +89,7 @@ def parse():
     ap.add_argument("--tight-gb", type=float, default=2.0, help="served stream: a run under this HBM budget (0: skip)")
     ap.add_argument("--batch-count", type=int, default=256)
     ap.add_argument("--batch-smax", type=float, default=1e6)
+    ap.add_argument("--no-batch-tune", action="store_true", help="batch: heuristic tiles, no tuning at create")
     ap.add_argument("--tuning", default="", help="K,P,C override")
     ap.add_argument("--arith", default="auto", choices=["auto", "int", "fp64", "pm"],
                     help="modular product of the evaluation kernel (fp64: the paper's Alg. 2, p < 2^50)")
@@ -294,6 +295,11 @@ def batch_main(args):
     from paper_2004_11571_amd import workloads as W
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calib_copy_mib:  # a plain device copy of known size (counter calibration)
+        src = torch.ones(args.calib_copy_mib << 18, dtype=torch.float32, device="cuda")
+        torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
+        del src
     t_gen = time.time()
     ws = W.uneven_batch(count=args.batch_count, s_max=args.batch_smax)
     gen_s = time.time() - t_gen
@@ -306,18 +312,34 @@ def batch_main(args):
             for w, q in zip(ws, polys)]
     betas = [w.beta for w in ws]
     stream = torch.cuda.current_stream()
-    b = PV.Batch(polys, Ts, graph=True)
+    # the batch's tiles are tuned on the device before anything is timed
+    t_tune = time.time()
+    b = PV.Batch(polys, Ts, graph=True, tune=not args.no_batch_tune)
+    tune_s = time.time() - t_tune
     info = b.info()
+    mi = b.members()
+    kind_names = ["w64_k16", "w64_k<=8", "fp64", "w32_k32", "w32_k<=16"]
+    tiles = {}
+    for w, k, c, kd in zip(ws, mi["K"], mi["C"], mi["kind"]):
+        e = tiles.setdefault(kind_names[int(kd)], {"members": 0, "term_evals": 0, "K": {}})
+        e["members"] += 1
+        e["term_evals"] += w.s * w.T
+        e["K"][str(int(k))] = e["K"].get(str(int(k)), 0) + 1
     steps = args.steps or 20
     warm = max(1, args.warmup)
     for _ in range(warm):
         b.run(betas, outs, stream=stream)
     torch.cuda.synchronize()
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = time.perf_counter()
-    for _ in range(steps):
+    marks[0].record(stream)
+    for i in range(steps):
         b.run(betas, outs, stream=stream)
+        marks[i + 1].record(stream)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    step_ms = sorted(marks[i].elapsed_time(marks[i + 1]) for i in range(steps))
+    spread = {"min": step_ms[0], "median": step_ms[len(step_ms) // 2], "max": step_ms[-1]}
     batched = [o.cpu().numpy().view(q.dtype).copy() for o, q in zip(outs, polys)]
 
     # the same members as plain launches, one after another on one stream
@@ -351,9 +373,13 @@ def batch_main(args):
         "vs_baseline": None, "dtype": "u32+u64", "data": "synthetic",
         "config": {"workload": f"batch{len(ws)}_uneven_s1e3-{args.batch_smax:.0e}_T32-2048_p31p63",
                    "members": len(ws), "term_evals_per_step": te, **info},
+        "tiles": {"tuned": not args.no_batch_tune, "tune_trials": mi["tune_trials"], "tuned_pass_ms": mi["tuned_ms"],
+                  "create_and_tune_s": tune_s, "by_kernel": tiles},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                      "unit": "Tops/s (int32 lane-ops)", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
-                     "kernel": "whole batched pass (graph replay), all kernels"},
+                     "kernel": "whole batched pass (graph replay), all kernels",
+                     "frac_at_median_step": ops / (spread["median"] / 1e3) / VALU_PEAK_OPS},
+        "step_ms_spread": spread,
         "sequential_plain": {"value": te * steps / el_seq, "ms_per_step": el_seq / steps * 1e3,
                              "batched_over_sequential": el_seq / el, "identical_outputs": same},
         "generate_s": gen_s, "create_s": create_s,

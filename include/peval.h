@@ -223,7 +223,8 @@ int peval_destroy(peval_poly *h);
 
 /*
  * Tuning knobs of the evaluation kernel for one handle (0 = automatic):
- *   K      terms held per thread (1, 2, 4, 8, 16)
+ *   K      terms held per thread (1, 2, 4, 8, 16; 32 for p < 2^31 under the
+ *          integer product, with P <= 16; EINVAL otherwise)
  *   P      evaluations per pass before each coefficient reduction (8, 16, 32;
  *          the role of the paper's dependent evaluations T_d, Section 4.2)
  *   C      independent evaluation chains (>= 1; chain c does t = t0+c,
@@ -300,15 +301,16 @@ int peval_tune_load(const char *path);
  *
  * peval_batch_create plans one pass over `count` resident polynomials,
  * polys[j] evaluated Ts[j] times: it fixes every member's thread layout
- * (K from the tuning cache or the heuristic; P = 16) and its
+ * (K from the tuning cache or the heuristic) and its
  * chains so that the work items (one wave of one chain of one polynomial)
  * have similar costs, allocates all device scratch, and captures the pass
  * (power tables, monomials, persistent evaluation kernels fed by work
  * queues in decreasing item cost, one for each kind of member: 64-bit
- * residues with the integer product, 64-bit residues with the FP64 product
- * (members whose arithmetic resolves to it when the batch is created), and
- * 32-bit residues; combine) into a hipGraph unless flags has
- * PEVAL_BATCH_NO_GRAPH.  The handles must outlive the batch; a later
+ * residues with the integer product and K = 16 (16 evaluations per pass),
+ * the same with K <= 8 (8 per pass), 64-bit residues with the FP64 product
+ * (members whose arithmetic resolves to it when the batch is created),
+ * 32-bit residues with K = 32, and with K <= 16; combine) into a hipGraph
+ * unless flags has PEVAL_BATCH_NO_GRAPH.  The handles must outlive the batch; a later
  * peval_set_arith on a member does not change the batch.
  *
  * peval_batch_run evaluates polys[j] at betas[j] (n_j - 2 values each) for
@@ -321,14 +323,32 @@ int peval_tune_load(const char *path);
  *
  * peval_batch_info fills info[5]: members, work items, persistent blocks
  * (all evaluation kernels), scratch bytes, term-evaluations per run.
+ *
+ * flags PEVAL_BATCH_TUNE: before planning, time candidate plans of this
+ * batch on the device (the analogue of the paper's tile sweep, Section 4.4)
+ * and keep the fastest: members are grouped by product and width and by
+ * whether their K is the largest allowed, each group's K is moved one
+ * doubling either way in turn (coordinate search), then the work items'
+ * target cost is halved and doubled.  Candidates run with base point 2 into
+ * scratch outputs of sum(T_j G_j elem_bytes) bytes allocated for the search;
+ * a choice is kept only when it is at least 1% faster.  Results never
+ * depend on the plan.
+ * peval_batch_members reports, per member j, its terms per thread K[j],
+ * chains C[j] and kernel kind[j] (0: 64-bit Shoup with K = 16; 1: 64-bit
+ * Shoup, K <= 8; 2: FP64 product; 3: 32-bit, K = 32; 4: 32-bit, K <= 16),
+ * and the tuner's pass time and number of timed candidates (0 if the batch
+ * was not tuned).  Any output pointer may be NULL.
  */
 typedef struct peval_batch peval_batch;
 #define PEVAL_BATCH_NO_GRAPH 1u
+#define PEVAL_BATCH_TUNE 2u
 int peval_batch_create(uint32_t count, peval_poly *const *polys, const uint32_t *Ts, uint32_t flags,
                        peval_batch **out);
 int peval_batch_run(peval_batch *b, const uint64_t *const *betas, const uint64_t *t0s,
                     void *const *dev_outs, void *stream);
 int peval_batch_info(const peval_batch *b, uint64_t *info);
+int peval_batch_members(const peval_batch *b, uint32_t *K, uint32_t *C, uint32_t *kind, float *tuned_ms,
+                        uint32_t *tune_trials);
 int peval_batch_destroy(peval_batch *b);
 
 /*

@@ -36,9 +36,8 @@ static int persistent_blocks(int blocks[kKinds]) {
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipGetDeviceProperties(&prop, dev));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[kKindW64], batch_eval_kernel<W64>, kEvalBlock, 0));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[kKindF64], batch_eval_kernel<WF64>, kEvalBlock, 0));
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[kKindW32], batch_eval_kernel<W32>, kEvalBlock, 0));
+    for (uint32_t k = 0; k < kKinds; ++k)
+      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[k], batch_eval_fn(k), kEvalBlock, 0));
     for (int k = 0; k < kKinds; ++k) cached[k] = std::max(1, per_cu[k]) * prop.multiProcessorCount;
   }
   for (int k = 0; k < kKinds; ++k) blocks[k] = cached[k];
@@ -58,10 +57,11 @@ int batch_set_blocks(BatchCore &b) {
 // The product a member's evaluations take: that of its handle when the
 // batch is planned (FP64 where the handle's arithmetic resolves to it and
 // the plan keeps K <= 8, so that a thread's sum of doubles stays exact;
-// the Shoup product, exact for every p, otherwise).
-static uint32_t member_kind(const peval_poly *h, uint32_t K) {
-  if (h->w == 4) return kKindW32;
-  return (h->arith == 1 && K <= 8) ? kKindF64 : kKindW64;
+// the Shoup product, exact for every p, otherwise); and the kernel of its K.
+uint32_t member_kind(const peval_poly *h, uint32_t K) {
+  if (h->w == 4) return K == 32 ? kKindW32K32 : kKindW32Lo;
+  if (h->arith == 1 && K <= 8) return kKindF64;
+  return K == 16 ? kKindW64K16 : kKindW64Lo;
 }
 
 // Bytes of device scratch one member needs (power tables, chain starts,
@@ -88,6 +88,26 @@ uint32_t member_chains(const Plan &pl, uint32_t T, double target_cost) {
   c = std::min(c, std::floor(T / (4.0 * (2.0 * std::log2(std::max<double>(T, 2.0)) + 2.0))));
   c = std::min<double>(std::max(c, 1.0), std::min<uint32_t>(T, 256));
   return (uint32_t)c;
+}
+
+// Chains of every member: each kind's kernel runs on its own, so each kind
+// sizes its work items from its own work: about eight items per wave slot
+// of its kernel on the chip (so that the last items, the smallest, leave
+// little idle), none below one wave's 64 x 8 x 64 term-evaluations, times
+// `scale`.  One target for the whole batch left a kind with little work too
+// few items to fill the chip, waiting on its longest one.
+int batch_chains(std::vector<BatchMember> &mem, double scale) {
+  int blocks[kKinds];
+  PEVAL_TRY(persistent_blocks(blocks));
+  double work[kKinds] = {};
+  for (const auto &m : mem) work[member_kind(m.h, m.plan->K)] += 64.0 * m.plan->K * m.plan->NW * m.T;
+  for (auto &m : mem) {
+    const uint32_t k = member_kind(m.h, m.plan->K);
+    const double slots = (double)blocks[k] * (kEvalBlock / 64);  // waves of the kernel on the chip
+    const double target = std::max(work[k] / (8.0 * slots), 64.0 * 8 * 64) * scale;
+    m.C = member_chains(*m.plan, m.T, target);
+  }
+  return PEVAL_OK;
 }
 
 size_t batch_scratch_need(const std::vector<BatchMember> &mem) {
@@ -239,12 +259,7 @@ int batch_enqueue(const BatchCore &b, hipStream_t st) {
     if (!n) continue;
     const BatchItem *it = b.d_items + first;
     uint32_t *ctr = b.d_counter + kind;
-    if (kind == kKindW64)
-      batch_eval_kernel<W64><<<b.eval_blocks[kind], kEvalBlock, 0, st>>>(b.d_desc, it, n, ctr);
-    else if (kind == kKindF64)
-      batch_eval_kernel<WF64><<<b.eval_blocks[kind], kEvalBlock, 0, st>>>(b.d_desc, it, n, ctr);
-    else
-      batch_eval_kernel<W32><<<b.eval_blocks[kind], kEvalBlock, 0, st>>>(b.d_desc, it, n, ctr);
+    batch_eval_fn(kind)<<<b.eval_blocks[kind], kEvalBlock, 0, st>>>(b.d_desc, it, n, ctr);
     HIP_TRY(hipGetLastError());
   }
   if (b.out_total) {  // out_total counts combine tiles
@@ -274,6 +289,8 @@ struct peval_batch {
   hipEvent_t done = nullptr;
   bool have_done = false;
   bool use_graph = true;
+  uint32_t tune_trials = 0;  // passes timed by the batch tuner (0: not tuned)
+  float tuned_ms = 0;        // the chosen plan's pass time while tuning
   std::mutex mu;
 };
 
@@ -290,6 +307,146 @@ static void batch_free(peval_batch *b) {
   }
   batch_release(b->core);
   delete b;
+}
+
+// ---------------------------------------------------------------------------
+// planning and tuning of a batch
+// ---------------------------------------------------------------------------
+// Members whose tiles the tuner moves together: product and width (64-bit
+// Shoup, FP64, 32-bit Shoup) times whether their own heuristic K is the
+// largest the product allows (big groups) or smaller.
+constexpr int kTuneClasses = 6;
+static uint32_t k_max(const peval_poly *h) { return h->arith == 1 ? 8 : (h->w == 4 && h->arith == 0) ? 32 : 16; }
+static int tune_class(const peval_poly *h, uint32_t K0) {
+  const int prod = h->w == 4 ? 2 : (h->arith == 1 ? 1 : 0);
+  return prod * 2 + (K0 >= k_max(h) ? 1 : 0);
+}
+
+struct BatchChoice {
+  int shift[kTuneClasses] = {0, 0, 0, 0, 0, 0};  // K moved by this many doublings from its own choice
+  double chain_scale = 1.0;                      // work items' target cost, relative to the default
+};
+
+// Members' plans for one choice: K from the tuning cache or the heuristic,
+// moved by the class's shift (within 1 .. the product's largest K), then the
+// chains that give items of similar cost.
+static int plan_members(const std::vector<peval_poly *> &polys, const std::vector<uint32_t> &Ts,
+                        const BatchChoice &ch, std::vector<BatchMember> &mem) {
+  const uint32_t count = (uint32_t)polys.size();
+  mem.assign(count, BatchMember{});
+  for (uint32_t j = 0; j < count; ++j) {
+    peval_poly *h = polys[j];
+    std::lock_guard<std::mutex> lk(h->mu);
+    const uint32_t K0 = choose_tuning(h, Ts[j]).K;
+    uint32_t K = K0;
+    const int sh = ch.shift[tune_class(h, K0)];
+    for (int i = 0; i < sh && K < k_max(h); ++i) K *= 2;
+    for (int i = 0; i > sh && K > 1; --i) K /= 2;
+    Plan *pl = nullptr;
+    PEVAL_TRY(get_plan(h, K, kBatchP, &pl));
+    mem[j] = BatchMember{h, pl, 1, Ts[j]};
+  }
+  return batch_chains(mem, ch.chain_scale);
+}
+
+// Device time of one pass of a planned batch (base points 2, outputs in
+// `outs`), the mean of two passes after one untimed pass.
+static int time_pass(const std::vector<BatchMember> &mem, const std::vector<void *> &outs, hipStream_t st,
+                     float *ms) {
+  BatchCore core;
+  int rc = batch_build(core, mem);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (rc == PEVAL_OK) {
+    std::vector<BatchRun> runs(mem.size());
+    for (size_t j = 0; j < mem.size(); ++j) {
+      memset(&runs[j], 0, sizeof(BatchRun));
+      for (uint32_t k = 0; k + 2 < mem[j].h->n; ++k) runs[j].beta.b[k] = 2;
+      runs[j].t0 = 1;
+      runs[j].out = outs[j];
+    }
+    do {
+      if (hipMemcpy(core.d_run, runs.data(), runs.size() * sizeof(BatchRun), hipMemcpyHostToDevice) != hipSuccess ||
+          hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        rc = fail(PEVAL_EDEVICE, "tuning set-up");
+        break;
+      }
+      if ((rc = batch_enqueue(core, st)) != PEVAL_OK) break;
+      if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(PEVAL_EDEVICE, "event record"); break; }
+      for (int r = 0; r < 2 && rc == PEVAL_OK; ++r) rc = batch_enqueue(core, st);
+      if (rc != PEVAL_OK) break;
+      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(ms, e0, e1) != hipSuccess) {
+        rc = fail(PEVAL_EDEVICE, "tuning timing");
+        break;
+      }
+      *ms /= 2;
+    } while (false);
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipStreamSynchronize(st);
+  batch_release(core);
+  return rc;
+}
+
+// Coordinate search over the classes' K shifts (one doubling either way),
+// then over the items' target cost (half, double): the analogue for a batch
+// of the paper's sweep of its tiling parameters.  Every candidate pass runs
+// on the device into scratch outputs.
+static int tune_batch(const std::vector<peval_poly *> &polys, const std::vector<uint32_t> &Ts, BatchChoice *best,
+                      float *best_ms, uint32_t *trials) {
+  const uint32_t count = (uint32_t)polys.size();
+  std::vector<size_t> off(count + 1, 0);
+  bool present[kTuneClasses] = {};
+  for (uint32_t j = 0; j < count; ++j) {
+    off[j + 1] = off[j] + (((size_t)Ts[j] * polys[j]->G * polys[j]->w + 255) & ~(size_t)255);
+    std::lock_guard<std::mutex> lk(polys[j]->mu);
+    present[tune_class(polys[j], choose_tuning(polys[j], Ts[j]).K)] = true;
+  }
+  void *obuf = nullptr;
+  hipStream_t st = nullptr;
+  HIP_TRY(hipMalloc(&obuf, std::max<size_t>(off[count], 256)));
+  std::vector<void *> outs(count);
+  for (uint32_t j = 0; j < count; ++j) outs[j] = (char *)obuf + off[j];
+  int rc = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess ? PEVAL_OK
+                                                                            : fail(PEVAL_EDEVICE, "stream creation");
+  *trials = 0;
+  auto measure = [&](const BatchChoice &ch, float *ms) {
+    std::vector<BatchMember> mem;
+    int r = plan_members(polys, Ts, ch, mem);
+    if (r == PEVAL_OK) r = time_pass(mem, outs, st, ms);
+    ++*trials;
+    return r;
+  };
+  *best = BatchChoice{};
+  if (rc == PEVAL_OK) rc = measure(*best, best_ms);
+  for (int c = 0; c < kTuneClasses && rc == PEVAL_OK; ++c) {
+    if (!present[c]) continue;
+    for (int d : {-1, 1}) {
+      BatchChoice ch = *best;
+      ch.shift[c] += d;
+      float ms = 0;
+      if ((rc = measure(ch, &ms)) != PEVAL_OK) break;
+      if (ms < *best_ms * 0.99f) {  // a clear gain only: timings vary by about 1%
+        *best = ch;
+        *best_ms = ms;
+      }
+    }
+  }
+  for (double sc : {0.5, 2.0}) {
+    if (rc != PEVAL_OK) break;
+    BatchChoice ch = *best;
+    ch.chain_scale = sc;
+    float ms = 0;
+    if ((rc = measure(ch, &ms)) != PEVAL_OK) break;
+    if (ms < *best_ms * 0.99f) {
+      *best = ch;
+      *best_ms = ms;
+    }
+  }
+  if (st) (void)hipStreamDestroy(st);
+  (void)hipFree(obuf);
+  return rc;
 }
 
 extern "C" int peval_batch_create(uint32_t count, peval_poly *const *polys, const uint32_t *Ts, uint32_t flags,
@@ -312,23 +469,20 @@ extern "C" int peval_batch_create(uint32_t count, peval_poly *const *polys, cons
     return rc;
   };
 
-  // plans (autotuned K where a cached tuning exists; P fixed for batches)
-  std::vector<BatchMember> mem(count);
-  double work = 0;
-  for (uint32_t j = 0; j < count; ++j) {
-    peval_poly *h = polys[j];
-    std::lock_guard<std::mutex> lk(h->mu);
-    Tuning t = choose_tuning(h, Ts[j]);
-    uint32_t K = t.K;
-    Plan *pl = nullptr;
-    int rc = get_plan(h, K, kBatchP, &pl);
-    if (rc != PEVAL_OK) return bail(rc);
-    mem[j] = BatchMember{h, pl, 1, Ts[j]};
-    work += 64.0 * pl->K * pl->NW * Ts[j];
+  // plans: K from the tuning cache or the heuristic (moved by the batch
+  // tuner when asked); P is set by the member's kind and does not change
+  // the layout
+  BatchChoice choice;
+  if (flags & PEVAL_BATCH_TUNE) {
+    float ms = 0;
+    int trc = tune_batch(b->polys, b->Ts, &choice, &ms, &b->tune_trials);
+    if (trc != PEVAL_OK) return bail(trc);
+    b->tuned_ms = ms;
   }
-  const double target = std::max(work / 65536.0, 64.0 * 8 * 64);
-  for (auto &m : mem) m.C = member_chains(*m.plan, m.T, target);
-  int rc = batch_build(b->core, mem);
+  std::vector<BatchMember> mem;
+  int rc = plan_members(b->polys, b->Ts, choice, mem);
+  if (rc != PEVAL_OK) return bail(rc);
+  rc = batch_build(b->core, mem);
   if (rc != PEVAL_OK) return bail(rc);
   for (int k = 0; k < kRunSlots; ++k) {
     if (hipHostMalloc((void **)&b->h_run[k], count * sizeof(BatchRun), hipHostMallocDefault) != hipSuccess)
@@ -407,6 +561,19 @@ extern "C" int peval_batch_info(const peval_batch *b, uint64_t *info) {
   uint64_t te = 0;
   for (uint32_t j = 0; j < b->core.count; ++j) te += b->polys[j]->s * (uint64_t)b->Ts[j];
   info[4] = te;
+  return PEVAL_OK;
+}
+
+extern "C" int peval_batch_members(const peval_batch *b, uint32_t *K, uint32_t *C, uint32_t *kind, float *tuned_ms,
+                                   uint32_t *tune_trials) {
+  if (!b) return fail(PEVAL_EINVAL, "null batch");
+  for (uint32_t j = 0; j < b->core.count; ++j) {
+    if (K) K[j] = b->core.descs[j].K;
+    if (C) C[j] = b->core.descs[j].C;
+    if (kind) kind[j] = b->core.descs[j].kind;
+  }
+  if (tuned_ms) *tuned_ms = b->tuned_ms;
+  if (tune_trials) *tune_trials = b->tune_trials;
   return PEVAL_OK;
 }
 

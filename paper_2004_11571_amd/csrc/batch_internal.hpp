@@ -42,6 +42,9 @@ struct BatchCore {
 
 size_t member_scratch_bytes(const peval_poly *h, const Plan &pl, uint32_t C, uint32_t T);
 uint32_t member_chains(const Plan &pl, uint32_t T, double target_cost);
+uint32_t member_kind(const peval_poly *h, uint32_t K);
+// Chains of every member from its kind's work, items' target cost times scale.
+int batch_chains(std::vector<BatchMember> &mem, double scale);
 size_t batch_scratch_need(const std::vector<BatchMember> &mem);
 // Host planning: descriptors pointing into `arena` (batch_scratch_need bytes),
 // work items in decreasing cost, prefixes, and the blob image (with the run

@@ -1,11 +1,12 @@
 // Batched evaluation of many polynomials in one pass: flattened prologue and
-// combine kernels plus a persistent evaluation kernel that pulls work items
-// (polynomial, wave, chain) from a queue, biggest first.
+// combine kernels plus persistent evaluation kernels, one per kind of member
+// (product, residue width, range of K), each pulling work items
+// (polynomial, wave, chain) from its own queue, biggest first.
 //
 // Each polynomial keeps its own modulus, residue width, thread layout and
 // chains; the per-wave work is exactly eval_wave of the single-polynomial
-// path, selected per item by a wave-uniform switch on (width, K).  The queue
-// counter only decides which wave does an item; every item writes its own
+// path, selected per item by a wave-uniform switch on K.  The queue counter
+// only decides which wave does an item; every item writes its own
 // partial-sum slots, so results never depend on the schedule.
 #pragma once
 
@@ -99,7 +100,7 @@ __global__ void batch_mono_kernel(const BatchDesc *D, const BatchRun *R, uint32_
   else batch_mono_one<W64>(d, R[j].t0, local, d.m64);
 }
 
-template <class A, int K>
+template <class A, int K, int P>
 __device__ __forceinline__ void batch_eval_item(const BatchDesc &d, const BatchItem &it, void *lds, int lane,
                                                 const typename A::M &m) {
   using T = typename A::T;
@@ -117,7 +118,7 @@ __device__ __forceinline__ void batch_eval_item(const BatchDesc &d, const BatchI
   a.T = d.T;
   a.Lmax = d.Lmax;
   a.m = m;
-  eval_wave<A, K, kBatchP>(a, it.wave, it.chain, *reinterpret_cast<Stage<A, kBatchP> *>(lds), lane);
+  eval_wave<A, K, P>(a, it.wave, it.chain, *reinterpret_cast<Stage<A, P> *>(lds), lane);
 }
 
 template <class A>
@@ -129,21 +130,15 @@ __device__ __forceinline__ const Mod64 &member_mod<W64>(const BatchDesc &d) { re
 template <>
 __device__ __forceinline__ const ModF64 &member_mod<WF64>(const BatchDesc &d) { return d.mf; }
 
-template <class A>
-constexpr uint32_t policy_kind() {
-  return std::is_same<A, W32>::value ? kKindW32 : std::is_same<A, WF64>::value ? kKindF64 : kKindW64;
-}
-
-// Persistent evaluation over the work queue of the members of one kind (one
-// kernel per kind, so that each gets the registers and LDS of its own
-// widest variant rather than those of the 64-bit one).  The 64-bit integer
-// kernel runs two waves per SIMD: held to three it spilled some 20
-// registers at item boundaries and measured 1-3% slower.
-template <class A>
-__global__ __launch_bounds__(kEvalBlock, (std::is_same<A, W64>::value ? 2 : (sizeof(typename A::T) == 8 ? 3 : 4)))
-void batch_eval_kernel(
-    const BatchDesc *D, const BatchItem *items, uint32_t n_items, uint32_t *counter) {
-  __shared__ __align__(16) unsigned char stage[kEvalBlock / 64][sizeof(Stage<A, kBatchP>)];
+// Persistent evaluation over the work queue of the members of one kind
+// (policy A, terms per thread KLO..KHI, P evaluations per pass, WAVES
+// waves per SIMD as a register bound).  A wave takes the next item; an item
+// of another kind is never planned into this queue and is skipped rather
+// than misread.
+template <class A, int KLO, int KHI, int P, int WAVES, uint32_t KIND>
+__global__ __launch_bounds__(kEvalBlock, WAVES) void batch_eval_kernel(const BatchDesc *D, const BatchItem *items,
+                                                                       uint32_t n_items, uint32_t *counter) {
+  __shared__ __align__(16) unsigned char stage[kEvalBlock / 64][sizeof(Stage<A, P>)];
   const int lane = threadIdx.x & 63;
   const int warp = threadIdx.x >> 6;
   void *lds = stage[warp];
@@ -154,19 +149,33 @@ void batch_eval_kernel(
     if (next >= n_items) break;  // every wave reaches this once the queue is drained
     const BatchItem it = items[next];
     const BatchDesc &d = D[it.poly];
-    if (d.kind != policy_kind<A>()) continue;  // never planned so; skipped rather than misread
+    if (d.kind != KIND) continue;
     const typename A::M &m = member_mod<A>(d);
     switch (d.K) {
-      case 1: batch_eval_item<A, 1>(d, it, lds, lane, m); break;
-      case 2: batch_eval_item<A, 2>(d, it, lds, lane, m); break;
-      case 4: batch_eval_item<A, 4>(d, it, lds, lane, m); break;
-      case 8: batch_eval_item<A, 8>(d, it, lds, lane, m); break;
-      default:
-        // the FP64 product sums at most 8 doubles exactly: its members are
-        // planned with K <= 8
-        if constexpr (!std::is_same<A, WF64>::value) batch_eval_item<A, 16>(d, it, lds, lane, m);
-        break;
+      case 1: if constexpr (KLO <= 1 && 1 <= KHI) batch_eval_item<A, 1, P>(d, it, lds, lane, m); break;
+      case 2: if constexpr (KLO <= 2 && 2 <= KHI) batch_eval_item<A, 2, P>(d, it, lds, lane, m); break;
+      case 4: if constexpr (KLO <= 4 && 4 <= KHI) batch_eval_item<A, 4, P>(d, it, lds, lane, m); break;
+      case 8: if constexpr (KLO <= 8 && 8 <= KHI) batch_eval_item<A, 8, P>(d, it, lds, lane, m); break;
+      case 16: if constexpr (KLO <= 16 && 16 <= KHI) batch_eval_item<A, 16, P>(d, it, lds, lane, m); break;
+      case 32: if constexpr (KLO <= 32 && 32 <= KHI) batch_eval_item<A, 32, P>(d, it, lds, lane, m); break;
+      default: break;
     }
+  }
+}
+
+// The kernel of each kind.  The FP64 product sums at most 8 doubles exactly,
+// so its members are planned with K <= 8; 32 running values per thread are
+// held for 32-bit residues only.  Waves per SIMD: those of the widest
+// single-polynomial kernel of the range (the 64-bit K = 16 one needs
+// three to issue nearly every cycle).
+using BatchEvalFn = void (*)(const BatchDesc *, const BatchItem *, uint32_t, uint32_t *);
+inline BatchEvalFn batch_eval_fn(uint32_t kind) {
+  switch (kind) {
+    case kKindW64K16: return batch_eval_kernel<W64, 16, 16, kind_P(kKindW64K16), kind_waves(kKindW64K16), kKindW64K16>;
+    case kKindW64Lo: return batch_eval_kernel<W64, 1, 8, kind_P(kKindW64Lo), kind_waves(kKindW64Lo), kKindW64Lo>;
+    case kKindF64: return batch_eval_kernel<WF64, 1, 8, kind_P(kKindF64), kind_waves(kKindF64), kKindF64>;
+    case kKindW32K32: return batch_eval_kernel<W32, 32, 32, kind_P(kKindW32K32), kind_waves(kKindW32K32), kKindW32K32>;
+    default: return batch_eval_kernel<W32, 1, 16, kind_P(kKindW32Lo), kind_waves(kKindW32Lo), kKindW32Lo>;
   }
 }
 

@@ -8,16 +8,30 @@
 
 namespace peval {
 
-constexpr int kBatchP = 16;  // evaluations per pass in batched launches
+constexpr int kBatchP = 16;  // evaluations per pass in batched launches (all kinds but kKindW64Lo)
 
-// Product a member's evaluations take; one work queue and one persistent
-// evaluation kernel per kind.
+// The product a member's evaluations take and the range of its terms per
+// thread K.  Each kind has its own work queue and persistent evaluation
+// kernel, compiled for that K range only, so that it gets the registers
+// (and waves per SIMD) of its own widest member rather than those of the
+// widest of all: one kernel for every 64-bit K held two waves per SIMD,
+// where the K = 16 evaluation alone fits three.
 enum BatchKind : uint32_t {
-  kKindW64 = 0,  // 64-bit residues, Shoup product
-  kKindF64 = 1,  // 64-bit residues, FP64 product (Alg. 2, 2^31 <= p < 2^50)
-  kKindW32 = 2,  // 32-bit residues, Shoup product
-  kKinds = 3
+  kKindW64K16 = 0,  // 64-bit residues, Shoup product, K = 16
+  kKindW64Lo = 1,   // 64-bit residues, Shoup product, K <= 8; 8 evaluations per pass
+  kKindF64 = 2,     // 64-bit residues, FP64 product (Alg. 2, 2^31 <= p < 2^50), K <= 8
+  kKindW32K32 = 3,  // 32-bit residues, K = 32
+  kKindW32Lo = 4,   // 32-bit residues, K <= 16
+  kKinds = 5
 };
+
+// Evaluations per pass of a kind's kernel: the small-K 64-bit kernel stages
+// 8, so that its stage leaves room for more waves per CU.
+__host__ __device__ constexpr int kind_P(uint32_t kind) { return kind == kKindW64Lo ? 8 : kBatchP; }
+// Waves per SIMD a kind's kernel is compiled for (its register bound).
+__host__ __device__ constexpr int kind_waves(uint32_t kind) {
+  return (kind == kKindW64K16 || kind == kKindW32K32) ? 3 : 4;
+}
 
 // Static part of one polynomial in a batch (device table).
 struct BatchDesc {

@@ -144,12 +144,16 @@ __device__ __forceinline__ void monomial_entry(const MonoArgs<A> &a, const uint3
     lam = A::mul_lazy(a.coeff[i], mt, shoup_quot(mt, a.m), a.m);
   }
   a.lam[pos] = out(lam);
+  // Gamma = m_i^C, the multiplier of every chain: for a few chains by the
+  // same products that step the chain starts, else by squaring
+  const bool stepped = a.C <= 16;
+  T g = mi;
   for (uint32_t c = 1; c < a.C; ++c) {
     lam = A::mul_lazy(lam, mi, mq, a.m);
     a.lam[c * NTK + pos] = out(lam);
+    if (stepped) g = A::mul_lazy(g, mi, mq, a.m);
   }
-  // Gamma = m_i^C, the multiplier of every chain
-  T g = (a.C == 1) ? mi : pow_mod(mi, (uint64_t)a.C, a.m);
+  g = stepped ? canon(g, (T)p) : pow_mod(mi, (uint64_t)a.C, a.m);
   a.gam[pos] = out(g);
   a.gamq[pos] = shoup_quot(g, a.m);
 }
@@ -338,7 +342,7 @@ __device__ __forceinline__ void eval_wave(const EvalArgs<A> &a, uint64_t wave, u
 // With P = 32 the stages alone hold a block's LDS to one or two blocks per
 // CU, so a register bound would only cost spills.
 template <class A, int K, int P>
-__global__ __launch_bounds__(kEvalBlock, (P <= 16 ? 3 : 1)) void eval_kernel(EvalArgs<A> a) {
+__global__ __launch_bounds__(kEvalBlock, (P <= 16 ? (K >= 32 ? 2 : 3) : 1)) void eval_kernel(EvalArgs<A> a) {
   __shared__ Stage<A, P> stage[kEvalBlock / 64];
   const int lane = threadIdx.x & 63;
   const int warp = threadIdx.x >> 6;

@@ -218,7 +218,7 @@ extern "C" int peval_layout(const uint64_t *group_sizes, uint64_t G, uint32_t K,
                             uint64_t *sizes, uint32_t *thr_first, uint8_t *thr_cnt,
                             uint64_t *endmask, uint32_t *slot_base, uint32_t *slot_off) {
   if ((G && !group_sizes) || !sizes) return fail(PEVAL_EINVAL, "null argument");
-  if (!(K == 1 || K == 2 || K == 4 || K == 8 || K == 16)) return fail(PEVAL_EINVAL, "K=%u", K);
+  if (!valid_K(K)) return fail(PEVAL_EINVAL, "K=%u", K);
   if (!(P == 8 || P == 16 || P == 32)) return fail(PEVAL_EINVAL, "P=%u", P);
   std::vector<uint64_t> off(G + 1, 0);
   for (uint64_t g = 0; g < G; ++g) {
@@ -559,7 +559,7 @@ extern "C" int peval_groups(const peval_poly *h, uint32_t *d, uint32_t *e) {
 // ---------------------------------------------------------------------------
 namespace peval {
 
-bool valid_K(uint32_t K) { return K == 1 || K == 2 || K == 4 || K == 8 || K == 16; }
+bool valid_K(uint32_t K) { return K == 1 || K == 2 || K == 4 || K == 8 || K == 16 || K == 32; }
 bool valid_P(uint32_t P) { return P == 8 || P == 16 || P == 32; }
 
 uint64_t padded_threads(const peval_poly *h, uint32_t K) {
@@ -576,11 +576,14 @@ uint32_t chains_for_waves(uint64_t nw, uint64_t target_waves, uint32_t T) {
 }
 
 // Heuristic used before any autotuning: the largest K whose zero padding
-// stays under 1/8 of the terms, P = 16, and enough chains for about 8192
+// stays under 1/8 of the terms (up to 32 for 32-bit residues under the
+// Shoup product, 16 otherwise), P = 16, and enough chains for about 8192
 // waves.
 Tuning heuristic_tuning(const peval_poly *h, uint32_t T) {
   Tuning t{1, 16, 1};
-  for (uint32_t cand : {16u, 8u, 4u, 2u}) {
+  const uint32_t kmax = (h->w == 4 && h->arith == 0) ? 32 : 16;
+  for (uint32_t cand : {32u, 16u, 8u, 4u, 2u}) {
+    if (cand > kmax) continue;
     if (padded_threads(h, cand) * cand * 8 <= h->s * 9) {
       t.K = cand;
       break;
@@ -614,6 +617,7 @@ Tuning choose_tuning(const peval_poly *h, uint32_t T) {
   if (h->tune_P) t.P = h->tune_P;
   if (h->tune_C) t.C = h->tune_C;
   if (h->arith == 1) t.K = std::min<uint32_t>(t.K, 8);  // exact double sums of at most 8 residues
+  if (h->w == 8 || h->arith != 0) t.K = std::min<uint32_t>(t.K, 16);  // K = 32: 32-bit Shoup only
   if (T) t.C = std::min<uint32_t>(t.C, T);
   t.C = std::max<uint32_t>(t.C, 1);
   const bool forced = h->tune_K || h->tune_P || h->tune_C;
@@ -625,7 +629,8 @@ Tuning choose_tuning(const peval_poly *h, uint32_t T) {
 
 extern "C" int peval_set_tuning(peval_poly *h, uint32_t K, uint32_t P, uint32_t C) {
   if (!h) return fail(PEVAL_EINVAL, "null handle");
-  if (K && !valid_K(K)) return fail(PEVAL_EINVAL, "K must be 1, 2, 4, 8 or 16");
+  if (K && !valid_K(K)) return fail(PEVAL_EINVAL, "K must be 1, 2, 4, 8, 16 or 32");
+  if (K == 32 && h->w != 4) return fail(PEVAL_EINVAL, "K = 32 needs 32-bit residues (p < 2^31)");
   if (P && !valid_P(P)) return fail(PEVAL_EINVAL, "P must be 8, 16 or 32");
   if (C > 65535) return fail(PEVAL_EINVAL, "C must be <= 65535");
   std::lock_guard<std::mutex> lk(h->mu);
@@ -692,6 +697,10 @@ struct Dispatch {
     PEVAL_CASES_K(4)
     PEVAL_CASES_K(8)
     PEVAL_CASES_K(16)
+    if constexpr (sizeof(typename A::T) == 4) {  // 32 running values of 64 bits would not fit two waves
+      PEVAL_CASE(32, 8)
+      PEVAL_CASE(32, 16)
+    }
 #undef PEVAL_CASES_K
 #undef PEVAL_CASE
     return nullptr;

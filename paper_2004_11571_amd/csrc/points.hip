@@ -292,6 +292,7 @@ Tuning points_tuning(peval_poly *h, uint32_t T) {
   Tuning t = heuristic_tuning(h, T);
   if (h->tune_K) t.K = h->tune_K;
   if (h->arith == 1) t.K = std::min<uint32_t>(t.K, 8);  // FP64 product: exact sums of at most 8 doubles
+  t.K = std::min<uint32_t>(t.K, 16);                    // the point kernels hold at most 16 terms
   t.P = kPointsP;
   const uint64_t nw = (padded_threads(h, t.K) + 63) / 64;
   t.C = h->tune_C ? h->tune_C : chains_for_waves(nw, 8192, T);

@@ -79,7 +79,7 @@ struct Pass {
 };
 
 constexpr int kStreams = 2;
-constexpr int kUploaders = 2;  // threads making polynomials resident (each ingest is multi-threaded itself)
+constexpr int kUploaders = 4;  // threads making polynomials resident (each ingest is multi-threaded itself)
 
 }  // namespace
 
@@ -148,18 +148,18 @@ struct peval_server {
 // residency
 // ---------------------------------------------------------------------------
 static uint64_t estimate_poly_bytes(const SPoly &sp) {
-  // resident terms + one thread layout (K <= 16, P = 16) + tables
+  // resident terms + one thread layout (K <= 32, P = 16) + tables
   uint64_t b = sp.s * (sp.w + 2ull * (sp.n - 2));
   b += (sp.s + 64) * 5 + (sp.s / 64 + 2) * 12 + sp.G * 4;
   return b + 4096;
 }
 
 // Upper bound of the scratch one slice of ts evaluations with at most c
-// chains needs (any K <= 16, P = 16): power tables, chain starts, Gamma,
+// chains needs (any K <= 32, P = 16): power tables, chain starts, Gamma,
 // Gamma', partial sums.  Used for reservations, so that every pass fits.
 static uint64_t slice_scratch_bound(const SPoly &sp, uint32_t ts, uint32_t c) {
   const uint64_t w = sp.w;
-  const uint64_t kn = sp.s + 16 * sp.G + 1024;           // >= K * NT for K <= 16
+  const uint64_t kn = sp.s + 32 * sp.G + 2048;           // >= K * NT for K <= 32
   const uint64_t slots = (sp.s + sp.G) / 16 + 2 * sp.G + 64;  // >= nslots for K >= 1, P = 16
   const uint64_t lmax = ((uint64_t)ts + c - 1) / c;
   uint64_t b = 2 * (std::max<uint64_t>(sp.tab_total, 1) * w + 256);
@@ -465,12 +465,15 @@ static bool launch_pass_impl(peval_server *S, std::unique_lock<std::mutex> &lk) 
   if (S->simulate) {
     ps.t_sim_end = std::max(ps.t_launch, S->inflight.empty() ? 0.0 : S->inflight.back().t_sim_end) + te / S->sim_rate;
   } else {
-    // chains so that work items have similar costs, as in peval_batch_create
-    double work = 0;
-    for (auto &m : mem) work += 64.0 * m.plan->K * m.plan->NW * m.T;
-    const double target = std::max(work / 65536.0, 64.0 * 8 * 64);
-    for (size_t j = 0; j < mem.size(); ++j)
-      mem[j].C = std::min(member_chains(*mem[j].plan, mem[j].T, target), S->reqs[sl[j].rid].cmax);
+    // chains so that work items have similar costs, as in peval_batch_create,
+    // within what each request's scratch reservation allows
+    int crc = batch_chains(mem, 1.0);
+    if (crc != PEVAL_OK) {
+      S->err = crc;
+      S->cv_done.notify_all();
+      return false;
+    }
+    for (size_t j = 0; j < mem.size(); ++j) mem[j].C = std::min(mem[j].C, S->reqs[sl[j].rid].cmax);
     const size_t scratch = batch_scratch_need(mem);
     runs.resize(mem.size());
     for (size_t j = 0; j < mem.size(); ++j) {

@@ -95,12 +95,15 @@ extern "C" int peval_autotune(peval_poly *h, const uint64_t *beta, uint32_t T, u
   std::lock_guard<std::mutex> lk(h->mu);
   PEVAL_TRY(ensure(h->outbuf, (size_t)T * h->G * h->w, h));
 
-  // the FP64 product sums at most 8 doubles per thread exactly: K <= 8
-  const uint32_t kmax = (h->arith == 1) ? 8u : 16u;
+  // the FP64 product sums at most 8 doubles per thread exactly: K <= 8;
+  // 32 terms per thread for 32-bit residues under the Shoup product only,
+  // with at most 16 evaluations per pass
+  const uint32_t kmax = (h->arith == 1) ? 8u : (h->w == 4 && h->arith == 0) ? 32u : 16u;
   std::vector<uint32_t> Ks;
-  for (uint32_t k : {1u, 2u, 4u, 8u, 16u})
+  for (uint32_t k : {1u, 2u, 4u, 8u, 16u, 32u})
     if (k <= kmax && (k == 1 || padded_threads(h, k) * k * 2 <= h->s * 3)) Ks.push_back(k);
   const uint32_t Ps[] = {8, 16, 32};
+  auto has_kernel = [](uint32_t k, uint32_t p) { return k < 32 || p <= 16; };
   const uint64_t targets[] = {2048, 4096, 8192, 16384};
   auto chains = [&](uint32_t k, uint64_t target) {
     uint64_t nw = (padded_threads(h, k) + 63) / 64;
@@ -123,6 +126,7 @@ extern "C" int peval_autotune(peval_poly *h, const uint64_t *beta, uint32_t T, u
   if (exhaustive) {
     for (uint32_t k : Ks)
       for (uint32_t p : Ps) {
+        if (!has_kernel(k, p)) continue;
         std::vector<uint32_t> seen;
         for (uint64_t tg : targets) {
           uint32_t c = chains(k, tg);
@@ -136,7 +140,7 @@ extern "C" int peval_autotune(peval_poly *h, const uint64_t *beta, uint32_t T, u
     for (uint32_t k : Ks) PEVAL_TRY(consider(Tuning{k, t0.P, chains(k, 8192)}));
     Tuning t1 = best;
     for (uint32_t p : Ps)
-      if (p != t1.P) PEVAL_TRY(consider(Tuning{t1.K, p, t1.C}));
+      if (p != t1.P && has_kernel(t1.K, p)) PEVAL_TRY(consider(Tuning{t1.K, p, t1.C}));
     Tuning t2 = best;
     for (uint64_t tg : targets) {
       uint32_t c = chains(t2.K, tg);

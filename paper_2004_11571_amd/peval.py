@@ -93,6 +93,7 @@ def lib() -> ctypes.CDLL:
         "peval_batch_create": ([u32, vp, vp, u32, ctypes.POINTER(vp)], i32),
         "peval_batch_run": ([vp, vp, vp, vp, vp], i32),
         "peval_batch_info": ([vp, vp], i32),
+        "peval_batch_members": ([vp, vp, vp, vp, vp, vp], i32),
         "peval_batch_destroy": ([vp], i32),
         "peval_tune_clear": ([], i32),
         "peval_tune_save": ([ctypes.c_char_p], i32),
@@ -297,12 +298,13 @@ class Poly:
 
 
 BATCH_NO_GRAPH = 1
+BATCH_TUNE = 2
 
 
 class Batch:
     """A planned batched pass over resident polynomials (peval_batch_*)."""
 
-    def __init__(self, polys, Ts, graph: bool = True):
+    def __init__(self, polys, Ts, graph: bool = True, tune: bool = False):
         self.polys = list(polys)
         self.Ts = [int(t) for t in Ts]
         if len(self.polys) != len(self.Ts) or not self.polys:
@@ -310,9 +312,19 @@ class Batch:
         hs = (ctypes.c_void_p * len(self.polys))(*[q.handle.value for q in self.polys])
         ts = np.ascontiguousarray(self.Ts, dtype=np.uint32)
         b = ctypes.c_void_p()
-        _check(lib().peval_batch_create(len(self.polys), hs, ts.ctypes.data, 0 if graph else BATCH_NO_GRAPH,
-                                        ctypes.byref(b)))
+        flags = (0 if graph else BATCH_NO_GRAPH) | (BATCH_TUNE if tune else 0)
+        _check(lib().peval_batch_create(len(self.polys), hs, ts.ctypes.data, flags, ctypes.byref(b)))
         self._b = b
+
+    def members(self) -> dict:
+        """Per member: terms per thread K, chains C and kernel kind; the
+        tuner's pass time (ms) and number of timed candidates (0: untuned)."""
+        n = len(self.polys)
+        K, C, kind = (np.zeros(n, np.uint32) for _ in range(3))
+        ms, trials = ctypes.c_float(), ctypes.c_uint32()
+        _check(lib().peval_batch_members(self._b, K.ctypes.data, C.ctypes.data, kind.ctypes.data,
+                                         ctypes.byref(ms), ctypes.byref(trials)))
+        return {"K": K, "C": C, "kind": kind, "tuned_ms": ms.value, "tune_trials": trials.value}
 
     def info(self) -> dict:
         v = np.zeros(5, np.uint64)

@@ -119,7 +119,7 @@ def _check_layout(sizes, K, P):
     assert so[-1] == len(slots)
 
 
-@pytest.mark.parametrize("K", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("K", [1, 2, 4, 8, 16, 32])
 @pytest.mark.parametrize("P", [8, 16, 32])
 def test_layout_invariants(K, P):
     rng = np.random.default_rng(K * 100 + P)

@@ -154,3 +154,38 @@ def test_batch_runs_pipeline_across_streams(graph):
     finally:
         for q in polys:
             q.destroy()
+
+
+def test_batch_tuned_tiles_equal_plain_runs():
+    """A batch whose tiles were tuned on the device (members' K moved per
+    class, items resized) gives every member's plain-run images; the members'
+    reported K and kernel kinds are consistent with their moduli."""
+    import torch
+    moduli = (W.P31, W.P63, W.P50)
+    ws = W.uneven_batch(count=30, instance=7, s_max=2e5, t_log2=(3, 9), moduli=moduli)
+    polys = [PV.Poly(w.p, w.exps, w.coeffs) for w in ws]
+    Ts = [w.T for w in ws]
+    _say("tuned batch members", [(q.s, q.G, T, q.elem_bytes) for q, T in zip(polys, Ts)])
+    try:
+        with PV.Batch(polys, Ts, graph=True, tune=True) as b:
+            mi = b.members()
+            _say("members", mi)
+            assert mi["tune_trials"] >= 3 and mi["tuned_ms"] > 0
+            for q, w, k, kd in zip(polys, ws, mi["K"], mi["kind"]):
+                assert k in (1, 2, 4, 8, 16, 32)
+                if q.elem_bytes == 4:
+                    assert kd in (3, 4) and (kd == 3) == (k == 32)
+                elif w.p == W.P50:
+                    assert kd == 2 and k <= 8
+                else:
+                    assert kd in (0, 1) and (kd == 0) == (k == 16)
+            outs = _outs(polys, Ts)
+            for rep in range(2):
+                betas = [np.asarray((w.beta.astype(object) * (rep + 2)) % w.p, np.uint64) for w in ws]
+                b.run(betas, outs, stream=torch.cuda.current_stream())
+                torch.cuda.synchronize()
+                for q, w, beta, o in zip(polys, ws, betas, outs):
+                    assert np.array_equal(_host(q, o), q.run(beta, w.T)), (rep, w.name)
+    finally:
+        for q in polys:
+            q.destroy()

@@ -81,9 +81,8 @@ def test_random_polys(orc, p, n):
     check(orc, p, poly.exps, poly.coeffs, poly.beta, poly.T)
 
 
-@pytest.mark.parametrize("p", [W.P31, W.P63])
-@pytest.mark.parametrize("K", [1, 2, 4, 8, 16])
-@pytest.mark.parametrize("P", [8, 16, 32])
+@pytest.mark.parametrize("p,K,P", [(p, K, P) for p in (W.P31, W.P63) for K in (1, 2, 4, 8, 16) for P in (8, 16, 32)] +
+                         [(W.P31, 32, 8), (W.P31, 32, 16)])   # 32 terms per thread: 32-bit residues, P <= 16
 def test_tuning_grid(orc, p, K, P):
     rng = np.random.default_rng(K * 31 + P)
     # a few big groups (span several waves), many small ones, a ragged tail
