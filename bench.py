@@ -128,13 +128,21 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def kernel_source_sha(sources=None, extra=()) -> str:
-    """Hash of the evaluation kernels' code: comments and whitespace are
-    dropped, so that only a change of the compiled code invalidates the
-    counter profiles taken on it.  extra: further headers of the kernel
-    (the single-launch kernel's own)."""
+# Headers each profiled kernel is compiled from.
+KERNEL_SOURCES = {
+    "eval_kernel": ("kernels.hpp", "modarith.hpp"),
+    "small_run_kernel": ("kernels.hpp", "modarith.hpp", "small_kernels.hpp"),
+    "points_eval_kernel": ("kernels.hpp", "modarith.hpp", "points_kernels.hpp"),
+    "batch_pass": ("kernels.hpp", "modarith.hpp", "batch_kernels.hpp", "batch_types.hpp"),
+}
+
+
+def kernel_source_sha(kernel: str = "eval_kernel", sources=None) -> str:
+    """Hash of one kernel's code (the headers it is compiled from):
+    comments and whitespace are dropped, so that only a change of the
+    compiled code invalidates the counter profiles taken on it."""
     h = hashlib.sha256()
-    for f in ("kernels.hpp", "modarith.hpp", "points_kernels.hpp", *extra):
+    for f in KERNEL_SOURCES[kernel]:
         text = sources[f] if sources else open(os.path.join(ROOT, "paper_2004_11571_amd", "csrc", f)).read()
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
         text = re.sub(r"//[^\n]*", " ", text)
@@ -376,7 +384,9 @@ def batch_main(args):
         "tiles": {"tuned": not args.no_batch_tune, "tune_trials": mi["tune_trials"], "tuned_pass_ms": mi["tuned_ms"],
                   "create_and_tune_s": tune_s, "by_kernel": tiles},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                     "unit": "Tops/s (int32 lane-ops)", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+                     "unit": "Tops/s (int32 lane-ops)", "frac": achieved / VALU_PEAK_OPS,
+                     "traffic": profile_traffic(kernel_source_sha("batch_pass"), f"batch{len(ws)}_uneven", "batch_pass"),
+                     "kernel_source_sha256": kernel_source_sha("batch_pass"),
                      "kernel": "whole batched pass (graph replay), all kernels",
                      "frac_at_median_step": ops / (spread["median"] / 1e3) / VALU_PEAK_OPS},
         "step_ms_spread": spread,
@@ -839,7 +849,7 @@ def main():
         ops = ALGO_OPS["fp64" if arith == "fp64" else poly.elem_bytes]
         kname = "small_run_kernel" if single else "eval_kernel"
     achieved = ops * te_per_launch / eval_avg_s
-    sha = kernel_source_sha(extra=("small_kernels.hpp",) if single else ())
+    sha = kernel_source_sha(kname)
     traffic = profile_traffic(sha, args.workload, kname)
     # algorithmic HBM bytes of one step: the resident term data read once
     # (coefficient and n-2 16-bit exponents per term) and the images written
