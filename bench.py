@@ -91,6 +91,8 @@ def parse():
     ap.add_argument("--batch-smax", type=float, default=1e6)
     ap.add_argument("--no-batch-tune", action="store_true", help="batch: heuristic tiles, no tuning at create")
     ap.add_argument("--tuning", default="", help="K,P,C override")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="power mode: the heuristic's K, P, C instead of timing candidates first")
     ap.add_argument("--arith", default="auto", choices=["auto", "int", "fp64", "pm"],
                     help="modular product of the evaluation kernel (fp64: the paper's Alg. 2, p < 2^50)")
     ap.add_argument("--cpu-rows", type=int, default=0,
@@ -746,8 +748,18 @@ def main():
     poly = PV.Poly(w.p, w.exps, w.coeffs)
     create_s = time.time() - t_gen
     poly.set_arith(args.arith)
+    tuned = None
     if args.tuning:
         poly.set_tuning(*[int(x) for x in args.tuning.split(",")])
+    elif not args.no_autotune and not points_mode:
+        # the evaluation kernel's K, P and C timed on the device for this
+        # polynomial before anything is timed (the tuning cache then serves
+        # every run of this shape)
+        heur = poly.get_tuning(w.T)
+        t_tune = time.time()
+        tk, tp, tc, tms = poly.autotune(w.beta, w.T)
+        tuned = {"K": tk, "P": tp, "C": tc, "tuned_run_ms": tms, "tune_s": time.time() - t_tune,
+                 "heuristic": dict(zip("KPC", heur))}
     K, P, C = poly.get_tuning(w.T)
     single = (K, P, C) == (0, 0, 0) and not points_mode  # one kernel for the whole run
     dt = torch.int64 if poly.elem_bytes == 8 else torch.int32
@@ -887,6 +899,8 @@ def main():
         "config": {"workload": w.name + ("_random_points" if points_mode else ""), "n": w.n, "s": w.s,
                    "T": w.T, "p": w.p, "G": poly.G,
                    "tuning": "single_launch" if single else {"K": K, "P": 8 if points_mode else P, "C": C},
+                   "tuning_source": "explicit" if args.tuning else ("autotuned" if tuned else "heuristic"),
+                   "autotune": tuned,
                    "arith": arith,
                    "points": "uniform random in [1,p)^(n-2)" if points_mode else "powers of one base point"},
         "roofline": roof,

@@ -278,7 +278,8 @@ int peval_get_tuning(peval_poly *h, uint32_t T, uint32_t *K, uint32_t *P, uint32
  * shape class (residue width, term count, mean group size and T, each on a
  * half-octave grid) in a process-wide cache that every later run of a
  * matching shape uses (explicit peval_set_tuning values take precedence).
- * exhaustive = 0: coordinate search over K, then P, then C (about a dozen
+ * exhaustive = 0: the heuristic's own choice, then a coordinate search
+ * over K, then P, then C (chains for 2048 .. 65536 waves; about fifteen
  * timed runs); 1: the full grid.  Where the run fits the single-launch path
  * (with the product on AUTO) that path is timed too.  Outputs (any may be
  * NULL): the chosen K, P, C (all 0 if the single-launch path won) and its

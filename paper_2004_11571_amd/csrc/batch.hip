@@ -66,6 +66,10 @@ uint32_t member_kind(const peval_poly *h, uint32_t K) {
 
 // Bytes of device scratch one member needs (power tables, chain starts,
 // Gamma, Gamma', partial sums).
+// A member whose groups all fit in one thread's K terms (thread j holds
+// group j) has its images written by the evaluation kernel.
+static bool member_direct(const peval_poly *h, const Plan &pl) { return (uint64_t)pl.K >= h->max_group; }
+
 size_t member_scratch_bytes(const peval_poly *h, const Plan &pl, uint32_t C, uint32_t T) {
   const size_t w = h->w;
   size_t b = 0;
@@ -73,7 +77,7 @@ size_t member_scratch_bytes(const peval_poly *h, const Plan &pl, uint32_t C, uin
   b += align_up((size_t)C * pl.K * pl.NT * w, 256);
   b += align_up((size_t)pl.K * pl.NT * w, 256) * 2;
   const size_t lmax = ((size_t)T + C - 1) / C;
-  b += align_up((size_t)C * lmax * pl.nslots * w, 256);
+  if (!member_direct(h, pl)) b += align_up((size_t)C * lmax * pl.nslots * w, 256);
   return b;
 }
 
@@ -161,14 +165,17 @@ void batch_plan(BatchCore &b, const std::vector<BatchMember> &mem, void *arena, 
     d.endmask = pl.d_endmask;
     d.slot_base = pl.d_slot_base;
     d.slot_off = pl.d_slot_off;
+    d.direct = member_direct(h, pl) ? 1 : 0;
     d.lam = take((size_t)d.C * pl.K * pl.NT * w);
     d.gam = take((size_t)pl.K * pl.NT * w);
     d.gamq = take((size_t)pl.K * pl.NT * w);
-    d.partial = take((size_t)d.C * d.Lmax * pl.nslots * w);
+    d.partial = d.direct ? nullptr : take((size_t)d.C * d.Lmax * pl.nslots * w);
     ptab[j + 1] = ptab[j] + (d.ntail ? h->tab_total : 0);
     pmono[j + 1] = pmono[j] + (uint64_t)pl.K * pl.NT;
-    pout[j + 1] = pout[j] + ((h->G + kCombineTile - 1) / kCombineTile) * d.C *
-                               (((uint64_t)d.Lmax + kCombineTile - 1) / kCombineTile);
+    // combine tiles; none for a direct member
+    pout[j + 1] = pout[j] + (d.direct ? 0
+                                      : ((h->G + kCombineTile - 1) / kCombineTile) * d.C *
+                                            (((uint64_t)d.Lmax + kCombineTile - 1) / kCombineTile));
   }
   // Work items, biggest first.  An item costs K x (evaluations of its chain);
   // within one member the chains differ by at most one evaluation, so
@@ -259,7 +266,7 @@ int batch_enqueue(const BatchCore &b, hipStream_t st) {
     if (!n) continue;
     const BatchItem *it = b.d_items + first;
     uint32_t *ctr = b.d_counter + kind;
-    batch_eval_fn(kind)<<<b.eval_blocks[kind], kEvalBlock, 0, st>>>(b.d_desc, it, n, ctr);
+    batch_eval_fn(kind)<<<b.eval_blocks[kind], kEvalBlock, 0, st>>>(b.d_desc, b.d_run, it, n, ctr);
     HIP_TRY(hipGetLastError());
   }
   if (b.out_total) {  // out_total counts combine tiles

@@ -101,8 +101,8 @@ __global__ void batch_mono_kernel(const BatchDesc *D, const BatchRun *R, uint32_
 }
 
 template <class A, int K, int P>
-__device__ __forceinline__ void batch_eval_item(const BatchDesc &d, const BatchItem &it, void *lds, int lane,
-                                                const typename A::M &m) {
+__device__ __forceinline__ void batch_eval_item(const BatchDesc &d, const BatchItem &it, void *out, void *lds,
+                                                int lane, const typename A::M &m) {
   using T = typename A::T;
   EvalArgs<A> a;
   a.lam = (const T *)d.lam;
@@ -118,6 +118,9 @@ __device__ __forceinline__ void batch_eval_item(const BatchDesc &d, const BatchI
   a.T = d.T;
   a.Lmax = d.Lmax;
   a.m = m;
+  a.direct = d.direct;
+  a.G = d.G;
+  a.out = (typename A::PT *)out;
   eval_wave<A, K, P>(a, it.wave, it.chain, *reinterpret_cast<Stage<A, P> *>(lds), lane);
 }
 
@@ -136,8 +139,9 @@ __device__ __forceinline__ const ModF64 &member_mod<WF64>(const BatchDesc &d) { 
 // of another kind is never planned into this queue and is skipped rather
 // than misread.
 template <class A, int KLO, int KHI, int P, int WAVES, uint32_t KIND>
-__global__ __launch_bounds__(kEvalBlock, WAVES) void batch_eval_kernel(const BatchDesc *D, const BatchItem *items,
-                                                                       uint32_t n_items, uint32_t *counter) {
+__global__ __launch_bounds__(kEvalBlock, WAVES) void batch_eval_kernel(const BatchDesc *D, const BatchRun *R,
+                                                                       const BatchItem *items, uint32_t n_items,
+                                                                       uint32_t *counter) {
   __shared__ __align__(16) unsigned char stage[kEvalBlock / 64][sizeof(Stage<A, P>)];
   const int lane = threadIdx.x & 63;
   const int warp = threadIdx.x >> 6;
@@ -151,13 +155,14 @@ __global__ __launch_bounds__(kEvalBlock, WAVES) void batch_eval_kernel(const Bat
     const BatchDesc &d = D[it.poly];
     if (d.kind != KIND) continue;
     const typename A::M &m = member_mod<A>(d);
+    void *out = R[it.poly].out;
     switch (d.K) {
-      case 1: if constexpr (KLO <= 1 && 1 <= KHI) batch_eval_item<A, 1, P>(d, it, lds, lane, m); break;
-      case 2: if constexpr (KLO <= 2 && 2 <= KHI) batch_eval_item<A, 2, P>(d, it, lds, lane, m); break;
-      case 4: if constexpr (KLO <= 4 && 4 <= KHI) batch_eval_item<A, 4, P>(d, it, lds, lane, m); break;
-      case 8: if constexpr (KLO <= 8 && 8 <= KHI) batch_eval_item<A, 8, P>(d, it, lds, lane, m); break;
-      case 16: if constexpr (KLO <= 16 && 16 <= KHI) batch_eval_item<A, 16, P>(d, it, lds, lane, m); break;
-      case 32: if constexpr (KLO <= 32 && 32 <= KHI) batch_eval_item<A, 32, P>(d, it, lds, lane, m); break;
+      case 1: if constexpr (KLO <= 1 && 1 <= KHI) batch_eval_item<A, 1, P>(d, it, out, lds, lane, m); break;
+      case 2: if constexpr (KLO <= 2 && 2 <= KHI) batch_eval_item<A, 2, P>(d, it, out, lds, lane, m); break;
+      case 4: if constexpr (KLO <= 4 && 4 <= KHI) batch_eval_item<A, 4, P>(d, it, out, lds, lane, m); break;
+      case 8: if constexpr (KLO <= 8 && 8 <= KHI) batch_eval_item<A, 8, P>(d, it, out, lds, lane, m); break;
+      case 16: if constexpr (KLO <= 16 && 16 <= KHI) batch_eval_item<A, 16, P>(d, it, out, lds, lane, m); break;
+      case 32: if constexpr (KLO <= 32 && 32 <= KHI) batch_eval_item<A, 32, P>(d, it, out, lds, lane, m); break;
       default: break;
     }
   }
@@ -168,7 +173,7 @@ __global__ __launch_bounds__(kEvalBlock, WAVES) void batch_eval_kernel(const Bat
 // held for 32-bit residues only.  Waves per SIMD: those of the widest
 // single-polynomial kernel of the range (the 64-bit K = 16 one needs
 // three to issue nearly every cycle).
-using BatchEvalFn = void (*)(const BatchDesc *, const BatchItem *, uint32_t, uint32_t *);
+using BatchEvalFn = void (*)(const BatchDesc *, const BatchRun *, const BatchItem *, uint32_t, uint32_t *);
 inline BatchEvalFn batch_eval_fn(uint32_t kind) {
   switch (kind) {
     case kKindW64K16: return batch_eval_kernel<W64, 16, 16, kind_P(kKindW64K16), kind_waves(kKindW64K16), kKindW64K16>;

@@ -36,7 +36,8 @@ __host__ __device__ constexpr int kind_waves(uint32_t kind) {
 // Static part of one polynomial in a batch (device table).
 struct BatchDesc {
   uint32_t w, ntail, K, C, T, Lmax;
-  uint32_t kind, pad;
+  uint32_t kind;
+  uint32_t direct;  // every group within one thread's K terms: images written by the evaluation kernel
   uint64_t s, NT, NW, nslots, G;
   Mod64 m64;
   Mod32 m32;

@@ -22,6 +22,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "modarith.hpp"
 
 namespace peval {
@@ -182,6 +184,11 @@ struct EvalArgs {
   uint32_t C, T;                // chains, evaluations in this launch
   uint32_t Lmax;                // ceil(T / C): evaluations of the longest chain
   typename A::M m;
+  // direct layout (every group within one thread's K terms, so thread j
+  // holds exactly group j): images straight to out, no partial sums
+  uint32_t direct;
+  uint64_t G;
+  typename A::PT *out;          // [T][G] of this launch (direct layout)
 };
 
 // LDS staging of one wave's per-thread sums: [lane][point] with one pad column.
@@ -297,6 +304,24 @@ __device__ __forceinline__ void segmented_walk(Stage<A, P> &st, int lane, int np
   }
 }
 
+// A thread's whole group as a canonical coefficient (direct layout).  Few
+// 64-bit values are made canonical and added modulo p (about 7 ops each);
+// more, and every other product, go through the lazy sum and one reduction.
+template <class A, int K>
+__device__ __forceinline__ typename A::PT group_value(const typename A::T (&lam)[K], const typename A::M &m) {
+  if constexpr (std::is_same<A, W64>::value && K <= 4) {
+    uint64_t v = canon(lam[0], m.p);
+#pragma unroll
+    for (int k = 1; k < K; ++k) v = add_mod(v, canon(lam[k], m.p), m.p);
+    return v;
+  } else {
+    typename A::Sum acc = A::sum_zero();
+#pragma unroll
+    for (int k = 0; k < K; ++k) A::sum_add(acc, lam[k]);
+    return A::reduce(A::stage(acc, m), m);
+  }
+}
+
 // One wave's share of the evaluations: threads wave*64 .. wave*64+63, chain c.
 template <class A, int K, int P>
 __device__ __forceinline__ void eval_wave(const EvalArgs<A> &a, uint64_t wave, uint32_t c, Stage<A, P> &st,
@@ -313,9 +338,23 @@ __device__ __forceinline__ void eval_wave(const EvalArgs<A> &a, uint64_t wave, u
     g[k] = a.gam[(uint64_t)k * a.NT + j];
     gq[k] = a.gamq[(uint64_t)k * a.NT + j];
   }
+  const uint32_t L = (c < a.T) ? (a.T - 1 - c) / a.C + 1 : 0;  // evaluations of chain c
+
+  if (a.direct) {  // wave-uniform: thread j's sum is the coefficient of group j
+    const bool live = j < a.G;
+    typename A::PT *col = a.out + (uint64_t)c * a.G + j;
+    const uint64_t row_stride = (uint64_t)a.C * a.G;
+#pragma unroll 1
+    for (uint32_t i = 0; i < L; ++i) {
+      const typename A::PT v = group_value<A, K>(lam, a.m);
+#pragma unroll
+      for (int k = 0; k < K; ++k) lam[k] = A::mul_lazy(lam[k], g[k], gq[k], a.m);
+      if (live) col[(uint64_t)i * row_stride] = v;  // neighbouring lanes: neighbouring groups
+    }
+    return;
+  }
   const uint64_t emask = a.endmask[wave];
   const uint32_t sbase = a.slot_base[wave];
-  const uint32_t L = (c < a.T) ? (a.T - 1 - c) / a.C + 1 : 0;  // evaluations of chain c
 
   for (uint32_t i0 = 0; i0 < L; i0 += P) {
     const int np = (L - i0 < (uint32_t)P) ? (int)(L - i0) : P;

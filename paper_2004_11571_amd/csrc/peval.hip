@@ -575,13 +575,24 @@ uint32_t chains_for_waves(uint64_t nw, uint64_t target_waves, uint32_t T) {
   return (uint32_t)std::max<uint64_t>(c, 1);
 }
 
+static uint64_t eval_block_slots(const peval_poly *h, uint32_t K, uint32_t P);
+
 // Heuristic used before any autotuning: the largest K whose zero padding
 // stays under 1/8 of the terms (up to 32 for 32-bit residues under the
-// Shoup product, 16 otherwise), P = 16, and enough chains for about 8192
-// waves.
+// Shoup product, 8 under the FP64 product, 16 otherwise), P = 16, and
+// enough chains for about 8192 waves; then up to four times as many chains
+// (at least 8) where that fills the last round of blocks on the chip better
+// than the extra chains cost.  Every wave of a run does the same work, so the blocks
+// run in rounds of as many as the chip holds: 1e7 terms with K = 16 are 2442
+// blocks per chain, 3.2 rounds of the 768 that fit, and the last round left
+// four fifths of the chip idle (measured: 1 chain 18.7-18.8 ms, 5 chains
+// 17.2 ms).  The model: evaluation time at the chip's rate times
+// 1 + (idle share of the rounds) / 2 (the last round's waves run faster,
+// having their SIMDs to fewer), plus per chain its chain starts written and
+// read back (2 w bytes per term at about 4 TB/s).
 Tuning heuristic_tuning(const peval_poly *h, uint32_t T) {
   Tuning t{1, 16, 1};
-  const uint32_t kmax = (h->w == 4 && h->arith == 0) ? 32 : 16;
+  const uint32_t kmax = h->arith == 1 ? 8 : (h->w == 4 && h->arith == 0) ? 32 : 16;
   for (uint32_t cand : {32u, 16u, 8u, 4u, 2u}) {
     if (cand > kmax) continue;
     if (padded_threads(h, cand) * cand * 8 <= h->s * 9) {
@@ -589,8 +600,32 @@ Tuning heuristic_tuning(const peval_poly *h, uint32_t T) {
       break;
     }
   }
+  // Small groups: a K that holds every group in one thread (the images come
+  // straight from the evaluation kernel, no segmented sums, partial sums or
+  // combine) is worth up to three times the terms in zero padding.
+  uint32_t kd = 1;
+  while (kd < h->max_group && kd < kmax) kd *= 2;
+  if (kd > t.K && kd >= h->max_group && (double)kd * h->G <= 3.0 * (double)h->s) t.K = kd;
   uint64_t nw = (padded_threads(h, t.K) + 63) / 64;
   t.C = chains_for_waves(nw, 8192, T);
+  const uint64_t slots = eval_block_slots(h, t.K, t.P);
+  if (slots && T) {
+    const double per_chain = (double)((nw + 3) / 4);  // blocks of one chain
+    const double terms = (double)nw * 64 * t.K;       // padded
+    const double ops = h->arith == 1 ? 7 : (h->w == 4 ? 4 : 14);
+    const double eval_s = terms * T * ops / 3.0e13, chain_s = terms * 2.0 * h->w / 4.0e12;
+    auto cost = [&](uint32_t c) {
+      const double r = c * per_chain / (double)slots;  // rounds of blocks
+      return eval_s * (1.0 + 0.5 * (std::ceil(r) - r) / r) + c * chain_s;
+    };
+    double best = cost(t.C);
+    const uint32_t c0 = t.C, cmax = std::min<uint32_t>(std::min<uint32_t>(std::max<uint32_t>(4 * c0, 8), 64), T);
+    for (uint32_t c = c0 + 1; c <= cmax; ++c)
+      if (cost(c) < best) {
+        best = cost(c);
+        t.C = c;
+      }
+  }
   return t;
 }
 
@@ -748,6 +783,36 @@ struct Dispatch<W32PM> {
   static void (*eval(uint32_t K, uint32_t))(EvalArgs<W32PM>) { return DispatchPM<W32PM>::eval(K); }
 };
 
+// Blocks of the evaluation kernel for (K, P) and the handle's product that
+// the device holds at once (0 if unknown); queried once per variant.
+namespace peval {
+static uint64_t eval_block_slots(const peval_poly *h, uint32_t K, uint32_t P) {
+  static std::mutex mu;
+  static std::map<uint32_t, uint64_t> cache;
+  const uint32_t key = (uint32_t)h->w << 24 | h->arith << 16 | K << 8 | P;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  const void *fn = nullptr;
+  if (h->w == 4)
+    fn = h->arith == 2 ? (const void *)Dispatch<W32PM>::eval(K, 16) : (const void *)Dispatch<W32>::eval(K, P);
+  else
+    fn = h->arith == 1   ? (const void *)Dispatch<WF64>::eval(K, P)
+         : h->arith == 2 ? (const void *)Dispatch<W64PM>::eval(K, 16)
+                         : (const void *)Dispatch<W64>::eval(K, P);
+  int dev = 0, per_cu = 0;
+  hipDeviceProp_t prop;
+  uint64_t slots = 0;
+  if (fn && hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kEvalBlock, 0) == hipSuccess)
+    slots = (uint64_t)per_cu * prop.multiProcessorCount;
+  else
+    (void)hipGetLastError();
+  cache[key] = slots;
+  return slots;
+}
+}  // namespace peval
+
 template <class A>
 static const typename A::M &mod_of(const peval_poly *h);
 template <>
@@ -789,10 +854,13 @@ static int run_impl(peval_poly *h, const BetaArg &beta, uint64_t t0, uint32_t T,
   auto eval = Dispatch<E>::eval(K, P);
   if (!eval) return fail(PEVAL_EINVAL, "no kernel for K=%u P=%u", K, P);
 
+  // Every group within one thread's K terms: the evaluation kernel writes
+  // the images itself (no partial sums, no combine).
+  const bool direct = (uint64_t)K >= h->max_group;
   // T is processed in chunks so that the partial sums stay within budget
   const size_t tab_bytes = (size_t)std::max<uint32_t>(h->tab_total, 1) * w;
   const size_t chain_bytes = (size_t)K * pl->NT * w;  // chain starts of one chain; also Gamma, Gamma'
-  const size_t row_bytes = (size_t)pl->nslots * w;    // partial sums of one evaluation
+  const size_t row_bytes = direct ? 1 : (size_t)pl->nslots * w;  // partial sums of one evaluation
   uint64_t tc = std::max<uint64_t>(1, kPartialBudget / std::max<size_t>(1, row_bytes));
   void *tabval, *tabquot, *lam, *gam, *gamq, *partial;
   uint64_t fit_rows = 0;  // rows of partial sums that fit the caller's region
@@ -895,12 +963,15 @@ static int run_impl(peval_poly *h, const BetaArg &beta, uint64_t t0, uint32_t T,
       ea.T = Tc;
       ea.Lmax = (Tc + Cc - 1) / Cc;
       ea.m = mod_of<E>(h);
+      ea.direct = direct ? 1 : 0;
+      ea.G = h->G;
+      ea.out = (typename E::PT *)dev_out + done * h->G;
       dim3 grid((unsigned)((pl->NW + 3) / 4), Cc);
       ProfScope ps(st, 2);
       eval<<<grid, kEvalBlock, 0, st>>>(ea);
       HIP_TRY(hipGetLastError());
     }
-    {  // A7: combine
+    if (!direct) {  // A7: combine
       CombineArgs<A> ca;
       ca.partial = (const T_ *)partial;
       ca.slot_off = pl->d_slot_off;

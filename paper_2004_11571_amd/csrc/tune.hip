@@ -104,7 +104,10 @@ extern "C" int peval_autotune(peval_poly *h, const uint64_t *beta, uint32_t T, u
     if (k <= kmax && (k == 1 || padded_threads(h, k) * k * 2 <= h->s * 3)) Ks.push_back(k);
   const uint32_t Ps[] = {8, 16, 32};
   auto has_kernel = [](uint32_t k, uint32_t p) { return k < 32 || p <= 16; };
-  const uint64_t targets[] = {2048, 4096, 8192, 16384};
+  // chain counts for about this many waves (the chip holds 3072-4096 of
+  // the evaluation kernel at once, so the larger ones fill the last round
+  // of a large run better)
+  const uint64_t targets[] = {2048, 4096, 8192, 16384, 32768, 65536};
   auto chains = [&](uint32_t k, uint64_t target) {
     uint64_t nw = (padded_threads(h, k) + 63) / 64;
     return chains_for_waves(nw, target, T);
@@ -112,6 +115,7 @@ extern "C" int peval_autotune(peval_poly *h, const uint64_t *beta, uint32_t T, u
 
   Tuning best = heuristic_tuning(h, T);
   best.K = std::min(best.K, kmax);
+  const Tuning heur = best;
   float best_ms = 1e30f;
   auto consider = [&](Tuning t) -> int {
     float m = 0;
@@ -135,16 +139,20 @@ extern "C" int peval_autotune(peval_poly *h, const uint64_t *beta, uint32_t T, u
           PEVAL_TRY(consider(Tuning{k, p, c}));
         }
       }
-  } else {  // coordinate search: K, then P, then C
+  } else {  // coordinate search from the heuristic's choice: K, then P, then C
+    PEVAL_TRY(consider(heur));
     Tuning t0 = best;
     for (uint32_t k : Ks) PEVAL_TRY(consider(Tuning{k, t0.P, chains(k, 8192)}));
     Tuning t1 = best;
     for (uint32_t p : Ps)
       if (p != t1.P && has_kernel(t1.K, p)) PEVAL_TRY(consider(Tuning{t1.K, p, t1.C}));
     Tuning t2 = best;
+    std::vector<uint32_t> tried{t2.C};
     for (uint64_t tg : targets) {
       uint32_t c = chains(t2.K, tg);
-      if (c != t2.C) PEVAL_TRY(consider(Tuning{t2.K, t2.P, c}));
+      if (std::find(tried.begin(), tried.end(), c) != tried.end()) continue;
+      tried.push_back(c);
+      PEVAL_TRY(consider(Tuning{t2.K, t2.P, c}));
     }
   }
   // the single-launch path, where the run fits it

@@ -488,3 +488,34 @@ def test_batch_full_size_sampled(orc):
     finally:
         for q in polys:
             q.destroy()
+
+
+@pytest.mark.parametrize("p", [W.P31, W.P63, W.P50, P_SMALL_W8])
+@pytest.mark.parametrize("K", [1, 2, 4, 8, 16])
+def test_direct_layout(orc, p, K):
+    """Every group within one thread's K terms: the evaluation kernel writes
+    the images itself (no segmented sums, partial sums or combine).  Group
+    sizes 1..K, several chains, a ragged T, a start past t = 1."""
+    if p == W.P50 and K > 8:
+        pytest.skip("the FP64 product holds at most 8 terms per thread")
+    rng = np.random.default_rng(K * 13 + p % 101)
+    G = 700
+    sizes = rng.integers(1, K + 1, size=G)
+    sizes[0] = K
+    rows = []
+    for g, m in enumerate(sizes):
+        d, e = divmod(g, 40)
+        for i in range(m):
+            rows.append([d, e, i, (7 * i + g) % 5, i % 3])
+    exps = np.asarray(rows, np.uint32)
+    coeffs = rng.integers(0, p, size=exps.shape[0], dtype=np.uint64)
+    coeffs[:5] = p - 1
+    beta = rng.integers(1, p, size=3, dtype=np.uint64)
+    for C, T, t0 in ((1, 37, 1), (5, 61, 1), (3, 29, 1000003)):
+        with PV.Poly(p, exps, coeffs) as poly:
+            if p == W.P50:
+                poly.set_arith("fp64")
+            poly.set_tuning(K, 16, C)
+            got = _run(poly, beta, T, t0)
+        want = orc.evaluate(p, exps, coeffs, beta, T, t0=t0, threads=8)
+        assert np.array_equal(got.astype(np.uint64), want), (p, K, C, T, t0)
