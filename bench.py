@@ -105,9 +105,11 @@ def parse():
     return ap.parse_args()
 
 
-def profile_traffic(kernel_sha: str, workload: str, kernel: str = "eval_kernel"):
+def profile_traffic(kernel_sha: str, workload: str, kernel: str = "eval_kernel", tuning=None):
     """HBM bytes per launch of the evaluation kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    rocprofv3 counter summary, if it was taken on the current kernel source
+    and (when the summary names one) with the run's own tiles: the chain
+    count changes what the kernel re-reads."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_counters.md")
     if not os.path.exists(path):
         return None
@@ -115,6 +117,9 @@ def profile_traffic(kernel_sha: str, workload: str, kernel: str = "eval_kernel")
     m_sha = re.search(r"kernel_source_sha256:\s*([0-9a-f]+)", text)
     m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
     if not m_sha or not m_b or m_sha.group(1) != kernel_sha:
+        return None
+    m_t = re.search(r"counted_tuning:\s*K=(\d+) P=(\d+) C=(\d+)", text)
+    if m_t and tuning is not None and tuple(int(x) for x in m_t.groups()) != tuple(tuning):
         return None
     return float(m_b.group(1))
 
@@ -336,7 +341,9 @@ def batch_main(args):
         e["term_evals"] += w.s * w.T
         e["K"][str(int(k))] = e["K"].get(str(int(k)), 0) + 1
     steps = args.steps or 20
-    warm = max(1, args.warmup)
+    # the first replays of a newly instantiated graph can run far slower
+    # (alternate replays up to the eighth or so); at least ten untimed ones
+    warm = max(10, args.warmup)
     for _ in range(warm):
         b.run(betas, outs, stream=stream)
     torch.cuda.synchronize()
@@ -862,7 +869,7 @@ def main():
         kname = "small_run_kernel" if single else "eval_kernel"
     achieved = ops * te_per_launch / eval_avg_s
     sha = kernel_source_sha(kname)
-    traffic = profile_traffic(sha, args.workload, kname)
+    traffic = profile_traffic(sha, args.workload, kname, None if (single or points_mode) else (K, P, C))
     # algorithmic HBM bytes of one step: the resident term data read once
     # (coefficient and n-2 16-bit exponents per term) and the images written
     # once; against the HBM peak they give the step's bandwidth fraction

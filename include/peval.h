@@ -281,7 +281,9 @@ int peval_get_tuning(peval_poly *h, uint32_t T, uint32_t *K, uint32_t *P, uint32
  * exhaustive = 0: the heuristic's own choice, then a coordinate search
  * over K, then P, then C (chains for 2048 .. 65536 waves; about fifteen
  * timed runs); 1: the full grid.  Where the run fits the single-launch path
- * (with the product on AUTO) that path is timed too.  Outputs (any may be
+ * (with the product on AUTO) that path is timed too.  A candidate replaces
+ * the one chosen so far only when it is more than 1.5% faster (the best of
+ * two timed runs each), so near-ties keep the earlier one.  Outputs (any may be
  * NULL): the chosen K, P, C (all 0 if the single-launch path won) and its
  * time in ms.  Blocks until the timing runs are done.
  */

@@ -171,7 +171,8 @@ void batch_plan(BatchCore &b, const std::vector<BatchMember> &mem, void *arena, 
     d.gamq = take((size_t)pl.K * pl.NT * w);
     d.partial = d.direct ? nullptr : take((size_t)d.C * d.Lmax * pl.nslots * w);
     ptab[j + 1] = ptab[j] + (d.ntail ? h->tab_total : 0);
-    pmono[j + 1] = pmono[j] + (uint64_t)pl.K * pl.NT;
+    // whole blocks per member, so that a block's member is one table entry
+    pmono[j + 1] = pmono[j] + align_up((size_t)pl.K * pl.NT, kMonoBlock);
     // combine tiles; none for a direct member
     pout[j + 1] = pout[j] + (d.direct ? 0
                                       : ((h->G + kCombineTile - 1) / kCombineTile) * d.C *
@@ -204,6 +205,12 @@ void batch_plan(BatchCore &b, const std::vector<BatchMember> &mem, void *arena, 
   b.tab_total = ptab[count];
   b.mono_total = pmono[count];
   b.out_total = pout[count];
+  b.mono_blocks = b.mono_total / kMonoBlock;
+  std::vector<uint32_t> bmono(b.mono_blocks), bout(b.out_total);
+  for (uint32_t j = 0; j < count; ++j) {
+    std::fill(bmono.begin() + pmono[j] / kMonoBlock, bmono.begin() + pmono[j + 1] / kMonoBlock, j);
+    std::fill(bout.begin() + pout[j], bout.begin() + pout[j + 1], j);
+  }
 
   // blob image: descriptors, runs, items, prefixes, queue counter
   b.off_desc = 0;
@@ -212,7 +219,9 @@ void batch_plan(BatchCore &b, const std::vector<BatchMember> &mem, void *arena, 
   b.off_ptab = align_up(b.off_items + std::max<size_t>(items.size(), 1) * sizeof(BatchItem), 256);
   b.off_pmono = align_up(b.off_ptab + (count + 1) * 8, 256);
   b.off_pout = align_up(b.off_pmono + (count + 1) * 8, 256);
-  b.off_ctr = align_up(b.off_pout + (count + 1) * 8, 256);
+  b.off_bmono = align_up(b.off_pout + (count + 1) * 8, 256);
+  b.off_bout = align_up(b.off_bmono + bmono.size() * 4, 256);
+  b.off_ctr = align_up(b.off_bout + bout.size() * 4, 256);
   b.blob_bytes = b.off_ctr + 256;
   b.image.assign(b.blob_bytes, 0);
   char *img = b.image.data();
@@ -222,6 +231,8 @@ void batch_plan(BatchCore &b, const std::vector<BatchMember> &mem, void *arena, 
   memcpy(img + b.off_ptab, ptab.data(), (count + 1) * 8);
   memcpy(img + b.off_pmono, pmono.data(), (count + 1) * 8);
   memcpy(img + b.off_pout, pout.data(), (count + 1) * 8);
+  if (!bmono.empty()) memcpy(img + b.off_bmono, bmono.data(), bmono.size() * 4);
+  if (!bout.empty()) memcpy(img + b.off_bout, bout.data(), bout.size() * 4);
 }
 
 void batch_bind(BatchCore &b, void *d_blob) {
@@ -233,6 +244,8 @@ void batch_bind(BatchCore &b, void *d_blob) {
   b.d_ptab = (uint64_t *)(base + b.off_ptab);
   b.d_pmono = (uint64_t *)(base + b.off_pmono);
   b.d_pout = (uint64_t *)(base + b.off_pout);
+  b.d_bmono = (uint32_t *)(base + b.off_bmono);
+  b.d_bout = (uint32_t *)(base + b.off_bout);
   b.d_counter = (uint32_t *)(base + b.off_ctr);
 }
 
@@ -256,9 +269,10 @@ int batch_enqueue(const BatchCore &b, hipStream_t st) {
     batch_power_kernel<<<(unsigned)((b.tab_total + 255) / 256), 256, 0, st>>>(b.d_desc, b.d_run, b.count, b.d_ptab);
     HIP_TRY(hipGetLastError());
   }
-  if (b.mono_total) {
-    const uint32_t xchunk = (uint32_t)(((b.mono_total + 255) / 256 + kXcds - 1) / kXcds);
-    batch_mono_kernel<<<kXcds * xchunk, 256, 0, st>>>(b.d_desc, b.d_run, b.count, b.d_pmono, xchunk);
+  if (b.mono_blocks) {
+    const uint32_t xchunk = (uint32_t)((b.mono_blocks + kXcds - 1) / kXcds);
+    batch_mono_kernel<<<kXcds * xchunk, kMonoBlock, 0, st>>>(b.d_desc, b.d_run, b.d_bmono, b.d_pmono,
+                                                             b.mono_blocks, xchunk);
     HIP_TRY(hipGetLastError());
   }
   for (uint32_t kind = 0; kind < kKinds; ++kind) {
@@ -270,7 +284,7 @@ int batch_enqueue(const BatchCore &b, hipStream_t st) {
     HIP_TRY(hipGetLastError());
   }
   if (b.out_total) {  // out_total counts combine tiles
-    batch_combine_kernel<<<(unsigned)b.out_total, kCombineBlock, 0, st>>>(b.d_desc, b.d_run, b.count, b.d_pout);
+    batch_combine_kernel<<<(unsigned)b.out_total, kCombineBlock, 0, st>>>(b.d_desc, b.d_run, b.d_bout, b.d_pout);
     HIP_TRY(hipGetLastError());
   }
   return PEVAL_OK;

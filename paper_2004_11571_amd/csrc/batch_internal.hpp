@@ -24,6 +24,7 @@ struct BatchCore {
   uint32_t kind_first[kKinds + 1] = {};  // items of kind k: kind_first[k] .. kind_first[k+1]-1
   int eval_blocks[kKinds] = {};          // persistent blocks of each kind's evaluation kernel
   uint64_t tab_total = 0, mono_total = 0, out_total = 0;
+  uint64_t mono_blocks = 0;  // blocks of the monomial kernel (each member's entries padded to whole blocks)
   size_t scratch_bytes = 0;
   std::vector<BatchDesc> descs;
   void *d_blob = nullptr;  // descriptors, run table, items, prefixes, queue counter
@@ -31,6 +32,7 @@ struct BatchCore {
   BatchRun *d_run = nullptr;
   BatchItem *d_items = nullptr;
   uint64_t *d_ptab = nullptr, *d_pmono = nullptr, *d_pout = nullptr;
+  uint32_t *d_bmono = nullptr, *d_bout = nullptr;  // member of each monomial block, of each combine tile
   uint32_t *d_counter = nullptr;
   void *arena = nullptr;  // per-member scratch
   bool own_arena = false;
@@ -38,6 +40,7 @@ struct BatchCore {
   std::vector<char> image;
   size_t blob_bytes = 0;
   size_t off_desc = 0, off_run = 0, off_items = 0, off_ptab = 0, off_pmono = 0, off_pout = 0, off_ctr = 0;
+  size_t off_bmono = 0, off_bout = 0;
 };
 
 size_t member_scratch_bytes(const peval_poly *h, const Plan &pl, uint32_t C, uint32_t T);

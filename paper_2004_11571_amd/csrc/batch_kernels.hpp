@@ -85,17 +85,24 @@ __device__ __forceinline__ void batch_mono_one(const BatchDesc &d, uint64_t t0, 
   monomial_entry<A>(a, d.to.off, local);
 }
 
-// Blocks renumbered per XCD as in monomial_kernel (xchunk logical blocks per
-// XCD, grid 8 xchunk).
-__global__ void batch_mono_kernel(const BatchDesc *D, const BatchRun *R, uint32_t count, const uint64_t *prefix,
-                                  uint32_t xchunk) {
-  __shared__ uint32_t first;
-  const uint64_t block_first = xcd_logical_block(xchunk) * blockDim.x;
-  const uint64_t idx = block_first + threadIdx.x;
-  uint32_t j = find_poly_block(prefix, count, idx, block_first, &first);  // every thread takes part in the barrier
-  if (idx >= prefix[count]) return;
+// Each member's entries start on a block boundary (its range padded to whole
+// blocks of kMonoBlock), so a block belongs to one member, read from a table:
+// the member and its descriptor are uniform over the block.  Blocks are
+// renumbered per XCD as in monomial_kernel (xchunk logical blocks per XCD,
+// grid 8 xchunk).
+constexpr uint32_t kMonoBlock = 256;
+
+__global__ __launch_bounds__(kMonoBlock) void batch_mono_kernel(const BatchDesc *__restrict__ D,
+                                                                const BatchRun *__restrict__ R,
+                                                                const uint32_t *__restrict__ block_member,
+                                                                const uint64_t *__restrict__ prefix, uint64_t nblocks,
+                                                                uint32_t xchunk) {
+  const uint64_t lb = xcd_logical_block(xchunk);
+  if (lb >= nblocks) return;
+  const uint32_t j = __builtin_amdgcn_readfirstlane(block_member[lb]);
   const BatchDesc &d = D[j];
-  uint64_t local = idx - prefix[j];
+  const uint64_t local = lb * kMonoBlock - prefix[j] + threadIdx.x;
+  if (local >= (uint64_t)d.K * d.NT) return;  // the member's padding
   if (d.w == 4) batch_mono_one<W32>(d, R[j].t0, local, d.m32);
   else batch_mono_one<W64>(d, R[j].t0, local, d.m64);
 }
@@ -208,12 +215,14 @@ __device__ __forceinline__ void batch_combine_one(const BatchDesc &d, void *out,
                   reinterpret_cast<T(*)[kCombineTile + 1]>(lds));
 }
 
-__global__ __launch_bounds__(kCombineBlock) void batch_combine_kernel(const BatchDesc *D, const BatchRun *R,
-                                                                      uint32_t count, const uint64_t *prefix) {
+// One tile per block; the tile's member from a table (uniform over the block).
+__global__ __launch_bounds__(kCombineBlock) void batch_combine_kernel(const BatchDesc *__restrict__ D,
+                                                                      const BatchRun *__restrict__ R,
+                                                                      const uint32_t *__restrict__ tile_member,
+                                                                      const uint64_t *__restrict__ prefix) {
   __shared__ __align__(16) uint64_t tile[kCombineTile][kCombineTile + 1];
-  const uint64_t idx = blockIdx.x;  // one tile per block; uniform over the block
-  if (idx >= prefix[count]) return;
-  const uint32_t j = find_poly(prefix, count, idx);
+  const uint64_t idx = blockIdx.x;  // the grid is exactly the batch's tiles
+  const uint32_t j = __builtin_amdgcn_readfirstlane(tile_member[idx]);
   const BatchDesc &d = D[j];
   const uint64_t local = idx - prefix[j];
   if (d.w == 4) batch_combine_one<W32>(d, R[j].out, local, d.m32, tile);

@@ -117,10 +117,14 @@ extern "C" int peval_autotune(peval_poly *h, const uint64_t *beta, uint32_t T, u
   best.K = std::min(best.K, kmax);
   const Tuning heur = best;
   float best_ms = 1e30f;
+  // a candidate replaces the current choice only when it is faster by more
+  // than the spread of repeated timings, so that ties keep the heuristic's
+  // (considered first) and the choice is stable from process to process
+  const float margin = 0.985f;
   auto consider = [&](Tuning t) -> int {
     float m = 0;
     PEVAL_TRY(time_run(h, ba, T, t, 2, &m));
-    if (m < best_ms) {
+    if (m < best_ms * margin) {
       best_ms = m;
       best = t;
     }
