@@ -27,6 +27,8 @@ extern "C" {
  *   PEVAL_TOP_SHOUP64   a any 64-bit word, b canonical -> the lazy Shoup
  *                       product of a by b with b's quotient, in [0, 2p)
  *   PEVAL_TOP_REDUCE96  (b mod 2^32) 2^64 + a -> canonical residue
+ *   PEVAL_TOP_FOLD96    (b mod 2^32) 2^64 + a -> a 64-bit word congruent
+ *                       to it (the segmented sums' partial coefficients)
  *   PEVAL_TOP_POW64     a canonical, b exponent -> a^b mod p (0^0 = 1)
  *   PEVAL_TOP_SUM64     count sums: out[i] = sum of a[16 i .. 16 i + 15]
  *                       (any 64-bit words) reduced mod p through the
@@ -54,7 +56,7 @@ extern "C" {
  */
 enum {
     PEVAL_TOP_MUL64 = 0, PEVAL_TOP_QUOT64 = 1, PEVAL_TOP_SHOUP64 = 2, PEVAL_TOP_REDUCE96 = 3,
-    PEVAL_TOP_POW64 = 4, PEVAL_TOP_SUM64 = 5,
+    PEVAL_TOP_POW64 = 4, PEVAL_TOP_SUM64 = 5, PEVAL_TOP_FOLD96 = 6,
     PEVAL_TOP_ALG2 = 8, PEVAL_TOP_FOLD = 9, PEVAL_TOP_CANON_F64 = 10,
     PEVAL_TOP_PM63 = 12, PEVAL_TOP_PM31 = 13,
     PEVAL_TOP_MUL32 = 16, PEVAL_TOP_QUOT32 = 17, PEVAL_TOP_SHOUP32 = 18, PEVAL_TOP_REDUCE64_32 = 19,

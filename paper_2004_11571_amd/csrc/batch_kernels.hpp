@@ -117,7 +117,7 @@ __device__ __forceinline__ void batch_eval_item(const BatchDesc &d, const BatchI
   a.gamq = (const T *)d.gamq;
   a.endmask = d.endmask;
   a.slot_base = d.slot_base;
-  a.partial = (typename A::PT *)d.partial;  // partial sums as canonical integer residues
+  a.partial = (typename A::PT *)d.partial;
   a.NT = d.NT;
   a.NW = d.NW;
   a.nslots = d.nslots;

@@ -179,7 +179,7 @@ struct EvalArgs {
   const typename A::T *gamq;    // [K][NT]
   const uint64_t *endmask;      // per wave: bit l set if lane l closes a segment
   const uint32_t *slot_base;    // per wave: index of its first segment slot
-  typename A::PT *partial;      // [nslots][C][Lmax] canonical partial coefficients
+  typename A::PT *partial;      // [nslots][C][Lmax] partial coefficients (64-bit: any representative)
   uint64_t NT, NW, nslots;
   uint32_t C, T;                // chains, evaluations in this launch
   uint32_t Lmax;                // ceil(T / C): evaluations of the longest chain
@@ -245,6 +245,9 @@ constexpr int kEvalBlock = 256;  // 4 waves, each independent
 // end (its head) and the one after its last end (its tail) are handed, through
 // the stage, to lanes (0, pp), which chain the sub-tiles: a group that spans
 // several sub-tiles of the wave leaves it as one partial.
+// Partials are written as the policy's reduce_partial: canonical, except
+// 64-bit residues, which may be any 64-bit representative (the combine makes
+// them canonical).
 // partial[(slot * C + c) * Lmax + i]: the P lanes of a sub-tile write P
 // consecutive evaluations of one slot.  Merge = false is the plain walk for
 // layouts whose endmask also closes every sub-tile: every end is emitted.
@@ -271,7 +274,7 @@ __device__ __forceinline__ void segmented_walk(Stage<A, P> &st, int lane, int np
           first = false;
         } else {
           const uint32_t slot = sbase + (uint32_t)__popcll(emask & ((1ull << src) - 1ull));
-          pcol[slot * slot_stride] = A::reduce(sum, m);
+          pcol[slot * slot_stride] = A::reduce_partial(sum, m);
         }
         sum = A::zero();
       }
@@ -294,7 +297,7 @@ __device__ __forceinline__ void segmented_walk(Stage<A, P> &st, int lane, int np
         A::add_walk(hd, carry, m);
         const int first_end = hh * P + (int)__builtin_ctzll(bits);
         const uint32_t slot = sbase + (uint32_t)__popcll(emask & ((1ull << first_end) - 1ull));
-        pcol[slot * slot_stride] = A::reduce(hd, m);
+        pcol[slot * slot_stride] = A::reduce_partial(hd, m);
         carry = st.get(hh * P + 1, pp);
       } else {
         A::add_walk(carry, st.get(hh * P + 1, pp), m);
@@ -442,7 +445,7 @@ __device__ __forceinline__ void combine_tile(const CombineArgs<A> &a, uint64_t g
           ++gl;
           next_end = a.slot_off[g0 + gl + 1];
         }
-        acc = add_mod(acc, v[u], (T)a.m.p);
+        acc = add_mod(acc, A::canon_partial(v[u], a.m), (T)a.m.p);
       }
     }
     tile[gl][lane] = acc;  // last group of the run

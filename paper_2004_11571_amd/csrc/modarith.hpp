@@ -157,6 +157,17 @@ __device__ __forceinline__ uint64_t reduce96(uint64_t lo, uint32_t hi, const Mod
   return add_mod(a, reduce64(lo, m), m.p);
 }
 
+// hi * 2^64 + lo -> some 64-bit word congruent to it mod p (hi < 2^32), with
+// one product where reduce96 takes two: y = hi R lazily (R = 2^64 mod p,
+// y < 2p), then lo + y; if that sum carries out of 64 bits, the carry's 2^64
+// is replaced by R.  The wrapped sum is below y < 2p, and R = 2^64 - k p with
+// k = floor(2^64 / p) >= 2 for p < 2^63, so adding R cannot carry again.
+__device__ __forceinline__ uint64_t fold96(uint64_t lo, uint32_t hi, const Mod64 &m) {
+  const uint64_t y = shoup_mul(hi, m.R, m.Rq, m.p);
+  const uint64_t s = lo + y;
+  return s < y ? s + m.R : s;
+}
+
 // base^e mod p by square-and-multiply, canonical base, e >= 0.
 __device__ __forceinline__ uint64_t pow_mod(uint64_t base, uint64_t e, const Mod64 &m) {
   uint64_t r = 1 % m.p;
@@ -254,6 +265,12 @@ struct W64 {
   __device__ static __forceinline__ T reduce(const Acc &a, const M &m) {
     return reduce96(((uint64_t)a.w1 << 32) | a.w0, a.w2, m);
   }
+  // A partial coefficient (segment sum) as any 64-bit representative: the
+  // combine makes it canonical after the walk, where the VALUs are idle.
+  __device__ static __forceinline__ T reduce_partial(const Acc &a, const M &m) {
+    return fold96(((uint64_t)a.w1 << 32) | a.w0, a.w2, m);
+  }
+  __device__ static __forceinline__ T canon_partial(T v, const M &m) { return reduce64(v, m); }
   // A thread's sum over its terms: the low and high 32-bit halves of the
   // values are summed separately in 64 bits (value = lo + hi 2^32), one
   // multiply-add by 1 each and no carry chain; exact for up to 2^32 values.
@@ -292,6 +309,8 @@ struct W32 {
   __device__ static __forceinline__ void add(Acc &a, T x) { a.v += x; }
   __device__ static __forceinline__ void add(Acc &a, const Acc &b) { a.v += b.v; }
   __device__ static __forceinline__ T reduce(const Acc &a, const M &m) { return reduce64(a.v, m); }
+  __device__ static __forceinline__ T reduce_partial(const Acc &a, const M &m) { return reduce64(a.v, m); }
+  __device__ static __forceinline__ T canon_partial(T v, const M &) { return v; }
   using Sum = Acc;  // a thread's sum over its terms
   __device__ static __forceinline__ Sum sum_zero() { return zero(); }
   // one multiply-add by 1 into the 64-bit sum (no carry chain)
@@ -342,6 +361,7 @@ struct W64PM {
   __device__ static __forceinline__ Acc zero() { return W64::zero(); }
   __device__ static __forceinline__ void add(Acc &a, T x) { W64::add(a, x); }
   __device__ static __forceinline__ T reduce(const Acc &a, const M &m) { return W64::reduce(a, m.m); }
+  __device__ static __forceinline__ T reduce_partial(const Acc &a, const M &m) { return W64::reduce_partial(a, m.m); }
   using Sum = W64::Sum;
   __device__ static __forceinline__ Sum sum_zero() { return W64::sum_zero(); }
   __device__ static __forceinline__ void sum_add(Sum &s, T x) { W64::sum_add(s, x); }
@@ -371,6 +391,7 @@ struct W32PM {
   __device__ static __forceinline__ Acc zero() { return W32::zero(); }
   __device__ static __forceinline__ void add(Acc &a, T x) { W32::add(a, x); }
   __device__ static __forceinline__ T reduce(const Acc &a, const M &m) { return W32::reduce(a, m.m); }
+  __device__ static __forceinline__ T reduce_partial(const Acc &a, const M &m) { return W32::reduce(a, m.m); }
   using Sum = Acc;
   __device__ static __forceinline__ Sum sum_zero() { return zero(); }
   __device__ static __forceinline__ void sum_add(Sum &s, T x) { W32::sum_add(s, x); }
@@ -455,6 +476,7 @@ struct WF64 {
   __device__ static __forceinline__ PT reduce(const Acc &a, const M &m) {
     return fp_to_u64(a.s < 0.0 ? a.s + m.p : a.s);
   }
+  __device__ static __forceinline__ PT reduce_partial(const Acc &a, const M &m) { return reduce(a, m); }
   __device__ static __forceinline__ Acc stage(const Acc &a, const M &m) { return Acc{fp_fold(a.s, m.p, m.u)}; }
   __device__ static __forceinline__ T mul_lazy(T x, T w, T, const M &m) { return alg2_mul_signed(x, w, m.p, m.u); }
 };

@@ -40,6 +40,7 @@ __global__ __launch_bounds__(256) void arith_test_kernel(ArithArgs x) {
     case PEVAL_TOP_QUOT64: r = shoup_quot(a, x.m64); break;
     case PEVAL_TOP_SHOUP64: r = shoup_mul(a, b, shoup_quot(b, x.m64), x.m64.p); break;
     case PEVAL_TOP_REDUCE96: r = reduce96(a, (uint32_t)b, x.m64); break;
+    case PEVAL_TOP_FOLD96: r = fold96(a, (uint32_t)b, x.m64); break;
     case PEVAL_TOP_POW64: r = pow_mod(a, b, x.m64); break;
     case PEVAL_TOP_SUM64: {
       W64::Sum s = W64::sum_zero();
@@ -77,7 +78,7 @@ bool is_pm31(uint64_t p) { return p < (1ull << 31) && p > (1ull << 31) - (1ull <
 int op_class(uint32_t op) {
   switch (op) {
     case PEVAL_TOP_MUL64: case PEVAL_TOP_QUOT64: case PEVAL_TOP_SHOUP64: case PEVAL_TOP_REDUCE96:
-    case PEVAL_TOP_POW64: case PEVAL_TOP_SUM64: return 64;
+    case PEVAL_TOP_POW64: case PEVAL_TOP_SUM64: case PEVAL_TOP_FOLD96: return 64;
     case PEVAL_TOP_ALG2: case PEVAL_TOP_FOLD: case PEVAL_TOP_CANON_F64: return 50;
     case PEVAL_TOP_PM63: return 63;
     case PEVAL_TOP_PM31: return 31;

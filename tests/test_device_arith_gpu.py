@@ -87,7 +87,7 @@ def _mismatch(got, want, a, b=None):
            f"got={got[i]} want={want[i]}"
 
 
-OPS = {"MUL64": 0, "QUOT64": 1, "SHOUP64": 2, "REDUCE96": 3, "POW64": 4, "SUM64": 5, "ALG2": 8, "FOLD": 9,
+OPS = {"MUL64": 0, "QUOT64": 1, "SHOUP64": 2, "REDUCE96": 3, "POW64": 4, "SUM64": 5, "FOLD96": 6, "ALG2": 8, "FOLD": 9,
        "CANON_F64": 10, "PM63": 12, "PM31": 13, "MUL32": 16, "QUOT32": 17, "SHOUP32": 18, "REDUCE64_32": 19,
        "POW32": 20, "SUM32": 21}
 
@@ -123,6 +123,10 @@ def test_reduce96_pow_sum_64(p):
     got = _objs(_run(OPS["REDUCE96"], p, lo, hi))
     want = (_objs(hi) * M64 + _objs(lo)) % p
     assert (err := _mismatch(got, want, lo, hi)) is None, err
+    # the partial coefficients' fold: congruent, any 64-bit word (the output
+    # array holds 64 bits, so only congruence is left to check)
+    got = _objs(_run(OPS["FOLD96"], p, lo, hi))
+    assert (err := _mismatch(got % p, want, lo, hi)) is None, err
     # powers: bases canonical, exponents up to 2^64 - 1 (and 0: 0^0 = 1)
     n = 1 << 14
     base = rng.integers(0, p, size=n, dtype=np.uint64)

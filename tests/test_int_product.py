@@ -15,7 +15,11 @@ on:
   as the addend of x0 w0;
 * for p < 2^31, the remainder as the low word of x w + q (2^32 - p);
 * a thread's sum as two 64-bit sums of the values' 32-bit halves, folded to
-  96 bits.
+  96 bits;
+* a 96-bit segment sum hi 2^64 + lo folded to one 64-bit word congruent to
+  it (the partial coefficients): lo + hi R with R = 2^64 mod p, and on a
+  carry out of 64 bits R added in place of the carry, which never carries
+  again for p < 2^63.
 
 A dropped carry, a wrong cross product or a missing shift fails here.
 """
@@ -123,3 +127,33 @@ def test_half_sums_fold_to_96_bits():
     cases += [[rng.randrange(M64) for _ in range(rng.randrange(1, 17))] for _ in range(2000)]
     for vals in cases:
         assert half_sums(vals) == sum(vals)
+
+
+def fold96(lo, hi, p):
+    """The partial coefficients' fold: y = hi R lazily, lo + y, a carry
+    replaced by R (R = 2^64 mod p)."""
+    R = M64 % p
+    y = shoup64(hi, R, (R << 64) // p, p)
+    s = lo + y
+    if s >= M64:
+        s = s - M64 + R
+        assert s < M64, "second carry"
+    return s
+
+
+@pytest.mark.parametrize("p", [3, 5, (1 << 31) + 11, (1 << 50) - 27, (1 << 62) - 57, (1 << 62) + 135,
+                               (1 << 63) - 25, (1 << 63) - 1])
+def test_fold96_congruent_and_below_2_64(p):
+    rng = random.Random(p ^ 0x5EED)
+    R = M64 % p
+    # extremes: the largest lo with the largest lazy y (hi chosen so that
+    # hi R mod p is p - 1, when p - 1 is a multiple of gcd(R, p) = 1)
+    hi_max = ((p - 1) * pow(R, -1, p)) % p % M32 if R else 0
+    cases = [(M64 - 1, M32 - 1), (M64 - 1, hi_max), (0, 0), (M64 - 1, 0), (p - 1, 1)]
+    cases += [(rng.randrange(M64), rng.randrange(M32)) for _ in range(5000)]
+    carried = 0
+    for lo, hi in cases:
+        v = fold96(lo, hi, p)
+        assert v < M64 and (v - (hi * M64 + lo)) % p == 0, (lo, hi)
+        carried += lo + shoup64(hi, R, (R << 64) // p, p) >= M64
+    assert carried > 0 or p < (1 << 32)
