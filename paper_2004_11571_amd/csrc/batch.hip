@@ -172,7 +172,7 @@ void batch_plan(BatchCore &b, const std::vector<BatchMember> &mem, void *arena, 
     d.partial = d.direct ? nullptr : take((size_t)d.C * d.Lmax * pl.nslots * w);
     ptab[j + 1] = ptab[j] + (d.ntail ? h->tab_total : 0);
     // whole blocks per member, so that a block's member is one table entry
-    pmono[j + 1] = pmono[j] + align_up((size_t)pl.K * pl.NT, kMonoBlock);
+    pmono[j + 1] = pmono[j] + align_up((size_t)pl.K * pl.NT / mono_slots(pl.K), kMonoBlock);
     // combine tiles; none for a direct member
     pout[j + 1] = pout[j] + (d.direct ? 0
                                       : ((h->G + kCombineTile - 1) / kCombineTile) * d.C *

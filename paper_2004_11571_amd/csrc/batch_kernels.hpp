@@ -102,7 +102,7 @@ __global__ __launch_bounds__(kMonoBlock) void batch_mono_kernel(const BatchDesc 
   const uint32_t j = __builtin_amdgcn_readfirstlane(block_member[lb]);
   const BatchDesc &d = D[j];
   const uint64_t local = lb * kMonoBlock - prefix[j] + threadIdx.x;
-  if (local >= (uint64_t)d.K * d.NT) return;  // the member's padding
+  if (local >= (uint64_t)d.K * d.NT / mono_slots(d.K)) return;  // the member's padding
   if (d.w == 4) batch_mono_one<W32>(d, R[j].t0, local, d.m32);
   else batch_mono_one<W64>(d, R[j].t0, local, d.m64);
 }

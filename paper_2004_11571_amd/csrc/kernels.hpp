@@ -94,25 +94,33 @@ struct MonoArgs {
   typename A::M m;
 };
 
+// Slots of one thread handled by one work-item of the monomial kernels: the
+// R slots share the thread's term range, and their loads are all issued
+// before any product, so a work-item waits for memory a few times instead
+// of each slot waiting on its own.
+__host__ __device__ constexpr uint32_t mono_slots(uint32_t K) { return K >= 4 ? 4 : K; }
+constexpr int kMonoFastTail = 8;  // tail exponents held in registers per slot
+
 // off: power-table offsets per tail variable (read through a pointer so that
 // a dynamically indexed copy never lands in scratch memory).
-// idx enumerates tiles of 64 threads x K slots, the slot k of a tile
-// changing every 64 indices: the lanes of a wave store 64 consecutive
-// threads' values of one slot (coalesced, [k][thread] layout), and the few
-// consecutive blocks that cover one tile read all K terms of its threads, so
-// every cache line of term data is fetched once.  (With idx = k NT + j the
-// waves of slot k read one term in K, and the term data came from HBM about
-// K times over.)  NT is a multiple of 64 and K a power of two.
-template <class A>
-__device__ __forceinline__ void monomial_entry(const MonoArgs<A> &a, const uint32_t *off, uint64_t idx) {
+// idx enumerates tiles of 64 threads x K/R work-items of R consecutive
+// slots, the item changing every 64 indices: the lanes of a wave store 64
+// consecutive threads' values of one slot (coalesced, [k][thread] layout),
+// and the few consecutive blocks that cover one tile read all K terms of its
+// threads, so every cache line of term data is fetched once.  (With idx =
+// k NT + j the waves of slot k read one term in K, and the term data came
+// from HBM about K times over.)  NT is a multiple of 64, K a power of two
+// and R = mono_slots(K).
+template <class A, int R>
+__device__ __forceinline__ void monomial_entries(const MonoArgs<A> &a, const uint32_t *off, uint64_t idx) {
   using T = typename A::T;
-  const uint32_t sh = 6 + __builtin_ctz(a.K);  // log2(64 K)
+  const uint32_t sh = 6 + __builtin_ctz(a.K / R);  // log2(64 K / R)
   const uint64_t tile = idx >> sh;
   const uint32_t r = (uint32_t)(idx & ((1ull << sh) - 1));
-  const uint32_t k = r >> 6;
+  const uint32_t k0 = (r >> 6) * R;
   const uint64_t j = (tile << 6) + (r & 63);
-  const uint64_t pos = (uint64_t)k * a.NT + j;  // slot (k, j) in the [k][thread] arrays
   const uint64_t NTK = (uint64_t)a.K * a.NT;
+  const uint64_t p = a.m.p;
   // canonical value, or its double image when the evaluation uses Alg. 2
   auto out = [&](T v) -> T {
     if constexpr (sizeof(T) == 8) {
@@ -120,52 +128,99 @@ __device__ __forceinline__ void monomial_entry(const MonoArgs<A> &a, const uint3
     }
     return v;
   };
-  if (k >= a.thr_cnt[j]) {  // padding: a zero term stays zero (0.0 has the same bits)
-    for (uint32_t c = 0; c < a.C; ++c) a.lam[c * NTK + pos] = 0;
-    a.gam[pos] = 0;
-    a.gamq[pos] = 0;
-    return;
+  const uint32_t cnt = a.thr_cnt[j];
+  const uint64_t first = a.thr_first[j];
+  bool live[R];
+  T co[R];
+  uint32_t ex[R][kMonoFastTail];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    live[u] = k0 + u < cnt;
+    const uint64_t i = first + k0 + u;
+    co[u] = live[u] ? a.coeff[i] : (T)0;
+#pragma unroll
+    for (int v = 0; v < kMonoFastTail; ++v)
+      ex[u][v] = (live[u] && (uint32_t)v < a.ntail) ? a.exps[(uint64_t)v * a.s + i] : 0u;
   }
-  const uint64_t i = (uint64_t)a.thr_first[j] + k;
-  const uint64_t p = a.m.p;
-  // m_i = prod_k beta_k^{g_ik}, n-3 products using the tables (Section 2.3)
-  T mi = (T)(1 % p);
-  for (uint32_t v = 0; v < a.ntail; ++v) {
-    uint32_t e = a.exps[(uint64_t)v * a.s + i];
-    uint32_t at = off[v] + e;
-    mi = (v == 0) ? a.tval[at] : A::mul_lazy(mi, a.tval[at], a.tquot[at], a.m);
+  // m_i = prod_k beta_k^{g_ik}, n-3 products using the tables (Section 2.3);
+  // a padding slot's exponents are 0 and its product is never stored
+  T mi[R];
+#pragma unroll
+  for (int v = 0; v < kMonoFastTail; ++v) {
+    if ((uint32_t)v >= a.ntail) break;
+    T tv[R], tq[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const uint32_t at = off[v] + ex[u][v];
+      tv[u] = a.tval[at];
+      tq[u] = a.tquot[at];
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) mi[u] = (v == 0) ? tv[u] : A::mul_lazy(mi[u], tv[u], tq[u], a.m);
   }
-  mi = canon(mi, (T)p);
-  const T mq = shoup_quot(mi, a.m);
-  // Lambda_0 = a_i m_i^{t0}; Lambda_c = Lambda_{c-1} m_i
-  T lam;
-  if (a.t0 == 1) {
-    lam = A::mul_lazy(a.coeff[i], mi, mq, a.m);
-  } else {
-    T mt = pow_mod(mi, a.t0, a.m);
-    lam = A::mul_lazy(a.coeff[i], mt, shoup_quot(mt, a.m), a.m);
+  if (a.ntail == 0) {
+#pragma unroll
+    for (int u = 0; u < R; ++u) mi[u] = (T)(1 % p);
   }
-  a.lam[pos] = out(lam);
-  // Gamma = m_i^C, the multiplier of every chain: for a few chains by the
-  // same products that step the chain starts, else by squaring
-  const bool stepped = a.C <= 16;
-  T g = mi;
-  for (uint32_t c = 1; c < a.C; ++c) {
-    lam = A::mul_lazy(lam, mi, mq, a.m);
-    a.lam[c * NTK + pos] = out(lam);
-    if (stepped) g = A::mul_lazy(g, mi, mq, a.m);
+  for (uint32_t v = kMonoFastTail; v < a.ntail; ++v) {  // more than 8 tail variables
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const uint32_t e = live[u] ? a.exps[(uint64_t)v * a.s + first + k0 + u] : 0u;
+      const uint32_t at = off[v] + e;
+      mi[u] = A::mul_lazy(mi[u], a.tval[at], a.tquot[at], a.m);
+    }
   }
-  g = stepped ? canon(g, (T)p) : pow_mod(mi, (uint64_t)a.C, a.m);
-  a.gam[pos] = out(g);
-  a.gamq[pos] = shoup_quot(g, a.m);
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const uint64_t pos = (uint64_t)(k0 + u) * a.NT + j;  // slot (k, j) in the [k][thread] arrays
+    if (!live[u]) {  // padding: a zero term stays zero (0.0 has the same bits)
+      for (uint32_t c = 0; c < a.C; ++c) a.lam[c * NTK + pos] = 0;
+      a.gam[pos] = 0;
+      a.gamq[pos] = 0;
+      continue;
+    }
+    const T m1 = canon(mi[u], (T)p);
+    const T mq = shoup_quot(m1, a.m);
+    // Lambda_0 = a_i m_i^{t0}; Lambda_c = Lambda_{c-1} m_i
+    T lam;
+    if (a.t0 == 1) {
+      lam = A::mul_lazy(co[u], m1, mq, a.m);
+    } else {
+      T mt = pow_mod(m1, a.t0, a.m);
+      lam = A::mul_lazy(co[u], mt, shoup_quot(mt, a.m), a.m);
+    }
+    a.lam[pos] = out(lam);
+    // Gamma = m_i^C, the multiplier of every chain: for a few chains by the
+    // same products that step the chain starts, else by squaring
+    const bool stepped = a.C <= 16;
+    T g = m1;
+    for (uint32_t c = 1; c < a.C; ++c) {
+      lam = A::mul_lazy(lam, m1, mq, a.m);
+      a.lam[c * NTK + pos] = out(lam);
+      if (stepped) g = A::mul_lazy(g, m1, mq, a.m);
+    }
+    g = stepped ? canon(g, (T)p) : pow_mod(m1, (uint64_t)a.C, a.m);
+    a.gam[pos] = out(g);
+    a.gamq[pos] = shoup_quot(g, a.m);
+  }
 }
 
-// The blocks of one tile of slots (K / 4 blocks for K >= 4) share their
-// term data's cache lines, so they are kept on one XCD.
+template <class A>
+__device__ __forceinline__ void monomial_entry(const MonoArgs<A> &a, const uint32_t *off, uint64_t idx) {
+  switch (mono_slots(a.K)) {
+    case 4: monomial_entries<A, 4>(a, off, idx); break;
+    case 2: monomial_entries<A, 2>(a, off, idx); break;
+    default: monomial_entries<A, 1>(a, off, idx); break;
+  }
+}
+
+// The work-items of one tile (64 K / R of them: at most one block for
+// K <= 16) share their term data's cache lines; neighbouring tiles are kept
+// on one XCD.
 template <class A>
 __global__ void monomial_kernel(MonoArgs<A> a) {
   const uint64_t idx = xcd_logical_block(a.xchunk) * blockDim.x + threadIdx.x;
-  if (idx >= (uint64_t)a.K * a.NT) return;
+  if (idx >= (uint64_t)a.K * a.NT / mono_slots(a.K)) return;
   monomial_entry<A>(a, a.to.off, idx);
 }
 
