@@ -81,6 +81,7 @@ __device__ __forceinline__ void batch_mono_one(const BatchDesc &d, uint64_t t0, 
   a.K = d.K;
   a.C = d.C;
   a.as_double = d.kind == kKindF64;  // FP64 members take chain starts and Gamma as doubles
+  a.R = mono_slots(d.K);             // fixed per member: its work-items are counted when the batch is planned
   a.m = m;
   monomial_entry<A>(a, d.to.off, local);
 }

@@ -90,6 +90,7 @@ struct MonoArgs {
   uint64_t t0;
   uint32_t ntail, K, C;
   uint32_t as_double;           // store canonical values as doubles (for the FP64 product)
+  uint32_t R;                   // slots per work-item: 1 or mono_slots(K)
   uint32_t xchunk;              // logical blocks per XCD (grid = 8 xchunk blocks of 256)
   typename A::M m;
 };
@@ -97,8 +98,14 @@ struct MonoArgs {
 // Slots of one thread handled by one work-item of the monomial kernels: the
 // R slots share the thread's term range, and their loads are all issued
 // before any product, so a work-item waits for memory a few times instead
-// of each slot waiting on its own.
+// of each slot waiting on its own.  A launch of fewer slots than a few
+// rounds of the chip's resident threads keeps R = 1 (more threads waiting
+// at once, and the first round is the whole launch).
 __host__ __device__ constexpr uint32_t mono_slots(uint32_t K) { return K >= 4 ? 4 : K; }
+constexpr uint64_t kMonoMultiSlots = 4ull << 20;
+__host__ __device__ constexpr uint32_t mono_slots_for(uint32_t K, uint64_t slots) {
+  return slots >= kMonoMultiSlots ? mono_slots(K) : 1u;
+}
 constexpr int kMonoFastTail = 8;  // tail exponents held in registers per slot
 
 // off: power-table offsets per tail variable (read through a pointer so that
@@ -110,7 +117,7 @@ constexpr int kMonoFastTail = 8;  // tail exponents held in registers per slot
 // threads, so every cache line of term data is fetched once.  (With idx =
 // k NT + j the waves of slot k read one term in K, and the term data came
 // from HBM about K times over.)  NT is a multiple of 64, K a power of two
-// and R = mono_slots(K).
+// and R (1, 2 or 4) divides K.
 template <class A, int R>
 __device__ __forceinline__ void monomial_entries(const MonoArgs<A> &a, const uint32_t *off, uint64_t idx) {
   using T = typename A::T;
@@ -207,7 +214,7 @@ __device__ __forceinline__ void monomial_entries(const MonoArgs<A> &a, const uin
 
 template <class A>
 __device__ __forceinline__ void monomial_entry(const MonoArgs<A> &a, const uint32_t *off, uint64_t idx) {
-  switch (mono_slots(a.K)) {
+  switch (a.R) {
     case 4: monomial_entries<A, 4>(a, off, idx); break;
     case 2: monomial_entries<A, 2>(a, off, idx); break;
     default: monomial_entries<A, 1>(a, off, idx); break;
@@ -220,7 +227,7 @@ __device__ __forceinline__ void monomial_entry(const MonoArgs<A> &a, const uint3
 template <class A>
 __global__ void monomial_kernel(MonoArgs<A> a) {
   const uint64_t idx = xcd_logical_block(a.xchunk) * blockDim.x + threadIdx.x;
-  if (idx >= (uint64_t)a.K * a.NT / mono_slots(a.K)) return;
+  if (idx >= (uint64_t)a.K * a.NT / a.R) return;
   monomial_entry<A>(a, a.to.off, idx);
 }
 
@@ -452,6 +459,7 @@ __global__ __launch_bounds__(kEvalBlock, (P <= 16 ? (K >= 32 ? 2 : 3) : 1)) void
 // A7: combine partial coefficients into the dense images
 // ---------------------------------------------------------------------------
 constexpr int kCombineTile = 64;   // groups x evaluations per block
+constexpr int kCombineLoads = 16;  // partial sums in flight per lane
 constexpr int kCombineBlock = 256;
 
 template <class A>
@@ -476,8 +484,9 @@ __device__ __forceinline__ void combine_tile(const CombineArgs<A> &a, uint64_t g
   const bool live = i0 + lane < Lc;
   const uint64_t slot_stride = (uint64_t)a.C * a.Lmax;
   const T *col = a.partial + (uint64_t)c * a.Lmax + i0 + lane;
-  // the wave's 16 groups own one contiguous run of slots; walk it with four
-  // independent loads in flight and close a group whenever its slots end
+  // the wave's 16 groups own one contiguous run of slots; walk it with
+  // kCombineLoads independent loads in flight (the kernel waits on memory,
+  // not on its few VALU operations) and close a group whenever its slots end
   const int gl_first = warp * (kCombineTile / 4), gl_last = gl_first + kCombineTile / 4;
   for (int gl = gl_first; gl < gl_last; ++gl) tile[gl][lane] = 0;
   const uint64_t ga = g0 + gl_first;
@@ -487,12 +496,13 @@ __device__ __forceinline__ void combine_tile(const CombineArgs<A> &a, uint64_t g
     int gl = gl_first;
     uint32_t next_end = a.slot_off[ga + 1];
     T acc = 0;
-    for (uint32_t sl = s_begin; sl < s_end; sl += 4) {
-      T v[4];
+    for (uint32_t sl = s_begin; sl < s_end; sl += kCombineLoads) {
+      T v[kCombineLoads];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) v[u] = (live && sl + u < s_end) ? col[(uint64_t)(sl + u) * slot_stride] : 0;
+      for (int u = 0; u < kCombineLoads; ++u)
+        v[u] = (live && sl + u < s_end) ? col[(uint64_t)(sl + u) * slot_stride] : 0;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < kCombineLoads; ++u) {
         if (sl + u >= s_end) break;
         while (sl + u >= next_end) {  // uniform: slot boundaries are the same for every lane
           tile[gl][lane] = acc;

@@ -941,7 +941,8 @@ static int run_impl(peval_poly *h, const BetaArg &beta, uint64_t t0, uint32_t T,
       ma.C = Cc;
       ma.as_double = fp ? 1 : 0;
       ma.m = m;
-      const uint64_t total = (uint64_t)K * pl->NT / mono_slots(K);  // work-items
+      ma.R = mono_slots_for(K, (uint64_t)K * pl->NT);
+      const uint64_t total = (uint64_t)K * pl->NT / ma.R;  // work-items
       ma.xchunk = (uint32_t)(((total + 255) / 256 + kXcds - 1) / kXcds);
       ProfScope ps(st, 1);
       monomial_kernel<A><<<kXcds * ma.xchunk, 256, 0, st>>>(ma);
