@@ -333,8 +333,9 @@ int peval_tune_load(const char *path);
  * whether their K is the largest allowed, each group's K is moved one
  * doubling either way in turn (coordinate search), then the work items'
  * target cost is halved and doubled.  Candidates run with base point 2 into
- * scratch outputs of sum(T_j G_j elem_bytes) bytes allocated for the search;
- * a choice is kept only when it is at least 1% faster.  Results never
+ * scratch outputs of sum(T_j G_j elem_bytes) bytes allocated for the search
+ * (each timed as the median of five passes after a warm-up); a choice is
+ * kept only when it is at least 1% faster.  Results never
  * depend on the plan.
  * peval_batch_members reports, per member j, its terms per thread K[j],
  * chains C[j] and kernel kind[j] (0: 64-bit Shoup with K = 16; 1: 64-bit

@@ -374,9 +374,10 @@ static int plan_members(const std::vector<peval_poly *> &polys, const std::vecto
 // `outs`), the mean of two passes after one untimed pass.
 static int time_pass(const std::vector<BatchMember> &mem, const std::vector<void *> &outs, hipStream_t st,
                      float *ms) {
+  constexpr int kTimed = 5;  // passes timed one by one after a warm-up; the median is kept
   BatchCore core;
   int rc = batch_build(core, mem);
-  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipEvent_t ev[kTimed + 1] = {};
   if (rc == PEVAL_OK) {
     std::vector<BatchRun> runs(mem.size());
     for (size_t j = 0; j < mem.size(); ++j) {
@@ -386,25 +387,31 @@ static int time_pass(const std::vector<BatchMember> &mem, const std::vector<void
       runs[j].out = outs[j];
     }
     do {
-      if (hipMemcpy(core.d_run, runs.data(), runs.size() * sizeof(BatchRun), hipMemcpyHostToDevice) != hipSuccess ||
-          hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+      if (hipMemcpy(core.d_run, runs.data(), runs.size() * sizeof(BatchRun), hipMemcpyHostToDevice) != hipSuccess) {
         rc = fail(PEVAL_EDEVICE, "tuning set-up");
         break;
       }
-      if ((rc = batch_enqueue(core, st)) != PEVAL_OK) break;
-      if (hipEventRecord(e0, st) != hipSuccess) { rc = fail(PEVAL_EDEVICE, "event record"); break; }
-      for (int r = 0; r < 2 && rc == PEVAL_OK; ++r) rc = batch_enqueue(core, st);
+      for (auto &e : ev)
+        if (rc == PEVAL_OK && hipEventCreate(&e) != hipSuccess) rc = fail(PEVAL_EDEVICE, "tuning set-up");
       if (rc != PEVAL_OK) break;
-      if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(ms, e0, e1) != hipSuccess) {
-        rc = fail(PEVAL_EDEVICE, "tuning timing");
-        break;
+      if ((rc = batch_enqueue(core, st)) != PEVAL_OK) break;
+      if (hipEventRecord(ev[0], st) != hipSuccess) { rc = fail(PEVAL_EDEVICE, "event record"); break; }
+      for (int r = 0; r < kTimed && rc == PEVAL_OK; ++r) {
+        rc = batch_enqueue(core, st);
+        if (rc == PEVAL_OK && hipEventRecord(ev[r + 1], st) != hipSuccess) rc = fail(PEVAL_EDEVICE, "event record");
       }
-      *ms /= 2;
+      if (rc != PEVAL_OK) break;
+      if (hipEventSynchronize(ev[kTimed]) != hipSuccess) { rc = fail(PEVAL_EDEVICE, "tuning timing"); break; }
+      float t[kTimed];
+      for (int r = 0; r < kTimed && rc == PEVAL_OK; ++r)
+        if (hipEventElapsedTime(&t[r], ev[r], ev[r + 1]) != hipSuccess) rc = fail(PEVAL_EDEVICE, "tuning timing");
+      if (rc != PEVAL_OK) break;
+      std::sort(t, t + kTimed);
+      *ms = t[kTimed / 2];
     } while (false);
   }
-  if (e0) (void)hipEventDestroy(e0);
-  if (e1) (void)hipEventDestroy(e1);
+  for (auto &e : ev)
+    if (e) (void)hipEventDestroy(e);
   (void)hipStreamSynchronize(st);
   batch_release(core);
   return rc;

@@ -28,9 +28,11 @@ enum BatchKind : uint32_t {
 // Evaluations per pass of a kind's kernel: the small-K 64-bit kernel stages
 // 8, so that its stage leaves room for more waves per CU.
 __host__ __device__ constexpr int kind_P(uint32_t kind) { return kind == kKindW64Lo ? 8 : kBatchP; }
-// Waves per SIMD a kind's kernel is compiled for (its register bound).
+// Waves per SIMD a kind's kernel is compiled for (its register bound): the
+// 32-bit K = 32 one holds 96 running values, Gammas and quotients and needs
+// about 200 registers (two waves; with three it spilled over a hundred).
 __host__ __device__ constexpr int kind_waves(uint32_t kind) {
-  return (kind == kKindW64K16 || kind == kKindW32K32) ? 3 : 4;
+  return kind == kKindW32K32 ? 2 : kind == kKindW64K16 ? 3 : 4;
 }
 
 // Static part of one polynomial in a batch (device table).
