@@ -62,7 +62,8 @@ __global__ void batch_power_kernel(const BatchDesc *D, const BatchRun *R, uint32
 }
 
 template <class A>
-__device__ __forceinline__ void batch_mono_one(const BatchDesc &d, uint64_t t0, uint64_t local, const typename A::M &m) {
+__device__ __forceinline__ void batch_mono_one(const BatchDesc &d, uint64_t t0, uint64_t local, const typename A::M &m,
+                                               MonoTables<A> &lds) {
   using T = typename A::T;
   MonoArgs<A> a;
   a.coeff = (const T *)d.coeff;
@@ -82,8 +83,9 @@ __device__ __forceinline__ void batch_mono_one(const BatchDesc &d, uint64_t t0, 
   a.C = d.C;
   a.as_double = d.kind == kKindF64;  // FP64 members take chain starts and Gamma as doubles
   a.R = mono_slots(d.K);             // fixed per member: its work-items are counted when the batch is planned
+  a.tab_total = d.tab_total;
   a.m = m;
-  monomial_entry<A>(a, d.to.off, local);
+  monomial_block<A>(a, d.to.off, local, (uint64_t)d.K * d.NT / a.R, d.ntail ? d.tab_total : 0, lds);
 }
 
 // Each member's entries start on a block boundary (its range padded to whole
@@ -98,14 +100,17 @@ __global__ __launch_bounds__(kMonoBlock) void batch_mono_kernel(const BatchDesc 
                                                                 const uint32_t *__restrict__ block_member,
                                                                 const uint64_t *__restrict__ prefix, uint64_t nblocks,
                                                                 uint32_t xchunk) {
+  __shared__ union {
+    MonoTables<W32> w32;
+    MonoTables<W64> w64;
+  } lds;
   const uint64_t lb = xcd_logical_block(xchunk);
-  if (lb >= nblocks) return;
+  if (lb >= nblocks) return;  // uniform over the block
   const uint32_t j = __builtin_amdgcn_readfirstlane(block_member[lb]);
   const BatchDesc &d = D[j];
-  const uint64_t local = lb * kMonoBlock - prefix[j] + threadIdx.x;
-  if (local >= (uint64_t)d.K * d.NT / mono_slots(d.K)) return;  // the member's padding
-  if (d.w == 4) batch_mono_one<W32>(d, R[j].t0, local, d.m32);
-  else batch_mono_one<W64>(d, R[j].t0, local, d.m64);
+  const uint64_t local = lb * kMonoBlock - prefix[j] + threadIdx.x;  // past the member's items: padding
+  if (d.w == 4) batch_mono_one<W32>(d, R[j].t0, local, d.m32, lds.w32);
+  else batch_mono_one<W64>(d, R[j].t0, local, d.m64, lds.w64);
 }
 
 template <class A, int K, int P>

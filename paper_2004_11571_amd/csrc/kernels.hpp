@@ -91,6 +91,7 @@ struct MonoArgs {
   uint32_t ntail, K, C;
   uint32_t as_double;           // store canonical values as doubles (for the FP64 product)
   uint32_t R;                   // slots per work-item: 1 or mono_slots(K)
+  uint32_t tab_total;           // power-table entries (all tail variables)
   uint32_t xchunk;              // logical blocks per XCD (grid = 8 xchunk blocks of 256)
   typename A::M m;
 };
@@ -119,7 +120,8 @@ constexpr int kMonoFastTail = 8;  // tail exponents held in registers per slot
 // from HBM about K times over.)  NT is a multiple of 64, K a power of two
 // and R (1, 2 or 4) divides K.
 template <class A, int R>
-__device__ __forceinline__ void monomial_entries(const MonoArgs<A> &a, const uint32_t *off, uint64_t idx) {
+__device__ __forceinline__ void monomial_entries(const MonoArgs<A> &a, const uint32_t *off, uint64_t idx,
+                                                 const typename A::T *tval, const typename A::T *tquot) {
   using T = typename A::T;
   const uint32_t sh = 6 + __builtin_ctz(a.K / R);  // log2(64 K / R)
   const uint64_t tile = idx >> sh;
@@ -159,8 +161,8 @@ __device__ __forceinline__ void monomial_entries(const MonoArgs<A> &a, const uin
 #pragma unroll
     for (int u = 0; u < R; ++u) {
       const uint32_t at = off[v] + ex[u][v];
-      tv[u] = a.tval[at];
-      tq[u] = a.tquot[at];
+      tv[u] = tval[at];
+      tq[u] = tquot[at];
     }
 #pragma unroll
     for (int u = 0; u < R; ++u) mi[u] = (v == 0) ? tv[u] : A::mul_lazy(mi[u], tv[u], tq[u], a.m);
@@ -174,7 +176,7 @@ __device__ __forceinline__ void monomial_entries(const MonoArgs<A> &a, const uin
     for (int u = 0; u < R; ++u) {
       const uint32_t e = live[u] ? a.exps[(uint64_t)v * a.s + first + k0 + u] : 0u;
       const uint32_t at = off[v] + e;
-      mi[u] = A::mul_lazy(mi[u], a.tval[at], a.tquot[at], a.m);
+      mi[u] = A::mul_lazy(mi[u], tval[at], tquot[at], a.m);
     }
   }
 #pragma unroll
@@ -213,11 +215,40 @@ __device__ __forceinline__ void monomial_entries(const MonoArgs<A> &a, const uin
 }
 
 template <class A>
-__device__ __forceinline__ void monomial_entry(const MonoArgs<A> &a, const uint32_t *off, uint64_t idx) {
+__device__ __forceinline__ void monomial_entry(const MonoArgs<A> &a, const uint32_t *off, uint64_t idx,
+                                               const typename A::T *tval, const typename A::T *tquot) {
   switch (a.R) {
-    case 4: monomial_entries<A, 4>(a, off, idx); break;
-    case 2: monomial_entries<A, 2>(a, off, idx); break;
-    default: monomial_entries<A, 1>(a, off, idx); break;
+    case 4: monomial_entries<A, 4>(a, off, idx, tval, tquot); break;
+    case 2: monomial_entries<A, 2>(a, off, idx, tval, tquot); break;
+    default: monomial_entries<A, 1>(a, off, idx, tval, tquot); break;
+  }
+}
+
+// The power tables of a run (a few hundred entries for the usual degrees)
+// are copied into LDS by every block of the monomial kernels, so that the
+// tail variables' lookups, one after another, wait on LDS instead of L2;
+// larger tables are read where they are.
+constexpr uint32_t kMonoLdsEntries = 1024;
+
+template <class A>
+struct MonoTables {
+  typename A::T val[kMonoLdsEntries], quot[kMonoLdsEntries];
+};
+
+// Every thread of the block calls this (it holds a barrier when the tables
+// are staged); idx past `total` does nothing.
+template <class A>
+__device__ __forceinline__ void monomial_block(const MonoArgs<A> &a, const uint32_t *off, uint64_t idx,
+                                               uint64_t total, uint32_t tab_total, MonoTables<A> &lds) {
+  if (tab_total <= kMonoLdsEntries) {  // uniform over the block
+    for (uint32_t e = threadIdx.x; e < tab_total; e += blockDim.x) {
+      lds.val[e] = a.tval[e];
+      lds.quot[e] = a.tquot[e];
+    }
+    __syncthreads();
+    if (idx < total) monomial_entry<A>(a, off, idx, lds.val, lds.quot);
+  } else if (idx < total) {
+    monomial_entry<A>(a, off, idx, a.tval, a.tquot);
   }
 }
 
@@ -226,9 +257,9 @@ __device__ __forceinline__ void monomial_entry(const MonoArgs<A> &a, const uint3
 // on one XCD.
 template <class A>
 __global__ void monomial_kernel(MonoArgs<A> a) {
+  __shared__ MonoTables<A> lds;
   const uint64_t idx = xcd_logical_block(a.xchunk) * blockDim.x + threadIdx.x;
-  if (idx >= (uint64_t)a.K * a.NT / a.R) return;
-  monomial_entry<A>(a, a.to.off, idx);
+  monomial_block<A>(a, a.to.off, idx, (uint64_t)a.K * a.NT / a.R, a.ntail ? a.tab_total : 0, lds);
 }
 
 // ---------------------------------------------------------------------------

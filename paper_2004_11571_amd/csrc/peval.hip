@@ -942,6 +942,7 @@ static int run_impl(peval_poly *h, const BetaArg &beta, uint64_t t0, uint32_t T,
       ma.as_double = fp ? 1 : 0;
       ma.m = m;
       ma.R = mono_slots_for(K, (uint64_t)K * pl->NT);
+      ma.tab_total = h->tab_total;
       const uint64_t total = (uint64_t)K * pl->NT / ma.R;  // work-items
       ma.xchunk = (uint32_t)(((total + 255) / 256 + kXcds - 1) / kXcds);
       ProfScope ps(st, 1);
