@@ -342,8 +342,8 @@ def batch_main(args):
         e["K"][str(int(k))] = e["K"].get(str(int(k)), 0) + 1
     steps = args.steps or 20
     # the first replays of a newly instantiated graph can run far slower
-    # (alternate replays up to the eighth or so); at least ten untimed ones
-    warm = max(10, args.warmup)
+    # (up to the eighth or so); at least twenty untimed ones
+    warm = max(20, args.warmup)
     for _ in range(warm):
         b.run(betas, outs, stream=stream)
     torch.cuda.synchronize()

@@ -124,7 +124,7 @@ void batch_plan(BatchCore &b, const std::vector<BatchMember> &mem, void *arena, 
   const uint32_t count = (uint32_t)mem.size();
   b.count = count;
   b.descs.assign(count, BatchDesc{});
-  std::vector<uint64_t> ptab(count + 1, 0), pmono(count + 1, 0), pout(count + 1, 0);
+  std::vector<uint64_t> ptab(count + 1, 0), pmono(count + 1, 0), pout(count + 1, 0), mblocks(count), tiles(count);
   std::vector<BatchItem> items;
   b.scratch_bytes = batch_scratch_need(mem);
   b.arena = arena;
@@ -172,12 +172,31 @@ void batch_plan(BatchCore &b, const std::vector<BatchMember> &mem, void *arena, 
     d.partial = d.direct ? nullptr : take((size_t)d.C * d.Lmax * pl.nslots * w);
     ptab[j + 1] = ptab[j] + (d.ntail ? h->tab_total : 0);
     // whole blocks per member, so that a block's member is one table entry
-    pmono[j + 1] = pmono[j] + align_up((size_t)pl.K * pl.NT / mono_slots(pl.K), kMonoBlock);
+    mblocks[j] = align_up((size_t)pl.K * pl.NT / mono_slots(pl.K), kMonoBlock) / kMonoBlock;
     // combine tiles; none for a direct member
-    pout[j + 1] = pout[j] + (d.direct ? 0
-                                      : ((h->G + kCombineTile - 1) / kCombineTile) * d.C *
-                                            (((uint64_t)d.Lmax + kCombineTile - 1) / kCombineTile));
+    tiles[j] = d.direct ? 0
+                        : ((h->G + kCombineTile - 1) / kCombineTile) * d.C *
+                              (((uint64_t)d.Lmax + kCombineTile - 1) / kCombineTile);
   }
+  // monomial blocks and combine tiles grouped by kind (each kind's members
+  // in index order), so that every kind's range is contiguous: pmono[j] and
+  // pout[j] are member j's first entry and first tile
+  uint64_t mcur = 0, tcur = 0;
+  for (uint32_t kind = 0; kind < kKinds; ++kind) {
+    b.kind_mono[kind] = mcur / kMonoBlock;
+    b.kind_tiles[kind] = tcur;
+    for (uint32_t j = 0; j < count; ++j) {
+      if (b.descs[j].kind != kind) continue;
+      pmono[j] = mcur;
+      pout[j] = tcur;
+      mcur += mblocks[j] * kMonoBlock;
+      tcur += tiles[j];
+    }
+  }
+  b.kind_mono[kKinds] = mcur / kMonoBlock;
+  b.kind_tiles[kKinds] = tcur;
+  pmono[count] = mcur;
+  pout[count] = tcur;
   // Work items, biggest first.  An item costs K x (evaluations of its chain);
   // within one member the chains differ by at most one evaluation, so
   // ordering members by K x Lmax and emitting each member's items chain by
@@ -208,8 +227,8 @@ void batch_plan(BatchCore &b, const std::vector<BatchMember> &mem, void *arena, 
   b.mono_blocks = b.mono_total / kMonoBlock;
   std::vector<uint32_t> bmono(b.mono_blocks), bout(b.out_total);
   for (uint32_t j = 0; j < count; ++j) {
-    std::fill(bmono.begin() + pmono[j] / kMonoBlock, bmono.begin() + pmono[j + 1] / kMonoBlock, j);
-    std::fill(bout.begin() + pout[j], bout.begin() + pout[j + 1], j);
+    std::fill(bmono.begin() + pmono[j] / kMonoBlock, bmono.begin() + pmono[j] / kMonoBlock + mblocks[j], j);
+    std::fill(bout.begin() + pout[j], bout.begin() + pout[j] + tiles[j], j);
   }
 
   // blob image: descriptors, runs, items, prefixes, queue counter
@@ -261,32 +280,95 @@ int batch_build(BatchCore &b, const std::vector<BatchMember> &mem) {
   return batch_set_blocks(b);
 }
 
+int BatchFork::create() {
+  if (hipEventCreateWithFlags(&fork, hipEventDisableTiming) != hipSuccess) return fail(PEVAL_EDEVICE, "event creation");
+  for (uint32_t k = 0; k < kKinds; ++k) {
+    if (hipStreamCreateWithFlags(&aux[k], hipStreamNonBlocking) != hipSuccess)
+      return fail(PEVAL_EDEVICE, "stream creation");
+    if (hipEventCreateWithFlags(&join[k], hipEventDisableTiming) != hipSuccess)
+      return fail(PEVAL_EDEVICE, "event creation");
+  }
+  return PEVAL_OK;
+}
+
+void BatchFork::destroy() {
+  for (uint32_t k = 0; k < kKinds; ++k) {
+    if (aux[k]) (void)hipStreamDestroy(aux[k]);
+    if (join[k]) (void)hipEventDestroy(join[k]);
+    aux[k] = nullptr;
+    join[k] = nullptr;
+  }
+  if (fork) (void)hipEventDestroy(fork);
+  fork = nullptr;
+}
+
+// Monomial blocks [b0, b1) and combine tiles [t0, t1) of one batched pass.
+static int enqueue_mono(const BatchCore &b, hipStream_t st, uint64_t b0, uint64_t b1) {
+  if (b1 <= b0) return PEVAL_OK;
+  const uint32_t xchunk = (uint32_t)((b1 - b0 + kXcds - 1) / kXcds);
+  batch_mono_kernel<<<kXcds * xchunk, kMonoBlock, 0, st>>>(b.d_desc, b.d_run, b.d_bmono, b.d_pmono, b0, b1 - b0,
+                                                           xchunk);
+  HIP_TRY(hipGetLastError());
+  return PEVAL_OK;
+}
+
+static int enqueue_combine(const BatchCore &b, hipStream_t st, uint64_t t0, uint64_t t1) {
+  if (t1 <= t0) return PEVAL_OK;
+  batch_combine_kernel<<<(unsigned)(t1 - t0), kCombineBlock, 0, st>>>(b.d_desc, b.d_run, b.d_bout, b.d_pout, t0);
+  HIP_TRY(hipGetLastError());
+  return PEVAL_OK;
+}
+
+static int enqueue_eval(const BatchCore &b, hipStream_t st, uint32_t kind) {
+  const uint32_t first = b.kind_first[kind], n = b.kind_first[kind + 1] - first;
+  if (!n) return PEVAL_OK;
+  batch_eval_fn(kind)<<<b.eval_blocks[kind], kEvalBlock, 0, st>>>(b.d_desc, b.d_run, b.d_items + first, n,
+                                                                  b.d_counter + kind);
+  HIP_TRY(hipGetLastError());
+  return PEVAL_OK;
+}
+
 // Kernels of one batched pass (the run table must already be on the device).
-int batch_enqueue(const BatchCore &b, hipStream_t st) {
+// With side streams (fork) and more than one kind of member, each kind's
+// monomial, evaluation and combine kernels run in order on a stream of their
+// own, the streams side by side after the power tables: one kind's
+// memory-bound monomial and combine kernels overlap another kind's ALU-bound
+// evaluation, and each evaluation kernel's last items drain while other
+// kernels take the freed CUs.  Without, all kernels follow one another on st.
+int batch_enqueue(const BatchCore &b, hipStream_t st, const BatchFork *fork) {
   batch_reset_kernel<<<1, 64, 0, st>>>(b.d_counter);
   HIP_TRY(hipGetLastError());
   if (b.tab_total) {
     batch_power_kernel<<<(unsigned)((b.tab_total + 255) / 256), 256, 0, st>>>(b.d_desc, b.d_run, b.count, b.d_ptab);
     HIP_TRY(hipGetLastError());
   }
-  if (b.mono_blocks) {
-    const uint32_t xchunk = (uint32_t)((b.mono_blocks + kXcds - 1) / kXcds);
-    batch_mono_kernel<<<kXcds * xchunk, kMonoBlock, 0, st>>>(b.d_desc, b.d_run, b.d_bmono, b.d_pmono,
-                                                             b.mono_blocks, xchunk);
-    HIP_TRY(hipGetLastError());
+  uint32_t kinds_present = 0;
+  for (uint32_t kind = 0; kind < kKinds; ++kind) kinds_present += b.kind_first[kind + 1] > b.kind_first[kind];
+  if (!fork || kinds_present < 2) {
+    PEVAL_TRY(enqueue_mono(b, st, 0, b.mono_blocks));
+    for (uint32_t kind = 0; kind < kKinds; ++kind) PEVAL_TRY(enqueue_eval(b, st, kind));
+    return enqueue_combine(b, st, 0, b.out_total);
   }
+  HIP_TRY(hipEventRecord(fork->fork, st));  // reset and power tables done
+  bool joins[kKinds] = {}, first_kind = true;
   for (uint32_t kind = 0; kind < kKinds; ++kind) {
-    const uint32_t first = b.kind_first[kind], n = b.kind_first[kind + 1] - first;
-    if (!n) continue;
-    const BatchItem *it = b.d_items + first;
-    uint32_t *ctr = b.d_counter + kind;
-    batch_eval_fn(kind)<<<b.eval_blocks[kind], kEvalBlock, 0, st>>>(b.d_desc, b.d_run, it, n, ctr);
-    HIP_TRY(hipGetLastError());
+    if (b.kind_first[kind + 1] == b.kind_first[kind]) continue;
+    hipStream_t ks = st;
+    if (!first_kind) {
+      ks = fork->aux[kind];
+      HIP_TRY(hipStreamWaitEvent(ks, fork->fork, 0));
+    }
+    first_kind = false;
+    PEVAL_TRY(enqueue_mono(b, ks, b.kind_mono[kind], b.kind_mono[kind + 1]));
+    PEVAL_TRY(enqueue_eval(b, ks, kind));
+    PEVAL_TRY(enqueue_combine(b, ks, b.kind_tiles[kind], b.kind_tiles[kind + 1]));
+    if (ks != st) {
+      HIP_TRY(hipEventRecord(fork->join[kind], ks));
+      joins[kind] = true;
+    }
   }
-  if (b.out_total) {  // out_total counts combine tiles
-    batch_combine_kernel<<<(unsigned)b.out_total, kCombineBlock, 0, st>>>(b.d_desc, b.d_run, b.d_bout, b.d_pout);
-    HIP_TRY(hipGetLastError());
-  }
+  for (uint32_t kind = 0; kind < kKinds; ++kind)
+    if (joins[kind]) HIP_TRY(hipStreamWaitEvent(st, fork->join[kind], 0));
   return PEVAL_OK;
 }
 
@@ -305,6 +387,7 @@ struct peval_batch {
   bool slot_used[kRunSlots] = {};
   int next_slot = 0;
   hipStream_t cap_stream = nullptr;
+  BatchFork fork;  // side streams of the evaluation kernels
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t done = nullptr;
@@ -321,6 +404,7 @@ static void batch_free(peval_batch *b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  b->fork.destroy();
   if (b->done) (void)hipEventDestroy(b->done);
   for (int k = 0; k < kRunSlots; ++k) {
     if (b->copied[k]) (void)hipEventDestroy(b->copied[k]);
@@ -373,7 +457,7 @@ static int plan_members(const std::vector<peval_poly *> &polys, const std::vecto
 // Device time of one pass of a planned batch (base points 2, outputs in
 // `outs`), the mean of two passes after one untimed pass.
 static int time_pass(const std::vector<BatchMember> &mem, const std::vector<void *> &outs, hipStream_t st,
-                     float *ms) {
+                     const BatchFork *fork, float *ms) {
   constexpr int kTimed = 5;  // passes timed one by one after a warm-up; the median is kept
   BatchCore core;
   int rc = batch_build(core, mem);
@@ -394,10 +478,10 @@ static int time_pass(const std::vector<BatchMember> &mem, const std::vector<void
       for (auto &e : ev)
         if (rc == PEVAL_OK && hipEventCreate(&e) != hipSuccess) rc = fail(PEVAL_EDEVICE, "tuning set-up");
       if (rc != PEVAL_OK) break;
-      if ((rc = batch_enqueue(core, st)) != PEVAL_OK) break;
+      if ((rc = batch_enqueue(core, st, fork)) != PEVAL_OK) break;
       if (hipEventRecord(ev[0], st) != hipSuccess) { rc = fail(PEVAL_EDEVICE, "event record"); break; }
       for (int r = 0; r < kTimed && rc == PEVAL_OK; ++r) {
-        rc = batch_enqueue(core, st);
+        rc = batch_enqueue(core, st, fork);
         if (rc == PEVAL_OK && hipEventRecord(ev[r + 1], st) != hipSuccess) rc = fail(PEVAL_EDEVICE, "event record");
       }
       if (rc != PEVAL_OK) break;
@@ -438,11 +522,13 @@ static int tune_batch(const std::vector<peval_poly *> &polys, const std::vector<
   for (uint32_t j = 0; j < count; ++j) outs[j] = (char *)obuf + off[j];
   int rc = hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess ? PEVAL_OK
                                                                             : fail(PEVAL_EDEVICE, "stream creation");
+  BatchFork fork;  // candidates run as the batch will
+  if (rc == PEVAL_OK) rc = fork.create();
   *trials = 0;
   auto measure = [&](const BatchChoice &ch, float *ms) {
     std::vector<BatchMember> mem;
     int r = plan_members(polys, Ts, ch, mem);
-    if (r == PEVAL_OK) r = time_pass(mem, outs, st, ms);
+    if (r == PEVAL_OK) r = time_pass(mem, outs, st, &fork, ms);
     ++*trials;
     return r;
   };
@@ -472,6 +558,7 @@ static int tune_batch(const std::vector<peval_poly *> &polys, const std::vector<
       *best_ms = ms;
     }
   }
+  fork.destroy();
   if (st) (void)hipStreamDestroy(st);
   (void)hipFree(obuf);
   return rc;
@@ -521,12 +608,13 @@ extern "C" int peval_batch_create(uint32_t count, peval_poly *const *polys, cons
   }
   if (hipEventCreateWithFlags(&b->done, hipEventDisableTiming) != hipSuccess)
     return bail(fail(PEVAL_EDEVICE, "event creation"));
+  if ((rc = b->fork.create()) != PEVAL_OK) return bail(rc);
   if (b->use_graph) {
     if (hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
       return bail(fail(PEVAL_EDEVICE, "stream creation"));
     if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
       return bail(fail(PEVAL_EDEVICE, "begin capture"));
-    int erc = batch_enqueue(b->core, b->cap_stream);
+    int erc = batch_enqueue(b->core, b->cap_stream, &b->fork);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(b->cap_stream, &g);
     if (erc != PEVAL_OK) return bail(erc);
@@ -572,7 +660,7 @@ extern "C" int peval_batch_run(peval_batch *b, const uint64_t *const *betas, con
   if (b->use_graph) {
     HIP_TRY(hipGraphLaunch(b->exec, st));
   } else {
-    PEVAL_TRY(batch_enqueue(b->core, st));
+    PEVAL_TRY(batch_enqueue(b->core, st, &b->fork));
   }
   HIP_TRY(hipEventRecord(b->done, st));
   b->have_done = true;

@@ -18,6 +18,18 @@ struct BatchMember {
 };
 
 // Device state of one batched pass.
+// Side streams on which the evaluation kernels of the second and later kinds
+// run beside the first (forked after the monomial kernel, joined before the
+// combine), so that one kind's blocks start on CUs as another kind's last
+// items drain.  Owned by whoever owns the BatchCore's launches.
+struct BatchFork {
+  hipStream_t aux[kKinds] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kKinds] = {};
+  int create();   // PEVAL_OK or an error; default-priority non-blocking streams
+  void destroy();
+};
+
 struct BatchCore {
   uint32_t count = 0;
   uint32_t n_items = 0;
@@ -25,6 +37,8 @@ struct BatchCore {
   int eval_blocks[kKinds] = {};          // persistent blocks of each kind's evaluation kernel
   uint64_t tab_total = 0, mono_total = 0, out_total = 0;
   uint64_t mono_blocks = 0;  // blocks of the monomial kernel (each member's entries padded to whole blocks)
+  uint64_t kind_mono[kKinds + 1] = {};   // monomial blocks of kind k: kind_mono[k] .. kind_mono[k+1]-1
+  uint64_t kind_tiles[kKinds + 1] = {};  // combine tiles of kind k, likewise
   size_t scratch_bytes = 0;
   std::vector<BatchDesc> descs;
   void *d_blob = nullptr;  // descriptors, run table, items, prefixes, queue counter
@@ -58,7 +72,8 @@ void batch_bind(BatchCore &b, void *d_blob);
 // Allocates scratch and blob with hipMalloc and uploads the image.  Handles
 // must stay alive while the batch is used.
 int batch_build(BatchCore &b, const std::vector<BatchMember> &mem);
-int batch_enqueue(const BatchCore &b, hipStream_t st);
+// fork: optional side streams for the evaluation kernels (nullptr: all on st)
+int batch_enqueue(const BatchCore &b, hipStream_t st, const BatchFork *fork = nullptr);
 void batch_release(BatchCore &b);
 // Persistent blocks of the evaluation kernels for this batch's items.
 int batch_set_blocks(BatchCore &b);

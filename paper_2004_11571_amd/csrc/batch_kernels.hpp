@@ -89,8 +89,9 @@ __device__ __forceinline__ void batch_mono_one(const BatchDesc &d, uint64_t t0, 
 }
 
 // Each member's entries start on a block boundary (its range padded to whole
-// blocks of kMonoBlock), so a block belongs to one member, read from a table:
-// the member and its descriptor are uniform over the block.  Blocks are
+// blocks of kMonoBlock, the members of one kind together), so a block belongs
+// to one member, read from a table: the member and its descriptor are
+// uniform over the block.  A launch covers blocks base .. base + nblocks - 1,
 // renumbered per XCD as in monomial_kernel (xchunk logical blocks per XCD,
 // grid 8 xchunk).
 constexpr uint32_t kMonoBlock = 256;
@@ -98,14 +99,15 @@ constexpr uint32_t kMonoBlock = 256;
 __global__ __launch_bounds__(kMonoBlock) void batch_mono_kernel(const BatchDesc *__restrict__ D,
                                                                 const BatchRun *__restrict__ R,
                                                                 const uint32_t *__restrict__ block_member,
-                                                                const uint64_t *__restrict__ prefix, uint64_t nblocks,
-                                                                uint32_t xchunk) {
+                                                                const uint64_t *__restrict__ prefix, uint64_t base,
+                                                                uint64_t nblocks, uint32_t xchunk) {
   __shared__ union {
     MonoTables<W32> w32;
     MonoTables<W64> w64;
   } lds;
-  const uint64_t lb = xcd_logical_block(xchunk);
-  if (lb >= nblocks) return;  // uniform over the block
+  const uint64_t rel = xcd_logical_block(xchunk);
+  if (rel >= nblocks) return;  // uniform over the block
+  const uint64_t lb = base + rel;  // blocks base .. base + nblocks - 1 of the pass
   const uint32_t j = __builtin_amdgcn_readfirstlane(block_member[lb]);
   const BatchDesc &d = D[j];
   const uint64_t local = lb * kMonoBlock - prefix[j] + threadIdx.x;  // past the member's items: padding
@@ -197,8 +199,9 @@ inline BatchEvalFn batch_eval_fn(uint32_t kind) {
   }
 }
 
-// Flattened combine tiles: member j owns tiles prefix[j] .. prefix[j+1]-1,
-// ordered (evaluation tile, chain, group tile) with the group tile fastest.
+// Flattened combine tiles: member j owns its tiles from prefix[j] on (the
+// members of one kind together), ordered (evaluation tile, chain, group
+// tile) with the group tile fastest.
 template <class A>
 __device__ __forceinline__ void batch_combine_one(const BatchDesc &d, void *out, uint64_t local, const typename A::M &m,
                                                   void *lds) {
@@ -225,9 +228,9 @@ __device__ __forceinline__ void batch_combine_one(const BatchDesc &d, void *out,
 __global__ __launch_bounds__(kCombineBlock) void batch_combine_kernel(const BatchDesc *__restrict__ D,
                                                                       const BatchRun *__restrict__ R,
                                                                       const uint32_t *__restrict__ tile_member,
-                                                                      const uint64_t *__restrict__ prefix) {
+                                                                      const uint64_t *__restrict__ prefix, uint64_t base) {
   __shared__ __align__(16) uint64_t tile[kCombineTile][kCombineTile + 1];
-  const uint64_t idx = blockIdx.x;  // the grid is exactly the batch's tiles
+  const uint64_t idx = base + blockIdx.x;  // the grid is exactly tiles base .. base + gridDim.x - 1
   const uint32_t j = __builtin_amdgcn_readfirstlane(tile_member[idx]);
   const BatchDesc &d = D[j];
   const uint64_t local = idx - prefix[j];
