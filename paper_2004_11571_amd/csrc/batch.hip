@@ -387,7 +387,7 @@ struct peval_batch {
   bool slot_used[kRunSlots] = {};
   int next_slot = 0;
   hipStream_t cap_stream = nullptr;
-  BatchFork fork;  // side streams of the evaluation kernels
+  BatchFork fork;  // a stream per kind of member (see batch_enqueue)
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipEvent_t done = nullptr;

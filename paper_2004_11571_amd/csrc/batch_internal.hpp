@@ -18,10 +18,11 @@ struct BatchMember {
 };
 
 // Device state of one batched pass.
-// Side streams on which the evaluation kernels of the second and later kinds
-// run beside the first (forked after the monomial kernel, joined before the
-// combine), so that one kind's blocks start on CUs as another kind's last
-// items drain.  Owned by whoever owns the BatchCore's launches.
+// Side streams on which the kernels of the second and later kinds of member
+// run beside the first kind's (forked after the power tables, joined at the
+// end of the pass; see batch_enqueue).  Every wait is on an event recorded
+// earlier in submission order, so streams sharing a hardware queue only
+// lose overlap, never progress.  Owned by whoever owns the launches.
 struct BatchFork {
   hipStream_t aux[kKinds] = {};
   hipEvent_t fork = nullptr;
@@ -72,7 +73,7 @@ void batch_bind(BatchCore &b, void *d_blob);
 // Allocates scratch and blob with hipMalloc and uploads the image.  Handles
 // must stay alive while the batch is used.
 int batch_build(BatchCore &b, const std::vector<BatchMember> &mem);
-// fork: optional side streams for the evaluation kernels (nullptr: all on st)
+// fork: optional side streams, one per kind of member (nullptr: all on st)
 int batch_enqueue(const BatchCore &b, hipStream_t st, const BatchFork *fork = nullptr);
 void batch_release(BatchCore &b);
 // Persistent blocks of the evaluation kernels for this batch's items.

@@ -111,6 +111,7 @@ struct peval_server {
   double t_start = 0, t_last_done = 0;
   // device resources
   hipStream_t st[kStreams] = {nullptr, nullptr};
+  BatchFork fork[kStreams];  // side streams of each pass stream's kinds
   hipStream_t copy_st = nullptr;
   hipEvent_t ev[kStreams] = {nullptr, nullptr};
   hipEvent_t ev0[kStreams] = {nullptr, nullptr};  // pass start (timing)
@@ -539,7 +540,7 @@ static bool launch_pass_impl(peval_server *S, std::unique_lock<std::mutex> &lk) 
       }
       batch_bind(core, blob);
       launch_rc = batch_set_blocks(core);
-      if (launch_rc == PEVAL_OK) launch_rc = batch_enqueue(core, st);
+      if (launch_rc == PEVAL_OK) launch_rc = batch_enqueue(core, st, &S->fork[slot]);
       if (launch_rc == PEVAL_OK && hipEventRecord(S->ev[slot], st) != hipSuccess)
         launch_rc = fail(PEVAL_EDEVICE, "event record");
     } while (false);
@@ -743,6 +744,7 @@ extern "C" int peval_server_create(uint64_t hbm_budget_bytes, uint32_t flags, pe
     for (int k = 0; ok && k < kStreams; ++k)
       ok = hipStreamCreateWithFlags(&S->st[k], hipStreamNonBlocking) == hipSuccess &&
            hipEventCreate(&S->ev[k]) == hipSuccess && hipEventCreate(&S->ev0[k]) == hipSuccess;
+    for (int k = 0; ok && k < kStreams; ++k) ok = S->fork[k].create() == PEVAL_OK;
     ok = ok && hipStreamCreateWithFlags(&S->copy_st, hipStreamNonBlocking) == hipSuccess;
     for (int k = 0; ok && k < 4; ++k) ok = hipStreamCreateWithFlags(&S->copy_sts[k], hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
@@ -1053,6 +1055,7 @@ extern "C" int peval_server_destroy(peval_server *S) {
     if (S->ev[k]) (void)hipEventDestroy(S->ev[k]);
     if (S->ev0[k]) (void)hipEventDestroy(S->ev0[k]);
     if (S->st[k]) (void)hipStreamDestroy(S->st[k]);
+    S->fork[k].destroy();
   }
   if (S->copy_st) (void)hipStreamDestroy(S->copy_st);
   for (int k = 0; k < 4; ++k)
