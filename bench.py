@@ -767,7 +767,7 @@ def main():
         tk, tp, tc, tms = poly.autotune(w.beta, w.T)
         tuned = {"K": tk, "P": tp, "C": tc, "tuned_run_ms": tms, "tune_s": time.time() - t_tune,
                  "heuristic": dict(zip("KPC", heur))}
-    K, P, C = poly.get_tuning(w.T)
+    K, P, C = poly.points_tuning(w.T) if points_mode else poly.get_tuning(w.T)
     single = (K, P, C) == (0, 0, 0) and not points_mode  # one kernel for the whole run
     dt = torch.int64 if poly.elem_bytes == 8 else torch.int32
     out = torch.empty((w.T, poly.G), dtype=dt, device=dev)
@@ -905,7 +905,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name + ("_random_points" if points_mode else ""), "n": w.n, "s": w.s,
                    "T": w.T, "p": w.p, "G": poly.G,
-                   "tuning": "single_launch" if single else {"K": K, "P": 8 if points_mode else P, "C": C},
+                   "tuning": "single_launch" if single else {"K": K, "P": P, "C": C},
                    "tuning_source": "explicit" if args.tuning else ("autotuned" if tuned else "heuristic"),
                    "autotune": tuned,
                    "arith": arith,

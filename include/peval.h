@@ -183,6 +183,11 @@ int peval_run_points(peval_poly *h, const uint64_t *points, uint32_t T, void *ou
 int peval_run_points_async(peval_poly *h, const uint64_t *points, uint32_t T, void *dev_out,
                            void *stream);
 
+/* The tiles the next point-mode run with T points would use: terms per
+ * thread K (at most 16; 8 under the FP64 product), points per pass P and
+ * chains C.  Outputs must not be NULL. */
+int peval_points_tuning(peval_poly *h, uint32_t T, uint32_t *K, uint32_t *P, uint32_t *C);
+
 /*
  * Host-only planner of the point mode's tables (for tests): residue width
  * w (4 or 8), ntail = n-2 tail degree bounds -> number of factor tables nf

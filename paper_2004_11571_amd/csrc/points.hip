@@ -338,6 +338,16 @@ extern "C" int peval_run_points_async(peval_poly *h, const uint64_t *points_dev,
   return points_locked(h, points_dev, T, dev_out, (hipStream_t)stream);
 }
 
+extern "C" int peval_points_tuning(peval_poly *h, uint32_t T, uint32_t *K, uint32_t *P, uint32_t *C) {
+  if (!h || !K || !P || !C) return fail(PEVAL_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lk(h->mu);
+  const Tuning t = points_tuning(h, T);
+  *K = t.K;
+  *P = t.P;
+  *C = t.C;
+  return PEVAL_OK;
+}
+
 extern "C" int peval_run_points(peval_poly *h, const uint64_t *points_host, uint32_t T, void *out) {
   PEVAL_TRY(check_points_args(h, points_host, T));
   if (T == 0 || h->G == 0) return PEVAL_OK;

@@ -71,6 +71,7 @@ def lib() -> ctypes.CDLL:
         "peval_destroy": ([vp], i32),
         "peval_set_tuning": ([vp, u32, u32, u32], i32),
         "peval_get_tuning": ([vp, u32, vp, vp, vp], i32),
+        "peval_points_tuning": ([vp, u32, vp, vp, vp], i32),
         "peval_prof_enable": ([i32], i32),
         "peval_prof_read": ([vp, vp], i32),
         "peval_layout": ([vp, u64, u32, u32, vp, vp, vp, vp, vp, vp], i32),
@@ -267,6 +268,12 @@ class Poly:
         """(K, P, C) of the next run of T evaluations; (0, 0, 0) for the single-launch path."""
         k, p, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
         _check(lib().peval_get_tuning(self.handle, T, ctypes.byref(k), ctypes.byref(p), ctypes.byref(c)))
+        return k.value, p.value, c.value
+
+    def points_tuning(self, T: int) -> Tuple[int, int, int]:
+        """(K, P, C) of the next point-mode run with T points."""
+        k, p, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().peval_points_tuning(self.handle, T, ctypes.byref(k), ctypes.byref(p), ctypes.byref(c)))
         return k.value, p.value, c.value
 
     def autotune(self, beta, T: int, exhaustive: bool = False):

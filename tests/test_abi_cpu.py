@@ -203,6 +203,7 @@ def test_points_factor_plan_bad_arguments():
     L = PV.lib()
     assert L.peval_run_points(None, None, 1, None) == PV.EINVAL
     assert L.peval_run_points_async(None, None, 1, None, None) == PV.EINVAL
+    assert L.peval_points_tuning(None, 1, None, None, None) == PV.EINVAL
 
 
 def test_interpolate_null_arguments():

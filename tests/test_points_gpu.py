@@ -42,6 +42,12 @@ def check_points(orc, p, exps, coeffs, points, K=0, C=0):
     with PV.Poly(p, exps, coeffs) as poly:
         if K or C:
             poly.set_tuning(K, 0, C)
+        tk, tp, tc = poly.points_tuning(points.shape[0])  # the tiles the run below takes
+        assert tk <= 16 and tp == 8 and 1 <= tc <= max(points.shape[0], 1)
+        if K:
+            assert tk == min(K, 16)
+        if C:
+            assert tc == min(C, max(points.shape[0], 1))
         got = poly.run_points(points)
     want = orc.evaluate_points(p, exps, coeffs, points, threads=8).astype(got.dtype)
     assert got.shape == want.shape
@@ -205,6 +211,7 @@ def test_points_fp64_product(orc, p, K):
         h.set_tuning(K, 0, 3)
         for mode in ("auto", "int", "fp64", "int"):
             h.set_arith(mode)
+            assert h.points_tuning(pts.shape[0])[0] == (min(K, 8) if mode != "int" else K)
             got = h.run_points(pts)
             assert np.array_equal(got.astype(np.uint64), want), (mode, K)
 
