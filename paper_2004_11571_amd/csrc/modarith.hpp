@@ -98,7 +98,10 @@ __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) {
 // subtraction); the two cross products that do not involve q fill the two
 // wait states between the carry mask of the quotient's middle multiply-add
 // and its read.  Written in assembly (arithmetic only) because the compiler
-// turns the same steps in C back into 64x64-bit multiply expansions.
+// turns the same steps in C back into 64x64-bit multiply expansions.  The
+// words of 2^64 - p are read from scalar registers (p is the same for every
+// lane of a wave in every caller; each multiply-add reads one of them), so
+// they are not copied into vector registers on every product.
 __device__ __forceinline__ uint64_t shoup_mul(uint64_t x, uint64_t w, uint64_t wq, uint64_t p) {
   const uint64_t n = 0 - p;
   const uint32_t x0 = (uint32_t)x, x1 = (uint32_t)(x >> 32), w0 = (uint32_t)w, w1 = (uint32_t)(w >> 32);
@@ -122,7 +125,7 @@ __device__ __forceinline__ uint64_t shoup_mul(uint64_t x, uint64_t w, uint64_t w
       "v_mad_u64_u32 %[x], %[z], %[x0], %[w0], %[h]\n\t"  // x = x0 w0 + h
       "v_mad_u64_u32 %[x], %[z], %[q0], %[n0], %[x]"        // x += q0 n0
       : [x] "+v"(x), [h] "+v"(h), [z] "=&s"(unused)
-      : [q1] "v"(q1), [n0] "v"(n0), [q0] "v"(q0), [n1] "v"(n1), [x0] "v"(x0), [w0] "v"(w0));
+      : [q1] "v"(q1), [n0] "s"(n0), [q0] "v"(q0), [n1] "s"(n1), [x0] "v"(x0), [w0] "v"(w0));
   return x;
 }
 
