@@ -457,9 +457,10 @@ __device__ __forceinline__ void eval_wave(const EvalArgs<A> &a, uint64_t wave, u
     // P evaluations: reduce (sum the running values), then multiply by Gamma
 #pragma unroll 1
     for (int q = 0; q < np; ++q) {
-      typename A::Sum acc = A::sum_zero();
+      typename A::Sum acc = A::sum_first(lam[0]);
+      lam[0] = A::mul_lazy(lam[0], g[0], gq[0], a.m);
 #pragma unroll
-      for (int k = 0; k < K; ++k) {
+      for (int k = 1; k < K; ++k) {
         A::sum_add(acc, lam[k]);
         lam[k] = A::mul_lazy(lam[k], g[k], gq[k], a.m);
       }

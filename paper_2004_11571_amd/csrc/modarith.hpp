@@ -282,6 +282,17 @@ struct W64 {
     uint64_t lo, hi;
   };
   __device__ static __forceinline__ Sum sum_zero() { return Sum{0, 0}; }
+  // a sum started from its first value: each half by one multiply-add by 1
+  // (the zero-extended half in a fresh pair, no clearing of the pair first)
+  __device__ static __forceinline__ Sum sum_first(T x) {
+    Sum s;
+    uint64_t carry;
+    asm("v_mad_u64_u32 %0, %2, %3, 1, 0\n\t"
+        "v_mad_u64_u32 %1, %2, %4, 1, 0"
+        : "=&v"(s.lo), "=&v"(s.hi), "=&s"(carry)
+        : "v"((uint32_t)x), "v"((uint32_t)(x >> 32)));
+    return s;
+  }
   __device__ static __forceinline__ void sum_add(Sum &s, T x) {
     uint64_t carry;
     asm("v_mad_u64_u32 %0, %2, %3, 1, %0\n\t"
@@ -289,9 +300,12 @@ struct W64 {
         : "+v"(s.lo), "+v"(s.hi), "=&s"(carry)
         : "v"((uint32_t)x), "v"((uint32_t)(x >> 32)));
   }
+  // value = lo + hi 2^32 = w0 + w1 2^32 + w2 2^64: the middle word with one
+  // add-with-carry, the carry into the top word with a second
   __device__ static __forceinline__ Acc stage(const Sum &s, const M &) {
-    const uint64_t t = (s.lo >> 32) + (uint32_t)s.hi;
-    return Acc{(uint32_t)s.lo, (uint32_t)t, (uint32_t)(s.hi >> 32) + (uint32_t)(t >> 32)};
+    unsigned c;
+    const uint32_t w1 = __builtin_addc((uint32_t)(s.lo >> 32), (uint32_t)s.hi, 0u, &c);
+    return Acc{(uint32_t)s.lo, w1, (uint32_t)(s.hi >> 32) + c};
   }
   __device__ static __forceinline__ void add_walk(Acc &a, const Acc &b, const M &) { add(a, b); }
   __device__ static __forceinline__ T mul_lazy(T x, T w, T wq, const M &m) {
@@ -316,6 +330,12 @@ struct W32 {
   __device__ static __forceinline__ T canon_partial(T v, const M &) { return v; }
   using Sum = Acc;  // a thread's sum over its terms
   __device__ static __forceinline__ Sum sum_zero() { return zero(); }
+  __device__ static __forceinline__ Sum sum_first(T x) {
+    Sum s;
+    uint64_t carry;
+    asm("v_mad_u64_u32 %0, %1, %2, 1, 0" : "=v"(s.v), "=s"(carry) : "v"(x));
+    return s;
+  }
   // one multiply-add by 1 into the 64-bit sum (no carry chain)
   __device__ static __forceinline__ void sum_add(Sum &s, T x) {
     uint64_t carry;
@@ -367,6 +387,7 @@ struct W64PM {
   __device__ static __forceinline__ T reduce_partial(const Acc &a, const M &m) { return W64::reduce_partial(a, m.m); }
   using Sum = W64::Sum;
   __device__ static __forceinline__ Sum sum_zero() { return W64::sum_zero(); }
+  __device__ static __forceinline__ Sum sum_first(T x) { return W64::sum_first(x); }
   __device__ static __forceinline__ void sum_add(Sum &s, T x) { W64::sum_add(s, x); }
   __device__ static __forceinline__ Acc stage(const Sum &s, const M &m) { return W64::stage(s, m.m); }
   __device__ static __forceinline__ void add_walk(Acc &a, const Acc &b, const M &) { W64::add(a, b); }
@@ -397,6 +418,7 @@ struct W32PM {
   __device__ static __forceinline__ T reduce_partial(const Acc &a, const M &m) { return W32::reduce(a, m.m); }
   using Sum = Acc;
   __device__ static __forceinline__ Sum sum_zero() { return zero(); }
+  __device__ static __forceinline__ Sum sum_first(T x) { return W32::sum_first(x); }
   __device__ static __forceinline__ void sum_add(Sum &s, T x) { W32::sum_add(s, x); }
   __device__ static __forceinline__ Acc stage(const Acc &a, const M &) { return a; }
   __device__ static __forceinline__ void add_walk(Acc &a, const Acc &b, const M &) { W32::add(a, b); }
@@ -471,6 +493,7 @@ struct WF64 {
   __device__ static __forceinline__ void add(Acc &a, T x) { a.s += x; }
   using Sum = Acc;  // a thread's sum over its terms (at most 8, exact)
   __device__ static __forceinline__ Sum sum_zero() { return zero(); }
+  __device__ static __forceinline__ Sum sum_first(T x) { return Sum{x}; }
   __device__ static __forceinline__ void sum_add(Sum &s, T x) { add(s, x); }
   // staged values and walk sums: folded, in (-p, p)
   __device__ static __forceinline__ void add_walk(Acc &a, const Acc &b, const M &m) {
