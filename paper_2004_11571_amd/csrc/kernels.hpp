@@ -356,19 +356,23 @@ __device__ __forceinline__ void segmented_walk(Stage<A, P> &st, int lane, int np
   const uint64_t slot_stride = (uint64_t)C * Lmax;
   typename A::Acc head = A::zero(), sum = A::zero();
   if (live) {
+    static_assert(P <= 32, "a sub-tile's segment ends fit one 32-bit word");
+    // this sub-tile's end bits, and the slot of its first end (one slot per
+    // end of the wave, in lane order)
+    const uint32_t mybits = (uint32_t)((emask >> (h * P)) & kSubMask);
+    uint32_t slot = sbase + (uint32_t)__popcll(emask & ((1ull << (h * P)) - 1ull));
     bool first = true;
 #pragma unroll 4
     for (int jj = 0; jj < P; ++jj) {
-      const int src = h * P + jj;
-      A::add_walk(sum, st.get(src, pp), m);
-      if ((emask >> src) & 1ull) {
+      A::add_walk(sum, st.get(h * P + jj, pp), m);
+      if ((mybits >> jj) & 1u) {
         if (Merge && first) {
           head = sum;
           first = false;
         } else {
-          const uint32_t slot = sbase + (uint32_t)__popcll(emask & ((1ull << src) - 1ull));
           pcol[slot * slot_stride] = A::reduce_partial(sum, m);
         }
+        ++slot;
         sum = A::zero();
       }
     }
@@ -434,7 +438,9 @@ __device__ __forceinline__ void eval_wave(const EvalArgs<A> &a, uint64_t wave, u
     g[k] = a.gam[(uint64_t)k * a.NT + j];
     gq[k] = a.gamq[(uint64_t)k * a.NT + j];
   }
-  const uint32_t L = (c < a.T) ? (a.T - 1 - c) / a.C + 1 : 0;  // evaluations of chain c
+  // evaluations of chain c, the same for the whole wave (the division is
+  // done in vector registers; read back into a scalar one)
+  const uint32_t L = __builtin_amdgcn_readfirstlane((c < a.T) ? (a.T - 1 - c) / a.C + 1 : 0);
 
   if (a.direct) {  // wave-uniform: thread j's sum is the coefficient of group j
     const bool live = j < a.G;
@@ -453,7 +459,9 @@ __device__ __forceinline__ void eval_wave(const EvalArgs<A> &a, uint64_t wave, u
   const uint32_t sbase = a.slot_base[wave];
 
   for (uint32_t i0 = 0; i0 < L; i0 += P) {
-    const int np = (L - i0 < (uint32_t)P) ? (int)(L - i0) : P;
+    // (kept in a scalar register: the compiler forms the clamp with a vector
+    // instruction, and the row loop would count in vector registers)
+    const int np = __builtin_amdgcn_readfirstlane((L - i0 < (uint32_t)P) ? (int)(L - i0) : P);
     // P evaluations: reduce (sum the running values), then multiply by Gamma
 #pragma unroll 1
     for (int q = 0; q < np; ++q) {

@@ -209,7 +209,9 @@ __global__ __launch_bounds__(kEvalBlock, ((K == 16 && NF > 2) ? 2 : 3)) void poi
   }
   const uint64_t emask = active ? a.endmask[wave] : 0;
   const uint32_t sbase = active ? a.slot_base[wave] : 0;
-  const uint32_t L = (c < a.T) ? (a.T - 1 - c) / a.C + 1 : 0;  // points of chain c
+  // points of chain c, the same for the whole wave (the division is done
+  // in vector registers; read back into a scalar one)
+  const uint32_t L = __builtin_amdgcn_readfirstlane((c < a.T) ? (a.T - 1 - c) / a.C + 1 : 0);
   const uint32_t nvec = a.E * 2 * (uint32_t)sizeof(T) / 16;       // 16-byte pieces of one point's tables
 
   // The first PRE x 256 pieces of the next point's tables are loaded into
@@ -235,7 +237,9 @@ __global__ __launch_bounds__(kEvalBlock, ((K == 16 && NF > 2) ? 2 : 3)) void poi
   if (L) prefetch(reinterpret_cast<const uint4 *>(a.tables + (uint64_t)c * a.E * 2));
 
   for (uint32_t i0 = 0; i0 < L; i0 += P) {
-    const int np = (L - i0 < (uint32_t)P) ? (int)(L - i0) : P;
+    // (kept in a scalar register: the compiler forms the clamp with a vector
+    // instruction, and the row loop would count in vector registers)
+    const int np = __builtin_amdgcn_readfirstlane((L - i0 < (uint32_t)P) ? (int)(L - i0) : P);
 #pragma unroll 1
     for (int q = 0; q < np; ++q) {
       const uint64_t t = (uint64_t)c + (uint64_t)(i0 + q) * a.C;
