@@ -118,6 +118,10 @@ def profile_traffic(kernel_sha: str, workload: str, kernel: str = "eval_kernel",
     m_b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
     if not m_sha or not m_b or m_sha.group(1) != kernel_sha:
         return None
+    if tuning is not None:  # the bytes counted with these tiles, if any were
+        for m in re.finditer(r"traffic_for_tuning:\s*K=(\d+) P=(\d+) C=(\d+) bytes=([0-9.eE+]+)", text):
+            if tuple(int(x) for x in m.groups()[:3]) == tuple(tuning):
+                return float(m.group(4))
     m_t = re.search(r"counted_tuning:\s*K=(\d+) P=(\d+) C=(\d+)", text)
     if m_t and tuning is not None and tuple(int(x) for x in m_t.groups()) != tuple(tuning):
         return None

@@ -131,6 +131,12 @@ extern "C" int peval_autotune(peval_poly *h, const uint64_t *beta, uint32_t T, u
     return PEVAL_OK;
   };
 
+  // a few untimed runs first: the candidate timed first would otherwise meet
+  // the device still raising its clocks
+  {
+    float warm_ms = 0;
+    PEVAL_TRY(time_run(h, ba, T, heur, 3, &warm_ms));
+  }
   if (exhaustive) {
     for (uint32_t k : Ks)
       for (uint32_t p : Ps) {
