@@ -337,10 +337,13 @@ def batch_main(args):
     tune_s = time.time() - t_tune
     info = b.info()
     mi = b.members()
+    kinds = b.kinds()
     kind_names = ["w64_k16", "w64_k<=8", "fp64", "w32_k32", "w32_k<=16"]
     tiles = {}
     for w, k, c, kd in zip(ws, mi["K"], mi["C"], mi["kind"]):
-        e = tiles.setdefault(kind_names[int(kd)], {"members": 0, "term_evals": 0, "K": {}})
+        e = tiles.setdefault(kind_names[int(kd)], {"members": 0, "term_evals": 0, "K": {},
+                                                   "P": int(kinds["P"][int(kd)]),
+                                                   "blocks": int(kinds["blocks"][int(kd)])})
         e["members"] += 1
         e["term_evals"] += w.s * w.T
         e["K"][str(int(k))] = e["K"].get(str(int(k)), 0) + 1

@@ -314,12 +314,14 @@ int peval_tune_load(const char *path);
  * have similar costs, allocates all device scratch, and captures the pass
  * (power tables, monomials, persistent evaluation kernels fed by work
  * queues in decreasing item cost, one for each kind of member: 64-bit
- * residues with the integer product and K = 16 (16 evaluations per pass),
- * the same with K <= 8 (8 per pass), 64-bit residues with the FP64 product
- * (members whose arithmetic resolves to it when the batch is created),
- * 32-bit residues with K = 32, and with K <= 16; combine) into a hipGraph
- * unless flags has PEVAL_BATCH_NO_GRAPH.  The handles must outlive the batch; a later
- * peval_set_arith on a member does not change the batch.
+ * residues with the integer product and K = 16 (16 evaluations per pass by
+ * default), the same with K <= 8 (8 per pass), 64-bit residues with the
+ * FP64 product (members whose arithmetic resolves to it when the batch is
+ * created), 32-bit residues with K = 32, and with K <= 16; combine) into a
+ * hipGraph unless flags has PEVAL_BATCH_NO_GRAPH.  Each kind's kernels run
+ * on a stream of their own inside the pass, the kinds side by side.  The
+ * handles must outlive the batch; a later peval_set_arith on a member does
+ * not change the batch.
  *
  * peval_batch_run evaluates polys[j] at betas[j] (n_j - 2 values each) for
  * t = t0s[j] .. t0s[j]+Ts[j]-1 (t0s may be NULL: all 1) into dev_outs[j]
@@ -337,7 +339,8 @@ int peval_tune_load(const char *path);
  * and keep the fastest: members are grouped by product and width and by
  * whether their K is the largest allowed, each group's K is moved one
  * doubling either way in turn (coordinate search), then the work items'
- * target cost is halved and doubled.  Candidates run with base point 2 into
+ * target cost is halved and doubled, then each kind's evaluations per pass
+ * switched between 8 and 16.  Candidates run with base point 2 into
  * scratch outputs of sum(T_j G_j elem_bytes) bytes allocated for the search
  * (each timed as the median of five passes after a warm-up); a choice is
  * kept only when it is at least 1% faster.  Results never
@@ -347,10 +350,16 @@ int peval_tune_load(const char *path);
  * Shoup, K <= 8; 2: FP64 product; 3: 32-bit, K = 32; 4: 32-bit, K <= 16),
  * and the tuner's pass time and number of timed candidates (0 if the batch
  * was not tuned).  Any output pointer may be NULL.
+ * flags PEVAL_BATCH_PASS8: every kind stages 8 evaluations per pass (without
+ * PEVAL_BATCH_TUNE; for comparisons and tests).
+ * peval_batch_kinds fills P[5] and blocks[5]: per kind (numbered as above)
+ * its evaluations per pass and its kernel's persistent blocks, 0 for a kind
+ * with no member.  Neither pointer may be NULL.
  */
 typedef struct peval_batch peval_batch;
 #define PEVAL_BATCH_NO_GRAPH 1u
 #define PEVAL_BATCH_TUNE 2u
+#define PEVAL_BATCH_PASS8 4u
 int peval_batch_create(uint32_t count, peval_poly *const *polys, const uint32_t *Ts, uint32_t flags,
                        peval_batch **out);
 int peval_batch_run(peval_batch *b, const uint64_t *const *betas, const uint64_t *t0s,
@@ -358,6 +367,7 @@ int peval_batch_run(peval_batch *b, const uint64_t *const *betas, const uint64_t
 int peval_batch_info(const peval_batch *b, uint64_t *info);
 int peval_batch_members(const peval_batch *b, uint32_t *K, uint32_t *C, uint32_t *kind, float *tuned_ms,
                         uint32_t *tune_trials);
+int peval_batch_kinds(const peval_batch *b, uint32_t *P, uint32_t *blocks);
 int peval_batch_destroy(peval_batch *b);
 
 /*

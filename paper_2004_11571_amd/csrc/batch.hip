@@ -27,26 +27,37 @@ void batch_release(BatchCore &b) {
 }
 
 // Blocks that fill the chip with each kind's evaluation kernel.
-static int persistent_blocks(int blocks[kKinds]) {
-  static int cached[kKinds] = {};
+// Blocks of each kind's evaluation kernel that the chip holds at once, for
+// its pass size (occupancy x CUs; per (kind, P), cached).
+static int persistent_blocks(int blocks[kKinds], const uint32_t *kind_p = nullptr) {
+  static int cached[kKinds][2] = {};
   static std::mutex mu;
   std::lock_guard<std::mutex> lk(mu);
-  if (!cached[0]) {
-    int dev = 0, per_cu[kKinds] = {};
+  if (!cached[0][0]) {
+    int dev = 0;
     hipDeviceProp_t prop;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipGetDeviceProperties(&prop, dev));
     for (uint32_t k = 0; k < kKinds; ++k)
-      HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu[k], batch_eval_fn(k), kEvalBlock, 0));
-    for (int k = 0; k < kKinds; ++k) cached[k] = std::max(1, per_cu[k]) * prop.multiProcessorCount;
+      for (int i = 0; i < 2; ++i) {
+        int per_cu = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_eval_fn(k, kKindPOptions[i]),
+                                                             kEvalBlock, 0));
+        cached[k][i] = std::max(1, per_cu) * prop.multiProcessorCount;
+      }
   }
-  for (int k = 0; k < kKinds; ++k) blocks[k] = cached[k];
+  for (uint32_t k = 0; k < kKinds; ++k) {
+    const uint32_t P = kind_p ? kind_p[k] : (uint32_t)kind_P(k);
+    blocks[k] = cached[k][P == kKindPOptions[0] ? 0 : 1];
+  }
   return PEVAL_OK;
 }
 
 int batch_set_blocks(BatchCore &b) {
+  for (uint32_t k = 0; k < kKinds; ++k)
+    if (!b.kind_p[k]) b.kind_p[k] = kind_P(k);
   int bl[kKinds];
-  PEVAL_TRY(persistent_blocks(bl));
+  PEVAL_TRY(persistent_blocks(bl, b.kind_p));
   for (int k = 0; k < kKinds; ++k) {
     const uint64_t n = (uint64_t)b.kind_first[k + 1] - b.kind_first[k];
     b.eval_blocks[k] = (int)std::min<uint64_t>((uint64_t)bl[k], (n + 3) / 4);
@@ -268,7 +279,7 @@ void batch_bind(BatchCore &b, void *d_blob) {
   b.d_counter = (uint32_t *)(base + b.off_ctr);
 }
 
-int batch_build(BatchCore &b, const std::vector<BatchMember> &mem) {
+int batch_build(BatchCore &b, const std::vector<BatchMember> &mem, const uint32_t *kind_p) {
   void *arena = nullptr, *blob = nullptr;
   size_t need = batch_scratch_need(mem);
   HIP_TRY(hipMalloc(&arena, std::max<size_t>(need, 256)));
@@ -277,6 +288,7 @@ int batch_build(BatchCore &b, const std::vector<BatchMember> &mem) {
   HIP_TRY(hipMalloc(&blob, b.blob_bytes));
   batch_bind(b, blob);
   HIP_TRY(hipMemcpy(blob, b.image.data(), b.blob_bytes, hipMemcpyHostToDevice));
+  for (uint32_t k = 0; k < kKinds; ++k) b.kind_p[k] = kind_p ? kind_p[k] : (uint32_t)kind_P(k);
   return batch_set_blocks(b);
 }
 
@@ -322,8 +334,9 @@ static int enqueue_combine(const BatchCore &b, hipStream_t st, uint64_t t0, uint
 static int enqueue_eval(const BatchCore &b, hipStream_t st, uint32_t kind) {
   const uint32_t first = b.kind_first[kind], n = b.kind_first[kind + 1] - first;
   if (!n) return PEVAL_OK;
-  batch_eval_fn(kind)<<<b.eval_blocks[kind], kEvalBlock, 0, st>>>(b.d_desc, b.d_run, b.d_items + first, n,
-                                                                  b.d_counter + kind);
+  batch_eval_fn(kind, b.kind_p[kind])<<<b.eval_blocks[kind], kEvalBlock, 0, st>>>(b.d_desc, b.d_run,
+                                                                                    b.d_items + first, n,
+                                                                                    b.d_counter + kind);
   HIP_TRY(hipGetLastError());
   return PEVAL_OK;
 }
@@ -430,6 +443,7 @@ static int tune_class(const peval_poly *h, uint32_t K0) {
 struct BatchChoice {
   int shift[kTuneClasses] = {0, 0, 0, 0, 0, 0};  // K moved by this many doublings from its own choice
   double chain_scale = 1.0;                      // work items' target cost, relative to the default
+  uint32_t kind_p[kKinds] = {kind_P(0), kind_P(1), kind_P(2), kind_P(3), kind_P(4)};  // evaluations per pass
 };
 
 // Members' plans for one choice: K from the tuning cache or the heuristic,
@@ -455,12 +469,12 @@ static int plan_members(const std::vector<peval_poly *> &polys, const std::vecto
 }
 
 // Device time of one pass of a planned batch (base points 2, outputs in
-// `outs`), the mean of two passes after one untimed pass.
-static int time_pass(const std::vector<BatchMember> &mem, const std::vector<void *> &outs, hipStream_t st,
-                     const BatchFork *fork, float *ms) {
-  constexpr int kTimed = 5;  // passes timed one by one after a warm-up; the median is kept
+// `outs`): the median of five passes timed one by one after a warm-up.
+static int time_pass(const std::vector<BatchMember> &mem, const uint32_t *kind_p, const std::vector<void *> &outs,
+                     hipStream_t st, const BatchFork *fork, float *ms) {
+  constexpr int kTimed = 5;
   BatchCore core;
-  int rc = batch_build(core, mem);
+  int rc = batch_build(core, mem, kind_p);
   hipEvent_t ev[kTimed + 1] = {};
   if (rc == PEVAL_OK) {
     std::vector<BatchRun> runs(mem.size());
@@ -528,7 +542,7 @@ static int tune_batch(const std::vector<peval_poly *> &polys, const std::vector<
   auto measure = [&](const BatchChoice &ch, float *ms) {
     std::vector<BatchMember> mem;
     int r = plan_members(polys, Ts, ch, mem);
-    if (r == PEVAL_OK) r = time_pass(mem, outs, st, &fork, ms);
+    if (r == PEVAL_OK) r = time_pass(mem, ch.kind_p, outs, st, &fork, ms);
     ++*trials;
     return r;
   };
@@ -551,6 +565,24 @@ static int tune_batch(const std::vector<peval_poly *> &polys, const std::vector<
     if (rc != PEVAL_OK) break;
     BatchChoice ch = *best;
     ch.chain_scale = sc;
+    float ms = 0;
+    if ((rc = measure(ch, &ms)) != PEVAL_OK) break;
+    if (ms < *best_ms * 0.99f) {
+      *best = ch;
+      *best_ms = ms;
+    }
+  }
+  // then each present kind's evaluations per pass (8 or 16)
+  bool kind_present[kKinds] = {};
+  if (rc == PEVAL_OK) {
+    std::vector<BatchMember> mem;
+    rc = plan_members(polys, Ts, *best, mem);
+    for (const auto &m : mem) kind_present[member_kind(m.h, m.plan->K)] = true;
+  }
+  for (uint32_t k = 0; k < kKinds && rc == PEVAL_OK; ++k) {
+    if (!kind_present[k]) continue;
+    BatchChoice ch = *best;
+    ch.kind_p[k] = ch.kind_p[k] == kKindPOptions[0] ? kKindPOptions[1] : kKindPOptions[0];
     float ms = 0;
     if ((rc = measure(ch, &ms)) != PEVAL_OK) break;
     if (ms < *best_ms * 0.99f) {
@@ -588,6 +620,8 @@ extern "C" int peval_batch_create(uint32_t count, peval_poly *const *polys, cons
   // tuner when asked); P is set by the member's kind and does not change
   // the layout
   BatchChoice choice;
+  if (flags & PEVAL_BATCH_PASS8)
+    for (auto &pk : choice.kind_p) pk = kKindPOptions[0];
   if (flags & PEVAL_BATCH_TUNE) {
     float ms = 0;
     int trc = tune_batch(b->polys, b->Ts, &choice, &ms, &b->tune_trials);
@@ -597,7 +631,7 @@ extern "C" int peval_batch_create(uint32_t count, peval_poly *const *polys, cons
   std::vector<BatchMember> mem;
   int rc = plan_members(b->polys, b->Ts, choice, mem);
   if (rc != PEVAL_OK) return bail(rc);
-  rc = batch_build(b->core, mem);
+  rc = batch_build(b->core, mem, choice.kind_p);
   if (rc != PEVAL_OK) return bail(rc);
   for (int k = 0; k < kRunSlots; ++k) {
     if (hipHostMalloc((void **)&b->h_run[k], count * sizeof(BatchRun), hipHostMallocDefault) != hipSuccess)
@@ -690,6 +724,16 @@ extern "C" int peval_batch_members(const peval_batch *b, uint32_t *K, uint32_t *
   }
   if (tuned_ms) *tuned_ms = b->tuned_ms;
   if (tune_trials) *tune_trials = b->tune_trials;
+  return PEVAL_OK;
+}
+
+extern "C" int peval_batch_kinds(const peval_batch *b, uint32_t *P, uint32_t *blocks) {
+  if (!b || !P || !blocks) return fail(PEVAL_EINVAL, "null argument");
+  for (uint32_t k = 0; k < kKinds; ++k) {
+    const bool present = b->core.kind_first[k + 1] > b->core.kind_first[k];
+    P[k] = present ? b->core.kind_p[k] : 0;
+    blocks[k] = present ? (uint32_t)b->core.eval_blocks[k] : 0;
+  }
   return PEVAL_OK;
 }
 

@@ -36,6 +36,7 @@ struct BatchCore {
   uint32_t n_items = 0;
   uint32_t kind_first[kKinds + 1] = {};  // items of kind k: kind_first[k] .. kind_first[k+1]-1
   int eval_blocks[kKinds] = {};          // persistent blocks of each kind's evaluation kernel
+  uint32_t kind_p[kKinds] = {};          // evaluations per pass of each kind's kernel (8 or 16)
   uint64_t tab_total = 0, mono_total = 0, out_total = 0;
   uint64_t mono_blocks = 0;  // blocks of the monomial kernel (each member's entries padded to whole blocks)
   uint64_t kind_mono[kKinds + 1] = {};   // monomial blocks of kind k: kind_mono[k] .. kind_mono[k+1]-1
@@ -72,7 +73,8 @@ void batch_plan(BatchCore &b, const std::vector<BatchMember> &mem, void *arena, 
 void batch_bind(BatchCore &b, void *d_blob);
 // Allocates scratch and blob with hipMalloc and uploads the image.  Handles
 // must stay alive while the batch is used.
-int batch_build(BatchCore &b, const std::vector<BatchMember> &mem);
+// kind_p: evaluations per pass per kind (nullptr: each kind's default).
+int batch_build(BatchCore &b, const std::vector<BatchMember> &mem, const uint32_t *kind_p = nullptr);
 // fork: optional side streams, one per kind of member (nullptr: all on st)
 int batch_enqueue(const BatchCore &b, hipStream_t st, const BatchFork *fork = nullptr);
 void batch_release(BatchCore &b);

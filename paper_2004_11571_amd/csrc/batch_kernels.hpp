@@ -189,14 +189,19 @@ __global__ __launch_bounds__(kEvalBlock, WAVES) void batch_eval_kernel(const Bat
 // single-polynomial kernel of the range (the 64-bit K = 16 one needs
 // three to issue nearly every cycle).
 using BatchEvalFn = void (*)(const BatchDesc *, const BatchRun *, const BatchItem *, uint32_t, uint32_t *);
-inline BatchEvalFn batch_eval_fn(uint32_t kind) {
+template <int P>
+inline BatchEvalFn batch_eval_fn_p(uint32_t kind) {
   switch (kind) {
-    case kKindW64K16: return batch_eval_kernel<W64, 16, 16, kind_P(kKindW64K16), kind_waves(kKindW64K16), kKindW64K16>;
-    case kKindW64Lo: return batch_eval_kernel<W64, 1, 8, kind_P(kKindW64Lo), kind_waves(kKindW64Lo), kKindW64Lo>;
-    case kKindF64: return batch_eval_kernel<WF64, 1, 8, kind_P(kKindF64), kind_waves(kKindF64), kKindF64>;
-    case kKindW32K32: return batch_eval_kernel<W32, 32, 32, kind_P(kKindW32K32), kind_waves(kKindW32K32), kKindW32K32>;
-    default: return batch_eval_kernel<W32, 1, 16, kind_P(kKindW32Lo), kind_waves(kKindW32Lo), kKindW32Lo>;
+    case kKindW64K16: return batch_eval_kernel<W64, 16, 16, P, kind_waves(kKindW64K16), kKindW64K16>;
+    case kKindW64Lo: return batch_eval_kernel<W64, 1, 8, P, kind_waves(kKindW64Lo), kKindW64Lo>;
+    case kKindF64: return batch_eval_kernel<WF64, 1, 8, P, kind_waves(kKindF64), kKindF64>;
+    case kKindW32K32: return batch_eval_kernel<W32, 32, 32, P, kind_waves(kKindW32K32), kKindW32K32>;
+    default: return batch_eval_kernel<W32, 1, 16, P, kind_waves(kKindW32Lo), kKindW32Lo>;
   }
+}
+// P: evaluations per pass, 8 or 16
+inline BatchEvalFn batch_eval_fn(uint32_t kind, uint32_t P) {
+  return P == 8 ? batch_eval_fn_p<8>(kind) : batch_eval_fn_p<16>(kind);
 }
 
 // Flattened combine tiles: member j owns its tiles from prefix[j] on (the

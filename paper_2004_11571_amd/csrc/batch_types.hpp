@@ -25,9 +25,12 @@ enum BatchKind : uint32_t {
   kKinds = 5
 };
 
-// Evaluations per pass of a kind's kernel: the small-K 64-bit kernel stages
-// 8, so that its stage leaves room for more waves per CU.
+// Evaluations per pass of a kind's kernel by default: the small-K 64-bit
+// kernel stages 8, so that its stage leaves room for more waves per CU.
+// Every kind is compiled for 8 and 16 (the batch tuner picks one per kind);
+// 32 would leave one or two blocks per CU for the stages in LDS.
 __host__ __device__ constexpr int kind_P(uint32_t kind) { return kind == kKindW64Lo ? 8 : kBatchP; }
+constexpr uint32_t kKindPOptions[2] = {8, 16};
 // Waves per SIMD a kind's kernel is compiled for (its register bound): the
 // 32-bit K = 32 one holds 96 running values, Gammas and quotients and needs
 // about 200 registers (two waves; with three it spilled over a hundred).

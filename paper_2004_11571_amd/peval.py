@@ -95,6 +95,7 @@ def lib() -> ctypes.CDLL:
         "peval_batch_run": ([vp, vp, vp, vp, vp], i32),
         "peval_batch_info": ([vp, vp], i32),
         "peval_batch_members": ([vp, vp, vp, vp, vp, vp], i32),
+        "peval_batch_kinds": ([vp, vp, vp], i32),
         "peval_batch_destroy": ([vp], i32),
         "peval_tune_clear": ([], i32),
         "peval_tune_save": ([ctypes.c_char_p], i32),
@@ -306,12 +307,13 @@ class Poly:
 
 BATCH_NO_GRAPH = 1
 BATCH_TUNE = 2
+BATCH_PASS8 = 4
 
 
 class Batch:
     """A planned batched pass over resident polynomials (peval_batch_*)."""
 
-    def __init__(self, polys, Ts, graph: bool = True, tune: bool = False):
+    def __init__(self, polys, Ts, graph: bool = True, tune: bool = False, pass8: bool = False):
         self.polys = list(polys)
         self.Ts = [int(t) for t in Ts]
         if len(self.polys) != len(self.Ts) or not self.polys:
@@ -319,7 +321,7 @@ class Batch:
         hs = (ctypes.c_void_p * len(self.polys))(*[q.handle.value for q in self.polys])
         ts = np.ascontiguousarray(self.Ts, dtype=np.uint32)
         b = ctypes.c_void_p()
-        flags = (0 if graph else BATCH_NO_GRAPH) | (BATCH_TUNE if tune else 0)
+        flags = (0 if graph else BATCH_NO_GRAPH) | (BATCH_TUNE if tune else 0) | (BATCH_PASS8 if pass8 else 0)
         _check(lib().peval_batch_create(len(self.polys), hs, ts.ctypes.data, flags, ctypes.byref(b)))
         self._b = b
 
@@ -332,6 +334,13 @@ class Batch:
         _check(lib().peval_batch_members(self._b, K.ctypes.data, C.ctypes.data, kind.ctypes.data,
                                          ctypes.byref(ms), ctypes.byref(trials)))
         return {"K": K, "C": C, "kind": kind, "tuned_ms": ms.value, "tune_trials": trials.value}
+
+    def kinds(self) -> dict:
+        """Per kind of member (0..4): evaluations per pass P and persistent
+        blocks of its kernel (0 where the batch has no such member)."""
+        P, blocks = np.zeros(5, np.uint32), np.zeros(5, np.uint32)
+        _check(lib().peval_batch_kinds(self._b, P.ctypes.data, blocks.ctypes.data))
+        return {"P": P, "blocks": blocks}
 
     def info(self) -> dict:
         v = np.zeros(5, np.uint64)

@@ -165,6 +165,7 @@ def test_batch_rejects_bad_arguments():
     assert L.peval_batch_create(0, None, None, 0, ctypes.byref(b)) == PV.EINVAL
     assert L.peval_batch_run(None, None, None, None, None) == PV.EINVAL
     assert L.peval_batch_destroy(None) == PV.OK
+    assert L.peval_batch_kinds(None, None, None) == PV.EINVAL
 
 
 # --- point mode: factor-table planner (host only) ---------------------------

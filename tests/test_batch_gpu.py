@@ -171,6 +171,11 @@ def test_batch_tuned_tiles_equal_plain_runs():
             mi = b.members()
             _say("members", mi)
             assert mi["tune_trials"] >= 3 and mi["tuned_ms"] > 0
+            kinds = b.kinds()
+            present = set(int(k) for k in mi["kind"])
+            for kd in range(5):  # every present kind has its pass size and blocks
+                assert (kinds["P"][kd] in (8, 16)) == (kd in present), kinds
+                assert (kinds["blocks"][kd] > 0) == (kd in present), kinds
             for q, w, k, kd in zip(polys, ws, mi["K"], mi["kind"]):
                 assert k in (1, 2, 4, 8, 16, 32)
                 if q.elem_bytes == 4:
@@ -186,6 +191,31 @@ def test_batch_tuned_tiles_equal_plain_runs():
                 torch.cuda.synchronize()
                 for q, w, beta, o in zip(polys, ws, betas, outs):
                     assert np.array_equal(_host(q, o), q.run(beta, w.T)), (rep, w.name)
+    finally:
+        for q in polys:
+            q.destroy()
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_eight_per_pass_equals_plain_runs(graph):
+    """Every kind's kernel staging 8 evaluations per pass (the tuner's other
+    choice) gives the members' plain-run images; kinds report P = 8."""
+    import torch
+    moduli = (W.P31, W.P63, W.P50)
+    ws = W.uneven_batch(count=24, instance=11, s_max=1e5, t_log2=(3, 9), moduli=moduli)
+    polys = [PV.Poly(w.p, w.exps, w.coeffs) for w in ws]
+    Ts = [w.T for w in ws]
+    _say("pass8 batch members", [(q.s, q.G, T, q.elem_bytes) for q, T in zip(polys, Ts)], "graph", graph)
+    try:
+        with PV.Batch(polys, Ts, graph=graph, pass8=True) as b:
+            kinds = b.kinds()
+            present = set(int(k) for k in b.members()["kind"])
+            assert all(kinds["P"][kd] == (8 if kd in present else 0) for kd in range(5)), kinds
+            outs = _outs(polys, Ts)
+            b.run([w.beta for w in ws], outs, stream=torch.cuda.current_stream())
+            torch.cuda.synchronize()
+            for q, w, o in zip(polys, ws, outs):
+                assert np.array_equal(_host(q, o), q.run(w.beta, w.T)), w.name
     finally:
         for q in polys:
             q.destroy()
