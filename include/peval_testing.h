@@ -91,6 +91,23 @@ enum {
 };
 int peval_bench_product(uint32_t kind, uint64_t p, uint32_t iters, uint32_t blocks, double *ms, double *work);
 
+/*
+ * Point mode (paper, Section 2.1, random points): which term takes each
+ * thread slot of the point evaluation kernel, as the library deals them
+ * (host only, no device needed).  w: bytes per residue (4 or 8); the terms
+ * are given already sorted into G groups of group_sizes[g] >= 1 terms
+ * (group g owns the next group_sizes[g] term indices); tail_exps: their
+ * n - 2 tail exponents, variable-major (tail_exps[v * s + i], v < ntail);
+ * K: terms per thread (1, 2, 4, 8 or 16).  slot_term receives K x NT term
+ * indices (slot (k, j) at k * NT + j, 0xffffffff for padding), where NT is
+ * the thread count of the layout (peval_layout's sizes[0] for this K);
+ * slot_count must equal K * NT.  Every term lands in exactly one slot of
+ * one of its own group's threads.  Returns PEVAL_EINVAL for bad arguments,
+ * PEVAL_EUNSUPPORTED where the point mode's factor tables do not fit.
+ */
+int peval_test_deal_points(uint32_t w, uint32_t ntail, uint64_t s, const uint16_t *tail_exps, uint64_t G,
+                           const uint64_t *group_sizes, uint32_t K, uint32_t *slot_term, uint64_t slot_count);
+
 #ifdef __cplusplus
 }
 #endif

@@ -192,11 +192,11 @@ using BatchEvalFn = void (*)(const BatchDesc *, const BatchRun *, const BatchIte
 template <int P>
 inline BatchEvalFn batch_eval_fn_p(uint32_t kind) {
   switch (kind) {
-    case kKindW64K16: return batch_eval_kernel<W64, 16, 16, P, kind_waves(kKindW64K16), kKindW64K16>;
-    case kKindW64Lo: return batch_eval_kernel<W64, 1, 8, P, kind_waves(kKindW64Lo), kKindW64Lo>;
-    case kKindF64: return batch_eval_kernel<WF64, 1, 8, P, kind_waves(kKindF64), kKindF64>;
-    case kKindW32K32: return batch_eval_kernel<W32, 32, 32, P, kind_waves(kKindW32K32), kKindW32K32>;
-    default: return batch_eval_kernel<W32, 1, 16, P, kind_waves(kKindW32Lo), kKindW32Lo>;
+    case kKindW64K16: return batch_eval_kernel<W64, 16, 16, P, kind_waves(kKindW64K16, P), kKindW64K16>;
+    case kKindW64Lo: return batch_eval_kernel<W64, 1, 8, P, kind_waves(kKindW64Lo, P), kKindW64Lo>;
+    case kKindF64: return batch_eval_kernel<WF64, 1, 8, P, kind_waves(kKindF64, P), kKindF64>;
+    case kKindW32K32: return batch_eval_kernel<W32, 32, 32, P, kind_waves(kKindW32K32, P), kKindW32K32>;
+    default: return batch_eval_kernel<W32, 1, 16, P, kind_waves(kKindW32Lo, P), kKindW32Lo>;
   }
 }
 // P: evaluations per pass, 8 or 16

@@ -33,9 +33,10 @@ __host__ __device__ constexpr int kind_P(uint32_t kind) { return kind == kKindW6
 constexpr uint32_t kKindPOptions[2] = {8, 16};
 // Waves per SIMD a kind's kernel is compiled for (its register bound): the
 // 32-bit K = 32 one holds 96 running values, Gammas and quotients and needs
-// about 200 registers (two waves; with three it spilled over a hundred).
-__host__ __device__ constexpr int kind_waves(uint32_t kind) {
-  return kind == kKindW32K32 ? 2 : kind == kKindW64K16 ? 3 : 4;
+// about 200 registers (two waves; with three it spilled over a hundred); the
+// small-K 64-bit one fits four with 8 evaluations per pass, three with 16.
+__host__ __device__ constexpr int kind_waves(uint32_t kind, int P) {
+  return kind == kKindW32K32 ? 2 : kind == kKindW64K16 ? 3 : (kind == kKindW64Lo && P > 8) ? 3 : 4;
 }
 
 // Static part of one polynomial in a batch (device table).

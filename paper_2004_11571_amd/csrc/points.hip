@@ -6,10 +6,12 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
 #include <type_traits>
 
 #include "errors.hpp"
 #include "peval.h"
+#include "peval_testing.h"
 #include "peval_internal.hpp"
 
 using namespace peval;
@@ -117,44 +119,160 @@ template <class A>
 using PointsFn = void (*)(PointsArgs<A>);
 
 // Which term fills each thread slot (k, j), [K][NT]: the threads of a group
-// keep the group (the segmented walk relies on it), but the group's terms
-// are sorted by their entry in the first factor table, then the second, and
-// dealt k-major over the group's threads, so that at every k neighbouring
-// lanes hold terms with close entries (few LDS bank conflicts in the
-// lookups).  0xffffffff marks padding.
-int deal_slots(peval_poly *h, uint32_t K, uint64_t NT, const FactorPlan &fp, std::vector<uint32_t> *out) {
-  const uint64_t s = h->s;
-  const uint32_t ntail = h->n - 2;
-  std::vector<uint16_t> ex((size_t)ntail * s);
-  if (!ex.empty()) HIP_TRY(hipMemcpy(ex.data(), h->d_exps, ex.size() * 2, hipMemcpyDeviceToHost));
-  auto key = [&](uint64_t i) {
-    uint32_t local[kMaxFactors] = {0, 0, 0, 0};
-    for (uint32_t d = 0; d < fp.ndig; ++d) {
-      const uint32_t e = ex[(size_t)fp.var[d] * s + i];
-      local[fp.fac[d]] += ((e >> fp.shift[d]) & fp.mask[d]) * fp.stride[d];
-    }
-    return ((uint64_t)local[0] << 32) | local[1];
-  };
-  HostPlan hp = build_host_plan(h->grp_off, K, kPointsP, true);
+// keep the group (the segmented walk relies on it) and slot (k, t) of the
+// group's t-th thread is filled for k nt + t < m (k-major; the kernel adds
+// all K slots, padding ones with coefficient 0), but which of the group's
+// terms takes which slot is free.
+// The lookups of one k are one LDS gather per factor across the wave, and
+// lanes whose entries differ but share a bank serialise.  As measured on
+// gfx950, a 4- or 8-byte gather is served per 32 lanes, its banks the 4-byte
+// words modulo 32 (4 bytes) or the 8-byte words modulo 32 (8 bytes); a
+// 16-byte one per 16 lanes, 16-byte words modulo 16.  The first factor's
+// value (every 2nd word of the (value, quotient) entries) thus has 16 banks
+// per 32 lanes, the last factor's whole entry 32 (32-bit residues) or 16 per
+// 16 lanes (64-bit).  The slots are filled wave by wave, k by k, in lane
+// order: each lane takes, among its group's remaining terms with the
+// smallest first-factor entries (a few per bank of the last factor), the
+// one that adds the fewest conflicts to the gathers of its pass (whatever
+// group the other lanes belong to); among those, one whose first-factor
+// entry a lane of the pass already reads (a shared entry costs no bank),
+// then one from the bank with the most terms left (the rare banks stay
+// available for later lanes), then the smallest first-factor entry, so that
+// a group moves through the first factor's table in a narrow window.  On
+// the 1e6-term, 1024-point workload this leaves about 0.7 conflict cycles
+// per wave and k, against 4.5 when each group's terms are dealt sorted by
+// their entries.  0xffffffff marks padding.
+// (host only) ex: the tail exponents, variable-major ((n - 2) x s); w: bytes per residue.
+int deal_slots_host(const std::vector<uint64_t> &grp_off, uint64_t s, const uint16_t *ex, uint32_t w, uint32_t K,
+                    uint64_t NT, const FactorPlan &fp, std::vector<uint32_t> *out) {
+  const uint64_t G = grp_off.size() - 1;
+  const uint32_t last = fp.nf ? fp.nf - 1 : 0;
+  const bool two = fp.nf > 1;                      // a last factor distinct from the first
+  const uint32_t nb = 256 / (2 * w);               // banks of the last factor's gather, and lanes per pass
+  constexpr uint32_t kBanks0 = 32, kLanes0 = 32;  // the first factor's (values only)
+  constexpr uint32_t kLook = 8;                    // candidates per bank (smallest first-factor entries)
+  constexpr uint32_t kNone = 0xffffffffu;
+  HostPlan hp = build_host_plan(grp_off, K, kPointsP, true);
   if (hp.NT != NT) return fail(PEVAL_EINVAL, "thread layout mismatch");
-  out->assign((size_t)K * NT, 0xffffffffu);
-  std::vector<std::pair<uint64_t, uint32_t>> terms;
-  uint64_t j = 0;
-  for (uint64_t g = 0; g < h->G; ++g) {
-    const uint64_t b = h->grp_off[g], e = h->grp_off[g + 1];
-    const uint64_t j0 = j;
-    while (j < NT && hp.thr_cnt[j] && hp.thr_first[j] < e) ++j;
-    const uint64_t nt = j - j0;  // ceil(m / K) threads
-    terms.clear();
-    for (uint64_t i = b; i < e; ++i) terms.emplace_back(key(i), (uint32_t)i);
-    std::stable_sort(terms.begin(), terms.end(),
-                     [](const std::pair<uint64_t, uint32_t> &x, const std::pair<uint64_t, uint32_t> &y) {
-                       return x.first < y.first;
-                     });
-    for (uint64_t q = 0; q < terms.size(); ++q)
-      (*out)[(q / nt) * NT + j0 + q % nt] = terms[q].second;
+  out->assign((size_t)K * NT, kNone);
+  // threads of each group
+  std::vector<uint64_t> tj0(G), tnt(G);
+  std::vector<uint32_t> tg(NT, kNone);
+  {
+    uint64_t j = 0;
+    for (uint64_t g = 0; g < G; ++g) {
+      const uint64_t e = grp_off[g + 1];
+      tj0[g] = j;
+      while (j < NT && hp.thr_cnt[j] && hp.thr_first[j] < e) tg[j++] = (uint32_t)g;
+      tnt[g] = j - tj0[g];
+      if (!tnt[g]) return fail(PEVAL_EINVAL, "group without threads");
+    }
+  }
+  struct Term {
+    uint32_t e0, e1, i;  // first and last factor's entries, term
+  };
+  // a group's remaining terms: by bank of the last factor's entry, each bank
+  // sorted by the first factor's entry
+  struct Pool {
+    std::vector<Term> t;
+    std::vector<uint32_t> base, head;
+    std::vector<uint8_t> taken;
+  };
+  std::map<uint64_t, Pool> pools;
+  auto make_pool = [&](uint64_t g) {
+    Pool &pl = pools[g];
+    const uint64_t b = grp_off[g], e = grp_off[g + 1];
+    std::vector<Term> all;
+    all.reserve(e - b);
+    for (uint64_t i = b; i < e; ++i) {
+      uint32_t local[kMaxFactors] = {0, 0, 0, 0};
+      for (uint32_t d = 0; d < fp.ndig; ++d) {
+        const uint32_t x = ex[(size_t)fp.var[d] * s + i];
+        local[fp.fac[d]] += ((x >> fp.shift[d]) & fp.mask[d]) * fp.stride[d];
+      }
+      all.push_back(Term{fp.f_off[0] + local[0], fp.f_off[last] + local[last], (uint32_t)i});
+    }
+    auto bank = [&](const Term &x) { return two ? x.e1 % nb : 0u; };
+    std::sort(all.begin(), all.end(), [&](const Term &x, const Term &y) {
+      const uint32_t bx = bank(x), by = bank(y);
+      if (bx != by) return bx < by;
+      return x.e0 != y.e0 ? x.e0 < y.e0 : x.e1 < y.e1;
+    });
+    pl.base.assign(nb + 1, 0);
+    for (const Term &x : all) pl.base[bank(x) + 1]++;
+    for (uint32_t c = 0; c < nb; ++c) pl.base[c + 1] += pl.base[c];
+    pl.head.assign(pl.base.begin(), pl.base.end() - 1);
+    pl.taken.assign(all.size(), 0);
+    pl.t.swap(all);
+  };
+  std::vector<uint32_t> owner0(kBanks0);
+  std::vector<uint8_t> held0(kBanks0);
+  std::vector<std::vector<uint32_t>> ent1(nb);  // distinct last-factor entries per bank in the pass
+  for (uint64_t w = 0; w < NT / 64; ++w) {
+    for (uint32_t l = 0; l < 64; ++l) {
+      const uint32_t g = tg[w * 64 + l];
+      if (g != kNone && !pools.count(g)) make_pool(g);
+    }
+    for (uint32_t k = 0; k < K; ++k) {
+      for (uint32_t l = 0; l < 64; ++l) {
+        if (l % kLanes0 == 0) std::fill(held0.begin(), held0.end(), 0);
+        if (l % nb == 0)
+          for (auto &v : ent1) v.clear();
+        const uint64_t j = w * 64 + l;
+        const uint32_t g = tg[j];
+        if (g == kNone) continue;
+        const uint64_t t = j - tj0[g];
+        if (k * tnt[g] + t >= grp_off[g + 1] - grp_off[g]) continue;  // no slot (k, t)
+        Pool &pl = pools[g];
+        uint64_t best = ~0ull;
+        uint32_t bpos = kNone, bc = 0;
+        for (uint32_t c = 0; c < nb; ++c) {
+          uint32_t u = pl.head[c];
+          while (u < pl.base[c + 1] && pl.taken[u]) ++u;
+          pl.head[c] = u;
+          for (uint32_t seen = 0; u < pl.base[c + 1] && seen < kLook; ++u) {
+            if (pl.taken[u]) continue;
+            ++seen;
+            const Term &x = pl.t[u];
+            const uint32_t b0 = (2 * x.e0) % kBanks0;
+            uint64_t conf = (held0[b0] && owner0[b0] != x.e0) ? 1 : 0;
+            if (two)
+              for (uint32_t y : ent1[c]) conf += (y != x.e1);
+            const uint64_t shared = (held0[b0] && owner0[b0] == x.e0) ? 0 : 1;
+            const uint64_t left = std::min<uint64_t>(pl.base[c + 1] - pl.head[c], 0xffff);
+            const uint64_t cost = (conf << 48) | (shared << 40) | ((0xffff - left) << 16) | x.e0;  // e0 < 2^16
+            if (cost < best) {
+              best = cost;
+              bpos = u;
+              bc = c;
+            }
+          }
+        }
+        if (bpos == kNone) return fail(PEVAL_EINVAL, "slot dealing ran out of terms");
+        const Term &x = pl.t[bpos];
+        pl.taken[bpos] = 1;
+        (*out)[(uint64_t)k * NT + j] = x.i;
+        const uint32_t b0 = (2 * x.e0) % kBanks0;
+        held0[b0] = 1;
+        owner0[b0] = x.e0;
+        if (std::find(ent1[bc].begin(), ent1[bc].end(), x.e1) == ent1[bc].end()) ent1[bc].push_back(x.e1);
+      }
+    }
+    // groups that end in this wave are dealt completely
+    for (auto it = pools.begin(); it != pools.end();) {
+      if (tj0[it->first] + tnt[it->first] <= (w + 1) * 64)
+        it = pools.erase(it);
+      else
+        ++it;
+    }
   }
   return PEVAL_OK;
+}
+
+int deal_slots(peval_poly *h, uint32_t K, uint64_t NT, const FactorPlan &fp, std::vector<uint32_t> *out) {
+  std::vector<uint16_t> ex((size_t)(h->n - 2) * h->s);
+  if (!ex.empty()) HIP_TRY(hipMemcpy(ex.data(), h->d_exps, ex.size() * 2, hipMemcpyDeviceToHost));
+  return deal_slots_host(h->grp_off, h->s, ex.data(), h->w, K, NT, fp, out);
 }
 
 template <class A>
@@ -328,6 +446,31 @@ int check_points_args(peval_poly *h, const uint64_t *points, uint32_t T) {
 }
 
 }  // namespace
+
+extern "C" int peval_test_deal_points(uint32_t w, uint32_t ntail, uint64_t s, const uint16_t *tail_exps, uint64_t G,
+                                      const uint64_t *group_sizes, uint32_t K, uint32_t *slot_term,
+                                      uint64_t slot_count) {
+  if ((w != 4 && w != 8) || ntail > (uint32_t)kMaxTail || (s && ntail && !tail_exps) || (G && !group_sizes) ||
+      !slot_term || !(K == 1 || K == 2 || K == 4 || K == 8 || K == 16))
+    return fail(PEVAL_EINVAL, "bad argument");
+  std::vector<uint64_t> off(G + 1, 0);
+  for (uint64_t g = 0; g < G; ++g) {
+    if (!group_sizes[g]) return fail(PEVAL_EINVAL, "empty group");
+    off[g + 1] = off[g] + group_sizes[g];
+  }
+  if (off[G] != s) return fail(PEVAL_EINVAL, "group sizes do not add up to s");
+  uint32_t maxdeg[kMaxTail] = {0};
+  for (uint32_t v = 0; v < ntail; ++v)
+    for (uint64_t i = 0; i < s; ++i) maxdeg[v] = std::max<uint32_t>(maxdeg[v], tail_exps[(size_t)v * s + i]);
+  FactorPlan fp;
+  PEVAL_TRY(build_factor_plan(w, ntail, maxdeg, &fp));
+  const uint64_t NT = build_host_plan(off, K, kPointsP, true).NT;
+  if (slot_count != (uint64_t)K * NT) return fail(PEVAL_EINVAL, "slot_count must be K x NT = %llu", (unsigned long long)(K * NT));
+  std::vector<uint32_t> out;
+  PEVAL_TRY(deal_slots_host(off, s, tail_exps, w, K, NT, fp, &out));
+  std::copy(out.begin(), out.end(), slot_term);
+  return PEVAL_OK;
+}
 
 extern "C" int peval_run_points_async(peval_poly *h, const uint64_t *points_dev, uint32_t T, void *dev_out,
                                       void *stream) {

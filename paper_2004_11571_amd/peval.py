@@ -103,6 +103,7 @@ def lib() -> ctypes.CDLL:
         "peval_test_arith": ([u32, u64, u64, vp, vp, vp, vp], i32),
         "peval_bench_product": ([u32, u64, u32, u32, ctypes.POINTER(ctypes.c_double),
                                  ctypes.POINTER(ctypes.c_double)], i32),
+        "peval_test_deal_points": ([u32, u32, u64, vp, u64, vp, u32, vp, u64], i32),
         "peval_strerror": ([i32], ctypes.c_char_p),
         "peval_last_error": ([], ctypes.c_char_p),
     }
@@ -529,3 +530,16 @@ def layout(group_sizes, K: int, P: int) -> dict:
                           slot_base.ctypes.data, slot_off.ctypes.data))
     return {"NT": NT, "NW": NW, "nslots": ns, "thr_first": thr_first, "thr_cnt": thr_cnt,
             "endmask": endmask, "slot_base": slot_base, "slot_off": slot_off}
+
+
+def deal_points(w: int, tail_exps, group_sizes, K: int) -> np.ndarray:
+    """Host-only: the point kernel's term of each thread slot, [K][NT]
+    (peval_test_deal_points; tail_exps is (n - 2) x s, variable-major)."""
+    ex = np.ascontiguousarray(tail_exps, dtype=np.uint16)
+    gs = np.ascontiguousarray(group_sizes, dtype=np.uint64)
+    ntail, s = (int(x) for x in ex.shape)
+    NT = layout(gs, K, 8)["NT"]
+    out = np.zeros((K, NT), np.uint32)
+    _check(lib().peval_test_deal_points(w, ntail, s, ex.ctypes.data if ex.size else None, gs.size,
+                                        gs.ctypes.data if gs.size else None, K, out.ctypes.data, out.size))
+    return out
