@@ -130,7 +130,8 @@ using PointsFn = void (*)(PointsArgs<A>);
 // 16-byte one per 16 lanes, 16-byte words modulo 16.  The first factor's
 // value (every 2nd word of the (value, quotient) entries) thus has 16 banks
 // per 32 lanes, the last factor's whole entry 32 (32-bit residues) or 16 per
-// 16 lanes (64-bit).  The slots are filled wave by wave, k by k, in lane
+// 16 lanes (64-bit), its value alone (the FP64 product's 8-byte gather of
+// 16-byte entries) 16 per 32 lanes.  The slots are filled wave by wave, k by k, in lane
 // order: each lane takes, among its group's remaining terms with the
 // smallest first-factor entries (a few per bank of the last factor), the
 // one that adds the fewest conflicts to the gathers of its pass (whatever
@@ -142,13 +143,18 @@ using PointsFn = void (*)(PointsArgs<A>);
 // the 1e6-term, 1024-point workload this leaves about 0.7 conflict cycles
 // per wave and k, against 4.5 when each group's terms are dealt sorted by
 // their entries.  0xffffffff marks padding.
-// (host only) ex: the tail exponents, variable-major ((n - 2) x s); w: bytes per residue.
-int deal_slots_host(const std::vector<uint64_t> &grp_off, uint64_t s, const uint16_t *ex, uint32_t w, uint32_t K,
-                    uint64_t NT, const FactorPlan &fp, std::vector<uint32_t> *out) {
+// (host only) ex: the tail exponents, variable-major ((n - 2) x s); w: bytes per residue;
+// last_bytes: bytes the kernel gathers per entry of the last factor (2 w, or w
+// for the FP64 product, which reads the value only).
+int deal_slots_host(const std::vector<uint64_t> &grp_off, uint64_t s, const uint16_t *ex, uint32_t w,
+                    uint32_t last_bytes, uint32_t K, uint64_t NT, const FactorPlan &fp, std::vector<uint32_t> *out) {
   const uint64_t G = grp_off.size() - 1;
   const uint32_t last = fp.nf ? fp.nf - 1 : 0;
   const bool two = fp.nf > 1;                      // a last factor distinct from the first
-  const uint32_t nb = 256 / (2 * w);               // banks of the last factor's gather, and lanes per pass
+  // the last factor's gather: banks (in its read width) and lanes per pass
+  const uint32_t nb = last_bytes == 16 ? 16 : 32;
+  const uint32_t lanes1 = nb;
+  const uint32_t scale1 = 2 * w / last_bytes;  // bank words per entry
   constexpr uint32_t kBanks0 = 32, kLanes0 = 32;  // the first factor's (values only)
   constexpr uint32_t kLook = 8;                    // candidates per bank (smallest first-factor entries)
   constexpr uint32_t kNone = 0xffffffffu;
@@ -192,7 +198,7 @@ int deal_slots_host(const std::vector<uint64_t> &grp_off, uint64_t s, const uint
       }
       all.push_back(Term{fp.f_off[0] + local[0], fp.f_off[last] + local[last], (uint32_t)i});
     }
-    auto bank = [&](const Term &x) { return two ? x.e1 % nb : 0u; };
+    auto bank = [&](const Term &x) { return two ? (x.e1 * scale1) % nb : 0u; };
     std::sort(all.begin(), all.end(), [&](const Term &x, const Term &y) {
       const uint32_t bx = bank(x), by = bank(y);
       if (bx != by) return bx < by;
@@ -216,7 +222,7 @@ int deal_slots_host(const std::vector<uint64_t> &grp_off, uint64_t s, const uint
     for (uint32_t k = 0; k < K; ++k) {
       for (uint32_t l = 0; l < 64; ++l) {
         if (l % kLanes0 == 0) std::fill(held0.begin(), held0.end(), 0);
-        if (l % nb == 0)
+        if (l % lanes1 == 0)
           for (auto &v : ent1) v.clear();
         const uint64_t j = w * 64 + l;
         const uint32_t g = tg[j];
@@ -269,10 +275,11 @@ int deal_slots_host(const std::vector<uint64_t> &grp_off, uint64_t s, const uint
   return PEVAL_OK;
 }
 
-int deal_slots(peval_poly *h, uint32_t K, uint64_t NT, const FactorPlan &fp, std::vector<uint32_t> *out) {
+int deal_slots(peval_poly *h, uint32_t last_bytes, uint32_t K, uint64_t NT, const FactorPlan &fp,
+               std::vector<uint32_t> *out) {
   std::vector<uint16_t> ex((size_t)(h->n - 2) * h->s);
   if (!ex.empty()) HIP_TRY(hipMemcpy(ex.data(), h->d_exps, ex.size() * 2, hipMemcpyDeviceToHost));
-  return deal_slots_host(h->grp_off, h->s, ex.data(), h->w, K, NT, fp, out);
+  return deal_slots_host(h->grp_off, h->s, ex.data(), h->w, last_bytes, K, NT, fp, out);
 }
 
 template <class A>
@@ -318,7 +325,7 @@ int run_points_impl(peval_poly *h, const uint64_t *points, uint32_t T, void *dev
   auto it = h->pprep.find(prep_key);
   if (it == h->pprep.end()) {  // per-slot coefficients, quotients and entry indices
     std::vector<uint32_t> slot_term;
-    PEVAL_TRY(deal_slots(h, K, pl->NT, fp, &slot_term));
+    PEVAL_TRY(deal_slots(h, fp64 ? (uint32_t)w : 2 * (uint32_t)w, K, pl->NT, fp, &slot_term));
     PointsPrep pp;
     const uint64_t total = (uint64_t)K * pl->NT;
     const bool ok = hipMalloc(&pp.pa, total * w) == hipSuccess && hipMalloc(&pp.paq, total * w) == hipSuccess &&
@@ -467,7 +474,7 @@ extern "C" int peval_test_deal_points(uint32_t w, uint32_t ntail, uint64_t s, co
   const uint64_t NT = build_host_plan(off, K, kPointsP, true).NT;
   if (slot_count != (uint64_t)K * NT) return fail(PEVAL_EINVAL, "slot_count must be K x NT = %llu", (unsigned long long)(K * NT));
   std::vector<uint32_t> out;
-  PEVAL_TRY(deal_slots_host(off, s, tail_exps, w, K, NT, fp, &out));
+  PEVAL_TRY(deal_slots_host(off, s, tail_exps, w, 2 * w, K, NT, fp, &out));
   std::copy(out.begin(), out.end(), slot_term);
   return PEVAL_OK;
 }
