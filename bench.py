@@ -402,6 +402,8 @@ def batch_main(args):
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                      "unit": "Tops/s (int32 lane-ops)", "frac": achieved / VALU_PEAK_OPS,
                      "traffic": profile_traffic(kernel_source_sha("batch_pass"), f"batch{len(ws)}_uneven", "batch_pass"),
+                     # the counters are taken on the heuristic tiles (the same plan in every counter run)
+                     "traffic_tiles": "heuristic",
                      "kernel_source_sha256": kernel_source_sha("batch_pass"),
                      "kernel": "whole batched pass (graph replay), all kernels",
                      "frac_at_median_step": ops / (spread["median"] / 1e3) / VALU_PEAK_OPS},
