@@ -391,6 +391,8 @@ def batch_main(args):
     value = te * steps / el
     ops = sum(ALGO_OPS[q.elem_bytes] * w.s * w.T for q, w in zip(polys, ws))
     achieved = ops * steps / el
+    # term data read once and images written once, every member
+    algo_bytes = sum(w.s * (q.elem_bytes + 2 * (w.n - 2)) + w.T * q.G * q.elem_bytes for q, w in zip(polys, ws))
     res = {
         "metric": METRIC, "value": value, "unit": "term-evals/s", "n_gpus": 1, "steps": steps,
         "warmup": warm, "ms_per_step": el / steps * 1e3, "higher_is_better": True, "scaling": "weak",
@@ -406,7 +408,9 @@ def batch_main(args):
                      "traffic_tiles": "heuristic",
                      "kernel_source_sha256": kernel_source_sha("batch_pass"),
                      "kernel": "whole batched pass (graph replay), all kernels",
-                     "frac_at_median_step": ops / (spread["median"] / 1e3) / VALU_PEAK_OPS},
+                     "frac_at_median_step": ops / (spread["median"] / 1e3) / VALU_PEAK_OPS,
+                     "hbm_algorithmic_bytes_per_step": algo_bytes,
+                     "hbm_frac": algo_bytes / (el / steps) / HBM_PEAK},
         "step_ms_spread": spread,
         "sequential_plain": {"value": te * steps / el_seq, "ms_per_step": el_seq / steps * 1e3,
                              "batched_over_sequential": el_seq / el, "identical_outputs": same},
