@@ -46,7 +46,7 @@ int build_factor_plan(uint32_t w, uint32_t ntail, const uint32_t *maxdeg, Factor
     f.nf = 1;
     f.f_off[0] = 0;
     f.f_off[1] = 1;
-    f.E = 2;
+    f.E = w == 4 ? 4 : 2;
     *fp = f;
     return PEVAL_OK;
   }
@@ -80,7 +80,8 @@ int build_factor_plan(uint32_t w, uint32_t ntail, const uint32_t *maxdeg, Factor
     }
     f.f_off[0] = 0;
     for (uint32_t b = 0; b < nf; ++b) f.f_off[b + 1] = f.f_off[b] + (uint32_t)size[b];
-    f.E = (f.f_off[nf] + 1) & ~1u;
+    // whole 16-byte pieces: 4-byte entries (32-bit residues) in fours, 16-byte ones in twos
+    f.E = w == 4 ? (f.f_off[nf] + 3) & ~3u : (f.f_off[nf] + 1) & ~1u;
     *fp = f;
     return PEVAL_OK;
   }
@@ -127,11 +128,11 @@ using PointsFn = void (*)(PointsArgs<A>);
 // lanes whose entries differ but share a bank serialise.  As measured on
 // gfx950, a 4- or 8-byte gather is served per 32 lanes, its banks the 4-byte
 // words modulo 32 (4 bytes) or the 8-byte words modulo 32 (8 bytes); a
-// 16-byte one per 16 lanes, 16-byte words modulo 16.  The first factor's
-// value (every 2nd word of the (value, quotient) entries) thus has 16 banks
-// per 32 lanes, the last factor's whole entry 32 (32-bit residues) or 16 per
-// 16 lanes (64-bit), its value alone (the FP64 product's 8-byte gather of
-// 16-byte entries) 16 per 32 lanes.  The slots are filled wave by wave, k by k, in lane
+// 16-byte one per 16 lanes, 16-byte words modulo 16.  With 4-byte entries
+// (32-bit residues) every gather has 32 banks per 32 lanes; with 16-byte
+// (value, quotient) entries the first factor's 8-byte value has 16 per 32
+// lanes, the last factor's whole entry 16 per 16 lanes, its value alone (the
+// FP64 product's 8-byte gather) 16 per 32 lanes.  The slots are filled wave by wave, k by k, in lane
 // order: each lane takes, among its group's remaining terms with the
 // smallest first-factor entries (a few per bank of the last factor), the
 // one that adds the fewest conflicts to the gathers of its pass (whatever
@@ -143,19 +144,18 @@ using PointsFn = void (*)(PointsArgs<A>);
 // the 1e6-term, 1024-point workload this leaves about 0.7 conflict cycles
 // per wave and k, against 4.5 when each group's terms are dealt sorted by
 // their entries.  0xffffffff marks padding.
-// (host only) ex: the tail exponents, variable-major ((n - 2) x s); w: bytes per residue;
-// last_bytes: bytes the kernel gathers per entry of the last factor (2 w, or w
-// for the FP64 product, which reads the value only).
-int deal_slots_host(const std::vector<uint64_t> &grp_off, uint64_t s, const uint16_t *ex, uint32_t w,
-                    uint32_t last_bytes, uint32_t K, uint64_t NT, const FactorPlan &fp, std::vector<uint32_t> *out) {
+// (host only) ex: the tail exponents, variable-major ((n - 2) x s); eb: bytes
+// per table entry; r0, r1: bytes the kernel gathers per entry of the first
+// and of the last factor.
+int deal_slots_host(const std::vector<uint64_t> &grp_off, uint64_t s, const uint16_t *ex, uint32_t eb, uint32_t r0,
+                    uint32_t r1, uint32_t K, uint64_t NT, const FactorPlan &fp, std::vector<uint32_t> *out) {
   const uint64_t G = grp_off.size() - 1;
   const uint32_t last = fp.nf ? fp.nf - 1 : 0;
   const bool two = fp.nf > 1;                      // a last factor distinct from the first
-  // the last factor's gather: banks (in its read width) and lanes per pass
-  const uint32_t nb = last_bytes == 16 ? 16 : 32;
-  const uint32_t lanes1 = nb;
-  const uint32_t scale1 = 2 * w / last_bytes;  // bank words per entry
-  constexpr uint32_t kBanks0 = 32, kLanes0 = 32;  // the first factor's (values only)
+  // each gather: banks (in its read width), which are also its lanes per
+  // pass, and bank words per entry
+  const uint32_t nb = r1 == 16 ? 16 : 32, lanes1 = nb, scale1 = eb / r1;
+  const uint32_t kBanks0 = r0 == 16 ? 16 : 32, kLanes0 = kBanks0, scale0 = eb / r0;
   constexpr uint32_t kLook = 8;                    // candidates per bank (smallest first-factor entries)
   constexpr uint32_t kNone = 0xffffffffu;
   HostPlan hp = build_host_plan(grp_off, K, kPointsP, true);
@@ -240,7 +240,7 @@ int deal_slots_host(const std::vector<uint64_t> &grp_off, uint64_t s, const uint
             if (pl.taken[u]) continue;
             ++seen;
             const Term &x = pl.t[u];
-            const uint32_t b0 = (2 * x.e0) % kBanks0;
+            const uint32_t b0 = (x.e0 * scale0) % kBanks0;
             uint64_t conf = (held0[b0] && owner0[b0] != x.e0) ? 1 : 0;
             if (two)
               for (uint32_t y : ent1[c]) conf += (y != x.e1);
@@ -258,7 +258,7 @@ int deal_slots_host(const std::vector<uint64_t> &grp_off, uint64_t s, const uint
         const Term &x = pl.t[bpos];
         pl.taken[bpos] = 1;
         (*out)[(uint64_t)k * NT + j] = x.i;
-        const uint32_t b0 = (2 * x.e0) % kBanks0;
+        const uint32_t b0 = (x.e0 * scale0) % kBanks0;
         held0[b0] = 1;
         owner0[b0] = x.e0;
         if (std::find(ent1[bc].begin(), ent1[bc].end(), x.e1) == ent1[bc].end()) ent1[bc].push_back(x.e1);
@@ -275,11 +275,11 @@ int deal_slots_host(const std::vector<uint64_t> &grp_off, uint64_t s, const uint
   return PEVAL_OK;
 }
 
-int deal_slots(peval_poly *h, uint32_t last_bytes, uint32_t K, uint64_t NT, const FactorPlan &fp,
+int deal_slots(peval_poly *h, uint32_t eb, uint32_t r0, uint32_t r1, uint32_t K, uint64_t NT, const FactorPlan &fp,
                std::vector<uint32_t> *out) {
   std::vector<uint16_t> ex((size_t)(h->n - 2) * h->s);
   if (!ex.empty()) HIP_TRY(hipMemcpy(ex.data(), h->d_exps, ex.size() * 2, hipMemcpyDeviceToHost));
-  return deal_slots_host(h->grp_off, h->s, ex.data(), h->w, last_bytes, K, NT, fp, out);
+  return deal_slots_host(h->grp_off, h->s, ex.data(), eb, r0, r1, K, NT, fp, out);
 }
 
 template <class A>
@@ -325,7 +325,13 @@ int run_points_impl(peval_poly *h, const uint64_t *points, uint32_t T, void *dev
   auto it = h->pprep.find(prep_key);
   if (it == h->pprep.end()) {  // per-slot coefficients, quotients and entry indices
     std::vector<uint32_t> slot_term;
-    PEVAL_TRY(deal_slots(h, fp64 ? (uint32_t)w : 2 * (uint32_t)w, K, pl->NT, fp, &slot_term));
+    // gathers: 32-bit residues read 4-byte entries; 64-bit ones the 8-byte
+    // value of the first factor and the whole 16-byte entry of the others.
+    // (The FP64 product reads only the 8-byte value of those; dealing for
+    // that gather measured no faster on the Table 2 shape, and slower on
+    // one box, than dealing as for the whole entry, which is kept.)
+    const uint32_t eb = points_entry_bytes<T_>(), r0 = (uint32_t)w, r1 = w == 4 ? (uint32_t)w : eb;
+    PEVAL_TRY(deal_slots(h, eb, r0, r1, K, pl->NT, fp, &slot_term));
     PointsPrep pp;
     const uint64_t total = (uint64_t)K * pl->NT;
     const bool ok = hipMalloc(&pp.pa, total * w) == hipSuccess && hipMalloc(&pp.paq, total * w) == hipSuccess &&
@@ -351,13 +357,14 @@ int run_points_impl(peval_poly *h, const uint64_t *points, uint32_t T, void *dev
   const PointsPrep &pp = it->second;
 
   uint64_t tc = std::max<uint64_t>(1, kPointsPartialBudget / std::max<uint64_t>(1, pl->nslots * w));
-  tc = std::min<uint64_t>(tc, std::max<uint64_t>(1, kPointsTablesBudget / ((uint64_t)fp.E * 2 * w)));
+  const size_t eb = points_entry_bytes<T_>();
+  tc = std::min<uint64_t>(tc, std::max<uint64_t>(1, kPointsTablesBudget / ((uint64_t)fp.E * eb)));
   tc = std::min<uint64_t>(tc, (uint64_t)C * kCombineTile * 32768);
   tc = std::min<uint64_t>(tc, T);
   if (tc < T && tc > C) tc = tc / C * C;
-  PEVAL_TRY(ensure(h->ptab, (size_t)tc * fp.E * 2 * w, h));
+  PEVAL_TRY(ensure(h->ptab, (size_t)tc * fp.E * eb, h));
   PEVAL_TRY(ensure(h->partial, (size_t)((tc + C - 1) / C) * C * pl->nslots * w, h));
-  const size_t shmem = (kEvalBlock / 64) * sizeof(Stage<E, kPointsP>) + (size_t)fp.E * 2 * w;
+  const size_t shmem = (kEvalBlock / 64) * sizeof(Stage<E, kPointsP>) + (size_t)fp.E * eb;
 
   for (uint64_t done = 0; done < T; done += tc) {
     const uint32_t Tc = (uint32_t)std::min<uint64_t>(tc, T - done);
@@ -474,7 +481,7 @@ extern "C" int peval_test_deal_points(uint32_t w, uint32_t ntail, uint64_t s, co
   const uint64_t NT = build_host_plan(off, K, kPointsP, true).NT;
   if (slot_count != (uint64_t)K * NT) return fail(PEVAL_EINVAL, "slot_count must be K x NT = %llu", (unsigned long long)(K * NT));
   std::vector<uint32_t> out;
-  PEVAL_TRY(deal_slots_host(off, s, tail_exps, w, 2 * w, K, NT, fp, &out));
+  PEVAL_TRY(deal_slots_host(off, s, tail_exps, w == 4 ? 4 : 16, w, w == 4 ? 4 : 16, K, NT, fp, &out));
   std::copy(out.begin(), out.end(), slot_term);
   return PEVAL_OK;
 }

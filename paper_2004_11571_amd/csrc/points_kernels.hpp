@@ -12,7 +12,10 @@
 // products: every table entry carries its precomputed quotient, and so does
 // the coefficient (which is fixed per term).
 //
-//   points_table_kernel  factor tables for every point of the launch (HBM)
+//   points_table_kernel  factor tables for every point of the launch (HBM);
+//                        32-bit residues keep 4-byte entries, the factors
+//                        after the first in Montgomery form (their product
+//                        needs no quotient), 64-bit ones (value, quotient)
 //   points_prep_kernel   per thread slot: a_i, its quotient, packed entry
 //                        indices (once per polynomial and thread layout);
 //                        a group's terms are dealt to its slots sorted by
@@ -40,6 +43,11 @@ constexpr int kPointsP = 8;          // points per pass of the segmented walk
 constexpr int kMaxFactors = 4;
 constexpr int kMaxDigits = 2 * kMaxTail;
 constexpr uint32_t kPointsTableBytes = 32768;  // LDS for one point's tables
+// Bytes of one table entry: the value alone for 32-bit residues; the value
+// and its Shoup quotient for 64-bit ones (for the FP64 product, the value as
+// a double and an unused word).
+template <class T>
+constexpr uint32_t points_entry_bytes() { return sizeof(T) == 4 ? 4u : 16u; }
 // 16-byte pieces per thread of the next point's tables prefetched into
 // registers: four for 64-bit residues (tables up to 16 KiB; measured 10%
 // faster on the 1e6-term workload), none for 32-bit ones, whose kernels lose
@@ -83,12 +91,17 @@ __device__ __forceinline__ T load_value(const T *tab, uint32_t off) {
   return *reinterpret_cast<const T *>(reinterpret_cast<const unsigned char *>(tab) + off);
 }
 
+// -p^{-1} mod 2^32 for Montgomery's product (32-bit residues; unused otherwise)
+template <class M>
+__device__ __forceinline__ uint32_t mont_np(const M &) { return 0u; }
+__device__ __forceinline__ uint32_t mont_np(const Mod32 &m) { return 0u - m.pinv; }
+
 template <class A>
 struct PointsArgs {
   const typename A::T *pa;     // [K][NT] coefficients (0 for padding)
   const typename A::T *paq;    // [K][NT] their Shoup quotients
   const uint64_t *pidx;        // [K][NT] byte offset of each factor's entry, 16 bits per factor
-  const typename A::T *tables; // [T][E][2] (value, quotient) per entry
+  const typename A::T *tables; // [T][E] entries of points_entry_bytes
   const uint64_t *endmask;
   const uint32_t *slot_base;
   typename A::PT *partial;     // [nslots][C][Lmax]
@@ -121,15 +134,19 @@ __global__ void points_table_kernel(const uint64_t *points, uint32_t ntail, uint
       v = mul_mod(v, pow_mod(x, (uint64_t)digit << fp.shift[d], m), m);
     }
   }  // entries past the last factor (padding to an even count) hold 1
-  if constexpr (sizeof(T_) == 8) {
+  if constexpr (sizeof(T_) == 4) {  // Montgomery form v 2^32 mod p past the first factor
+    const bool mont = fp.nf > 1 && e >= fp.f_off[1] && e < fp.f_off[fp.nf];
+    tables[idx] = mont ? canon(shoup_mul(v, m.R, m.Rq, m.p), m.p) : v;
+    return;
+  } else {
     if (as_double) {
       tables[2 * idx] = (T_)__double_as_longlong((double)v);
       tables[2 * idx + 1] = 0;
       return;
     }
+    tables[2 * idx] = v;
+    tables[2 * idx + 1] = shoup_quot(v, m);
   }
-  tables[2 * idx] = v;
-  tables[2 * idx + 1] = shoup_quot(v, m);
 }
 
 // Per thread slot (k, j): coefficient, quotient and the entry index of each
@@ -166,13 +183,13 @@ __global__ void points_prep_kernel(const typename A::T *coeff, const uint16_t *e
         if (fp.fac[d] == f) local[f] += add;
     }
   }
-  // byte offsets of the (value, quotient) entries in one point's tables
-  // (entries of 2 * sizeof(T) bytes; every offset is below 32 KiB)
+  // byte offsets of the entries in one point's tables (every offset is
+  // below 32 KiB)
   uint64_t packed = 0;
 #pragma unroll
   for (int f = 0; f < kMaxFactors; ++f)
     if ((uint32_t)f < fp.nf)
-      packed |= (uint64_t)((fp.f_off[f] + local[f]) * 2 * (uint32_t)sizeof(typename A::T)) << (16 * f);
+      packed |= (uint64_t)((fp.f_off[f] + local[f]) * points_entry_bytes<typename A::T>()) << (16 * f);
   pa[idx] = a;
   paq[idx] = aq;
   pidx[idx] = packed;
@@ -212,7 +229,9 @@ __global__ __launch_bounds__(kEvalBlock, ((K == 16 && NF > 2) ? 2 : 3)) void poi
   // points of chain c, the same for the whole wave (the division is done
   // in vector registers; read back into a scalar one)
   const uint32_t L = __builtin_amdgcn_readfirstlane((c < a.T) ? (a.T - 1 - c) / a.C + 1 : 0);
-  const uint32_t nvec = a.E * 2 * (uint32_t)sizeof(T) / 16;       // 16-byte pieces of one point's tables
+  constexpr uint32_t EB = points_entry_bytes<T>();
+  const uint32_t nvec = a.E * EB / 16;  // 16-byte pieces of one point's tables (E EB is a multiple of 16)
+  const uint32_t pneg = mont_np(a.m);  // 32-bit residues: -p^{-1} mod 2^32
 
   // The first PRE x 256 pieces of the next point's tables are loaded into
   // registers while the current point is evaluated, so the HBM/L2 latency of
@@ -234,7 +253,8 @@ __global__ __launch_bounds__(kEvalBlock, ((K == 16 && NF > 2) ? 2 : 3)) void poi
       p3 = src[u3];
     }
   };
-  if (L) prefetch(reinterpret_cast<const uint4 *>(a.tables + (uint64_t)c * a.E * 2));
+  const uint64_t pt_words = (uint64_t)a.E * EB / sizeof(T);  // words of one point's tables
+  if (L) prefetch(reinterpret_cast<const uint4 *>(a.tables + (uint64_t)c * pt_words));
 
   for (uint32_t i0 = 0; i0 < L; i0 += P) {
     // (kept in a scalar register: the compiler forms the clamp with a vector
@@ -243,7 +263,7 @@ __global__ __launch_bounds__(kEvalBlock, ((K == 16 && NF > 2) ? 2 : 3)) void poi
 #pragma unroll 1
     for (int q = 0; q < np; ++q) {
       const uint64_t t = (uint64_t)c + (uint64_t)(i0 + q) * a.C;
-      const uint4 *src = reinterpret_cast<const uint4 *>(a.tables + t * a.E * 2);
+      const uint4 *src = reinterpret_cast<const uint4 *>(a.tables + t * pt_words);
       __syncthreads();  // the previous point's tables are no longer read
       {
         uint4 *t4 = reinterpret_cast<uint4 *>(tab);
@@ -258,7 +278,7 @@ __global__ __launch_bounds__(kEvalBlock, ((K == 16 && NF > 2) ? 2 : 3)) void poi
       for (uint32_t u = threadIdx.x + PRE * kEvalBlock; u < nvec; u += kEvalBlock)
         reinterpret_cast<uint4 *>(tab)[u] = src[u];
       __syncthreads();
-      if (i0 + q + 1 < L) prefetch(reinterpret_cast<const uint4 *>(a.tables + (t + a.C) * a.E * 2));
+      if (i0 + q + 1 < L) prefetch(reinterpret_cast<const uint4 *>(a.tables + (t + a.C) * pt_words));
       if (active) {
         typename A::Sum acc = A::sum_zero();
 #pragma unroll
@@ -267,9 +287,13 @@ __global__ __launch_bounds__(kEvalBlock, ((K == 16 && NF > 2) ? 2 : 3)) void poi
           T mv = load_value(tab, (uint32_t)x & 0xffff);
 #pragma unroll
           for (int f = 1; f < NF; ++f) {
-            T tv, tq;
-            load_entry(tab, (uint32_t)(x >> (16 * f)) & 0xffff, tv, tq);
-            mv = A::mul_lazy(mv, tv, tq, a.m);
+            if constexpr (sizeof(T) == 4) {  // Montgomery form: no quotient to read
+              mv = mont_mul32(mv, load_value(tab, (uint32_t)(x >> (16 * f)) & 0xffff), a.m.p, pneg);
+            } else {
+              T tv, tq;
+              load_entry(tab, (uint32_t)(x >> (16 * f)) & 0xffff, tv, tq);
+              mv = A::mul_lazy(mv, tv, tq, a.m);
+            }
           }
           A::sum_add(acc, A::mul_lazy(mv, av[k], aq[k], a.m));
         }

@@ -174,7 +174,7 @@ def test_batch_rejects_bad_arguments():
     (8, [20, 20, 20, 20], (2, 882)),            # 1e6-term shape: two tables of 21 x 21
     (8, [30] * 6, (4, 1984)),                   # 1e7-term shape: 31^2, 31^2, 31, 31
     (8, [10] * 4, (2, 242)),                    # Table 2 shape: 11^2 + 11^2
-    (4, [30] * 6, (3, 2884)),                   # 32-bit residues: twice the entries fit (3 x 961, even)
+    (4, [30] * 6, (3, 2884)),                   # 32-bit residues: twice the entries fit (3 x 961, padded to 4)
     (8, [100, 100, 100], (3, 304)),             # 101 + 101 + 101, padded to even
     (8, [65535], (2, 512)),                     # split into two base-256 digits
     (8, [300], (1, 512)),                       # digits of radix 256 and 2 in one table
@@ -184,8 +184,10 @@ def test_batch_rejects_bad_arguments():
 def test_points_factor_plans(w, maxdeg, want):
     nf, E = PV.points_factors(w, maxdeg)
     assert nf == want[0]
-    # every plan fits one point's tables in 32 KiB of LDS
-    assert E * 2 * w <= 32768 and E % 2 == 0
+    # every plan fits one point's tables in 32 KiB of LDS (entries of 2w
+    # bytes at most), in whole 16-byte pieces (4-byte entries for w = 4,
+    # 16-byte ones for w = 8)
+    assert E * 2 * w <= 32768 and E % (4 if w == 4 else 2) == 0
     if want[1] is not None:
         assert E == want[1]
 

@@ -8,7 +8,8 @@ a thread of its own group.  It also exists to spread the kernel's LDS
 gathers over the banks: the second test compares the bank conflicts of one
 k's gathers with those of dealing the terms sorted by their table entries,
 under the gfx950 bank model (4- and 8-byte gathers served per 32 lanes over
-32 banks of 4-byte or 8-byte words, 16-byte gathers per 16 lanes)."""
+32 banks of 4-byte or 8-byte words, 16-byte gathers per 16 lanes).  The
+tables have 4-byte entries for 32-bit residues, 16-byte ones for 64-bit."""
 import numpy as np
 import pytest
 
@@ -57,18 +58,22 @@ def test_dealing_is_a_bijection_within_groups(w, K, deg):
 
 def _extra_cycles(slots, e0, e1, w):
     """Bank-conflict cycles beyond one pass, summed over every (wave, k)
-    gather of the first factor's value and the last factor's entry."""
+    gather of the first factor's value and the last factor's entry: 4-byte
+    entries for 32-bit residues (both gathers: entry e in bank e mod 32),
+    16-byte (value, quotient) entries for 64-bit ones (the value: 8-byte
+    word 2e mod 32; the whole entry: e mod 16, per 16 lanes)."""
     K, NT = slots.shape
     lanes1, banks1 = (32, 32) if w == 4 else (16, 16)
+    scale0 = 1 if w == 4 else 2
     tot = 0
     for k in range(K):
         for w0 in range(0, NT, 64):
             row = slots[k, w0:w0 + 64]
-            for a in range(0, 64, 32):   # first factor: value at word 2 e0, 32 banks per 32 lanes
+            for a in range(0, 64, 32):   # first factor's value, 32 banks per 32 lanes
                 t = row[a:a + 32]
                 t = t[t != 0xFFFFFFFF]
                 if t.size:
-                    words = np.unique(2 * e0[t])
+                    words = np.unique(scale0 * e0[t])
                     tot += np.bincount(words % 32).max() - 1
             for a in range(0, 64, lanes1):  # last factor: whole entries
                 t = row[a:a + lanes1]
@@ -87,7 +92,7 @@ def test_dealing_spreads_the_gathers_over_banks(w):
     deg = 100
     ex = rng.integers(0, deg + 1, (2, s)).astype(np.uint16)
     nf, E = PV.points_factors(w, [deg, deg])
-    assert (nf, E) == (2, 2 * (deg + 1))  # x3 in the first table, x4 in the second
+    assert nf == 2 and E >= 2 * (deg + 1)  # x3 in the first table, x4 in the second
     e0 = ex[0].astype(np.int64)
     e1 = (deg + 1) + ex[1].astype(np.int64)
     K = 16
