@@ -50,6 +50,8 @@ extern "C" {
  *   PEVAL_TOP_SHOUP32 (a any 32-bit word), PEVAL_TOP_REDUCE64_32 (a any
  *   64-bit word -> canonical), PEVAL_TOP_POW32, PEVAL_TOP_SUM32 (16 values
  *   below 2^32 per sum) as for 64-bit residues.
+ *   PEVAL_TOP_MONT32    a < 2p, b < p -> Montgomery's product a b 2^-32 mod
+ *                       p, lazy in [0, 2p) (the point mode's factor tables)
  *
  * Returns PEVAL_EINVAL for an unknown op, a modulus outside the op's range
  * or null arrays with count > 0; enqueues on `stream` and returns.
@@ -60,7 +62,7 @@ enum {
     PEVAL_TOP_ALG2 = 8, PEVAL_TOP_FOLD = 9, PEVAL_TOP_CANON_F64 = 10,
     PEVAL_TOP_PM63 = 12, PEVAL_TOP_PM31 = 13,
     PEVAL_TOP_MUL32 = 16, PEVAL_TOP_QUOT32 = 17, PEVAL_TOP_SHOUP32 = 18, PEVAL_TOP_REDUCE64_32 = 19,
-    PEVAL_TOP_POW32 = 20, PEVAL_TOP_SUM32 = 21
+    PEVAL_TOP_POW32 = 20, PEVAL_TOP_SUM32 = 21, PEVAL_TOP_MONT32 = 22
 };
 int peval_test_arith(uint32_t op, uint64_t p, uint64_t count, const uint64_t *dev_a, const uint64_t *dev_b,
                      uint64_t *dev_out, void *stream);

@@ -326,11 +326,9 @@ int run_points_impl(peval_poly *h, const uint64_t *points, uint32_t T, void *dev
   if (it == h->pprep.end()) {  // per-slot coefficients, quotients and entry indices
     std::vector<uint32_t> slot_term;
     // gathers: 32-bit residues read 4-byte entries; 64-bit ones the 8-byte
-    // value of the first factor and the whole 16-byte entry of the others.
-    // (The FP64 product reads only the 8-byte value of those; dealing for
-    // that gather measured no faster on the Table 2 shape, and slower on
-    // one box, than dealing as for the whole entry, which is kept.)
-    const uint32_t eb = points_entry_bytes<T_>(), r0 = (uint32_t)w, r1 = w == 4 ? (uint32_t)w : eb;
+    // value of the first factor and the whole 16-byte entry of the others
+    // (the FP64 product: their 8-byte value)
+    const uint32_t eb = points_entry_bytes<T_>(), r0 = (uint32_t)w, r1 = (w == 4 || fp64) ? (uint32_t)w : eb;
     PEVAL_TRY(deal_slots(h, eb, r0, r1, K, pl->NT, fp, &slot_term));
     PointsPrep pp;
     const uint64_t total = (uint64_t)K * pl->NT;

@@ -60,6 +60,7 @@ __global__ __launch_bounds__(256) void arith_test_kernel(ArithArgs x) {
     case PEVAL_TOP_SHOUP32: r = shoup_mul((uint32_t)a, (uint32_t)b, shoup_quot((uint32_t)b, x.m32), x.m32.p); break;
     case PEVAL_TOP_REDUCE64_32: r = reduce64(a, x.m32); break;
     case PEVAL_TOP_POW32: r = pow_mod((uint32_t)a, b, x.m32); break;
+    case PEVAL_TOP_MONT32: r = mont_mul32((uint32_t)a, (uint32_t)b, x.m32.p, 0u - x.m32.pinv); break;
     case PEVAL_TOP_SUM32: {
       W32::Sum s = W32::sum_zero();
       for (int k = 0; k < 16; ++k) W32::sum_add(s, (uint32_t)x.a[16 * i + k]);
@@ -83,7 +84,7 @@ int op_class(uint32_t op) {
     case PEVAL_TOP_PM63: return 63;
     case PEVAL_TOP_PM31: return 31;
     case PEVAL_TOP_MUL32: case PEVAL_TOP_QUOT32: case PEVAL_TOP_SHOUP32: case PEVAL_TOP_REDUCE64_32:
-    case PEVAL_TOP_POW32: case PEVAL_TOP_SUM32: return 32;
+    case PEVAL_TOP_POW32: case PEVAL_TOP_SUM32: case PEVAL_TOP_MONT32: return 32;
     default: return 0;
   }
 }

@@ -89,7 +89,7 @@ def _mismatch(got, want, a, b=None):
 
 OPS = {"MUL64": 0, "QUOT64": 1, "SHOUP64": 2, "REDUCE96": 3, "POW64": 4, "SUM64": 5, "FOLD96": 6, "ALG2": 8, "FOLD": 9,
        "CANON_F64": 10, "PM63": 12, "PM31": 13, "MUL32": 16, "QUOT32": 17, "SHOUP32": 18, "REDUCE64_32": 19,
-       "POW32": 20, "SUM32": 21}
+       "POW32": 20, "SUM32": 21, "MONT32": 22}
 
 
 @pytest.mark.parametrize("p", MODULI_64)
@@ -179,6 +179,17 @@ def test_products_and_sums_32(p):
     got = _objs(_run(OPS["SUM32"], p, vals, None, count=m))
     want = _objs(vals).reshape(m, 16).sum(axis=1) % p
     assert (err := _mismatch(got, want, vals[::16])) is None, err
+    # Montgomery's product: any a < 2p by any b < p gives a value below 2p
+    # congruent to a b 2^-32 (edge operands first)
+    ma = rng.integers(0, 2 * p, size=N_RANDOM, dtype=np.uint64)
+    mb = rng.integers(0, p, size=N_RANDOM, dtype=np.uint64)
+    ma[:6] = [0, 1, p - 1, p, 2 * p - 1, 2 * p - 1]
+    mb[:6] = [p - 1, p - 1, p - 1, 1, p - 1, 0]
+    got = _objs(_run(OPS["MONT32"], p, ma, mb))
+    rinv = pow(1 << 32, -1, p)
+    want = (_objs(ma) * _objs(mb) * rinv) % p
+    assert (err := _mismatch(got % p, want, ma, mb)) is None, err
+    assert all(int(g) < 2 * p for g in got)
 
 
 def _signed(x):
