@@ -94,7 +94,13 @@ __device__ __forceinline__ T load_value(const T *tab, uint32_t off) {
 // -p^{-1} mod 2^32 for Montgomery's product (32-bit residues; unused otherwise)
 template <class M>
 __device__ __forceinline__ uint32_t mont_np(const M &) { return 0u; }
-__device__ __forceinline__ uint32_t mont_np(const Mod32 &m) { return 0u - m.pinv; }
+// (opaque to the compiler, which would otherwise move the negation after
+// the multiply, one more instruction per product)
+__device__ __forceinline__ uint32_t mont_np(const Mod32 &m) {
+  uint32_t r = 0u - m.pinv;
+  asm("" : "+s"(r));
+  return r;
+}
 
 template <class A>
 struct PointsArgs {
@@ -280,7 +286,7 @@ __global__ __launch_bounds__(kEvalBlock, ((K == 16 && NF > 2) ? 2 : 3)) void poi
       __syncthreads();
       if (i0 + q + 1 < L) prefetch(reinterpret_cast<const uint4 *>(a.tables + (t + a.C) * pt_words));
       if (active) {
-        typename A::Sum acc = A::sum_zero();
+        typename A::Sum acc;  // begun from the first term's value
 #pragma unroll
         for (int k = 0; k < K; ++k) {
           const uint64_t x = ix[k];
@@ -295,7 +301,11 @@ __global__ __launch_bounds__(kEvalBlock, ((K == 16 && NF > 2) ? 2 : 3)) void poi
               mv = A::mul_lazy(mv, tv, tq, a.m);
             }
           }
-          A::sum_add(acc, A::mul_lazy(mv, av[k], aq[k], a.m));
+          const T v = A::mul_lazy(mv, av[k], aq[k], a.m);
+          if (k == 0)
+            acc = A::sum_first(v);
+          else
+            A::sum_add(acc, v);
         }
         stage[warp].put(lane, q, A::stage(acc, a.m));
       }
