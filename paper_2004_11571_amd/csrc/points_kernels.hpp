@@ -50,10 +50,11 @@ template <class T>
 constexpr uint32_t points_entry_bytes() { return sizeof(T) == 4 ? 4u : 16u; }
 // 16-byte pieces per thread of the next point's tables prefetched into
 // registers: four for 64-bit residues (tables up to 16 KiB; measured 10%
-// faster on the 1e6-term workload), none for 32-bit ones, whose kernels lose
-// a wave per SIMD to the extra registers and measured slower with them
+// faster on the 1e6-term workload), one for 32-bit ones (4-byte entries:
+// tables up to 4 KiB in one piece per thread; four pieces cost those
+// kernels a wave per SIMD)
 template <class T>
-constexpr int points_prefetch() { return sizeof(T) == 8 ? 4 : 0; }
+constexpr int points_prefetch() { return sizeof(T) == 8 ? 4 : 1; }
 
 // How a term's tail monomial is split into factor-table lookups.
 struct FactorPlan {
@@ -250,10 +251,10 @@ __global__ __launch_bounds__(kEvalBlock, ((K == 16 && NF > 2) ? 2 : 3)) void poi
   const uint32_t last = nvec - 1;
   const uint32_t u0 = min(threadIdx.x, last), u1 = min(threadIdx.x + kEvalBlock, last);
   const uint32_t u2 = min(threadIdx.x + 2 * kEvalBlock, last), u3 = min(threadIdx.x + 3 * kEvalBlock, last);
-  static_assert(PRE == 0 || PRE == 4, "prefetch of 0 or 4 pieces per thread");
+  static_assert(PRE == 0 || PRE == 1 || PRE == 4, "prefetch of 0, 1 or 4 pieces per thread");
   auto prefetch = [&](const uint4 *src) {
+    if constexpr (PRE >= 1) p0 = src[u0];
     if constexpr (PRE == 4) {
-      p0 = src[u0];
       p1 = src[u1];
       p2 = src[u2];
       p3 = src[u3];
@@ -274,8 +275,10 @@ __global__ __launch_bounds__(kEvalBlock, ((K == 16 && NF > 2) ? 2 : 3)) void poi
       {
         uint4 *t4 = reinterpret_cast<uint4 *>(tab);
         const uint32_t u = threadIdx.x;
-        if constexpr (PRE == 4) {
+        if constexpr (PRE >= 1) {
           if (u < nvec) t4[u] = p0;
+        }
+        if constexpr (PRE == 4) {
           if (u + kEvalBlock < nvec) t4[u + kEvalBlock] = p1;
           if (u + 2 * kEvalBlock < nvec) t4[u + 2 * kEvalBlock] = p2;
           if (u + 3 * kEvalBlock < nvec) t4[u + 3 * kEvalBlock] = p3;
