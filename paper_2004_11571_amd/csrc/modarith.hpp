@@ -229,17 +229,6 @@ __device__ __forceinline__ uint32_t reduce64(uint64_t v, const Mod32 &m) {
   return add_mod(a, reduce32((uint32_t)v, m), m.p);
 }
 
-// Montgomery's product for 32-bit residues (R = 2^32): x y / R mod p, lazy
-// in [0, 2p), for x < 2p, y < p (so x y + m p < 2^64) and np = -p^{-1} mod
-// 2^32.  Three instructions (the 64-bit product, m = lo(x y) np, then
-// x y + m p, whose high word is the result) and no precomputed quotient of
-// y, whose Montgomery form y R mod p is stored instead of y.
-__device__ __forceinline__ uint32_t mont_mul32(uint32_t x, uint32_t y, uint32_t p, uint32_t np) {
-  const uint64_t t = (uint64_t)x * y;
-  const uint32_t mm = (uint32_t)t * np;
-  return (uint32_t)(((uint64_t)mm * p + t) >> 32);
-}
-
 __device__ __forceinline__ uint32_t pow_mod(uint32_t base, uint64_t e, const Mod32 &m) {
   uint32_t r = 1u % m.p;
   while (e) {
